@@ -1,0 +1,496 @@
+"""FP64 CPU oracle: the WENO5-CT ideal-MHD step, written out from the paper.
+
+Test infrastructure (see the package docstring): only the tests, the smoke
+check and the CPU-baseline leg of the benchmark use this module.
+
+Layout: scalars on zones are tensors [nz, ny, nx]; grid axis 0 = x is the last
+tensor dimension.  A face-centred array ``f`` of direction ``d`` holds at index
+(i, j, k) the value on the forward face (i+1/2 along d), the paper's convention
+for b (Sect. 2.3).  Edge arrays hold at (i, j, k) the value on the edge that
+shares the forward corner: E_z at (i+1/2, j+1/2, k), E_x at (i, j+1/2, k+1/2),
+E_y at (i+1/2, j, k+1/2) -- the corner fluxes Omega_x, Omega_y, Omega_z of
+eq. (ox1)-(ox3) in that order.
+
+Readings of passages that are garbled or silent (numbered as in the design doc):
+  R1  total pressure P* = P + |B|^2/2 (eq. for P* drops the parentheses)
+  R2  fast/slow speeds c^2 = (a^2 + b^2 +- D)/2 with
+      D = sqrt((a^2 - b^2)^2 + 4 a^2 b_perp^2), the expanded radicand of
+      eq. (slow)/(fast) with the 1/2 placed on the whole bracket; the slow speed
+      from the product of the roots, c_slow^2 = a^2 b_n^2 / c_fast^2
+  R3  Alfven speed |B_n|/sqrt(rho)
+  R4  Appendix A headings swapped: m = 2, 6 are the Alfven waves, m = 3, 5 slow
+  R5  fast-mode left eigenvector: the 1/(2 c_s^2) prefactor applies to every
+      component and the components are the ones of the slow row with the
+      fast/slow roles exchanged (the printed row is not a left eigenvector)
+  R6  entropy right eigenvector energy component v^2/2
+  R7  beta normalised by sqrt(B_t1^2 + B_t2^2)
+  R8  degenerate branch (alpha_f, alpha_s) = (1/sqrt2, 1/sqrt2); alpha_f^2 and
+      alpha_s^2 from (1 +- (a^2 - b^2)/D)/2 clamped to [0, 1], which equals
+      eq. (alpha) and is exactly 1/0 when B_perp = 0 (the explicit degeneracy
+      setting the appendix recommends)
+  R9  CT transport fluxes T^d_a = F_d[B_a] + <B_d v_a> (the d-face average of
+      the two zones), i.e. eq. (fct1)-(fct6) in the frame of each sweep
+  R10 face state for L, R: arithmetic mean of the primitive states of the two
+      zones sharing the face
+  R11 SSP-RK3 (Shu-Osher) in increment form, CFL 0.4, in place of the RK4 of
+      Sect. 2.1; classical RK4 is kept as :func:`step_rk4`
+  R12 zone-centred B is never advanced by the WENO flux; it is re-interpolated
+      from the face field after every stage (Sect. 2.3, 3D step list)
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import torch
+
+DT = torch.float64
+
+
+@dataclasses.dataclass
+class Config:
+    nx: int
+    ny: int
+    nz: int
+    h: float                  # zone size (one Delta x for all directions, Sect. 2.3)
+    gamma: float = 5.0 / 3.0
+    cfl: float = 0.4
+    eps: float = 1e-6         # WENO epsilon (Sect. 2.2)
+    eps_B: float = 1e-30      # degeneracy threshold (Appendix A)
+    weights: str = "js"       # "js" (Jiang-Shu) or "z" (WENO-Z)
+    eps_Z: float = 1e-40
+
+
+def cubic(n: int, L: float = 1.0, **kw) -> Config:
+    return Config(n, n, n, L / n, **kw)
+
+
+# ----------------------------------------------------------------------------
+# grid helpers
+# ----------------------------------------------------------------------------
+
+def at(f: torch.Tensor, o: int, axis: int) -> torch.Tensor:
+    """Value at index i+o along grid axis ``axis`` (0=x, 1=y, 2=z), periodic.
+
+    Works for any tensor whose last three dimensions are (z, y, x)."""
+    return torch.roll(f, shifts=-o, dims=f.dim() - 1 - axis)
+
+
+def frame(axis: int):
+    """Sweep frame (n, t1, t2): x -> (x, y, z), y -> (y, z, x), z -> (z, x, y)."""
+    return axis, (axis + 1) % 3, (axis + 2) % 3
+
+
+def interp4(b_a: torch.Tensor, axis: int) -> torch.Tensor:
+    """Zone-centred component from its face values, fourth order (Sect. 2.3):
+    B_i = (-b_{i-2} + 9 b_{i-1} + 9 b_i - b_{i+1}) / 16, b_i on face i+1/2."""
+    return (-at(b_a, -2, axis) + 9.0 * at(b_a, -1, axis) + 9.0 * b_a - at(b_a, 1, axis)) / 16.0
+
+
+def zone_B(b: torch.Tensor) -> torch.Tensor:
+    return torch.stack([interp4(b[a], a) for a in range(3)])
+
+
+def curl_edges(A: torch.Tensor, h: float) -> torch.Tensor:
+    """Face field from an edge vector potential by first-order differences
+    (Sect. 4.1): b = curl_h A, with A_x at (i, j+1/2, k+1/2) etc."""
+    Ax, Ay, Az = A[0], A[1], A[2]
+    bx = (Az - at(Az, -1, 1)) / h - (Ay - at(Ay, -1, 2)) / h
+    by = (Ax - at(Ax, -1, 2)) / h - (Az - at(Az, -1, 0)) / h
+    bz = (Ay - at(Ay, -1, 0)) / h - (Ax - at(Ax, -1, 1)) / h
+    return torch.stack([bx, by, bz])
+
+
+def div_faces(b: torch.Tensor, h: float) -> torch.Tensor:
+    """Zone divergence of the face field (the CT constraint, eq. divb)."""
+    return ((b[0] - at(b[0], -1, 0)) + (b[1] - at(b[1], -1, 1)) + (b[2] - at(b[2], -1, 2))) / h
+
+
+# ----------------------------------------------------------------------------
+# state
+# ----------------------------------------------------------------------------
+
+def init_from_potential(rho, v, A, P0: float, B0, cfg: Config):
+    """Conserved state from primitive fields and an edge vector potential:
+    b = B0 + curl_h A, zone B by fourth-order interpolation, m = rho v and
+    E = P/(gamma-1) + (rho v^2 + B^2)/2 (eq. P)."""
+    rho = torch.as_tensor(rho, dtype=DT)
+    v = torch.as_tensor(v, dtype=DT)
+    A = torch.as_tensor(A, dtype=DT)
+    b = curl_edges(A, cfg.h)
+    b = torch.stack([b[a] + float(B0[a]) for a in range(3)])
+    B = zone_B(b)
+    m = rho * v
+    E = P0 / (cfg.gamma - 1.0) + 0.5 * (rho * (v * v).sum(0) + (B * B).sum(0))
+    return dict(rho=rho, m=m, E=E, b=b)
+
+
+def primitives(U, gamma: float):
+    """rho, v, zone B and gas pressure from the conserved state (eq. P)."""
+    rho, m, E = U["rho"], U["m"], U["E"]
+    B = zone_B(U["b"])
+    v = m / rho
+    P = (gamma - 1.0) * (E - 0.5 * ((m * v).sum(0) + (B * B).sum(0)))
+    return rho, v, B, P
+
+
+# ----------------------------------------------------------------------------
+# fluxes, wave speeds, eigensystem (Sect. 2, Appendix A), in a sweep frame
+# ----------------------------------------------------------------------------
+
+def flux_vector(rho, mn, mt1, mt2, E, vn, vt1, vt2, Bn, Bt1, Bt2, P):
+    """The seven non-trivial components of the flux along n, eq. (fluxes), in the
+    order of the characteristic state (rho, m_n, m_t1, m_t2, B_t1, B_t2, E).
+    The B_n component is identically zero and B_n is a parameter."""
+    Pstar = P + 0.5 * (Bn * Bn + Bt1 * Bt1 + Bt2 * Bt2)              # R1
+    vB = vn * Bn + vt1 * Bt1 + vt2 * Bt2
+    return torch.stack([
+        rho * vn,
+        rho * vn * vn + Pstar - Bn * Bn,
+        rho * vn * vt1 - Bn * Bt1,
+        rho * vn * vt2 - Bn * Bt2,
+        Bt1 * vn - Bn * vt1,
+        Bt2 * vn - Bn * vt2,
+        (E + Pstar) * vn - Bn * vB,
+    ], dim=-1)
+
+
+def wave_speeds(rho, Bn, Bt1, Bt2, P, gamma: float):
+    """c_fast, c_A, c_slow along n, eq. (slow), (fast), (ca) with readings R2, R3."""
+    a2 = gamma * P / rho                     # c_s^2
+    b2 = (Bn * Bn + Bt1 * Bt1 + Bt2 * Bt2) / rho
+    bn2 = Bn * Bn / rho
+    bperp2 = (Bt1 * Bt1 + Bt2 * Bt2) / rho
+    D = torch.sqrt((a2 - b2) ** 2 + 4.0 * a2 * bperp2)
+    cf2 = 0.5 * (a2 + b2 + D)
+    cs2 = torch.where(cf2 > 0, a2 * bn2 / torch.where(cf2 > 0, cf2, torch.ones_like(cf2)),
+                      torch.zeros_like(cf2))
+    return torch.sqrt(cf2), torch.sqrt(bn2), torch.sqrt(cs2)
+
+
+def eigenvalues(vn, c_fast, c_A, c_slow):
+    """lambda(m), m = 1..7: v -+ c_fast, v -+ c_A, v -+ c_slow, v (Appendix A)."""
+    return torch.stack([vn - c_fast, vn - c_A, vn - c_slow, vn,
+                        vn + c_slow, vn + c_A, vn + c_fast], dim=-1)
+
+
+def eigenvectors(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P, gamma: float, eps_B: float):
+    """Left and right eigenvectors of the 7x7 flux Jacobian (Appendix A).
+
+    Returns L[..., m, j] (row m is L(m)) and R[..., j, m] (column m is R(m)),
+    with the upper signs of the appendix for m = 1, 2, 3 (lambda = v - c) and
+    the lower signs for m = 7, 6, 5.  Readings R2, R4-R8 apply."""
+    a2 = gamma * P / rho
+    cs = torch.sqrt(a2)                                   # sound speed, stored (Appendix A)
+    sr = torch.sqrt(rho)
+    b2 = (Bn * Bn + Bt1 * Bt1 + Bt2 * Bt2) / rho
+    Bperp2 = Bt1 * Bt1 + Bt2 * Bt2
+    D = torch.sqrt((a2 - b2) ** 2 + 4.0 * a2 * Bperp2 / rho)
+    cf2 = 0.5 * (a2 + b2 + D)
+    c_fast = torch.sqrt(cf2)
+    cs2_slow = torch.where(cf2 > 0, a2 * (Bn * Bn / rho) / torch.where(cf2 > 0, cf2, torch.ones_like(cf2)),
+                           torch.zeros_like(cf2))
+    c_slow = torch.sqrt(cs2_slow)
+
+    # beta (R7) and sgn(B_n)
+    big = Bperp2 > eps_B
+    nb = torch.sqrt(torch.where(big, Bperp2, torch.ones_like(Bperp2)))
+    beta_y = torch.where(big, Bt1 / nb, torch.full_like(Bt1, 1.0 / math.sqrt(2.0)))
+    beta_z = torch.where(big, Bt2 / nb, torch.full_like(Bt2, 1.0 / math.sqrt(2.0)))
+    sgn = torch.where(Bn >= eps_B, torch.ones_like(Bn), -torch.ones_like(Bn))
+
+    # alpha_f, alpha_s (eq. alpha, R8)
+    nondeg = torch.sqrt(D) >= eps_B
+    Dsafe = torch.where(nondeg, D, torch.ones_like(D))
+    r = (a2 - b2) / Dsafe
+    af2 = torch.clamp(0.5 * (1.0 + r), 0.0, 1.0)
+    as2 = torch.clamp(0.5 * (1.0 - r), 0.0, 1.0)
+    alpha_f = torch.where(nondeg, torch.sqrt(af2), torch.full_like(D, 1.0 / math.sqrt(2.0)))
+    alpha_s = torch.where(nondeg, torch.sqrt(as2), torch.full_like(D, 1.0 / math.sqrt(2.0)))
+
+    gamma_1 = (gamma - 1.0) / 2.0
+    gamma_2 = (gamma - 2.0) / (gamma - 1.0)
+    tau = (gamma - 1.0) / a2
+    v2 = vn * vn + vt1 * vt1 + vt2 * vt2
+    bv = beta_y * vt1 + beta_z * vt2
+    Gamma_f = alpha_f * c_fast * vn - alpha_s * c_slow * sgn * bv
+    Gamma_a = sgn * (beta_z * vt1 - beta_y * vt2)
+    Gamma_s = alpha_s * c_slow * vn + alpha_f * c_fast * sgn * bv
+    half_a2 = 1.0 / (2.0 * a2)
+    zero = torch.zeros_like(rho)
+    one = torch.ones_like(rho)
+
+    L_rows = [None] * 7
+    R_cols = [None] * 7
+    for m, sg in ((0, +1.0), (6, -1.0)):        # fast: m=1 upper (+), m=7 lower (-)
+        L_rows[m] = [half_a2 * (alpha_f * gamma_1 * v2 + sg * Gamma_f),
+                     half_a2 * ((1.0 - gamma) * alpha_f * vn - sg * alpha_f * c_fast),
+                     half_a2 * ((1.0 - gamma) * alpha_f * vt1 + sg * c_slow * alpha_s * beta_y * sgn),
+                     half_a2 * ((1.0 - gamma) * alpha_f * vt2 + sg * c_slow * alpha_s * beta_z * sgn),
+                     half_a2 * ((1.0 - gamma) * alpha_f * Bt1 + sr * cs * alpha_s * beta_y),
+                     half_a2 * ((1.0 - gamma) * alpha_f * Bt2 + sr * cs * alpha_s * beta_z),
+                     half_a2 * ((gamma - 1.0) * alpha_f)]
+        R_cols[m] = [alpha_f,
+                     alpha_f * (vn - sg * c_fast),
+                     alpha_f * vt1 + sg * c_slow * alpha_s * beta_y * sgn,
+                     alpha_f * vt2 + sg * c_slow * alpha_s * beta_z * sgn,
+                     cs * alpha_s * beta_y / sr,
+                     cs * alpha_s * beta_z / sr,
+                     alpha_f * (0.5 * v2 + c_fast * c_fast - gamma_2 * a2) - sg * Gamma_f]
+    for m, sg in ((1, +1.0), (5, -1.0)):        # Alfven (R4): m=2 upper, m=6 lower
+        L_rows[m] = [0.5 * Gamma_a, zero,
+                     -0.5 * beta_z * sgn, 0.5 * beta_y * sgn,
+                     -sg * 0.5 * sr * beta_z, sg * 0.5 * sr * beta_y, zero]
+        R_cols[m] = [zero, zero,
+                     -beta_z * sgn, beta_y * sgn,
+                     -sg * beta_z / sr, sg * beta_y / sr, -Gamma_a]
+    for m, sg in ((2, +1.0), (4, -1.0)):        # slow (R4): m=3 upper, m=5 lower
+        L_rows[m] = [half_a2 * (gamma_1 * alpha_s * v2 + sg * Gamma_s),
+                     half_a2 * ((1.0 - gamma) * alpha_s * vn - sg * alpha_s * c_slow),
+                     half_a2 * ((1.0 - gamma) * alpha_s * vt1 - sg * c_fast * alpha_f * beta_y * sgn),
+                     half_a2 * ((1.0 - gamma) * alpha_s * vt2 - sg * c_fast * alpha_f * beta_z * sgn),
+                     half_a2 * ((1.0 - gamma) * alpha_s * Bt1 - sr * cs * alpha_f * beta_y),
+                     half_a2 * ((1.0 - gamma) * alpha_s * Bt2 - sr * cs * alpha_f * beta_z),
+                     half_a2 * ((gamma - 1.0) * alpha_s)]
+        R_cols[m] = [alpha_s,
+                     alpha_s * (vn - sg * c_slow),
+                     alpha_s * vt1 - sg * c_fast * alpha_f * beta_y * sgn,
+                     alpha_s * vt2 - sg * c_fast * alpha_f * beta_z * sgn,
+                     -cs * alpha_f * beta_y / sr,
+                     -cs * alpha_f * beta_z / sr,
+                     alpha_s * (0.5 * v2 + c_slow * c_slow - gamma_2 * a2) - sg * Gamma_s]
+    L_rows[3] = [1.0 - 0.5 * tau * v2, tau * vn, tau * vt1, tau * vt2, tau * Bt1, tau * Bt2, -tau * one]
+    R_cols[3] = [one, vn, vt1, vt2, zero, zero, 0.5 * v2]                       # R6
+
+    L = torch.stack([torch.stack(row, dim=-1) for row in L_rows], dim=-2)      # [..., m, j]
+    R = torch.stack([torch.stack(col, dim=-1) for col in R_cols], dim=-1)      # [..., j, m]
+    return L, R
+
+
+# ----------------------------------------------------------------------------
+# WENO5 (Sect. 2.2)
+# ----------------------------------------------------------------------------
+
+def phi_N(a, b, c, d, cfg: Config):
+    """The WENO interpolant phi_N(a, b, c, d) of eq. (FWENO) with the Jiang-Shu
+    weights (or the WENO-Z weights, R13 in the design doc, when cfg.weights == 'z')."""
+    IS_0 = 13.0 * (a - b) ** 2 + 3.0 * (a - 3.0 * b) ** 2
+    IS_1 = 13.0 * (b - c) ** 2 + 3.0 * (b + c) ** 2
+    IS_2 = 13.0 * (c - d) ** 2 + 3.0 * (3.0 * c - d) ** 2
+    if cfg.weights == "js":
+        alpha_0 = 1.0 / (cfg.eps + IS_0) ** 2
+        alpha_1 = 6.0 / (cfg.eps + IS_1) ** 2
+        alpha_2 = 3.0 / (cfg.eps + IS_2) ** 2
+    elif cfg.weights == "z":
+        tau_5 = torch.abs(IS_0 - IS_2)
+        alpha_0 = 1.0 * (1.0 + (tau_5 / (cfg.eps_Z + IS_0)) ** 2)
+        alpha_1 = 6.0 * (1.0 + (tau_5 / (cfg.eps_Z + IS_1)) ** 2)
+        alpha_2 = 3.0 * (1.0 + (tau_5 / (cfg.eps_Z + IS_2)) ** 2)
+    else:
+        raise ValueError(cfg.weights)
+    s = alpha_0 + alpha_1 + alpha_2
+    omega_0 = alpha_0 / s
+    omega_2 = alpha_2 / s
+    return omega_0 * (a - 2.0 * b + c) / 3.0 + (omega_2 - 0.5) * (b - 2.0 * c + d) / 6.0
+
+
+def weno_split_flux(Fs, qs, alpha, cfg: Config):
+    """Characteristic flux at i+1/2 from projected zone values, eq. (FWENO).
+
+    ``Fs[k]``, ``qs[k]`` for k = 0..5 are F^s, q^s of zones i-2 .. i+3 (any
+    trailing shape); ``alpha`` the Lax-Friedrichs speed of each component."""
+    dF = [Fs[k + 1] - Fs[k] for k in range(5)]       # Delta F^s at i-3/2 .. i+5/2
+    dq = [qs[k + 1] - qs[k] for k in range(5)]
+    dFp = [0.5 * (dF[k] + alpha * dq[k]) for k in range(5)]
+    dFm = [0.5 * (dF[k] - alpha * dq[k]) for k in range(5)]
+    central = (-Fs[1] + 7.0 * Fs[2] + 7.0 * Fs[3] - Fs[4]) / 12.0
+    return (central
+            - phi_N(dFp[0], dFp[1], dFp[2], dFp[3], cfg)
+            + phi_N(dFm[4], dFm[3], dFm[2], dFm[1], cfg))
+
+
+def lf_speed(lam, axis: int):
+    """alpha(m) = max(|lambda_i(m)|, |lambda_{i+1}(m)|) on face i+1/2 (Sect. 2.2),
+    for zone eigenvalues ``lam`` [..., 7]."""
+    return torch.maximum(lam.abs(), at(lam.movedim(-1, 0), 1, axis).movedim(0, -1).abs())
+
+
+# ----------------------------------------------------------------------------
+# one directional sweep
+# ----------------------------------------------------------------------------
+
+def sweep(U, axis: int, cfg: Config, prims=None):
+    """WENO fluxes on the forward faces along ``axis`` (Sect. 2.2, 3D step list).
+
+    Returns (F_face, T): F_face[..., 7] the interface flux in the sweep frame,
+    T[2, ...] the CT transport fluxes T^n_t1, T^n_t2 of eq. (fct1)-(fct6) (R9)."""
+    rho, v, B, P = prims if prims is not None else primitives(U, cfg.gamma)
+    n, t1, t2 = frame(axis)
+    m, E = U["m"], U["E"]
+    vn, vt1, vt2 = v[n], v[t1], v[t2]
+    Bn, Bt1, Bt2 = B[n], B[t1], B[t2]
+
+    # zone values (steps 2 of the 3D step list): state q, flux F, eigenvalues
+    q = torch.stack([rho, m[n], m[t1], m[t2], Bt1, Bt2, E], dim=-1)
+    F = flux_vector(rho, m[n], m[t1], m[t2], E, vn, vt1, vt2, Bn, Bt1, Bt2, P)
+    c_fast, c_A, c_slow = wave_speeds(rho, Bn, Bt1, Bt2, P, cfg.gamma)
+    lam = eigenvalues(vn, c_fast, c_A, c_slow)
+
+    # face state by arithmetic averaging of zones i and i+1 (R10)
+    def face(x):
+        return 0.5 * (x + at(x, 1, axis))
+    L, R = eigenvectors(face(rho), face(vn), face(vt1), face(vt2), face(Bn), face(Bt1),
+                        face(Bt2), face(P), cfg.gamma, cfg.eps_B)
+    alpha = lf_speed(lam, axis)
+
+    # characteristic projections F^s_k(m) = L(m).F_k, q^s_k(m) = L(m).q_k, k = i-2..i+3
+    def shifted(x, o):
+        return at(x.movedim(-1, 0), o, axis).movedim(0, -1)
+    Fs = [torch.einsum("...mj,...j->...m", L, shifted(F, o)) for o in range(-2, 4)]
+    qs = [torch.einsum("...mj,...j->...m", L, shifted(q, o)) for o in range(-2, 4)]
+    Fs_face = weno_split_flux(Fs, qs, alpha, cfg)
+    F_face = torch.einsum("...jm,...m->...j", R, Fs_face)
+
+    # CT transport fluxes (R9): the B_t components plus the face mean of B_n v_t
+    T = torch.stack([F_face[..., 4] + face(Bn * vt1), F_face[..., 5] + face(Bn * vt2)])
+    return F_face, T
+
+
+# ----------------------------------------------------------------------------
+# right-hand side, CT, time step
+# ----------------------------------------------------------------------------
+
+def rhs(U, cfg: Config, return_parts: bool = False):
+    """dU/dt of the semi-discrete scheme: conservative WENO flux divergence
+    (eq. num) for rho, m, E summed over the three sweeps, and the CT update of
+    the face field from the corner fluxes (eq. ox1-ox3 and the b equations)."""
+    h = cfg.h
+    prims = primitives(U, cfg.gamma)
+    k_rho = torch.zeros_like(U["rho"])
+    k_m = torch.zeros_like(U["m"])
+    k_E = torch.zeros_like(U["E"])
+    Tt = {}
+    parts = {}
+    for axis in range(3):
+        n, t1, t2 = frame(axis)
+        F_face, T = sweep(U, axis, cfg, prims)
+        div = [-(F_face[..., c] - at(F_face[..., c], -1, axis)) / h for c in range(7)]
+        k_rho = k_rho + div[0]
+        k_m = k_m + torch.stack([div[1 + [n, t1, t2].index(c)] for c in range(3)])
+        k_E = k_E + div[6]
+        Tt[(axis, t1)] = T[0]
+        Tt[(axis, t2)] = T[1]
+        parts[axis] = (F_face, T)
+    X, Y, Z = 0, 1, 2
+    f_y, f_z = Tt[(X, Y)], Tt[(X, Z)]       # f*_y, f*_z on x-faces
+    g_z, g_x = Tt[(Y, Z)], Tt[(Y, X)]       # g*_z, g*_x on y-faces
+    h_x, h_y = Tt[(Z, X)], Tt[(Z, Y)]       # h*_x, h*_y on z-faces
+    Omega_x = 0.5 * (g_x + at(g_x, 1, X)) - 0.5 * (f_y + at(f_y, 1, Y))   # eq. (ox1), edge (i+1/2, j+1/2, k)
+    Omega_y = 0.5 * (h_y + at(h_y, 1, Y)) - 0.5 * (g_z + at(g_z, 1, Z))   # eq. (ox2), edge (i, j+1/2, k+1/2)
+    Omega_z = 0.5 * (f_z + at(f_z, 1, Z)) - 0.5 * (h_x + at(h_x, 1, X))   # eq. (ox3), edge (i+1/2, j, k+1/2)
+    k_bx = -(Omega_x - at(Omega_x, -1, Y)) / h + (Omega_z - at(Omega_z, -1, Z)) / h
+    k_by = -(Omega_y - at(Omega_y, -1, Z)) / h + (Omega_x - at(Omega_x, -1, X)) / h
+    k_bz = -(Omega_z - at(Omega_z, -1, X)) / h + (Omega_y - at(Omega_y, -1, Y)) / h
+    k = dict(rho=k_rho, m=k_m, E=k_E, b=torch.stack([k_bx, k_by, k_bz]))
+    if return_parts:
+        return k, dict(sweeps=parts, Omega=(Omega_x, Omega_y, Omega_z))
+    return k
+
+
+def max_signal_speeds(U, cfg: Config):
+    """max over zones of |v_d| + c_fast^d for d = x, y, z (denominator of eq. cfl)."""
+    rho, v, B, P = primitives(U, cfg.gamma)
+    out = []
+    for axis in range(3):
+        n, t1, t2 = frame(axis)
+        c_fast, _, _ = wave_speeds(rho, B[n], B[t1], B[t2], P, cfg.gamma)
+        out.append(torch.max(v[n].abs() + c_fast))
+    return torch.stack(out)
+
+
+def compute_dt(U, cfg: Config) -> float:
+    """Time step of eq. (cfl), taken at equality with cfg.cfl."""
+    s = max_signal_speeds(U, cfg)
+    return float(cfg.cfl * cfg.h / s.sum())
+
+
+def _axpy(U, k, c):
+    return {key: U[key] + c * k[key] for key in U}
+
+
+def rk_stage(stage: int, Un, acc, Us, dt: float, cfg: Config):
+    """One SSP-RK3 stage in increment form (R11).
+
+    stage 0: acc = k0,        U1 = Un + dt acc
+    stage 1: acc = k0 + k1,   U2 = Un + dt/4 acc
+    stage 2:                  Un+1 = Un + dt/6 (acc + 4 k2)
+    Returns (acc, U_next)."""
+    k = rhs(Us, cfg)
+    if stage == 0:
+        acc = {key: k[key] for key in k}
+        return acc, _axpy(Un, acc, dt)
+    if stage == 1:
+        acc = {key: acc[key] + k[key] for key in k}
+        return acc, _axpy(Un, acc, 0.25 * dt)
+    if stage == 2:
+        tot = {key: acc[key] + 4.0 * k[key] for key in k}
+        return acc, _axpy(Un, tot, dt / 6.0)
+    raise ValueError(stage)
+
+
+def step(U, cfg: Config, dt: float | None = None):
+    """One SSP-RK3 step; dt from eq. (cfl) on U unless given.  Returns (U, dt)."""
+    if dt is None:
+        dt = compute_dt(U, cfg)
+    acc, U1 = rk_stage(0, U, None, U, dt, cfg)
+    acc, U2 = rk_stage(1, U, acc, U1, dt, cfg)
+    _, U3 = rk_stage(2, U, acc, U2, dt, cfg)
+    return U3, dt
+
+
+def step_rk4(U, cfg: Config, dt: float | None = None):
+    """The classical four-stage RK4 of Sect. 2.1 with the q_save accumulator."""
+    if dt is None:
+        dt = compute_dt(U, cfg)
+    q0 = U
+    q_save = {key: -4.0 / 3.0 * q0[key] for key in q0}
+    q = q0
+    for fac, w in ((0.5, 1.0 / 3.0), (0.5, 2.0 / 3.0), (1.0, 1.0 / 3.0), (1.0 / 6.0, 1.0)):
+        k = rhs(q, cfg)
+        q = _axpy(q0, k, fac * dt)
+        q_save = {key: q_save[key] + w * q[key] for key in q}
+    return q_save, dt
+
+
+# ----------------------------------------------------------------------------
+# diagnostics
+# ----------------------------------------------------------------------------
+
+def diagnostics(U, cfg: Config):
+    """max|div_h b|, totals of rho, m, E, face-b sums, min rho, min P and the
+    number of zones with rho <= 0, P <= 0 or a non-finite value."""
+    rho, v, B, P = primitives(U, cfg.gamma)
+    bad = (rho <= 0) | (P <= 0) | ~torch.isfinite(rho) | ~torch.isfinite(P) | ~torch.isfinite(U["E"])
+    return dict(
+        max_divb=float(div_faces(U["b"], cfg.h).abs().max()),
+        mass=float(U["rho"].sum()),
+        mom=[float(U["m"][c].sum()) for c in range(3)],
+        energy=float(U["E"].sum()),
+        bflux=[float(U["b"][c].sum()) for c in range(3)],
+        min_rho=float(rho.min()),
+        min_p=float(P.min()),
+        n_unphysical=int(bad.sum()),
+    )
+
+
+def l1_error(Ua, Ub, n_zones: int | None = None):
+    """Per-variable L1 and the geometric norm of Sect. 3 (eq. for L_1).
+
+    Variables: rho, m_x, m_y, m_z, zone B_x, B_y, B_z, E."""
+    def comps(U):
+        B = zone_B(U["b"])
+        return [U["rho"], U["m"][0], U["m"][1], U["m"][2], B[0], B[1], B[2], U["E"]]
+    ca, cb = comps(Ua), comps(Ub)
+    N = n_zones or ca[0].numel()
+    per = [float((x - y).abs().sum() / N) for x, y in zip(ca, cb)]
+    return per, math.sqrt(sum(p * p for p in per))

@@ -1,0 +1,143 @@
+"""Seeded synthetic input fields for the WENO5-CT MHD step.
+
+This module draws random Fourier coefficients and evaluates them on the
+staggered mesh.  It holds none of the method's arithmetic: no curl, no
+interpolation, no energy or flux.  It returns the raw initial fields that both
+the HIP path and the CPU oracle turn into a conserved state on their own:
+
+* ``rho``   zone-centred density                      [nz, ny, nx]
+* ``v``     zone-centred velocity (x, y, z)           [3, nz, ny, nx]
+* ``A``     edge-centred vector potential (x, y, z)   [3, nz, ny, nx]
+            A_x at (i, j+1/2, k+1/2), A_y at (i+1/2, j, k+1/2),
+            A_z at (i+1/2, j+1/2, k), the placement of Sect. 4.1 (linear waves)
+* ``B0``, ``P0`` uniform background field and pressure.
+
+Recipe (documented in DESIGN.md, "Synthetic inputs"):
+
+* mode set K(kmax) = {k in Z^3 : 0 < |k| <= kmax}, one representative of each
+  +-k pair (k_z > 0, or k_z = 0 and k_y > 0, or k_z = k_y = 0 and k_x > 0),
+  listed in lexicographic (k_z, k_y, k_x) order;
+* density  rho = 1 + 0.1 * sum_{n<8} sin(2 pi k_n . x + phi_n), k_n uniform
+  in K(min(kmax, 4)), phi_n uniform in [0, 2 pi);
+* velocity v = sum_{k in K} a_k cos(2 pi k.x) + c_k sin(2 pi k.x), a_k, c_k
+  standard normal 3-vectors, scaled so that the grid rms of |v| is ``v_rms``;
+* potential A: same form with its own draws, scaled so that the rms of the
+  continuous field curl A is ``b_rms``;
+* the box is the unit cube, zone centres at ((i+1/2)h, (j+1/2)h, (k+1/2)h).
+
+Draw order from ``numpy.random.Generator(PCG64(seed))``: the 8 density mode
+indices, the 8 density phases, then a_k, c_k for every velocity mode (each a
+3-vector, in mode order), then the same for A.  The Fourier sums are evaluated
+with an inverse FFT on the N^3 grid (exact for N > 2 kmax), so the same seed
+sampled at a smaller N gives the same continuous field.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+__all__ = ["Fields", "mode_set", "random_fields", "config_fields"]
+
+
+@dataclasses.dataclass
+class Fields:
+    rho: np.ndarray          # [nz, ny, nx] float64
+    v: np.ndarray            # [3, nz, ny, nx] float64
+    A: np.ndarray            # [3, nz, ny, nx] float64 (edge placement above)
+    B0: tuple                # uniform field (Bx, By, Bz)
+    P0: float                # uniform pressure
+    gamma: float = 5.0 / 3.0
+
+
+def mode_set(kmax: int) -> np.ndarray:
+    """Half-space representatives of the integer wave vectors with 0<|k|<=kmax."""
+    out = []
+    r = int(kmax)
+    for kz in range(-r, r + 1):
+        for ky in range(-r, r + 1):
+            for kx in range(-r, r + 1):
+                k2 = kx * kx + ky * ky + kz * kz
+                if k2 == 0 or k2 > kmax * kmax:
+                    continue
+                if kz > 0 or (kz == 0 and ky > 0) or (kz == 0 and ky == 0 and kx > 0):
+                    out.append((kx, ky, kz))
+    return np.array(out, dtype=np.int64)
+
+
+def _evaluate(n: int, ks: np.ndarray, a: np.ndarray, c: np.ndarray, offset) -> np.ndarray:
+    """sum_k a_k cos(2 pi k.x) + c_k sin(2 pi k.x) at x = (idx + offset)/n.
+
+    ``offset`` is (ox, oy, oz) in units of the zone size.  Returns [nz, ny, nx].
+    """
+    if 2 * int(np.abs(ks).max()) >= n:
+        raise ValueError(f"grid n={n} too small for modes up to |k_i|={np.abs(ks).max()}")
+    grid = np.zeros((n, n, n), dtype=np.complex128)
+    ox, oy, oz = offset
+    for (kx, ky, kz), ak, ck in zip(ks, a, c):
+        phase = np.exp(2j * np.pi * (kx * ox + ky * oy + kz * oz) / n)
+        coef = (ak - 1j * ck) * phase            # a cos + c sin = Re[(a - i c) e^{i theta}]
+        grid[kz % n, ky % n, kx % n] += coef
+    # f[idx] = Re sum_k C_k exp(2 pi i k.idx / n) = Re(n^3 * ifftn(grid))
+    return np.real(np.fft.ifftn(grid) * (n ** 3))
+
+
+def random_fields(n: int, seed: int, v_rms: float, kmax: int = 4, b_rms: float = 0.1,
+                  B0=(1.0, 0.5, 0.0), P0: float = 0.6, gamma: float = 5.0 / 3.0) -> Fields:
+    """Seeded random initial fields on an n^3 unit box (recipe in the module doc)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kset_rho = mode_set(min(kmax, 4))
+    kset = mode_set(kmax)
+    idx = rng.integers(0, len(kset_rho), size=8)
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=8)
+    av = rng.standard_normal((len(kset), 3))
+    cv = rng.standard_normal((len(kset), 3))
+    aA = rng.standard_normal((len(kset), 3))
+    cA = rng.standard_normal((len(kset), 3))
+
+    # density: 0.1 sin(theta + phi) = 0.1 (sin phi) cos theta + 0.1 (cos phi) sin theta
+    ks_r = kset_rho[idx]
+    rho = 1.0 + _evaluate(n, ks_r, 0.1 * np.sin(phi), 0.1 * np.cos(phi), (0.5, 0.5, 0.5))
+
+    # velocity: grid mean of |v|^2 is 1/2 sum_k (|a_k|^2 + |c_k|^2) (no aliasing for n > 2 kmax)
+    msq = 0.5 * float(np.sum(av ** 2) + np.sum(cv ** 2))
+    sv = v_rms / np.sqrt(msq) if v_rms > 0 else 0.0
+    v = np.stack([_evaluate(n, kset, sv * av[:, d], sv * cv[:, d], (0.5, 0.5, 0.5))
+                  for d in range(3)])
+
+    # potential: continuous curl of a cos(2 pi k.x) is -2 pi (k x a) sin(...), so
+    # mean |curl A|^2 = 1/2 (2 pi)^2 sum_k (|k x a_k|^2 + |k x c_k|^2)
+    kf = kset.astype(np.float64)
+    cm = 0.5 * (2 * np.pi) ** 2 * float(np.sum(np.cross(kf, aA) ** 2) + np.sum(np.cross(kf, cA) ** 2))
+    sA = b_rms / np.sqrt(cm) if b_rms > 0 else 0.0
+    edge_offsets = [(0.5, 1.0, 1.0), (1.0, 0.5, 1.0), (1.0, 1.0, 0.5)]
+    A = np.stack([_evaluate(n, kset, sA * aA[:, d], sA * cA[:, d], edge_offsets[d])
+                  for d in range(3)])
+    return Fields(rho=np.ascontiguousarray(rho), v=np.ascontiguousarray(v),
+                  A=np.ascontiguousarray(A), B0=tuple(float(x) for x in B0), P0=float(P0),
+                  gamma=float(gamma))
+
+
+# Named workloads: grid, steps and generator parameters.
+CONFIGS = {
+    # one FP64 step on 32^3, Mach 0.1, beta ~ 1
+    "c1_32": dict(n=32, steps=1, seed=1, v_rms=0.1, kmax=4, B0=(1.0, 0.5, 0.0)),
+    # 10 FP64 steps on 256^3, Mach 2, beta ~ 1 (the throughput workload)
+    "c2_256": dict(n=256, steps=10, seed=1, v_rms=2.0, kmax=4, B0=(1.0, 0.5, 0.0)),
+    # same generator sampled at 64^3: the oracle-sized version of the 256^3 run
+    "c2_64": dict(n=64, steps=10, seed=1, v_rms=2.0, kmax=4, B0=(1.0, 0.5, 0.0)),
+    # mixed precision workload, Mach 0.1 inputs on 256^3
+    "c3_256": dict(n=256, steps=10, seed=1, v_rms=0.1, kmax=4, B0=(1.0, 0.5, 0.0)),
+    # adjoint workload, Mach 1 on 128^3, 20 steps
+    "c4_128": dict(n=128, steps=20, seed=1, v_rms=1.0, kmax=4, B0=(1.0, 0.5, 0.0)),
+    # Mach 5 turbulence on 512^3, k <= 8, beta = 0.5
+    "c5_512": dict(n=512, steps=10, seed=1, v_rms=5.0, kmax=8,
+                   B0=tuple(float(np.sqrt(2.4 / 1.25)) * x for x in (1.0, 0.5, 0.0))),
+}
+
+
+def config_fields(name: str, n: int | None = None, seed: int | None = None) -> Fields:
+    """Fields of a named workload, optionally resampled at another grid size/seed."""
+    c = CONFIGS[name]
+    return random_fields(n or c["n"], seed if seed is not None else c["seed"], c["v_rms"],
+                         kmax=c["kmax"], B0=c["B0"])

@@ -1,0 +1,110 @@
+"""Pins of the oracle's WENO5 flux (Sect. 2.2, eq. FWENO).
+
+* The difference form of eq. (FWENO) with phi_N equals the textbook three-stencil
+  Jiang-Shu reconstruction (candidate parabolas + smoothness indicators beta_k)
+  with epsilon/12, since IS_k = 12 beta_k.  The textbook form is written here
+  from its own definition, not from the oracle's code.
+* With epsilon -> infinity the weights become the linear ones and the flux is the
+  linear fifth-order upwind flux (2, -13, 47, 27, -3)/60.
+* A 1D scalar advection run with the oracle's split flux converges at 5th order.
+"""
+import math
+
+import numpy as np
+import torch
+
+from oracle import mhd
+
+T64 = torch.float64
+
+
+def textbook_js_plus(f, eps):
+    """Left-biased WENO5-JS value at i+1/2 from f_{i-2..i+2} (Jiang & Shu 1996)."""
+    fm2, fm1, f0, fp1, fp2 = f
+    q0 = (2 * fm2 - 7 * fm1 + 11 * f0) / 6
+    q1 = (-fm1 + 5 * f0 + 2 * fp1) / 6
+    q2 = (2 * f0 + 5 * fp1 - fp2) / 6
+    b0 = 13 / 12 * (fm2 - 2 * fm1 + f0) ** 2 + 0.25 * (fm2 - 4 * fm1 + 3 * f0) ** 2
+    b1 = 13 / 12 * (fm1 - 2 * f0 + fp1) ** 2 + 0.25 * (fm1 - fp1) ** 2
+    b2 = 13 / 12 * (f0 - 2 * fp1 + fp2) ** 2 + 0.25 * (3 * f0 - 4 * fp1 + fp2) ** 2
+    a0, a1, a2 = 0.1 / (eps + b0) ** 2, 0.6 / (eps + b1) ** 2, 0.3 / (eps + b2) ** 2
+    s = a0 + a1 + a2
+    return (a0 * q0 + a1 * q1 + a2 * q2) / s
+
+
+def split_values(seed, n, smooth):
+    g = torch.Generator().manual_seed(seed)
+    if smooth:
+        x = torch.linspace(0, 1, 6, dtype=T64)[:, None]
+        ph = torch.rand(1, n, generator=g, dtype=T64) * 6.28
+        amp = torch.rand(1, n, generator=g, dtype=T64)
+        return amp * torch.sin(2 * math.pi * 0.3 * x + ph)
+    return torch.randn(6, n, generator=g, dtype=T64) * torch.rand(1, n, generator=g, dtype=T64) * 3
+
+
+def test_phiN_equals_textbook_js():
+    cfg = mhd.Config(4, 4, 4, 0.25)
+    for smooth in (False, True):
+        fp = split_values(1, 5000, smooth)            # f^+ on zones i-2..i+3
+        fmv = split_values(2, 5000, smooth)           # f^- on zones i-2..i+3
+        # the oracle's characteristic flux is built from F^s and q^s with F^+- = (F +- alpha q)/2;
+        # choose F = f^+ + f^-, q = f^+ - f^- and alpha = 1
+        Fs = [fp[k] + fmv[k] for k in range(6)]
+        qs = [fp[k] - fmv[k] for k in range(6)]
+        got = mhd.weno_split_flux(Fs, qs, torch.ones(()), cfg)
+        plus = textbook_js_plus([fp[k] for k in range(0, 5)], cfg.eps / 12)
+        minus = textbook_js_plus([fmv[k] for k in range(5, 0, -1)], cfg.eps / 12)   # mirrored stencil
+        ref = plus + minus
+        np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=2e-14 * (1 + float(ref.abs().max())))
+
+
+def test_linear_limit_is_upwind5():
+    cfg = mhd.Config(4, 4, 4, 0.25, eps=1e30)
+    g = torch.Generator().manual_seed(3)
+    f = torch.randn(6, 1000, generator=g, dtype=T64)
+    Fs = [f[k] for k in range(6)]
+    qs = [f[k] for k in range(6)]           # alpha = 1: F^+ = F, F^- = 0
+    got = mhd.weno_split_flux(Fs, qs, torch.ones(()), cfg)
+    ref = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60
+    np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=1e-14)
+
+
+def _advect(n, t_end, cfl=0.4):
+    """u_t + u_x = 0 on [0,1), f(u) = u, alpha = 1, SSP-RK3, dt ~ h^(5/3)."""
+    cfg = mhd.Config(n, 1, 1, 1.0 / n)
+    h = 1.0 / n
+    x = (torch.arange(n, dtype=T64) + 0.5) * h
+    u0 = torch.sin(2 * math.pi * x)
+    dt_target = cfl * h ** (5.0 / 3.0)
+    nt = int(math.ceil(t_end / dt_target))
+    dt = t_end / nt
+
+    def L(u):
+        st = [torch.roll(u, -o) for o in range(-2, 4)]
+        F = mhd.weno_split_flux(st, st, torch.ones(()), cfg)
+        return -(F - torch.roll(F, 1)) / h
+    u = u0.clone()
+    for _ in range(nt):
+        u1 = u + dt * L(u)
+        u2 = 0.75 * u + 0.25 * (u1 + dt * L(u1))
+        u = u / 3 + 2.0 / 3.0 * (u2 + dt * L(u2))
+    exact = torch.sin(2 * math.pi * (x - t_end))
+    return float((u - exact).abs().mean())
+
+
+def test_scalar_advection_fifth_order():
+    e = [_advect(n, 0.5) for n in (20, 40, 80)]
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert orders[-1] > 4.6, (e, orders)
+
+
+def test_lax_friedrichs_speed_bounds_both_zones():
+    """alpha(m) on face i+1/2 is the larger |lambda(m)| of zones i and i+1, so
+    both split fluxes are monotone across the face (Sect. 2.2)."""
+    g = torch.Generator().manual_seed(7)
+    for axis in range(3):
+        lam = torch.randn(5, 6, 7, 7, generator=g, dtype=T64)
+        a = mhd.lf_speed(lam, axis)
+        nxt = mhd.at(lam.movedim(-1, 0), 1, axis).movedim(0, -1)
+        assert bool((a >= lam.abs()).all()) and bool((a >= nxt.abs()).all())
+        assert bool(((a == lam.abs()) | (a == nxt.abs())).all())
