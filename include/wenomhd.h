@@ -1,0 +1,178 @@
+/*
+ * wenomhd.h -- C ABI of the MI355X (gfx950) WENO5 constrained-transport ideal
+ * MHD step of Donnert et al., "WENO-Wombat" (arXiv:1812.04278).
+ *
+ * Method: per direction, the finite-difference WENO5 flux of Sect. 2.2
+ * (eq. FWENO, Jiang-Shu weights) computed in characteristic fields with the
+ * eigenvectors of Appendix A at the face, Lax-Friedrichs split; its
+ * conservative divergence (eq. num); the CT transport fluxes (eq. fct1-fct6),
+ * corner fluxes (eq. ox1-ox3) and the face-field update of Sect. 2.3; an
+ * SSP-RK3 stage in increment form at CFL 0.4.
+ *
+ * Grid: nx * ny * nz zones, periodic in all three directions, one zone size h
+ * for every direction (Sect. 2.3 divides every difference by the same Delta x).
+ * Every array is structure-of-arrays, [component][z][y][x] with x contiguous,
+ * double precision, in device memory of the GPU that is current when the
+ * patch is created.  Conventions of the field components:
+ *   hydro  [5][nz][ny][nx]  rho, m_x, m_y, m_z, E            (zone centred)
+ *   bface  [3][nz][ny][nx]  b_x at (i+1/2, j, k), b_y at (i, j+1/2, k),
+ *                           b_z at (i, j, k+1/2)              (face centred)
+ *   bcell  [3][nz][ny][nx]  zone B, the fourth-order interpolation of bface
+ *                           (Sect. 2.3); written by the library, never read
+ *                           as an input to a step
+ *   A_edge [3][nz][ny][nx]  A_x at (i, j+1/2, k+1/2), A_y at (i+1/2, j, k+1/2),
+ *                           A_z at (i+1/2, j+1/2, k)  (Sect. 4.1 placement)
+ *
+ * Ownership: the caller owns every buffer (state, scratch, outputs).  The
+ * library never allocates device memory: it launches kernels on the caller's
+ * stream and only allocates the small host-side patch object.  A patch is used
+ * by one host thread and one stream at a time; calls are stream ordered.
+ *
+ * Errors: every call returns a wm_status and never aborts.  Argument errors
+ * are detected synchronously (nothing is launched); launch failures return
+ * WM_ERR_HIP.  Physical failures (rho <= 0, P <= 0, non-finite values) are
+ * not checked inside a step; wm_diagnostics counts them and then returns
+ * WM_ERR_UNPHYSICAL.  wm_last_error() gives a message for the last failure on
+ * the calling thread.
+ */
+#ifndef WENOMHD_H
+#define WENOMHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WM_OK = 0,
+  WM_ERR_ARG = -1,          /* invalid argument or unsupported option       */
+  WM_ERR_HIP = -2,          /* a HIP runtime call or a launch failed        */
+  WM_ERR_UNPHYSICAL = -3,   /* diagnostics found rho<=0, P<=0 or NaN/Inf    */
+  WM_ERR_STATE = -4         /* call out of order (e.g. step before binding) */
+} wm_status;
+
+typedef enum {
+  WM_FP64 = 0,              /* everything in double precision                */
+  WM_MIXED = 1              /* FP64 state, pressure recovery, eigenvector
+                               renormalisation and central flux; FP32
+                               characteristic projections, WENO weights and
+                               split fluxes                                   */
+} wm_precision;
+
+typedef enum {
+  WM_WENO_JS = 0,           /* Jiang-Shu weights, Sect. 2.2                  */
+  WM_WENO_Z = 1             /* WENO-Z weights, Sect. 2.2 (reading: the
+                               bracket (tau_5/(eps_Z + IS_k))^2)              */
+} wm_weights;
+
+typedef struct {
+  int nx, ny, nz;           /* zones per direction, each >= 1                */
+  double h;                 /* zone size (> 0)                               */
+  double gamma;             /* adiabatic index (> 1)                         */
+  double cfl;               /* Courant number for wm_compute_dt (> 0)        */
+  double eps_weno;          /* WENO epsilon, 1e-6 in the paper               */
+  double eps_B;             /* degeneracy threshold, 1e-30 in the paper      */
+  double eps_Z;             /* WENO-Z epsilon, 1e-40 in the paper            */
+  int weights;              /* wm_weights                                    */
+  int precision;            /* wm_precision                                  */
+} wm_config;
+
+typedef struct {
+  double max_divb;          /* max over zones of |div_h b| (eq. divb)        */
+  double mass;              /* sum of rho over zones                         */
+  double mom[3];            /* sums of m_x, m_y, m_z                         */
+  double energy;            /* sum of E                                      */
+  double bflux[3];          /* sums of b_x, b_y, b_z over all faces          */
+  double min_rho;           /* minimum density                               */
+  double min_p;             /* minimum gas pressure (eq. P, zone B)          */
+  long long n_unphysical;   /* zones with rho<=0, P<=0 or non-finite values  */
+} wm_diag;
+
+typedef struct wm_patch wm_patch;   /* opaque; owns no device memory */
+
+/* Fills cfg with the paper's constants (gamma 5/3, CFL 0.4, eps 1e-6,
+ * eps_B 1e-30, eps_Z 1e-40, Jiang-Shu, FP64) for an n^3 box of length 1. */
+void wm_config_default(wm_config* cfg, int n);
+
+/* Bytes of device scratch a patch with this configuration needs: the stage
+ * state, the RK accumulator, the face fluxes of the three sweeps and the
+ * reduction buffers.  Returns 0 for an invalid configuration. */
+size_t wm_scratch_bytes(const wm_config* cfg);
+
+/* Creates a patch.  `hip_stream` is a hipStream_t (NULL = default stream);
+ * `scratch` is a device buffer of at least wm_scratch_bytes(cfg) bytes,
+ * 256-byte aligned, owned by the caller and reserved for this patch. */
+wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch,
+                          size_t scratch_bytes, wm_patch** out);
+wm_status wm_patch_destroy(wm_patch* p);
+
+/* Binds the caller's state arrays (layouts above).  hydro and bface are
+ * read and advanced in place by wm_rk_stage(2) / wm_step; bcell is written. */
+wm_status wm_bind_state(wm_patch* p, void* hydro, void* bface, void* bcell);
+
+/* Initial state from primitive fields and an edge vector potential
+ * (Sect. 4.1): b = B0 + curl_h A by first-order differences (div_h b = 0),
+ * zone B by the fourth-order interpolation of Sect. 2.3, m = rho v and
+ * E = P0/(gamma-1) + (rho v^2 + B^2)/2 (eq. P).  rho [nz][ny][nx],
+ * v [3][nz][ny][nx], A_edge [3][nz][ny][nx]: device arrays; B0 a host array. */
+wm_status wm_init_from_potential(wm_patch* p, const double* rho, const double* v,
+                                 const double* A_edge, double P0, const double B0[3]);
+
+/* Recomputes zone B of the bound state from its face field (the fourth-order
+ * interpolation of Sect. 2.3), for callers that wrote bface themselves. */
+wm_status wm_refresh_zone_field(wm_patch* p);
+
+/* Time step of eq. (cfl) at equality: dt = cfl h / sum_d max(|v_d| + c_fast^d),
+ * from the bound state.  The result stays in device memory for the stages; if
+ * dt_host is non-NULL the stream is synchronised and dt copied there. */
+wm_status wm_compute_dt(wm_patch* p, double* dt_host);
+
+/* One SSP-RK3 stage (increment form): stage 0 reads the bound state U^n and
+ * writes k0 and U1 = U^n + dt k0 into scratch; stage 1 writes k0+k1 and
+ * U2 = U^n + dt/4 (k0+k1); stage 2 writes U^{n+1} = U^n + dt/6 (k0+k1+4 k2)
+ * into the bound state.  Each stage ends with zone B re-interpolated from the
+ * new face field.  dt_host NULL: the device dt of the last wm_compute_dt. */
+wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host);
+
+/* wm_compute_dt followed by the three stages.  If dt_used is non-NULL the
+ * stream is synchronised and the dt of the step is returned there. */
+wm_status wm_step(wm_patch* p, double* dt_used);
+
+/* Diagnostics of the bound state (synchronises the stream).  Returns
+ * WM_ERR_UNPHYSICAL (with *out filled) when n_unphysical > 0. */
+wm_status wm_diagnostics(wm_patch* p, wm_diag* out);
+
+/* Direction-resolved output of one sweep of the bound state, for testing the
+ * rows of the step separately.  out [9][nz][ny][nx] (device): components
+ * 0..6 the WENO interface flux on the forward face along `axis` in the sweep
+ * frame (rho, m_n, m_t1, m_t2, B_t1, B_t2, E), with (n, t1, t2) = (x, y, z),
+ * (y, z, x), (z, x, y) for axis 0, 1, 2; components 7, 8 the CT transport
+ * fluxes T^n_t1, T^n_t2 of eq. (fct1)-(fct6). */
+wm_status wm_debug_sweep(wm_patch* p, int axis, void* out);
+
+/* Right-hand side dU/dt of the bound state: out [8][nz][ny][nx] (device) =
+ * d(rho, m_x, m_y, m_z, E)/dt from the flux divergence (eq. num) and
+ * d(b_x, b_y, b_z)/dt from the corner fluxes (Sect. 2.3). */
+wm_status wm_debug_rhs(wm_patch* p, void* out);
+
+/* Kernel timing with HIP events recorded on the patch's stream around every
+ * launch (for measurement; adds two event records per launch).  enable = 1
+ * starts a session (discarding earlier records), 0 stops it.  Records up to
+ * 8192 launches per session; later launches are not timed. */
+wm_status wm_profile(wm_patch* p, int enable);
+
+/* Synchronises the stream and reports the session: out[2*c] = number of
+ * launches and out[2*c+1] = summed milliseconds of kernel class c, with
+ * c = 0 sweeps, 1 update (divergence + CT + RK), 2 zone-B interpolation,
+ * 3 time-step reduction, 4 other.  n_out must be >= 10. */
+wm_status wm_profile_report(wm_patch* p, double* out, int n_out);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* wm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WENOMHD_H */

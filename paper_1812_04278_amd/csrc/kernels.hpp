@@ -1,0 +1,466 @@
+// HIP kernels of the WENO5-CT step for gfx950 (wave64, 256-thread blocks).
+//
+//   sweep_kernel<AXIS>   face fluxes along one axis: zone prologue staged in
+//                        LDS, one face per lane, eigensystem + projections in
+//                        registers.  Writes the five hydro flux components
+//                        (global frame) and the two CT transport fluxes.
+//   update_kernel<STAGE> flux divergence, corner fluxes, face-B right-hand
+//                        side and the SSP-RK3 increment, one zone per lane.
+//   bcell_kernel         zone B = fourth-order interpolation of the face field.
+//   init kernels, dt and diagnostics reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mhd_device.hpp"
+
+namespace wm {
+
+struct Grid {
+  int nx, ny, nz;
+  size_t N;   // nx * ny * nz
+  __device__ __forceinline__ size_t at(int i, int j, int k) const {
+    return ((size_t)k * ny + j) * nx + i;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// directional sweep
+// ---------------------------------------------------------------------------
+constexpr int SW_TA = 16;                    // faces per tile along the sweep axis
+constexpr int SW_TB = 16;                    // faces per tile across (x for y/z sweeps, y for x)
+constexpr int SW_HL = 2, SW_HR = 3;          // stencil zones i-2 .. i+3
+constexpr int SW_NA = SW_TA + SW_HL + SW_HR; // 21 zones along the axis
+constexpr int SW_NCELL = SW_NA * SW_TB;      // 336 zones per tile
+constexpr int SW_THREADS = SW_TA * SW_TB;    // 256
+
+struct SweepArgs {
+  Grid g;
+  Phys ph;
+  const double* hydro;   // [5][N] rho, mx, my, mz, E
+  const double* bcell;   // [3][N] zone B
+  double* fhydro;        // [5][N] interface flux, global frame (rho, mx, my, mz, E)
+  double* T;             // [2][N] transport fluxes T^n_t1, T^n_t2
+  double* dbg;           // optional [9][N]: 7 sweep-frame flux components + 2 T
+};
+
+template <int AXIS, bool WENO_Z>
+__global__ __launch_bounds__(SW_THREADS) void sweep_kernel(SweepArgs a) {
+  __shared__ double sh[Z_NVAR * SW_NCELL];
+  const Grid& g = a.g;
+  const int nA = AXIS == 0 ? g.nx : (AXIS == 1 ? g.ny : g.nz);
+  const int nB = AXIS == 0 ? g.ny : g.nx;
+  const int a0 = blockIdx.x * SW_TA;
+  const int b0 = blockIdx.y * SW_TB;
+  const int c = blockIdx.z;
+  // sweep frame component of global index: n, t1, t2
+  constexpr int CN = AXIS, CT1 = (AXIS + 1) % 3, CT2 = (AXIS + 2) % 3;
+
+  // ---- zone prologue into LDS (zones i-2 .. i+TA+2 along the axis, with periodic wrap)
+  for (int cell = threadIdx.x; cell < SW_NCELL; cell += SW_THREADS) {
+    int aa, bb;
+    if (AXIS == 0) { aa = cell % SW_NA; bb = cell / SW_NA; }
+    else           { bb = cell % SW_TB; aa = cell / SW_TB; }
+    const int ia = wrap(a0 - SW_HL + aa, nA);
+    const int ib = min(b0 + bb, nB - 1);
+    int i, j, k;
+    if (AXIS == 0)      { i = ia; j = ib; k = c; }
+    else if (AXIS == 1) { i = ib; j = ia; k = c; }
+    else                { i = ib; j = c;  k = ia; }
+    const size_t gi = g.at(i, j, k);
+    const double rho = a.hydro[gi];
+    const double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
+    const double E = a.hydro[4 * g.N + gi];
+    const double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
+    double z[Z_NVAR];
+    zone_prologue(rho, m[CN], m[CT1], m[CT2], E, B[CN], B[CT1], B[CT2], a.ph.gamma, z);
+#pragma unroll
+    for (int v = 0; v < Z_NVAR; ++v) sh[v * SW_NCELL + cell] = z[v];
+  }
+  __syncthreads();
+
+  // ---- one face per lane
+  int fa, fb;
+  if (AXIS == 0) { fa = threadIdx.x % SW_TA; fb = threadIdx.x / SW_TA; }
+  else           { fb = threadIdx.x % SW_TB; fa = threadIdx.x / SW_TB; }
+  auto L = [&](int v, int o) -> double {   // zone i-2+o of this lane's stencil
+    const int cell = AXIS == 0 ? fb * SW_NA + fa + o : (fa + o) * SW_TB + fb;
+    return sh[v * SW_NCELL + cell];
+  };
+
+  double dF[5][7], dq[5][7], Fc[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    double f[6], q[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+      f[o] = L(Z_F0 + j, o);
+      q[o] = L(Z_RHO + j, o);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      dF[k][j] = f[k + 1] - f[k];
+      dq[k][j] = q[k + 1] - q[k];
+    }
+    Fc[j] = (-f[1] + 7.0 * f[2] + 7.0 * f[3] - f[4]) * (1.0 / 12.0);
+  }
+  // face state: mean of the primitive states of zones i (o = 2) and i+1 (o = 3)
+  const double rho = 0.5 * (L(Z_RHO, 2) + L(Z_RHO, 3));
+  const double vn = 0.5 * (L(Z_VN, 2) + L(Z_VN, 3));
+  const double vt1 = 0.5 * (L(Z_VT1, 2) + L(Z_VT1, 3));
+  const double vt2 = 0.5 * (L(Z_VT2, 2) + L(Z_VT2, 3));
+  const double Bn = 0.5 * (L(Z_BN, 2) + L(Z_BN, 3));
+  const double Bt1 = 0.5 * (L(Z_BT1, 2) + L(Z_BT1, 3));
+  const double Bt2 = 0.5 * (L(Z_BT2, 2) + L(Z_BT2, 3));
+  const double P = 0.5 * (L(Z_P, 2) + L(Z_P, 3));
+  double corr[7];
+  face_char_flux<WENO_Z>(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P,
+                         L(Z_VN, 2), L(Z_CF, 2), L(Z_CA, 2), L(Z_CS, 2),
+                         L(Z_VN, 3), L(Z_CF, 3), L(Z_CA, 3), L(Z_CS, 3), dF, dq, a.ph, corr);
+  double Ff[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) Ff[j] = Fc[j] + corr[j];
+  // CT transport fluxes: B_t components plus the face mean of B_n v_t (eq. fct1-fct6)
+  const double T1 = Ff[4] + 0.5 * (L(Z_BN, 2) * L(Z_VT1, 2) + L(Z_BN, 3) * L(Z_VT1, 3));
+  const double T2 = Ff[5] + 0.5 * (L(Z_BN, 2) * L(Z_VT2, 2) + L(Z_BN, 3) * L(Z_VT2, 3));
+
+  if (a0 + fa >= nA || b0 + fb >= nB) return;
+  int i, j, k;
+  if (AXIS == 0)      { i = a0 + fa; j = b0 + fb; k = c; }
+  else if (AXIS == 1) { i = b0 + fb; j = a0 + fa; k = c; }
+  else                { i = b0 + fb; j = c;       k = a0 + fa; }
+  const size_t gi = g.at(i, j, k);
+  double fm[3];
+  fm[CN] = Ff[1]; fm[CT1] = Ff[2]; fm[CT2] = Ff[3];
+  a.fhydro[gi] = Ff[0];
+  a.fhydro[g.N + gi] = fm[0];
+  a.fhydro[2 * g.N + gi] = fm[1];
+  a.fhydro[3 * g.N + gi] = fm[2];
+  a.fhydro[4 * g.N + gi] = Ff[6];
+  a.T[gi] = T1;
+  a.T[g.N + gi] = T2;
+  if (a.dbg) {
+#pragma unroll
+    for (int v = 0; v < 7; ++v) a.dbg[v * g.N + gi] = Ff[v];
+    a.dbg[7 * g.N + gi] = T1;
+    a.dbg[8 * g.N + gi] = T2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// divergence + CT + RK stage
+// ---------------------------------------------------------------------------
+struct UpdateArgs {
+  Grid g;
+  double inv_h;
+  const double* faces;   // [21][N]: F^x[5], F^y[5], F^z[5], T^x[2], T^y[2], T^z[2]
+  const double* Un;      // hydro [5][N] of U^n
+  const double* bn;      // bface [3][N] of U^n
+  double* acc;           // [8][N] accumulated increments
+  double* hyd_out;       // hydro [5][N] of the stage result
+  double* b_out;         // bface [3][N] of the stage result
+  double* rhs_out;       // optional [8][N]: the right-hand side itself (no state update)
+  const double* dt;      // device scalar
+};
+
+// corner fluxes (eq. ox1-ox3), each from four transport fluxes:
+//   Ez(i+1/2, j+1/2, k) = (Tyx(i) + Tyx(i+1))/2 - (Txy(j) + Txy(j+1))/2   [Omega_x]
+//   Ex(i, j+1/2, k+1/2) = (Tzy(j) + Tzy(j+1))/2 - (Tyz(k) + Tyz(k+1))/2   [Omega_y]
+//   Ey(i+1/2, j, k+1/2) = (Txz(k) + Txz(k+1))/2 - (Tzx(i) + Tzx(i+1))/2   [Omega_z]
+struct TView {
+  const double *xy, *xz, *yz, *yx, *zx, *zy;
+};
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a) {
+  const Grid& g = a.g;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int im = i == 0 ? g.nx - 1 : i - 1, ip = i + 1 == g.nx ? 0 : i + 1;
+  const int jm = j == 0 ? g.ny - 1 : j - 1, jp = j + 1 == g.ny ? 0 : j + 1;
+  const int km = k == 0 ? g.nz - 1 : k - 1, kp = k + 1 == g.nz ? 0 : k + 1;
+  const size_t N = g.N;
+  const size_t c0 = g.at(i, j, k);
+  const size_t cxm = g.at(im, j, k), cym = g.at(i, jm, k), czm = g.at(i, j, km);
+  const double ih = a.inv_h;
+  const double* Fx = a.faces;
+  const double* Fy = a.faces + 5 * N;
+  const double* Fz = a.faces + 10 * N;
+  double kv[8];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const size_t o = v * N;
+    const double dx = -(Fx[o + c0] - Fx[o + cxm]) * ih;
+    const double dy = -(Fy[o + c0] - Fy[o + cym]) * ih;
+    const double dz = -(Fz[o + c0] - Fz[o + czm]) * ih;
+    kv[v] = (dx + dy) + dz;
+  }
+  TView T;
+  T.xy = a.faces + 15 * N; T.xz = a.faces + 16 * N;
+  T.yz = a.faces + 17 * N; T.yx = a.faces + 18 * N;
+  T.zx = a.faces + 19 * N; T.zy = a.faces + 20 * N;
+  auto Ez = [&](int ii, int jj, int kk) {
+    const int iip = ii + 1 == g.nx ? 0 : ii + 1, jjp = jj + 1 == g.ny ? 0 : jj + 1;
+    return 0.5 * (T.yx[g.at(ii, jj, kk)] + T.yx[g.at(iip, jj, kk)]) -
+           0.5 * (T.xy[g.at(ii, jj, kk)] + T.xy[g.at(ii, jjp, kk)]);
+  };
+  auto Ex = [&](int ii, int jj, int kk) {
+    const int jjp = jj + 1 == g.ny ? 0 : jj + 1, kkp = kk + 1 == g.nz ? 0 : kk + 1;
+    return 0.5 * (T.zy[g.at(ii, jj, kk)] + T.zy[g.at(ii, jjp, kk)]) -
+           0.5 * (T.yz[g.at(ii, jj, kk)] + T.yz[g.at(ii, jj, kkp)]);
+  };
+  auto Ey = [&](int ii, int jj, int kk) {
+    const int iip = ii + 1 == g.nx ? 0 : ii + 1, kkp = kk + 1 == g.nz ? 0 : kk + 1;
+    return 0.5 * (T.xz[g.at(ii, jj, kk)] + T.xz[g.at(ii, jj, kkp)]) -
+           0.5 * (T.zx[g.at(ii, jj, kk)] + T.zx[g.at(iip, jj, kk)]);
+  };
+  (void)ip; (void)jp; (void)kp;
+  const double ez = Ez(i, j, k), ez_jm = Ez(i, jm, k), ez_im = Ez(im, j, k);
+  const double ex = Ex(i, j, k), ex_km = Ex(i, j, km), ex_jm = Ex(i, jm, k);
+  const double ey = Ey(i, j, k), ey_km = Ey(i, j, km), ey_im = Ey(im, j, k);
+  // Sect. 2.3 face-field equations
+  kv[5] = -(ez - ez_jm) * ih + (ey - ey_km) * ih;
+  kv[6] = -(ex - ex_km) * ih + (ez - ez_im) * ih;
+  kv[7] = -(ey - ey_im) * ih + (ex - ex_jm) * ih;
+
+  if (a.rhs_out) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) a.rhs_out[v * N + c0] = kv[v];
+    return;
+  }
+  const double dt = *a.dt;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const double un = v < 5 ? a.Un[v * N + c0] : a.bn[(v - 5) * N + c0];
+    double out;
+    if (STAGE == 0) {
+      a.acc[v * N + c0] = kv[v];
+      out = un + dt * kv[v];
+    } else if (STAGE == 1) {
+      const double s = a.acc[v * N + c0] + kv[v];
+      a.acc[v * N + c0] = s;
+      out = un + (0.25 * dt) * s;
+    } else {
+      const double s = a.acc[v * N + c0] + 4.0 * kv[v];
+      out = un + (dt / 6.0) * s;
+    }
+    if (v < 5) a.hyd_out[v * N + c0] = out;
+    else a.b_out[(v - 5) * N + c0] = out;
+  }
+}
+
+// zone B = (-b_{i-2} + 9 b_{i-1} + 9 b_i - b_{i+1}) / 16 along each component's own axis
+__global__ __launch_bounds__(256) void bcell_kernel(Grid g, const double* b, double* B) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const size_t N = g.N, c0 = g.at(i, j, k);
+  const double* bx = b;
+  const double* by = b + N;
+  const double* bz = b + 2 * N;
+  B[c0] = (-bx[g.at(wrap(i - 2, g.nx), j, k)] + 9.0 * bx[g.at(wrap(i - 1, g.nx), j, k)] + 9.0 * bx[c0] -
+           bx[g.at(wrap(i + 1, g.nx), j, k)]) * (1.0 / 16.0);
+  B[N + c0] = (-by[g.at(i, wrap(j - 2, g.ny), k)] + 9.0 * by[g.at(i, wrap(j - 1, g.ny), k)] + 9.0 * by[c0] -
+               by[g.at(i, wrap(j + 1, g.ny), k)]) * (1.0 / 16.0);
+  B[2 * N + c0] = (-bz[g.at(i, j, wrap(k - 2, g.nz))] + 9.0 * bz[g.at(i, j, wrap(k - 1, g.nz))] + 9.0 * bz[c0] -
+                   bz[g.at(i, j, wrap(k + 1, g.nz))]) * (1.0 / 16.0);
+}
+
+// b = B0 + curl_h A (first-order differences on the edge potential)
+__global__ __launch_bounds__(256) void init_b_kernel(Grid g, double inv_h, const double* A, double B0x,
+                                                     double B0y, double B0z, double* b) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const size_t N = g.N, c0 = g.at(i, j, k);
+  const double* Ax = A;
+  const double* Ay = A + N;
+  const double* Az = A + 2 * N;
+  const int im = wrap(i - 1, g.nx), jm = wrap(j - 1, g.ny), km = wrap(k - 1, g.nz);
+  b[c0] = B0x + ((Az[c0] - Az[g.at(i, jm, k)]) * inv_h - (Ay[c0] - Ay[g.at(i, j, km)]) * inv_h);
+  b[N + c0] = B0y + ((Ax[c0] - Ax[g.at(i, j, km)]) * inv_h - (Az[c0] - Az[g.at(im, j, k)]) * inv_h);
+  b[2 * N + c0] = B0z + ((Ay[c0] - Ay[g.at(im, j, k)]) * inv_h - (Ax[c0] - Ax[g.at(i, jm, k)]) * inv_h);
+}
+
+// m = rho v, E = P0/(gamma-1) + (rho v^2 + B^2)/2 (zone B already interpolated)
+__global__ __launch_bounds__(256) void init_hydro_kernel(size_t N, double gamma, double P0, const double* rho,
+                                                         const double* v, const double* B, double* hydro) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  const double r = rho[c];
+  const double vx = v[c], vy = v[N + c], vz = v[2 * N + c];
+  const double Bx = B[c], By = B[N + c], Bz = B[2 * N + c];
+  hydro[c] = r;
+  hydro[N + c] = r * vx;
+  hydro[2 * N + c] = r * vy;
+  hydro[3 * N + c] = r * vz;
+  hydro[4 * N + c] = P0 / (gamma - 1.0) + 0.5 * (r * (vx * vx + vy * vy + vz * vz) + (Bx * Bx + By * By + Bz * Bz));
+}
+
+// ---------------------------------------------------------------------------
+// reductions (fixed order, no atomics: results are bitwise reproducible)
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double nanmax(double a, double b) {   // NaN-propagating max
+  return (a != a || b > a) ? (b != b ? b : (a != a ? a : b)) : a;
+}
+
+// max over zones of |v_d| + c_fast^d, d = x, y, z -> part[3 * block + d]
+__global__ __launch_bounds__(RED_THREADS) void speed_partial_kernel(size_t N, double gamma, const double* hydro,
+                                                                    const double* bcell, double* part) {
+  __shared__ double red[3][RED_THREADS];
+  double mx[3] = {0.0, 0.0, 0.0};
+  for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N; c += (size_t)gridDim.x * RED_THREADS) {
+    const double rho = hydro[c];
+    const double irho = 1.0 / rho;
+    const double v[3] = {hydro[N + c] * irho, hydro[2 * N + c] * irho, hydro[3 * N + c] * irho};
+    const double B[3] = {bcell[c], bcell[N + c], bcell[2 * N + c]};
+    const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+    const double P = (gamma - 1.0) *
+                     (hydro[4 * N + c] - 0.5 * ((hydro[N + c] * v[0] + hydro[2 * N + c] * v[1] + hydro[3 * N + c] * v[2]) + B2));
+    const double a2 = gamma * P * irho, b2 = B2 * irho;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double bperp2 = (B2 - B[d] * B[d]) * irho;
+      const double dab = a2 - b2;
+      const double D = sqrt(dab * dab + 4.0 * a2 * bperp2);
+      const double cf = sqrt(0.5 * (a2 + b2 + D));
+      mx[d] = nanmax(mx[d], fabs(v[d]) + cf);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = mx[d];
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = nanmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) part[3 * blockIdx.x + d] = red[d][0];
+  }
+}
+
+// dt = cfl h / sum_d max_d (eq. cfl); also keeps the three maxima
+__global__ __launch_bounds__(RED_THREADS) void dt_final_kernel(int nblocks, double cfl_h, const double* part,
+                                                               double* dt, double* smax) {
+  __shared__ double red[3][RED_THREADS];
+  double mx[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) mx[d] = nanmax(mx[d], part[3 * b + d]);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = mx[d];
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = nanmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double s = (red[0][0] + red[1][0]) + red[2][0];
+    *dt = cfl_h / s;
+    smax[0] = red[0][0]; smax[1] = red[1][0]; smax[2] = red[2][0];
+  }
+}
+
+__global__ void set_scalar_kernel(double* p, double v) { *p = v; }
+
+// diagnostics partials: per block, Neumaier sums of rho, m(3), E, b(3) and
+// max|div b|, min rho, min P, unphysical count
+struct Acc2 {
+  double s, c;
+  __device__ void add(double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+  }
+};
+
+__global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Grid g, double gamma, double inv_h,
+                                                                   const double* hydro, const double* b,
+                                                                   const double* bcell, double* part) {
+  // part layout per block: [0..7] sums, [8..15] compensations, [16] max|divb|, [17] min rho,
+  // [18] min P, [19] unphysical count
+  const size_t N = g.N;
+  Acc2 acc[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) { acc[v].s = 0.0; acc[v].c = 0.0; }
+  double mdiv = 0.0, mrho = 1.0e308, mp = 1.0e308, nbad = 0.0;
+  for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N; c += (size_t)gridDim.x * RED_THREADS) {
+    const int i = (int)(c % g.nx);
+    const int j = (int)((c / g.nx) % g.ny);
+    const int k = (int)(c / ((size_t)g.nx * g.ny));
+    const double rho = hydro[c];
+    const double m[3] = {hydro[N + c], hydro[2 * N + c], hydro[3 * N + c]};
+    const double E = hydro[4 * N + c];
+    acc[0].add(rho);
+    acc[1].add(m[0]); acc[2].add(m[1]); acc[3].add(m[2]);
+    acc[4].add(E);
+    acc[5].add(b[c]); acc[6].add(b[N + c]); acc[7].add(b[2 * N + c]);
+    const double div = ((b[c] - b[g.at(wrap(i - 1, g.nx), j, k)]) + (b[N + c] - b[N + g.at(i, wrap(j - 1, g.ny), k)]) +
+                        (b[2 * N + c] - b[2 * N + g.at(i, j, wrap(k - 1, g.nz))])) * inv_h;
+    mdiv = nanmax(mdiv, fabs(div));
+    const double Bx = bcell[c], By = bcell[N + c], Bz = bcell[2 * N + c];
+    const double P = (gamma - 1.0) * (E - 0.5 * ((m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / rho + (Bx * Bx + By * By + Bz * Bz)));
+    mrho = fmin(mrho, rho);
+    mp = fmin(mp, P);
+    const bool bad = !(rho > 0.0) || !(P > 0.0) || !isfinite(E) || !isfinite(rho) || !isfinite(P);
+    nbad += bad ? 1.0 : 0.0;
+  }
+  // wave-level then block-level reduction in fixed order
+  double vals[20];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) { vals[v] = acc[v].s; vals[8 + v] = acc[v].c; }
+  vals[16] = mdiv; vals[17] = mrho; vals[18] = mp; vals[19] = nbad;
+  __shared__ double tmp[20][RED_THREADS];
+#pragma unroll
+  for (int v = 0; v < 20; ++v) tmp[v][threadIdx.x] = vals[v];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Acc2 s[8];
+    for (int v = 0; v < 8; ++v) { s[v].s = 0.0; s[v].c = 0.0; }
+    double a16 = 0.0, a17 = 1.0e308, a18 = 1.0e308, a19 = 0.0;
+    for (int t = 0; t < RED_THREADS; ++t) {
+      for (int v = 0; v < 8; ++v) { s[v].add(tmp[v][t]); s[v].c += tmp[8 + v][t]; }
+      a16 = nanmax(a16, tmp[16][t]);
+      a17 = fmin(a17, tmp[17][t]);
+      a18 = fmin(a18, tmp[18][t]);
+      a19 += tmp[19][t];
+    }
+    double* o = part + 20 * blockIdx.x;
+    for (int v = 0; v < 8; ++v) { o[v] = s[v].s; o[8 + v] = s[v].c; }
+    o[16] = a16; o[17] = a17; o[18] = a18; o[19] = a19;
+  }
+}
+
+__global__ void diag_final_kernel(int nblocks, const double* part, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Acc2 s[8];
+  for (int v = 0; v < 8; ++v) { s[v].s = 0.0; s[v].c = 0.0; }
+  double a16 = 0.0, a17 = 1.0e308, a18 = 1.0e308, a19 = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double* p = part + 20 * b;
+    for (int v = 0; v < 8; ++v) { s[v].add(p[v]); s[v].c += p[8 + v]; }
+    a16 = nanmax(a16, p[16]);
+    a17 = fmin(a17, p[17]);
+    a18 = fmin(a18, p[18]);
+    a19 += p[19];
+  }
+  for (int v = 0; v < 8; ++v) out[v] = s[v].s + s[v].c;
+  out[8] = a16; out[9] = a17; out[10] = a18; out[11] = a19;
+}
+
+}  // namespace wm

@@ -1,0 +1,461 @@
+// C ABI of the WENO5-CT MHD step (declarations and contracts in
+// include/wenomhd.h).  Host-side orchestration only: argument checks, the
+// scratch layout, and stream-ordered kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/wenomhd.h"
+#include "kernels.hpp"
+
+using namespace wm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+wm_status fail(wm_status s, const char* fmt, const char* detail = "") {
+  std::snprintf(g_err, sizeof(g_err), fmt, detail);
+  return s;
+}
+
+wm_status hip_check(hipError_t e, const char* where) {
+  if (e != hipSuccess) {
+    std::snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
+    return WM_ERR_HIP;
+  }
+  return WM_OK;
+}
+
+#define WM_LAUNCH_CHECK(where)                                      \
+  do {                                                              \
+    wm_status _s = hip_check(hipGetLastError(), where);             \
+    if (_s != WM_OK) return _s;                                     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// scratch layout (bytes, each region 256-aligned), FP64:
+//   Us    [11][N]  stage state: hydro 5, bface 3, bcell 3
+//   acc   [8][N]   RK increment accumulator
+//   faces [21][N]  F^x, F^y, F^z (5 each), T^x, T^y, T^z (2 each)
+//   red            dt, 3 signal-speed maxima, reduction partials
+struct Layout {
+  size_t us, acc, faces, red, total;
+};
+
+constexpr size_t kRedDoubles = 8 + 3 * RED_BLOCKS + 20 * RED_BLOCKS + 16;
+
+bool valid_config(const wm_config* c, const char** why) {
+  if (!c) { *why = "null config"; return false; }
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) { *why = "grid sizes must be >= 1"; return false; }
+  if (c->nx > 8192 || c->ny > 8192 || c->nz > 8192) { *why = "grid size above 8192"; return false; }
+  const double n = (double)c->nx * c->ny * c->nz;
+  if (n > 2147483647.0) { *why = "more than 2^31-1 zones"; return false; }
+  if (!(c->h > 0.0) || !std::isfinite(c->h)) { *why = "h must be positive"; return false; }
+  if (!(c->gamma > 1.0)) { *why = "gamma must exceed 1"; return false; }
+  if (!(c->cfl > 0.0)) { *why = "cfl must be positive"; return false; }
+  if (!(c->eps_weno > 0.0) || !(c->eps_B >= 0.0) || !(c->eps_Z > 0.0)) { *why = "epsilons must be positive"; return false; }
+  if (c->weights != WM_WENO_JS && c->weights != WM_WENO_Z) { *why = "unknown weights"; return false; }
+  if (c->precision != WM_FP64) { *why = "precision mode not available in this build"; return false; }
+  return true;
+}
+
+Layout layout(const wm_config* c) {
+  const size_t N = (size_t)c->nx * c->ny * c->nz;
+  Layout L;
+  size_t off = 0;
+  L.us = off;    off = align_up(off + 11 * N * sizeof(double));
+  L.acc = off;   off = align_up(off + 8 * N * sizeof(double));
+  L.faces = off; off = align_up(off + 21 * N * sizeof(double));
+  L.red = off;   off = align_up(off + kRedDoubles * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct wm_patch {
+  wm_config cfg;
+  hipStream_t stream;
+  Grid g;
+  Phys ph;
+  char* scratch;
+  Layout lay;
+  double* hydro = nullptr;   // bound state
+  double* bface = nullptr;
+  double* bcell = nullptr;
+  int stage_done = -1;       // last completed stage of the current step (-1: none)
+  bool dt_valid = false;
+  // event timing (wm_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;       // pool, 2 per record
+  std::vector<int> ev_class;        // kernel class per record
+  size_t n_rec = 0;
+
+  double* us() const { return reinterpret_cast<double*>(scratch + lay.us); }
+  double* acc() const { return reinterpret_cast<double*>(scratch + lay.acc); }
+  double* faces() const { return reinterpret_cast<double*>(scratch + lay.faces); }
+  double* red() const { return reinterpret_cast<double*>(scratch + lay.red); }
+  double* dt_dev() const { return red(); }                 // red[0]
+  double* smax_dev() const { return red() + 1; }           // red[1..3]
+  double* diag_out() const { return red() + 4 + 3 * RED_BLOCKS + 20 * RED_BLOCKS; }  // 12 values
+  double* speed_part() const { return red() + 4; }
+  double* diag_part() const { return red() + 4 + 3 * RED_BLOCKS; }
+};
+
+namespace {
+
+constexpr size_t kMaxRec = 8192;
+enum KClass { K_SWEEP = 0, K_UPDATE = 1, K_BCELL = 2, K_DT = 3, K_OTHER = 4, K_NCLASS = 5 };
+
+// Records a start event before a launch of class c; returns the record index or -1.
+long prof_begin(wm_patch* p, int c) {
+  if (!p->prof || p->n_rec >= kMaxRec) return -1;
+  const size_t r = p->n_rec;
+  while (p->ev.size() < 2 * (r + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    p->ev.push_back(e);
+  }
+  if (p->ev_class.size() < r + 1) p->ev_class.resize(r + 1);
+  p->ev_class[r] = c;
+  if (hipEventRecord(p->ev[2 * r], p->stream) != hipSuccess) return -1;
+  return (long)r;
+}
+
+void prof_end(wm_patch* p, long r) {
+  if (r < 0) return;
+  if (hipEventRecord(p->ev[2 * r + 1], p->stream) == hipSuccess) p->n_rec = (size_t)r + 1;
+}
+
+dim3 zone_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
+
+template <int AXIS>
+wm_status launch_sweep(wm_patch* p, const double* hydro, const double* bcell, double* fh, double* T, double* dbg) {
+  SweepArgs a;
+  a.g = p->g;
+  a.ph = p->ph;
+  a.hydro = hydro;
+  a.bcell = bcell;
+  a.fhydro = fh;
+  a.T = T;
+  a.dbg = dbg;
+  const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
+  const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
+  const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
+  dim3 grid((nA + SW_TA - 1) / SW_TA, (nB + SW_TB - 1) / SW_TB, nC);
+  const long r = prof_begin(p, K_SWEEP);
+  if (p->ph.weno_z)
+    hipLaunchKernelGGL((sweep_kernel<AXIS, true>), grid, dim3(SW_THREADS), 0, p->stream, a);
+  else
+    hipLaunchKernelGGL((sweep_kernel<AXIS, false>), grid, dim3(SW_THREADS), 0, p->stream, a);
+  WM_LAUNCH_CHECK("sweep kernel");
+  prof_end(p, r);
+  return WM_OK;
+}
+
+wm_status sweeps(wm_patch* p, const double* hydro, const double* bcell) {
+  const size_t N = p->g.N;
+  double* f = p->faces();
+  wm_status s;
+  if ((s = launch_sweep<0>(p, hydro, bcell, f, f + 15 * N, nullptr)) != WM_OK) return s;
+  if ((s = launch_sweep<1>(p, hydro, bcell, f + 5 * N, f + 17 * N, nullptr)) != WM_OK) return s;
+  if ((s = launch_sweep<2>(p, hydro, bcell, f + 10 * N, f + 19 * N, nullptr)) != WM_OK) return s;
+  return WM_OK;
+}
+
+wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
+  const size_t N = p->g.N;
+  UpdateArgs a;
+  a.g = p->g;
+  a.inv_h = 1.0 / p->cfg.h;
+  a.faces = p->faces();
+  a.Un = p->hydro;
+  a.bn = p->bface;
+  a.acc = p->acc();
+  a.rhs_out = rhs_out;
+  a.dt = p->dt_dev();
+  if (stage == 2) {
+    a.hyd_out = p->hydro;
+    a.b_out = p->bface;
+  } else {
+    a.hyd_out = p->us();
+    a.b_out = p->us() + 5 * N;
+  }
+  dim3 grid = zone_grid(p->g);
+  const long r = prof_begin(p, K_UPDATE);
+  switch (stage) {
+    case 0: hipLaunchKernelGGL(update_kernel<0>, grid, dim3(256), 0, p->stream, a); break;
+    case 1: hipLaunchKernelGGL(update_kernel<1>, grid, dim3(256), 0, p->stream, a); break;
+    default: hipLaunchKernelGGL(update_kernel<2>, grid, dim3(256), 0, p->stream, a); break;
+  }
+  WM_LAUNCH_CHECK("update kernel");
+  prof_end(p, r);
+  return WM_OK;
+}
+
+wm_status launch_bcell(wm_patch* p, const double* b, double* B) {
+  const long r = prof_begin(p, K_BCELL);
+  hipLaunchKernelGGL(bcell_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, b, B);
+  WM_LAUNCH_CHECK("bcell kernel");
+  prof_end(p, r);
+  return WM_OK;
+}
+
+int red_blocks(const Grid& g) {
+  size_t b = (g.N + RED_THREADS - 1) / RED_THREADS;
+  return (int)(b < (size_t)RED_BLOCKS ? b : (size_t)RED_BLOCKS);
+}
+
+wm_status check_bound(wm_patch* p) {
+  if (!p) return fail(WM_ERR_ARG, "null patch");
+  if (!p->hydro || !p->bface || !p->bcell) return fail(WM_ERR_STATE, "state not bound (wm_bind_state)");
+  return WM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void wm_config_default(wm_config* c, int n) {
+  if (!c) return;
+  c->nx = c->ny = c->nz = n;
+  c->h = n > 0 ? 1.0 / n : 0.0;
+  c->gamma = 5.0 / 3.0;
+  c->cfl = 0.4;
+  c->eps_weno = 1e-6;
+  c->eps_B = 1e-30;
+  c->eps_Z = 1e-40;
+  c->weights = WM_WENO_JS;
+  c->precision = WM_FP64;
+}
+
+size_t wm_scratch_bytes(const wm_config* cfg) {
+  const char* why = "";
+  if (!valid_config(cfg, &why)) return 0;
+  return layout(cfg).total;
+}
+
+wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch, size_t scratch_bytes,
+                          wm_patch** out) {
+  const char* why = "";
+  if (!out) return fail(WM_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  if (!valid_config(cfg, &why)) return fail(WM_ERR_ARG, "invalid config: %s", why);
+  const Layout L = layout(cfg);
+  if (!scratch) return fail(WM_ERR_ARG, "null scratch");
+  if (reinterpret_cast<uintptr_t>(scratch) % kAlign) return fail(WM_ERR_ARG, "scratch not 256-byte aligned");
+  if (scratch_bytes < L.total) return fail(WM_ERR_ARG, "scratch smaller than wm_scratch_bytes");
+  wm_patch* p = new (std::nothrow) wm_patch;
+  if (!p) return fail(WM_ERR_ARG, "host allocation failed");
+  p->cfg = *cfg;
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  p->g.nx = cfg->nx; p->g.ny = cfg->ny; p->g.nz = cfg->nz;
+  p->g.N = (size_t)cfg->nx * cfg->ny * cfg->nz;
+  p->ph.gamma = cfg->gamma;
+  p->ph.inv_h = 1.0 / cfg->h;
+  p->ph.eps = cfg->eps_weno;
+  p->ph.eps_B = cfg->eps_B;
+  p->ph.eps_Z = cfg->eps_Z;
+  p->ph.weno_z = cfg->weights == WM_WENO_Z ? 1 : 0;
+  p->scratch = reinterpret_cast<char*>(scratch);
+  p->lay = L;
+  *out = p;
+  g_err[0] = 0;
+  return WM_OK;
+}
+
+wm_status wm_patch_destroy(wm_patch* p) {
+  if (p) {
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  }
+  delete p;
+  return WM_OK;
+}
+
+wm_status wm_bind_state(wm_patch* p, void* hydro, void* bface, void* bcell) {
+  if (!p) return fail(WM_ERR_ARG, "null patch");
+  if (!hydro || !bface || !bcell) return fail(WM_ERR_ARG, "null state pointer");
+  p->hydro = reinterpret_cast<double*>(hydro);
+  p->bface = reinterpret_cast<double*>(bface);
+  p->bcell = reinterpret_cast<double*>(bcell);
+  p->stage_done = -1;
+  p->dt_valid = false;
+  return WM_OK;
+}
+
+wm_status wm_init_from_potential(wm_patch* p, const double* rho, const double* v, const double* A_edge, double P0,
+                                 const double B0[3]) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  if (!rho || !v || !A_edge || !B0) return fail(WM_ERR_ARG, "null input pointer");
+  hipLaunchKernelGGL(init_b_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, A_edge, B0[0],
+                     B0[1], B0[2], p->bface);
+  WM_LAUNCH_CHECK("init_b kernel");
+  if ((s = launch_bcell(p, p->bface, p->bcell)) != WM_OK) return s;
+  const size_t N = p->g.N;
+  hipLaunchKernelGGL(init_hydro_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, N, p->cfg.gamma,
+                     P0, rho, v, p->bcell, p->hydro);
+  WM_LAUNCH_CHECK("init_hydro kernel");
+  p->stage_done = -1;
+  p->dt_valid = false;
+  return WM_OK;
+}
+
+wm_status wm_refresh_zone_field(wm_patch* p) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  return launch_bcell(p, p->bface, p->bcell);
+}
+
+wm_status wm_compute_dt(wm_patch* p, double* dt_host) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  const int nb = red_blocks(p->g);
+  const long r = prof_begin(p, K_DT);
+  hipLaunchKernelGGL(speed_partial_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g.N, p->cfg.gamma,
+                     p->hydro, p->bcell, p->speed_part());
+  WM_LAUNCH_CHECK("speed kernel");
+  hipLaunchKernelGGL(dt_final_kernel, dim3(1), dim3(RED_THREADS), 0, p->stream, nb, p->cfg.cfl * p->cfg.h,
+                     p->speed_part(), p->dt_dev(), p->smax_dev());
+  WM_LAUNCH_CHECK("dt kernel");
+  prof_end(p, r);
+  p->dt_valid = true;
+  if (dt_host) {
+    if ((s = hip_check(hipMemcpyAsync(dt_host, p->dt_dev(), sizeof(double), hipMemcpyDeviceToHost, p->stream),
+                       "dt copy")) != WM_OK)
+      return s;
+    if ((s = hip_check(hipStreamSynchronize(p->stream), "dt sync")) != WM_OK) return s;
+  }
+  return WM_OK;
+}
+
+wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  if (stage < 0 || stage > 2) return fail(WM_ERR_ARG, "stage must be 0, 1 or 2");
+  if (stage > 0 && p->stage_done != stage - 1) return fail(WM_ERR_STATE, "stages must run in order 0, 1, 2");
+  if (dt_host) {
+    if (!std::isfinite(*dt_host)) return fail(WM_ERR_ARG, "dt is not finite");
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, p->dt_dev(), *dt_host);
+    WM_LAUNCH_CHECK("set dt");
+    p->dt_valid = true;
+  } else if (!p->dt_valid) {
+    return fail(WM_ERR_STATE, "no dt: call wm_compute_dt or pass dt");
+  }
+  const size_t N = p->g.N;
+  const double* hyd_in = stage == 0 ? p->hydro : p->us();
+  const double* bcell_in = stage == 0 ? p->bcell : p->us() + 8 * N;
+  if ((s = sweeps(p, hyd_in, bcell_in)) != WM_OK) return s;
+  if ((s = launch_update(p, stage, nullptr)) != WM_OK) return s;
+  if (stage == 2) {
+    if ((s = launch_bcell(p, p->bface, p->bcell)) != WM_OK) return s;
+    p->stage_done = -1;
+    p->dt_valid = false;
+  } else {
+    if ((s = launch_bcell(p, p->us() + 5 * N, p->us() + 8 * N)) != WM_OK) return s;
+    p->stage_done = stage;
+  }
+  return WM_OK;
+}
+
+wm_status wm_step(wm_patch* p, double* dt_used) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  if ((s = wm_compute_dt(p, nullptr)) != WM_OK) return s;
+  if (dt_used) {
+    if ((s = hip_check(hipMemcpyAsync(dt_used, p->dt_dev(), sizeof(double), hipMemcpyDeviceToHost, p->stream),
+                       "dt copy")) != WM_OK)
+      return s;
+  }
+  p->stage_done = -1;
+  for (int st = 0; st < 3; ++st)
+    if ((s = wm_rk_stage(p, st, nullptr)) != WM_OK) return s;
+  if (dt_used) {
+    if ((s = hip_check(hipStreamSynchronize(p->stream), "step sync")) != WM_OK) return s;
+  }
+  return WM_OK;
+}
+
+wm_status wm_diagnostics(wm_patch* p, wm_diag* out) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  if (!out) return fail(WM_ERR_ARG, "null output");
+  const int nb = red_blocks(p->g);
+  hipLaunchKernelGGL(diag_partial_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g, p->cfg.gamma,
+                     1.0 / p->cfg.h, p->hydro, p->bface, p->bcell, p->diag_part());
+  WM_LAUNCH_CHECK("diag kernel");
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, p->stream, nb, p->diag_part(), p->diag_out());
+  WM_LAUNCH_CHECK("diag final kernel");
+  double h[12];
+  if ((s = hip_check(hipMemcpyAsync(h, p->diag_out(), sizeof(h), hipMemcpyDeviceToHost, p->stream), "diag copy")) !=
+      WM_OK)
+    return s;
+  if ((s = hip_check(hipStreamSynchronize(p->stream), "diag sync")) != WM_OK) return s;
+  out->mass = h[0];
+  out->mom[0] = h[1]; out->mom[1] = h[2]; out->mom[2] = h[3];
+  out->energy = h[4];
+  out->bflux[0] = h[5]; out->bflux[1] = h[6]; out->bflux[2] = h[7];
+  out->max_divb = h[8];
+  out->min_rho = h[9];
+  out->min_p = h[10];
+  out->n_unphysical = (long long)h[11];
+  if (out->n_unphysical > 0) return fail(WM_ERR_UNPHYSICAL, "unphysical zones in the state%s");
+  return WM_OK;
+}
+
+wm_status wm_debug_sweep(wm_patch* p, int axis, void* out) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  if (!out) return fail(WM_ERR_ARG, "null output");
+  const size_t N = p->g.N;
+  double* f = p->faces();
+  double* o = reinterpret_cast<double*>(out);
+  switch (axis) {
+    case 0: return launch_sweep<0>(p, p->hydro, p->bcell, f, f + 15 * N, o);
+    case 1: return launch_sweep<1>(p, p->hydro, p->bcell, f + 5 * N, f + 17 * N, o);
+    case 2: return launch_sweep<2>(p, p->hydro, p->bcell, f + 10 * N, f + 19 * N, o);
+    default: return fail(WM_ERR_ARG, "axis must be 0, 1 or 2");
+  }
+}
+
+wm_status wm_debug_rhs(wm_patch* p, void* out) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  if (!out) return fail(WM_ERR_ARG, "null output");
+  if ((s = sweeps(p, p->hydro, p->bcell)) != WM_OK) return s;
+  return launch_update(p, 0, reinterpret_cast<double*>(out));
+}
+
+wm_status wm_profile(wm_patch* p, int enable) {
+  if (!p) return fail(WM_ERR_ARG, "null patch");
+  p->prof = enable != 0;
+  if (enable) p->n_rec = 0;
+  return WM_OK;
+}
+
+wm_status wm_profile_report(wm_patch* p, double* out, int n_out) {
+  if (!p) return fail(WM_ERR_ARG, "null patch");
+  if (!out || n_out < 2 * K_NCLASS) return fail(WM_ERR_ARG, "output needs 10 doubles");
+  wm_status s = hip_check(hipStreamSynchronize(p->stream), "profile sync");
+  if (s != WM_OK) return s;
+  for (int c = 0; c < 2 * K_NCLASS; ++c) out[c] = 0.0;
+  for (size_t r = 0; r < p->n_rec; ++r) {
+    float ms = 0.f;
+    if ((s = hip_check(hipEventElapsedTime(&ms, p->ev[2 * r], p->ev[2 * r + 1]), "event time")) != WM_OK) return s;
+    out[2 * p->ev_class[r]] += 1.0;
+    out[2 * p->ev_class[r] + 1] += ms;
+  }
+  return WM_OK;
+}
+
+const char* wm_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same
+seeded inputs.  Bar: normwise relative difference per variable <= 1e-12
+(max_i |gpu_i - oracle_i| / max_i |oracle_i|), FP64."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mhd
+from paper_1812_04278_amd import binding as B
+from helpers import T64, assert_state_parity, fields, oracle_state, rel_err
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_patch(f, **kw):
+    nz, ny, nx = f.rho.shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=1.0 / nx, **kw))
+    p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+    return p
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load()
+
+
+def test_init_parity():
+    say("init parity 37x21x19")
+    f = fields(40, seed=3, v_rms=1.0, crop=(37, 21, 19))
+    U, cfg = oracle_state(f)
+    p = gpu_patch(f)
+    assert_state_parity(p.state(), U, label="init")
+    assert rel_err(p.bcell.cpu(), mhd.zone_B(U["b"])) <= TOL
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_sweep_parity(axis):
+    """Interface fluxes (7 sweep-frame components) and CT transport fluxes of one
+    sweep, on a box that spans several tiles with ragged tails in every direction."""
+    say(f"sweep parity axis {axis}")
+    f = fields(40, seed=4, v_rms=1.5, crop=(37, 21, 19))
+    U, cfg = oracle_state(f)
+    p = gpu_patch(f)
+    out = p.debug_sweep(axis).cpu()
+    F, T = mhd.sweep(U, axis, cfg)
+    for c in range(7):
+        e = rel_err(out[c], F[..., c])
+        assert e <= TOL, (axis, c, e)
+    for c in range(2):
+        e = rel_err(out[7 + c], T[c])
+        assert e <= TOL, (axis, "T", c, e)
+
+
+def test_rhs_parity():
+    say("rhs parity 37x21x19")
+    f = fields(40, seed=5, v_rms=1.5, crop=(37, 21, 19))
+    U, cfg = oracle_state(f)
+    p = gpu_patch(f)
+    k = p.debug_rhs().cpu()
+    ko = mhd.rhs(U, cfg)
+    ref = [ko["rho"], ko["m"][0], ko["m"][1], ko["m"][2], ko["E"], ko["b"][0], ko["b"][1], ko["b"][2]]
+    for c in range(8):
+        e = rel_err(k[c], ref[c])
+        assert e <= TOL, (c, e)
+
+
+def test_step_c1_32():
+    """One SSP-RK3 step on 32^3, Mach 0.1 (the small FP64 workload), dt from
+    eq. (cfl) on each side."""
+    say("step 32^3")
+    f = fields(32, seed=1, v_rms=0.1)
+    U, cfg = oracle_state(f)
+    p = gpu_patch(f)
+    dt_g = p.step(want_dt=True)
+    U1, dt_o = mhd.step(U, cfg)
+    assert abs(dt_g - dt_o) <= 1e-14 * dt_o
+    assert_state_parity(p.state(), U1, label="step")
+    assert rel_err(p.bcell.cpu(), mhd.zone_B(U1["b"])) <= TOL
+
+
+def test_stages_with_given_dt():
+    say("stages with host dt 24x20x28")
+    f = fields(32, seed=6, v_rms=1.0, crop=(24, 20, 28))
+    U, cfg = oracle_state(f)
+    p = gpu_patch(f)
+    dt = 0.3 * mhd.compute_dt(U, cfg)
+    for s in range(3):
+        p.rk_stage(s, dt)
+    U1, _ = mhd.step(U, cfg, dt)
+    assert_state_parity(p.state(), U1, label="stages")
+
+
+@pytest.mark.parametrize("n", [4, 5, 8])
+def test_tiny_grids(n):
+    """Brute force on tiny grids (every stage, two steps): the periodic wrap of the
+    6-zone stencil covers the whole box several times."""
+    say(f"tiny grid {n}")
+    f = fields(n, seed=7 + n, v_rms=0.5, kmax=1)
+    U, cfg = oracle_state(f)
+    p = gpu_patch(f)
+    for _ in range(2):
+        dt_g = p.step(want_dt=True)
+        U, dt_o = mhd.step(U, cfg)
+        assert abs(dt_g - dt_o) <= 1e-14 * dt_o
+    assert_state_parity(p.state(), U, label=f"tiny {n}")
+
+
+def test_crop_64_ten_steps_mach2():
+    """The 256^3 Mach-2 workload's generator sampled at 64^3, 10 steps, full-field
+    parity against the oracle (dt from each side's own eq. (cfl))."""
+    say("64^3 Mach 2, 10 steps")
+    f = fields(64, seed=1, v_rms=2.0)
+    U, cfg = oracle_state(f)
+    p = gpu_patch(f)
+    for s in range(10):
+        dt_g = p.step(want_dt=True)
+        U, dt_o = mhd.step(U, cfg)
+        assert abs(dt_g - dt_o) <= 1e-13 * dt_o, (s, dt_g, dt_o)
+        say(f"  step {s} dt {dt_g:.6e}")
+    assert_state_parity(p.state(), U, label="64^3 x 10")
+
+
+def test_uniform_state_bitwise():
+    say("uniform state")
+    n = 20
+    ones = np.ones((n, n, n))
+    v = np.stack([0.7 * ones, -0.4 * ones, 0.25 * ones])
+    p = B.Patch(B.config(n))
+    p.init_from_potential(1.3 * ones, v, np.zeros((3, n, n, n)), 0.6, (1.0, 0.5, -0.3))
+    h0, b0 = p.hydro.clone(), p.bface.clone()
+    for _ in range(3):
+        p.step()
+    torch.cuda.synchronize()
+    assert torch.equal(p.hydro, h0) and torch.equal(p.bface, b0)
+
+
+def test_determinism():
+    say("determinism")
+    f = fields(48, seed=8, v_rms=2.0)
+    outs = []
+    for _ in range(2):
+        p = gpu_patch(f)
+        for _ in range(3):
+            p.step()
+        torch.cuda.synchronize()
+        outs.append((p.hydro.clone(), p.bface.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_invariants_128_mach2():
+    """Conservation of totals and plane sums and div_h b at round-off, 128^3 x 5 steps."""
+    say("invariants 128^3")
+    f = fields(128, seed=1, v_rms=2.0)
+    p = gpu_patch(f)
+    d0 = p.diagnostics()
+    planes = ((0, (0, 1)), (1, (0, 2)), (2, (1, 2)))
+    s0 = [p.bface[c].sum(dim=d).cpu() for c, d in planes]
+    scale = [float(p.bface[c].abs().sum(dim=d).max()) for c, d in planes]   # sum of |b| over a plane
+    for _ in range(5):
+        p.step()
+    d1 = p.diagnostics()
+    assert d1["n_unphysical"] == 0
+    assert abs(d1["mass"] - d0["mass"]) <= 1e-13 * abs(d0["mass"])
+    assert abs(d1["energy"] - d0["energy"]) <= 1e-13 * abs(d0["energy"])
+    for c in range(3):
+        assert abs(d1["mom"][c] - d0["mom"][c]) <= 1e-13 * (abs(d0["mass"]) * 2.0)
+    s1 = [p.bface[c].sum(dim=d).cpu() for c, d in planes]
+    for a, b, sc in zip(s0, s1, scale):
+        assert float((a - b).abs().max()) <= 1e-13 * sc
+    h = 1.0 / 128
+    assert d1["max_divb"] <= 1e-12 / h
+
+
+def _subbox(t, centre, r):
+    """Periodic sub-box of half-width r around centre (k, j, i) of [..., nz, ny, nx]."""
+    k, j, i = centre
+    for dim, c in ((-3, k), (-2, j), (-1, i)):
+        n = t.shape[dim]
+        idx = torch.tensor([(c + o) % n for o in range(-r, r)], dtype=torch.long)
+        t = t.index_select(dim, idx)
+    return t
+
+
+def test_full_size_sampled_256():
+    """The 256^3 Mach-2 workload in the launch configuration the benchmark times:
+    the GPU right-hand side and one GPU step, checked at sampled zones against the
+    oracle run on a periodic sub-box around each sample (the step's dependence
+    radius is below the sub-box margin: 6 zones per stage)."""
+    say("256^3 sampled parity")
+    f = fields(256, seed=1, v_rms=2.0)
+    p = gpu_patch(f)
+    st0 = p.state()
+    k = p.debug_rhs().cpu()
+    dt = p.compute_dt()
+    # dt against the oracle's eq. (cfl) on the full box (cheap reduction)
+    cfg_full = mhd.cubic(256)
+    dt_o = mhd.compute_dt(st0, cfg_full)
+    assert abs(dt - dt_o) <= 1e-14 * dt_o
+    p.step()
+    st1 = p.state()
+    g = torch.Generator().manual_seed(11)
+    cents = [tuple(int(x) for x in torch.randint(0, 256, (3,), generator=g)) for _ in range(3)]
+    cfg16 = mhd.Config(16, 16, 16, 1.0 / 256)
+    cfg48 = mhd.Config(48, 48, 48, 1.0 / 256)
+    for c in cents:
+        sub = {key: _subbox(st0[key], c, 8) for key in st0}
+        ko = mhd.rhs(sub, cfg16)
+        ref = [ko["rho"], ko["m"][0], ko["m"][1], ko["m"][2], ko["E"], ko["b"][0], ko["b"][1], ko["b"][2]]
+        for comp in range(8):
+            gv = float(_subbox(k[comp], c, 8)[8, 8, 8])
+            ov = float(ref[comp][8, 8, 8])
+            scale = float(ref[comp].abs().max())
+            assert abs(gv - ov) <= TOL * scale, (c, comp, gv, ov)
+        sub = {key: _subbox(st0[key], c, 24) for key in st0}
+        U1, _ = mhd.step(sub, cfg48, dt)
+        for key in ("rho", "E"):
+            gv = _subbox(st1[key], c, 24)[20:28, 20:28, 20:28]
+            ov = U1[key][20:28, 20:28, 20:28]
+            assert rel_err(gv, ov) <= TOL, (c, key)
+        for key in ("m", "b"):
+            gv = _subbox(st1[key], c, 24)[:, 20:28, 20:28, 20:28]
+            ov = U1[key][:, 20:28, 20:28, 20:28]
+            for comp in range(3):
+                assert rel_err(gv[comp], ov[comp]) <= TOL, (c, key, comp)
+        say(f"  sample {c} ok")
