@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=80)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -143,6 +145,15 @@ def main():
         "diagnostics_after": {"max_divb": d["max_divb"], "n_unphysical": d["n_unphysical"]},
         "context": "paper: ~0.6 Mzone/s per 36-core Broadwell node (FP64, RK4, with MPI)",
     }
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written, for scaling
+        # the FETCH_SIZE / WRITE_SIZE counters of the kernels above
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 8
+        del src, dst
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle, {args.cpu_steps} step(s) at {args.cpu_n}^3)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)

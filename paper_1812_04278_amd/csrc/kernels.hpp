@@ -26,12 +26,17 @@ struct Grid {
 // ---------------------------------------------------------------------------
 // directional sweep
 // ---------------------------------------------------------------------------
-constexpr int SW_TA = 16;                    // faces per tile along the sweep axis
-constexpr int SW_TB = 16;                    // faces per tile across (x for y/z sweeps, y for x)
+// Tile of TA faces along the sweep axis by TB faces across it (256 lanes, one
+// face each).  The x sweep uses 64 x 4 so that a wave reads whole 128-byte
+// lines of a row; the y and z sweeps use 16 x 16 with x across, so that every
+// row of the tile is a 128-byte segment in x.
+template <int AXIS> struct SweepTile { static constexpr int TA = 16, TB = 16; };
+template <> struct SweepTile<0> { static constexpr int TA = 64, TB = 4; };
+constexpr int SW_THREADS = 256;
 constexpr int SW_HL = 2, SW_HR = 3;          // stencil zones i-2 .. i+3
-constexpr int SW_NA = SW_TA + SW_HL + SW_HR; // 21 zones along the axis
-constexpr int SW_NCELL = SW_NA * SW_TB;      // 336 zones per tile
-constexpr int SW_THREADS = SW_TA * SW_TB;    // 256
+constexpr int SW_NQ = 14;                    // q (7) and F (7) per zone
+constexpr int SW_NP = 11;                    // rho, v_n, v_t1, v_t2, B_n, B_t1, B_t2, P, c_f, c_A, c_s
+enum { P_RHO = 0, P_VN, P_VT1, P_VT2, P_BN, P_BT1, P_BT2, P_P, P_CF, P_CA, P_CS };
 
 struct SweepArgs {
   Grid g;
@@ -43,23 +48,45 @@ struct SweepArgs {
   double* dbg;           // optional [9][N]: 7 sweep-frame flux components + 2 T
 };
 
-template <int AXIS, bool WENO_Z>
-__global__ __launch_bounds__(SW_THREADS) void sweep_kernel(SweepArgs a) {
-  __shared__ double sh[Z_NVAR * SW_NCELL];
+template <int AXIS>
+constexpr size_t sweep_lds_bytes() {
+  return (size_t)(SW_NQ + SW_NP) * (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB * sizeof(double);
+}
+
+// Phases: (1) zone prologue of the tile and its halo into LDS; (2) per face:
+// central flux, face state, Lax-Friedrichs speeds and the interface
+// differences Delta F, Delta q (formed in FP64); (3) per face: eigen-system
+// and characteristic WENO in registers, reading the differences (in TW) from
+// LDS one eigen pair at a time.
+template <int AXIS, bool WENO_Z, typename TW>
+__global__ __launch_bounds__(SW_THREADS, 2) void sweep_kernel(SweepArgs a) {
+  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  constexpr int NA = TA + SW_HL + SW_HR;     // zones along the axis
+  constexpr int NI = TA + 4;                 // interfaces i-3/2 .. i+TA+3/2
+  constexpr int NC = NA * TB;
+  constexpr int NIF = NI * TB;
+  static_assert(TA * TB == SW_THREADS, "one face per lane");
+  static_assert(TA >= 4, "extra interfaces are built by lanes fa < 4");
+  __shared__ double smem[(SW_NQ + SW_NP) * NC];
+  double* Q = smem;                          // [14][NC] zone q and F, later the differences
+  double* Pz = smem + SW_NQ * NC;            // [11][NC] zone primitives and speeds
+  TW* Dl = reinterpret_cast<TW*>(smem);      // [14][NIF] interface differences (aliases Q)
+
   const Grid& g = a.g;
   const int nA = AXIS == 0 ? g.nx : (AXIS == 1 ? g.ny : g.nz);
   const int nB = AXIS == 0 ? g.ny : g.nx;
-  const int a0 = blockIdx.x * SW_TA;
-  const int b0 = blockIdx.y * SW_TB;
+  const int a0 = blockIdx.x * TA;
+  const int b0 = blockIdx.y * TB;
   const int c = blockIdx.z;
-  // sweep frame component of global index: n, t1, t2
   constexpr int CN = AXIS, CT1 = (AXIS + 1) % 3, CT2 = (AXIS + 2) % 3;
+  auto cidx = [](int aa, int bb) { return AXIS == 0 ? bb * NA + aa : aa * TB + bb; };
+  auto iidx = [](int ia, int bb) { return AXIS == 0 ? bb * NI + ia : ia * TB + bb; };
 
-  // ---- zone prologue into LDS (zones i-2 .. i+TA+2 along the axis, with periodic wrap)
-  for (int cell = threadIdx.x; cell < SW_NCELL; cell += SW_THREADS) {
+  // ---- (1) zone prologue, zones i-2 .. i+TA+2 along the axis with periodic wrap
+  for (int cell = threadIdx.x; cell < NC; cell += SW_THREADS) {
     int aa, bb;
-    if (AXIS == 0) { aa = cell % SW_NA; bb = cell / SW_NA; }
-    else           { bb = cell % SW_TB; aa = cell / SW_TB; }
+    if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
+    else           { bb = cell % TB; aa = cell / TB; }
     const int ia = wrap(a0 - SW_HL + aa, nA);
     const int ib = min(b0 + bb, nB - 1);
     int i, j, k;
@@ -67,62 +94,100 @@ __global__ __launch_bounds__(SW_THREADS) void sweep_kernel(SweepArgs a) {
     else if (AXIS == 1) { i = ib; j = ia; k = c; }
     else                { i = ib; j = c;  k = ia; }
     const size_t gi = g.at(i, j, k);
-    const double rho = a.hydro[gi];
     const double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
-    const double E = a.hydro[4 * g.N + gi];
     const double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
     double z[Z_NVAR];
-    zone_prologue(rho, m[CN], m[CT1], m[CT2], E, B[CN], B[CT1], B[CT2], a.ph.gamma, z);
+    zone_prologue(a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
 #pragma unroll
-    for (int v = 0; v < Z_NVAR; ++v) sh[v * SW_NCELL + cell] = z[v];
+    for (int v = 0; v < SW_NQ; ++v) Q[v * NC + cell] = z[v];
+    Pz[P_RHO * NC + cell] = z[Z_RHO];
+    Pz[P_VN * NC + cell] = z[Z_VN];
+    Pz[P_VT1 * NC + cell] = z[Z_VT1];
+    Pz[P_VT2 * NC + cell] = z[Z_VT2];
+    Pz[P_BN * NC + cell] = z[Z_BN];
+    Pz[P_BT1 * NC + cell] = z[Z_BT1];
+    Pz[P_BT2 * NC + cell] = z[Z_BT2];
+    Pz[P_P * NC + cell] = z[Z_P];
+    Pz[P_CF * NC + cell] = z[Z_CF];
+    Pz[P_CA * NC + cell] = z[Z_CA];
+    Pz[P_CS * NC + cell] = z[Z_CS];
   }
   __syncthreads();
 
-  // ---- one face per lane
+  // ---- (2) per face: central flux, face state, LF speeds, own interface differences
   int fa, fb;
-  if (AXIS == 0) { fa = threadIdx.x % SW_TA; fb = threadIdx.x / SW_TA; }
-  else           { fb = threadIdx.x % SW_TB; fa = threadIdx.x / SW_TB; }
-  auto L = [&](int v, int o) -> double {   // zone i-2+o of this lane's stencil
-    const int cell = AXIS == 0 ? fb * SW_NA + fa + o : (fa + o) * SW_TB + fb;
-    return sh[v * SW_NCELL + cell];
-  };
-
-  double dF[5][7], dq[5][7], Fc[7];
+  if (AXIS == 0) { fa = threadIdx.x % TA; fb = threadIdx.x / TA; }
+  else           { fb = threadIdx.x % TB; fa = threadIdx.x / TB; }
+  const int cL = cidx(fa + 2, fb), cR = cidx(fa + 3, fb);
+  double Fc[7];
 #pragma unroll
   for (int j = 0; j < 7; ++j) {
-    double f[6], q[6];
-#pragma unroll
-    for (int o = 0; o < 6; ++o) {
-      f[o] = L(Z_F0 + j, o);
-      q[o] = L(Z_RHO + j, o);
-    }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      dF[k][j] = f[k + 1] - f[k];
-      dq[k][j] = q[k + 1] - q[k];
-    }
-    Fc[j] = (-f[1] + 7.0 * f[2] + 7.0 * f[3] - f[4]) * (1.0 / 12.0);
+    const double* F = Q + (SW_NQ / 2 + j) * NC;
+    Fc[j] = (-F[cidx(fa + 1, fb)] + 7.0 * F[cL] + 7.0 * F[cR] - F[cidx(fa + 4, fb)]) * (1.0 / 12.0);
   }
-  // face state: mean of the primitive states of zones i (o = 2) and i+1 (o = 3)
-  const double rho = 0.5 * (L(Z_RHO, 2) + L(Z_RHO, 3));
-  const double vn = 0.5 * (L(Z_VN, 2) + L(Z_VN, 3));
-  const double vt1 = 0.5 * (L(Z_VT1, 2) + L(Z_VT1, 3));
-  const double vt2 = 0.5 * (L(Z_VT2, 2) + L(Z_VT2, 3));
-  const double Bn = 0.5 * (L(Z_BN, 2) + L(Z_BN, 3));
-  const double Bt1 = 0.5 * (L(Z_BT1, 2) + L(Z_BT1, 3));
-  const double Bt2 = 0.5 * (L(Z_BT2, 2) + L(Z_BT2, 3));
-  const double P = 0.5 * (L(Z_P, 2) + L(Z_P, 3));
+  auto PL = [&](int v) { return Pz[v * NC + cL]; };
+  auto PR = [&](int v) { return Pz[v * NC + cR]; };
+  double fp[8];   // face state: mean of the primitive states of zones i and i+1
+#pragma unroll
+  for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (PL(P_RHO + v) + PR(P_RHO + v));
+  TW al[7];
+  {
+    const double vL = PL(P_VN), vR = PR(P_VN);
+    const double cfL = PL(P_CF), cfR = PR(P_CF), cAL = PL(P_CA), cAR = PR(P_CA), csL = PL(P_CS), csR = PR(P_CS);
+    al[0] = TW(fmax(fabs(vL - cfL), fabs(vR - cfR)));
+    al[1] = TW(fmax(fabs(vL - cAL), fabs(vR - cAR)));
+    al[2] = TW(fmax(fabs(vL - csL), fabs(vR - csR)));
+    al[3] = TW(fmax(fabs(vL), fabs(vR)));
+    al[4] = TW(fmax(fabs(vL + csL), fabs(vR + csR)));
+    al[5] = TW(fmax(fabs(vL + cAL), fabs(vR + cAR)));
+    al[6] = TW(fmax(fabs(vL + cfL), fabs(vR + cfR)));
+  }
+  // CT transport-flux correction: face mean of B_n v_t (eq. fct1-fct6)
+  const double tc1 = 0.5 * (PL(P_BN) * PL(P_VT1) + PR(P_BN) * PR(P_VT1));
+  const double tc2 = 0.5 * (PL(P_BN) * PL(P_VT2) + PR(P_BN) * PR(P_VT2));
+  double d0[SW_NQ], d1[SW_NQ];
+  {
+    const int c0 = cidx(fa, fb), c1 = cidx(fa + 1, fb);
+#pragma unroll
+    for (int v = 0; v < SW_NQ; ++v) d0[v] = Q[v * NC + c1] - Q[v * NC + c0];
+    if (fa < 4) {
+      const int c2 = cidx(TA + fa, fb), c3 = cidx(TA + fa + 1, fb);
+#pragma unroll
+      for (int v = 0; v < SW_NQ; ++v) d1[v] = Q[v * NC + c3] - Q[v * NC + c2];
+    }
+  }
+  __syncthreads();
+  // differences stored as (Delta F, Delta q): j = 0..6 flux, 7..13 state
+#pragma unroll
+  for (int v = 0; v < 7; ++v) {
+    Dl[v * NIF + iidx(fa, fb)] = TW(d0[7 + v]);
+    Dl[(7 + v) * NIF + iidx(fa, fb)] = TW(d0[v]);
+  }
+  if (fa < 4) {
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      Dl[v * NIF + iidx(TA + fa, fb)] = TW(d1[7 + v]);
+      Dl[(7 + v) * NIF + iidx(TA + fa, fb)] = TW(d1[v]);
+    }
+  }
+  __syncthreads();
+
+  // ---- (3) characteristic WENO flux of this face
+  auto dl = [&](int j, int k) -> TW { return Dl[j * NIF + iidx(fa + k, fb)]; };
+  FaceEig e;
+  face_eig(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], fp[6], fp[7], a.ph, e);
   double corr[7];
-  face_char_flux<WENO_Z>(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P,
-                         L(Z_VN, 2), L(Z_CF, 2), L(Z_CA, 2), L(Z_CS, 2),
-                         L(Z_VN, 3), L(Z_CF, 3), L(Z_CA, 3), L(Z_CS, 3), dF, dq, a.ph, corr);
+  face_corr<WENO_Z, TW>(e, al, dl, a.ph, corr);
   double Ff[7];
 #pragma unroll
   for (int j = 0; j < 7; ++j) Ff[j] = Fc[j] + corr[j];
-  // CT transport fluxes: B_t components plus the face mean of B_n v_t (eq. fct1-fct6)
-  const double T1 = Ff[4] + 0.5 * (L(Z_BN, 2) * L(Z_VT1, 2) + L(Z_BN, 3) * L(Z_VT1, 3));
-  const double T2 = Ff[5] + 0.5 * (L(Z_BN, 2) * L(Z_VT2, 2) + L(Z_BN, 3) * L(Z_VT2, 3));
+  const double T1 = Ff[4] + tc1;
+  const double T2 = Ff[5] + tc2;
 
+  // keep the face computation ahead of the range guard: sinking it into the
+  // guarded block defeats register allocation (hundreds of spills)
+#pragma unroll
+  for (int j = 0; j < 7; ++j) asm volatile("" : "+v"(Ff[j]));
   if (a0 + fa >= nA || b0 + fb >= nB) return;
   int i, j, k;
   if (AXIS == 0)      { i = a0 + fa; j = b0 + fb; k = c; }

@@ -72,234 +72,259 @@ __host__ __device__ __forceinline__ void zone_prologue(double rho, double mn, do
   out[Z_CS] = sqrt(cs2);
 }
 
+// Scheduling fence: keeps the compiler from hoisting the LDS reads of later
+// interfaces / passes above earlier ones, which bounds register pressure.
+__host__ __device__ __forceinline__ void sched_fence() {
+#ifdef __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// Reciprocal for the WENO weights: hardware estimate refined by Newton steps
+// (relative error far below the rounding of the weights themselves).
+__host__ __device__ __forceinline__ double rcp_w(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(e, r, r);
+  e = fma(-x, r, 1.0);
+  return fma(e, r, r);
+#else
+  return 1.0 / x;
+#endif
+}
+__host__ __device__ __forceinline__ float rcp_w(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.0f), r, r);
+#else
+  return 1.0f / x;
+#endif
+}
+
 // WENO5 interpolant phi_N(a, b, c, d) of Sect. 2.2.  With s_k = eps + IS_k the
 // Jiang-Shu weights alpha_k = d_k / s_k^2 give
 //   omega_0 = s1^2 s2^2 / Q,  omega_2 = 3 s0^2 s1^2 / Q,
 //   Q = s1^2 s2^2 + 6 s0^2 s2^2 + 3 s0^2 s1^2,
-// one division instead of four.  WENO-Z: alpha_k = d_k (1 + (tau_5/(eps_Z + IS_k))^2).
-template <bool WENO_Z>
-__host__ __device__ __forceinline__ double phiN(double a, double b, double c, double d, double eps, double eps_Z) {
-  const double t0 = a - b, t1 = a - 3.0 * b;
-  const double t2 = b - c, t3 = b + c;
-  const double t4 = c - d, t5 = 3.0 * c - d;
-  const double IS0 = 13.0 * t0 * t0 + 3.0 * t1 * t1;
-  const double IS1 = 13.0 * t2 * t2 + 3.0 * t3 * t3;
-  const double IS2 = 13.0 * t4 * t4 + 3.0 * t5 * t5;
-  double w0, w2;
+// one reciprocal instead of four divisions.  WENO-Z: alpha_k = d_k (1 + (tau_5/(eps_Z + IS_k))^2).
+template <bool WENO_Z, typename T>
+__host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, T eps_Z) {
+  const T t0 = a - b, t1 = a - T(3) * b;
+  const T t2 = b - c, t3 = b + c;
+  const T t4 = c - d, t5 = T(3) * c - d;
+  const T IS0 = T(13) * t0 * t0 + T(3) * t1 * t1;
+  const T IS1 = T(13) * t2 * t2 + T(3) * t3 * t3;
+  const T IS2 = T(13) * t4 * t4 + T(3) * t5 * t5;
+  T w0, w2;
   if (!WENO_Z) {
-    double s0 = eps + IS0, s1 = eps + IS1, s2 = eps + IS2;
+    T s0 = eps + IS0, s1 = eps + IS1, s2 = eps + IS2;
     s0 *= s0; s1 *= s1; s2 *= s2;
-    const double p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
-    const double inv = 1.0 / (p12 + 6.0 * p02 + 3.0 * p01);
+    const T p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
+    const T inv = rcp_w(p12 + T(6) * p02 + T(3) * p01);
     w0 = p12 * inv;
-    w2 = 3.0 * p01 * inv;
+    w2 = T(3) * p01 * inv;
   } else {
-    const double tau5 = fabs(IS0 - IS2);
-    const double r0 = tau5 / (eps_Z + IS0), r1 = tau5 / (eps_Z + IS1), r2 = tau5 / (eps_Z + IS2);
-    const double al0 = 1.0 + r0 * r0, al1 = 6.0 * (1.0 + r1 * r1), al2 = 3.0 * (1.0 + r2 * r2);
-    const double inv = 1.0 / (al0 + al1 + al2);
+    const T tau5 = fabs(IS0 - IS2);
+    const T r0 = tau5 * rcp_w(eps_Z + IS0), r1 = tau5 * rcp_w(eps_Z + IS1), r2 = tau5 * rcp_w(eps_Z + IS2);
+    const T al0 = T(1) + r0 * r0, al1 = T(6) * (T(1) + r1 * r1), al2 = T(3) * (T(1) + r2 * r2);
+    const T inv = rcp_w(al0 + al1 + al2);
     w0 = al0 * inv;
     w2 = al2 * inv;
   }
-  return w0 * (a - 2.0 * b + c) * (1.0 / 3.0) + (w2 - 0.5) * (b - 2.0 * c + d) * (1.0 / 6.0);
+  return w0 * (a - T(2) * b + c) * T(1.0 / 3.0) + (w2 - T(0.5)) * (b - T(2) * c + d) * T(1.0 / 6.0);
 }
 
-// phi^- - phi^+ of eq. (FWENO) for one characteristic field, from the projected
-// differences pF[k], pq[k] at interfaces i-3/2 .. i+5/2 and the LF speed alpha.
-template <bool WENO_Z>
-__host__ __device__ __forceinline__ double weno_char(const double pF[5], const double pq[5], double alpha,
-                                            double eps, double eps_Z) {
-  double p0 = 0.5 * (pF[0] + alpha * pq[0]);
-  double p1 = 0.5 * (pF[1] + alpha * pq[1]);
-  double p2 = 0.5 * (pF[2] + alpha * pq[2]);
-  double p3 = 0.5 * (pF[3] + alpha * pq[3]);
-  double n1 = 0.5 * (pF[1] - alpha * pq[1]);
-  double n2 = 0.5 * (pF[2] - alpha * pq[2]);
-  double n3 = 0.5 * (pF[3] - alpha * pq[3]);
-  double n4 = 0.5 * (pF[4] - alpha * pq[4]);
-  return phiN<WENO_Z>(n4, n3, n2, n1, eps, eps_Z) - phiN<WENO_Z>(p0, p1, p2, p3, eps, eps_Z);
+// phi^- - phi^+ of eq. (FWENO) from the split values of one characteristic
+// field: v[0..3] = Delta F^+ at i-3/2 .. i+3/2, v[4..7] = Delta F^- at i-1/2 .. i+5/2.
+template <bool WENO_Z, typename T>
+__host__ __device__ __forceinline__ T weno_split(const T v[8], T eps, T eps_Z) {
+  return phiN<WENO_Z>(v[7], v[6], v[5], v[4], eps, eps_Z) - phiN<WENO_Z>(v[0], v[1], v[2], v[3], eps, eps_Z);
 }
 
-// Dot products of a row with the five differences of F and of q.
-__host__ __device__ __forceinline__ void project7(const double l[7], const double dF[5][7], const double dq[5][7],
-                                         double pF[5], double pq[5]) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double sF = l[0] * dF[k][0], sq = l[0] * dq[k][0];
-#pragma unroll
-    for (int j = 1; j < 7; ++j) {
-      sF += l[j] * dF[k][j];
-      sq += l[j] * dq[k][j];
-    }
-    pF[k] = sF;
-    pq[k] = sq;
-  }
-}
+// Eigen-system scalars of Appendix A at one face (always FP64: the
+// renormalisation near degeneracies is done in double precision).
+struct FaceEig {
+  double vn, vt1, vt2, Bt1, Bt2;
+  double a2, cs, sr, isr, cf, cf2, csl, csl2;
+  double by, bz, s, af, as;
+  double v2, Gf, Ga, Gs, ha2, tau, g1, g2, omg;
+};
 
-// Projections with a row split into its sign-even part S (full) and sign-odd
-// part A (nonzero in components 0..3 only): rows S + A and S - A at once.
-__host__ __device__ __forceinline__ void project_pair(const double S[7], const double A[4], const double dF[5][7],
-                                             const double dq[5][7], double pFu[5], double pqu[5],
-                                             double pFl[5], double pql[5]) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double sF = S[0] * dF[k][0], sq = S[0] * dq[k][0];
-#pragma unroll
-    for (int j = 1; j < 7; ++j) {
-      sF += S[j] * dF[k][j];
-      sq += S[j] * dq[k][j];
-    }
-    double aF = A[0] * dF[k][0], aq = A[0] * dq[k][0];
-#pragma unroll
-    for (int j = 1; j < 4; ++j) {
-      aF += A[j] * dF[k][j];
-      aq += A[j] * dq[k][j];
-    }
-    pFu[k] = sF + aF; pqu[k] = sq + aq;
-    pFl[k] = sF - aF; pql[k] = sq - aq;
-  }
-}
-
-// Characteristic part of the WENO interface flux at face i+1/2:
-//   corr = sum_m R(:,m) (phi^-_m - phi^+_m)
-// so that F_{i+1/2} = F_c + corr with the central term F_c taken in physical
-// space (R L = I), eq. (FWENO).  The face state is the mean of the primitive
-// states of zones i and i+1 (arithmetic averaging, Sect. 2.2 / Appendix A);
-// L and R follow Appendix A with m = 1, 2, 3 the upper signs and 7, 6, 5 the
-// lower, m = 2, 6 Alfven and m = 3, 5 slow.
-//
-// Inputs: face primitives, zone speeds of zones i and i+1 for alpha(m), and
-// the differences dF[k], dq[k] across interfaces i-3/2 .. i+5/2.
-template <bool WENO_Z>
-__host__ __device__ __forceinline__ void face_char_flux(
-    double rho, double vn, double vt1, double vt2, double Bn, double Bt1, double Bt2, double P,
-    double vnL, double cfL, double cAL, double csL, double vnR, double cfR, double cAR, double csR,
-    const double dF[5][7], const double dq[5][7], const Phys& ph, double corr[7]) {
+__host__ __device__ __forceinline__ void face_eig(double rho, double vn, double vt1, double vt2, double Bn, double Bt1,
+                                                  double Bt2, double P, const Phys& ph, FaceEig& e) {
   const double gamma = ph.gamma;
   const double irho = 1.0 / rho;
-  const double a2 = gamma * P * irho;
-  const double cs = sqrt(a2);
-  const double sr = sqrt(rho);
-  const double isr = 1.0 / sr;
+  e.vn = vn; e.vt1 = vt1; e.vt2 = vt2; e.Bt1 = Bt1; e.Bt2 = Bt2;
+  e.a2 = gamma * P * irho;
+  e.cs = sqrt(e.a2);
+  e.sr = sqrt(rho);
+  e.isr = 1.0 / e.sr;
   const double Bperp2 = Bt1 * Bt1 + Bt2 * Bt2;
   const double b2 = (Bn * Bn + Bperp2) * irho;
-  const double dab = a2 - b2;
-  const double D = sqrt(dab * dab + 4.0 * a2 * (Bperp2 * irho));
-  const double cf2 = 0.5 * (a2 + b2 + D);
-  const double cf = sqrt(cf2);
-  const double csl2 = cf2 > 0.0 ? a2 * (Bn * Bn * irho) / cf2 : 0.0;
-  const double csl = sqrt(csl2);
-  double by, bz;
+  const double dab = e.a2 - b2;
+  const double D = sqrt(dab * dab + 4.0 * e.a2 * (Bperp2 * irho));
+  e.cf2 = 0.5 * (e.a2 + b2 + D);
+  e.cf = sqrt(e.cf2);
+  e.csl2 = e.cf2 > 0.0 ? e.a2 * (Bn * Bn * irho) / e.cf2 : 0.0;
+  e.csl = sqrt(e.csl2);
   if (Bperp2 > ph.eps_B) {
     const double ib = 1.0 / sqrt(Bperp2);
-    by = Bt1 * ib;
-    bz = Bt2 * ib;
+    e.by = Bt1 * ib;
+    e.bz = Bt2 * ib;
   } else {
-    by = 0.70710678118654752440;
-    bz = 0.70710678118654752440;
+    e.by = 0.70710678118654752440;
+    e.bz = 0.70710678118654752440;
   }
-  const double s = Bn >= ph.eps_B ? 1.0 : -1.0;
-  double af, as;
+  e.s = Bn >= ph.eps_B ? 1.0 : -1.0;
   if (sqrt(D) >= ph.eps_B) {
     const double r = dab / D;
-    af = sqrt(fmin(fmax(0.5 * (1.0 + r), 0.0), 1.0));
-    as = sqrt(fmin(fmax(0.5 * (1.0 - r), 0.0), 1.0));
+    e.af = sqrt(fmin(fmax(0.5 * (1.0 + r), 0.0), 1.0));
+    e.as = sqrt(fmin(fmax(0.5 * (1.0 - r), 0.0), 1.0));
   } else {
-    af = 0.70710678118654752440;
-    as = 0.70710678118654752440;
+    e.af = 0.70710678118654752440;
+    e.as = 0.70710678118654752440;
   }
-  const double g1 = 0.5 * (gamma - 1.0);
-  const double g2 = (gamma - 2.0) / (gamma - 1.0);
-  const double omg = 1.0 - gamma;
-  const double ha2 = 0.5 / a2;
-  const double tau = (gamma - 1.0) / a2;
-  const double v2 = vn * vn + vt1 * vt1 + vt2 * vt2;
-  const double bv = by * vt1 + bz * vt2;
-  const double Gf = af * cf * vn - as * csl * s * bv;
-  const double Ga = s * (bz * vt1 - by * vt2);
-  const double Gs = as * csl * vn + af * cf * s * bv;
-  const double sra = sr * cs;
+  e.g1 = 0.5 * (gamma - 1.0);
+  e.g2 = (gamma - 2.0) / (gamma - 1.0);
+  e.omg = 1.0 - gamma;
+  e.ha2 = 0.5 / e.a2;
+  e.tau = (gamma - 1.0) / e.a2;
+  e.v2 = vn * vn + vt1 * vt1 + vt2 * vt2;
+  const double bv = e.by * vt1 + e.bz * vt2;
+  e.Gf = e.af * e.cf * vn - e.as * e.csl * e.s * bv;
+  e.Ga = e.s * (e.bz * vt1 - e.by * vt2);
+  e.Gs = e.as * e.csl * vn + e.af * e.cf * e.s * bv;
+}
 
-  double pFu[5], pqu[5], pFl[5], pql[5];
-  double fu, fl;   // phi^- - phi^+ of the upper / lower member of a pair
+// Split values of a pair of characteristic fields whose left rows are S + A
+// (upper, lambda = v - c) and S - A (lower), A nonzero in components 0..3,
+// for the five interface differences DL(j, k): j = 0..6 Delta F, 7..13 Delta q,
+// k = 0..4 interfaces i-3/2 .. i+5/2.  Lax-Friedrichs: Delta F^+- = (Delta F^s
+// +- alpha Delta q^s)/2.
+template <typename T, class DL>
+__host__ __device__ __forceinline__ void split_pair(const T S[7], const T A[4], T alu, T all, DL dl, T vu[8],
+                                                    T vl[8]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    T dF[7], dq[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) { dF[j] = dl(j, k); dq[j] = dl(7 + j, k); }
+    T sF = S[0] * dF[0], sq = S[0] * dq[0];
+#pragma unroll
+    for (int j = 1; j < 7; ++j) { sF += S[j] * dF[j]; sq += S[j] * dq[j]; }
+    T aF = A[0] * dF[0], aq = A[0] * dq[0];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) { aF += A[j] * dF[j]; aq += A[j] * dq[j]; }
+    const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
+    if (k <= 3) { vu[k] = T(0.5) * (uF + alu * uq); vl[k] = T(0.5) * (lF + all * lq); }
+    if (k >= 1) { vu[3 + k] = T(0.5) * (uF - alu * uq); vl[3 + k] = T(0.5) * (lF - all * lq); }
+    sched_fence();
+  }
+}
 
-  // ---- fast pair, m = 1 (v - c_fast) and m = 7 (v + c_fast)
+// Characteristic part of the interface flux at face i+1/2,
+//   corr = sum_m R(:,m) (phi^-_m - phi^+_m),
+// so that F_{i+1/2} = F_c + corr with the central term F_c in physical space
+// (R L = I), eq. (FWENO).  L and R follow Appendix A: m = 1, 2, 3 take the
+// upper signs and 7, 6, 5 the lower; m = 2, 6 are the Alfven waves and m = 3, 5
+// the slow waves.  `al[m]` is the Lax-Friedrichs speed of field m (0-based),
+// `dl(j, k)` reads interface difference j of interface k.  Projections, split
+// and weights run in T; the eigen scalars and the back-projection in FP64.
+template <bool WENO_Z, typename T, class DL>
+__host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[7], DL dl, const Phys& ph,
+                                                   double corr[7]) {
+  const T eps = T(ph.eps), epsZ = T(ph.eps_Z);
+  const double gm1 = -e.omg;
+  const double sra = e.sr * e.cs;
+  T vu[8], vl[8];
+  // ---- fast pair (m = 1, 7)
   {
-    const double S[7] = {ha2 * (af * g1 * v2), ha2 * (omg * af * vn), ha2 * (omg * af * vt1),
-                         ha2 * (omg * af * vt2), ha2 * (omg * af * Bt1 + sra * as * by),
-                         ha2 * (omg * af * Bt2 + sra * as * bz), ha2 * ((gamma - 1.0) * af)};
-    const double A[4] = {ha2 * Gf, -ha2 * (af * cf), ha2 * (csl * as * by * s), ha2 * (csl * as * bz * s)};
-    project_pair(S, A, dF, dq, pFu, pqu, pFl, pql);
-    const double alu = fmax(fabs(vnL - cfL), fabs(vnR - cfR));
-    const double all = fmax(fabs(vnL + cfL), fabs(vnR + cfR));
-    fu = weno_char<WENO_Z>(pFu, pqu, alu, ph.eps, ph.eps_Z);
-    fl = weno_char<WENO_Z>(pFl, pql, all, ph.eps, ph.eps_Z);
+    const T S[7] = {T(e.ha2 * (e.af * e.g1 * e.v2)), T(e.ha2 * (e.omg * e.af * e.vn)),
+                    T(e.ha2 * (e.omg * e.af * e.vt1)), T(e.ha2 * (e.omg * e.af * e.vt2)),
+                    T(e.ha2 * (e.omg * e.af * e.Bt1 + sra * e.as * e.by)),
+                    T(e.ha2 * (e.omg * e.af * e.Bt2 + sra * e.as * e.bz)), T(e.ha2 * (gm1 * e.af))};
+    const T A[4] = {T(e.ha2 * e.Gf), T(-e.ha2 * (e.af * e.cf)), T(e.ha2 * (e.csl * e.as * e.by * e.s)),
+                    T(e.ha2 * (e.csl * e.as * e.bz * e.s))};
+    split_pair(S, A, al[0], al[6], dl, vu, vl);
+    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
+    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
     const double sp = fu + fl, sm = fu - fl;
-    const double Rs6 = af * (0.5 * v2 + cf2 - g2 * a2);
-    corr[0] = af * sp;
-    corr[1] = af * vn * sp - af * cf * sm;
-    corr[2] = af * vt1 * sp + csl * as * by * s * sm;
-    corr[3] = af * vt2 * sp + csl * as * bz * s * sm;
-    corr[4] = cs * as * by * isr * sp;
-    corr[5] = cs * as * bz * isr * sp;
-    corr[6] = Rs6 * sp - Gf * sm;
+    corr[0] = e.af * sp;
+    corr[1] = e.af * e.vn * sp - e.af * e.cf * sm;
+    corr[2] = e.af * e.vt1 * sp + e.csl * e.as * e.by * e.s * sm;
+    corr[3] = e.af * e.vt2 * sp + e.csl * e.as * e.bz * e.s * sm;
+    corr[4] = e.cs * e.as * e.by * e.isr * sp;
+    corr[5] = e.cs * e.as * e.bz * e.isr * sp;
+    corr[6] = e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2) * sp - e.Gf * sm;
   }
-  // ---- Alfven pair, m = 2 (v - c_A) and m = 6 (v + c_A)
+  sched_fence();
+  // ---- slow pair (m = 3, 5)
   {
-    const double S[4] = {0.5 * Ga, 0.0, -0.5 * bz * s, 0.5 * by * s};
-    const double A4 = -0.5 * sr * bz, A5 = 0.5 * sr * by;
+    const T S[7] = {T(e.ha2 * (e.as * e.g1 * e.v2)), T(e.ha2 * (e.omg * e.as * e.vn)),
+                    T(e.ha2 * (e.omg * e.as * e.vt1)), T(e.ha2 * (e.omg * e.as * e.vt2)),
+                    T(e.ha2 * (e.omg * e.as * e.Bt1 - sra * e.af * e.by)),
+                    T(e.ha2 * (e.omg * e.as * e.Bt2 - sra * e.af * e.bz)), T(e.ha2 * (gm1 * e.as))};
+    const T A[4] = {T(e.ha2 * e.Gs), T(-e.ha2 * (e.as * e.csl)), T(-e.ha2 * (e.cf * e.af * e.by * e.s)),
+                    T(-e.ha2 * (e.cf * e.af * e.bz * e.s))};
+    split_pair(S, A, al[2], al[4], dl, vu, vl);
+    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
+    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
+    const double sp = fu + fl, sm = fu - fl;
+    corr[0] += e.as * sp;
+    corr[1] += e.as * e.vn * sp - e.as * e.csl * sm;
+    corr[2] += e.as * e.vt1 * sp - e.cf * e.af * e.by * e.s * sm;
+    corr[3] += e.as * e.vt2 * sp - e.cf * e.af * e.bz * e.s * sm;
+    corr[4] += -e.cs * e.af * e.by * e.isr * sp;
+    corr[5] += -e.cs * e.af * e.bz * e.isr * sp;
+    corr[6] += e.as * (0.5 * e.v2 + e.csl2 - e.g2 * e.a2) * sp - e.Gs * sm;
+  }
+  sched_fence();
+  // ---- Alfven pair (m = 2, 6): L = (Ga/2, 0, -bz s/2, by s/2, -+sr bz/2, +-sr by/2, 0)
+  {
+    const T S0 = T(0.5 * e.Ga), S2 = T(-0.5 * e.bz * e.s), S3 = T(0.5 * e.by * e.s);
+    const T A4 = T(-0.5 * e.sr * e.bz), A5 = T(0.5 * e.sr * e.by);
+    const T alu = al[1], all = al[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      const double sF = S[0] * dF[k][0] + S[2] * dF[k][2] + S[3] * dF[k][3];
-      const double sq = S[0] * dq[k][0] + S[2] * dq[k][2] + S[3] * dq[k][3];
-      const double aF = A4 * dF[k][4] + A5 * dF[k][5];
-      const double aq = A4 * dq[k][4] + A5 * dq[k][5];
-      pFu[k] = sF + aF; pqu[k] = sq + aq;
-      pFl[k] = sF - aF; pql[k] = sq - aq;
+      const T sF = S0 * dl(0, k) + S2 * dl(2, k) + S3 * dl(3, k);
+      const T sq = S0 * dl(7, k) + S2 * dl(9, k) + S3 * dl(10, k);
+      const T aF = A4 * dl(4, k) + A5 * dl(5, k);
+      const T aq = A4 * dl(11, k) + A5 * dl(12, k);
+      const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
+      if (k <= 3) { vu[k] = T(0.5) * (uF + alu * uq); vl[k] = T(0.5) * (lF + all * lq); }
+      if (k >= 1) { vu[3 + k] = T(0.5) * (uF - alu * uq); vl[3 + k] = T(0.5) * (lF - all * lq); }
+      sched_fence();
     }
-    const double alu = fmax(fabs(vnL - cAL), fabs(vnR - cAR));
-    const double all = fmax(fabs(vnL + cAL), fabs(vnR + cAR));
-    fu = weno_char<WENO_Z>(pFu, pqu, alu, ph.eps, ph.eps_Z);
-    fl = weno_char<WENO_Z>(pFl, pql, all, ph.eps, ph.eps_Z);
+    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
+    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
     const double sp = fu + fl, sm = fu - fl;
-    corr[2] += -bz * s * sp;
-    corr[3] += by * s * sp;
-    corr[4] += -bz * isr * sm;
-    corr[5] += by * isr * sm;
-    corr[6] += -Ga * sp;
+    corr[2] += -e.bz * e.s * sp;
+    corr[3] += e.by * e.s * sp;
+    corr[4] += -e.bz * e.isr * sm;
+    corr[5] += e.by * e.isr * sm;
+    corr[6] += -e.Ga * sp;
   }
-  // ---- slow pair, m = 3 (v - c_slow) and m = 5 (v + c_slow)
+  sched_fence();
+  // ---- entropy (m = 4): L = (1 - tau v^2/2, tau v, tau B_t, -tau)
   {
-    const double S[7] = {ha2 * (as * g1 * v2), ha2 * (omg * as * vn), ha2 * (omg * as * vt1),
-                         ha2 * (omg * as * vt2), ha2 * (omg * as * Bt1 - sra * af * by),
-                         ha2 * (omg * as * Bt2 - sra * af * bz), ha2 * ((gamma - 1.0) * as)};
-    const double A[4] = {ha2 * Gs, -ha2 * (as * csl), -ha2 * (cf * af * by * s), -ha2 * (cf * af * bz * s)};
-    project_pair(S, A, dF, dq, pFu, pqu, pFl, pql);
-    const double alu = fmax(fabs(vnL - csL), fabs(vnR - csR));
-    const double all = fmax(fabs(vnL + csL), fabs(vnR + csR));
-    fu = weno_char<WENO_Z>(pFu, pqu, alu, ph.eps, ph.eps_Z);
-    fl = weno_char<WENO_Z>(pFl, pql, all, ph.eps, ph.eps_Z);
-    const double sp = fu + fl, sm = fu - fl;
-    const double Rs6 = as * (0.5 * v2 + csl2 - g2 * a2);
-    corr[0] += as * sp;
-    corr[1] += as * vn * sp - as * csl * sm;
-    corr[2] += as * vt1 * sp - cf * af * by * s * sm;
-    corr[3] += as * vt2 * sp - cf * af * bz * s * sm;
-    corr[4] += -cs * af * by * isr * sp;
-    corr[5] += -cs * af * bz * isr * sp;
-    corr[6] += Rs6 * sp - Gs * sm;
-  }
-  // ---- entropy, m = 4 (v)
-  {
-    const double l[7] = {1.0 - 0.5 * tau * v2, tau * vn, tau * vt1, tau * vt2, tau * Bt1, tau * Bt2, -tau};
-    project7(l, dF, dq, pFu, pqu);
-    const double al = fmax(fabs(vnL), fabs(vnR));
-    const double f4 = weno_char<WENO_Z>(pFu, pqu, al, ph.eps, ph.eps_Z);
+    const T l[7] = {T(1.0 - 0.5 * e.tau * e.v2), T(e.tau * e.vn), T(e.tau * e.vt1), T(e.tau * e.vt2),
+                    T(e.tau * e.Bt1), T(e.tau * e.Bt2), T(-e.tau)};
+    const T a4 = al[3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      T sF = l[0] * dl(0, k), sq = l[0] * dl(7, k);
+#pragma unroll
+      for (int j = 1; j < 7; ++j) { sF += l[j] * dl(j, k); sq += l[j] * dl(7 + j, k); }
+      if (k <= 3) vu[k] = T(0.5) * (sF + a4 * sq);
+      if (k >= 1) vu[3 + k] = T(0.5) * (sF - a4 * sq);
+      sched_fence();
+    }
+    const double f4 = double(weno_split<WENO_Z>(vu, eps, epsZ));
     corr[0] += f4;
-    corr[1] += vn * f4;
-    corr[2] += vt1 * f4;
-    corr[3] += vt2 * f4;
-    corr[6] += 0.5 * v2 * f4;
+    corr[1] += e.vn * f4;
+    corr[2] += e.vt1 * f4;
+    corr[3] += e.vt2 * f4;
+    corr[6] += 0.5 * e.v2 * f4;
   }
 }
 

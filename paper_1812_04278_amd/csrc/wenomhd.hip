@@ -150,12 +150,13 @@ wm_status launch_sweep(wm_patch* p, const double* hydro, const double* bcell, do
   const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
   const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
   const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
-  dim3 grid((nA + SW_TA - 1) / SW_TA, (nB + SW_TB - 1) / SW_TB, nC);
+  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  dim3 grid((nA + TA - 1) / TA, (nB + TB - 1) / TB, nC);
   const long r = prof_begin(p, K_SWEEP);
   if (p->ph.weno_z)
-    hipLaunchKernelGGL((sweep_kernel<AXIS, true>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    hipLaunchKernelGGL((sweep_kernel<AXIS, true, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
   else
-    hipLaunchKernelGGL((sweep_kernel<AXIS, false>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    hipLaunchKernelGGL((sweep_kernel<AXIS, false, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
   WM_LAUNCH_CHECK("sweep kernel");
   prof_end(p, r);
   return WM_OK;
