@@ -15,6 +15,8 @@ struct Phys {
   double eps_B;     // degeneracy threshold of Appendix A
   double eps_Z;     // WENO-Z epsilon
   int weno_z;       // 0: Jiang-Shu weights, 1: WENO-Z
+  double g1;        // (gamma - 1) / 2
+  double g2;        // (gamma - 2) / (gamma - 1)
 };
 
 __host__ __device__ __forceinline__ int wrap(int i, int n) {
@@ -30,47 +32,6 @@ enum ZoneVar {
   Z_CF, Z_CA, Z_CS,                                        // c_fast, c_A, c_slow
   Z_NVAR
 };
-
-// Zone prologue of a sweep (step 2 of the 3D step list): primitives (eq. P),
-// the flux along n (eq. fluxes, total pressure P + |B|^2/2), and the fast,
-// Alfven and slow speeds.  Inputs are in the sweep frame (n, t1, t2).
-struct ZoneVals {
-  double v[Z_NVAR];
-};
-
-__host__ __device__ __forceinline__ void zone_prologue(double rho, double mn, double mt1, double mt2, double E,
-                                              double Bn, double Bt1, double Bt2, double gamma,
-                                              double* out) {
-  const double irho = 1.0 / rho;
-  const double vn = mn * irho, vt1 = mt1 * irho, vt2 = mt2 * irho;
-  const double Bperp2 = Bt1 * Bt1 + Bt2 * Bt2;
-  const double B2 = Bn * Bn + Bperp2;
-  const double P = (gamma - 1.0) * (E - 0.5 * ((mn * vn + mt1 * vt1 + mt2 * vt2) + B2));
-  const double Pstar = P + 0.5 * B2;
-  const double vB = vn * Bn + vt1 * Bt1 + vt2 * Bt2;
-  out[Z_RHO] = rho; out[Z_MN] = mn; out[Z_MT1] = mt1; out[Z_MT2] = mt2;
-  out[Z_BT1] = Bt1; out[Z_BT2] = Bt2; out[Z_E] = E;
-  out[Z_F0] = rho * vn;
-  out[Z_F1] = rho * vn * vn + Pstar - Bn * Bn;
-  out[Z_F2] = rho * vn * vt1 - Bn * Bt1;
-  out[Z_F3] = rho * vn * vt2 - Bn * Bt2;
-  out[Z_F4] = Bt1 * vn - Bn * vt1;
-  out[Z_F5] = Bt2 * vn - Bn * vt2;
-  out[Z_F6] = (E + Pstar) * vn - Bn * vB;
-  out[Z_VN] = vn; out[Z_VT1] = vt1; out[Z_VT2] = vt2; out[Z_BN] = Bn; out[Z_P] = P;
-  // c_f,s^2 = (a^2 + b^2 +- D)/2, D = sqrt((a^2 - b^2)^2 + 4 a^2 b_perp^2),
-  // c_slow^2 = a^2 b_n^2 / c_fast^2 (no cancellation), c_A = |B_n|/sqrt(rho)
-  const double a2 = gamma * P * irho;
-  const double b2 = B2 * irho;
-  const double bn2 = Bn * Bn * irho;
-  const double dab = a2 - b2;
-  const double D = sqrt(dab * dab + 4.0 * a2 * (Bperp2 * irho));
-  const double cf2 = 0.5 * (a2 + b2 + D);
-  const double cs2 = cf2 > 0.0 ? a2 * bn2 / cf2 : 0.0;
-  out[Z_CF] = sqrt(cf2);
-  out[Z_CA] = sqrt(bn2);
-  out[Z_CS] = sqrt(cs2);
-}
 
 // Scheduling fence: keeps the compiler from hoisting the LDS reads of later
 // interfaces / passes above earlier ones, which bounds register pressure.
@@ -102,6 +63,70 @@ __host__ __device__ __forceinline__ float rcp_w(float x) {
 #endif
 }
 
+// 1/sqrt(x) and sqrt(x) for x >= 0 from the hardware estimate and two Newton
+// steps (relative error ~1 ulp; sqrt(0) = 0).
+__host__ __device__ __forceinline__ double rsq_nr(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+__host__ __device__ __forceinline__ double sqrt_nr(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const double y = rsq_nr(fmax(x, 1e-300));
+  const double r = x * y;
+  return fma(0.5 * y, fma(-r, r, x), r);
+#else
+  return sqrt(x);
+#endif
+}
+
+// Zone prologue of a sweep (step 2 of the 3D step list): primitives (eq. P),
+// the flux along n (eq. fluxes, total pressure P + |B|^2/2), and the fast,
+// Alfven and slow speeds.  Inputs are in the sweep frame (n, t1, t2).
+struct ZoneVals {
+  double v[Z_NVAR];
+};
+
+__host__ __device__ __forceinline__ void zone_prologue(double rho, double mn, double mt1, double mt2, double E,
+                                              double Bn, double Bt1, double Bt2, double gamma,
+                                              double* out) {
+  const double irho = rcp_w(rho);
+  const double vn = mn * irho, vt1 = mt1 * irho, vt2 = mt2 * irho;
+  const double Bperp2 = Bt1 * Bt1 + Bt2 * Bt2;
+  const double B2 = Bn * Bn + Bperp2;
+  const double P = (gamma - 1.0) * (E - 0.5 * ((mn * vn + mt1 * vt1 + mt2 * vt2) + B2));
+  const double Pstar = P + 0.5 * B2;
+  const double vB = vn * Bn + vt1 * Bt1 + vt2 * Bt2;
+  out[Z_RHO] = rho; out[Z_MN] = mn; out[Z_MT1] = mt1; out[Z_MT2] = mt2;
+  out[Z_BT1] = Bt1; out[Z_BT2] = Bt2; out[Z_E] = E;
+  out[Z_F0] = rho * vn;
+  out[Z_F1] = rho * vn * vn + Pstar - Bn * Bn;
+  out[Z_F2] = rho * vn * vt1 - Bn * Bt1;
+  out[Z_F3] = rho * vn * vt2 - Bn * Bt2;
+  out[Z_F4] = Bt1 * vn - Bn * vt1;
+  out[Z_F5] = Bt2 * vn - Bn * vt2;
+  out[Z_F6] = (E + Pstar) * vn - Bn * vB;
+  out[Z_VN] = vn; out[Z_VT1] = vt1; out[Z_VT2] = vt2; out[Z_BN] = Bn; out[Z_P] = P;
+  // c_f,s^2 = (a^2 + b^2 +- D)/2, D = sqrt((a^2 - b^2)^2 + 4 a^2 b_perp^2),
+  // c_slow^2 = a^2 b_n^2 / c_fast^2 (no cancellation), c_A = |B_n|/sqrt(rho)
+  const double a2 = gamma * P * irho;
+  const double b2 = B2 * irho;
+  const double bn2 = Bn * Bn * irho;
+  const double dab = a2 - b2;
+  const double D = sqrt_nr(dab * dab + 4.0 * a2 * (Bperp2 * irho));
+  const double cf2 = 0.5 * (a2 + b2 + D);
+  const double cs2 = cf2 > 0.0 ? a2 * bn2 * rcp_w(cf2) : 0.0;
+  out[Z_CF] = sqrt_nr(cf2);
+  out[Z_CA] = sqrt_nr(bn2);
+  out[Z_CS] = sqrt_nr(cs2);
+}
+
 // WENO5 interpolant phi_N(a, b, c, d) of Sect. 2.2.  With s_k = eps + IS_k the
 // Jiang-Shu weights alpha_k = d_k / s_k^2 give
 //   omega_0 = s1^2 s2^2 / Q,  omega_2 = 3 s0^2 s1^2 / Q,
@@ -115,23 +140,26 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, T eps_Z) {
   const T IS0 = T(13) * t0 * t0 + T(3) * t1 * t1;
   const T IS1 = T(13) * t2 * t2 + T(3) * t3 * t3;
   const T IS2 = T(13) * t4 * t4 + T(3) * t5 * t5;
-  T w0, w2;
+  const T X = a - T(2) * b + c, Y = b - T(2) * c + d;
   if (!WENO_Z) {
+    // phi = [2 p12 X + (3 p01 - Q/2) Y] / (6 Q), p_ij = s_i^2 s_j^2
     T s0 = eps + IS0, s1 = eps + IS1, s2 = eps + IS2;
     s0 *= s0; s1 *= s1; s2 *= s2;
+    if (sizeof(T) == 4) {   // FP32: normalise so the products cannot overflow
+      const T r = rcp_w(fmax(s0, fmax(s1, s2)));
+      s0 *= r; s1 *= r; s2 *= r;
+    }
     const T p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
-    const T inv = rcp_w(p12 + T(6) * p02 + T(3) * p01);
-    w0 = p12 * inv;
-    w2 = T(3) * p01 * inv;
+    const T inv6 = rcp_w(T(6) * (p12 + T(6) * p02 + T(3) * p01));
+    const T cY = T(1.5) * p01 - T(0.5) * p12 - T(3) * p02;
+    return inv6 * ((p12 + p12) * X + cY * Y);
   } else {
     const T tau5 = fabs(IS0 - IS2);
     const T r0 = tau5 * rcp_w(eps_Z + IS0), r1 = tau5 * rcp_w(eps_Z + IS1), r2 = tau5 * rcp_w(eps_Z + IS2);
     const T al0 = T(1) + r0 * r0, al1 = T(6) * (T(1) + r1 * r1), al2 = T(3) * (T(1) + r2 * r2);
     const T inv = rcp_w(al0 + al1 + al2);
-    w0 = al0 * inv;
-    w2 = al2 * inv;
+    return inv * (al0 * X * T(1.0 / 3.0) + (al2 - T(0.5) * (al0 + al1 + al2)) * Y * T(1.0 / 6.0));
   }
-  return w0 * (a - T(2) * b + c) * T(1.0 / 3.0) + (w2 - T(0.5)) * (b - T(2) * c + d) * T(1.0 / 6.0);
 }
 
 // phi^- - phi^+ of eq. (FWENO) from the split values of one characteristic
@@ -142,33 +170,36 @@ __host__ __device__ __forceinline__ T weno_split(const T v[8], T eps, T eps_Z) {
 }
 
 // Eigen-system scalars of Appendix A at one face (always FP64: the
-// renormalisation near degeneracies is done in double precision).
+// renormalisation near degeneracies is done in double precision).  qa2 =
+// 1/(4 a^2) carries the 1/(2 c_s^2) of the fast and slow rows times the 1/2 of
+// the Lax-Friedrichs split, which is folded into every left row.
 struct FaceEig {
   double vn, vt1, vt2, Bt1, Bt2;
   double a2, cs, sr, isr, cf, cf2, csl, csl2;
   double by, bz, s, af, as;
-  double v2, Gf, Ga, Gs, ha2, tau, g1, g2, omg;
+  double v2, Gf, Ga, Gs, qa2, tau, g1, g2, omg;
 };
 
 __host__ __device__ __forceinline__ void face_eig(double rho, double vn, double vt1, double vt2, double Bn, double Bt1,
                                                   double Bt2, double P, const Phys& ph, FaceEig& e) {
   const double gamma = ph.gamma;
-  const double irho = 1.0 / rho;
   e.vn = vn; e.vt1 = vt1; e.vt2 = vt2; e.Bt1 = Bt1; e.Bt2 = Bt2;
+  e.isr = rsq_nr(rho);
+  e.sr = rho * e.isr;
+  const double irho = e.isr * e.isr;
   e.a2 = gamma * P * irho;
-  e.cs = sqrt(e.a2);
-  e.sr = sqrt(rho);
-  e.isr = 1.0 / e.sr;
+  e.cs = sqrt_nr(e.a2);
+  const double ia2 = rcp_w(e.a2);
   const double Bperp2 = Bt1 * Bt1 + Bt2 * Bt2;
   const double b2 = (Bn * Bn + Bperp2) * irho;
   const double dab = e.a2 - b2;
-  const double D = sqrt(dab * dab + 4.0 * e.a2 * (Bperp2 * irho));
+  const double D = sqrt_nr(dab * dab + 4.0 * e.a2 * (Bperp2 * irho));
   e.cf2 = 0.5 * (e.a2 + b2 + D);
-  e.cf = sqrt(e.cf2);
-  e.csl2 = e.cf2 > 0.0 ? e.a2 * (Bn * Bn * irho) / e.cf2 : 0.0;
-  e.csl = sqrt(e.csl2);
+  e.cf = sqrt_nr(e.cf2);
+  e.csl2 = e.cf2 > 0.0 ? e.a2 * (Bn * Bn * irho) * rcp_w(e.cf2) : 0.0;
+  e.csl = sqrt_nr(e.csl2);
   if (Bperp2 > ph.eps_B) {
-    const double ib = 1.0 / sqrt(Bperp2);
+    const double ib = rsq_nr(Bperp2);
     e.by = Bt1 * ib;
     e.bz = Bt2 * ib;
   } else {
@@ -176,19 +207,19 @@ __host__ __device__ __forceinline__ void face_eig(double rho, double vn, double 
     e.bz = 0.70710678118654752440;
   }
   e.s = Bn >= ph.eps_B ? 1.0 : -1.0;
-  if (sqrt(D) >= ph.eps_B) {
-    const double r = dab / D;
-    e.af = sqrt(fmin(fmax(0.5 * (1.0 + r), 0.0), 1.0));
-    e.as = sqrt(fmin(fmax(0.5 * (1.0 - r), 0.0), 1.0));
+  if (D >= ph.eps_B * ph.eps_B) {
+    const double r = dab * rcp_w(D);
+    e.af = sqrt_nr(fmin(fmax(0.5 * (1.0 + r), 0.0), 1.0));
+    e.as = sqrt_nr(fmin(fmax(0.5 * (1.0 - r), 0.0), 1.0));
   } else {
     e.af = 0.70710678118654752440;
     e.as = 0.70710678118654752440;
   }
-  e.g1 = 0.5 * (gamma - 1.0);
-  e.g2 = (gamma - 2.0) / (gamma - 1.0);
+  e.g1 = ph.g1;
+  e.g2 = ph.g2;
   e.omg = 1.0 - gamma;
-  e.ha2 = 0.5 / e.a2;
-  e.tau = (gamma - 1.0) / e.a2;
+  e.qa2 = 0.25 * ia2;
+  e.tau = (gamma - 1.0) * ia2;
   e.v2 = vn * vn + vt1 * vt1 + vt2 * vt2;
   const double bv = e.by * vt1 + e.bz * vt2;
   e.Gf = e.af * e.cf * vn - e.as * e.csl * e.s * bv;
@@ -200,7 +231,7 @@ __host__ __device__ __forceinline__ void face_eig(double rho, double vn, double 
 // (upper, lambda = v - c) and S - A (lower), A nonzero in components 0..3,
 // for the five interface differences DL(j, k): j = 0..6 Delta F, 7..13 Delta q,
 // k = 0..4 interfaces i-3/2 .. i+5/2.  Lax-Friedrichs: Delta F^+- = (Delta F^s
-// +- alpha Delta q^s)/2.
+// +- alpha Delta q^s)/2, with the 1/2 already carried by the rows.
 template <typename T, class DL>
 __host__ __device__ __forceinline__ void split_pair(const T S[7], const T A[4], T alu, T all, DL dl, T vu[8],
                                                     T vl[8]) {
@@ -216,8 +247,8 @@ __host__ __device__ __forceinline__ void split_pair(const T S[7], const T A[4], 
 #pragma unroll
     for (int j = 1; j < 4; ++j) { aF += A[j] * dF[j]; aq += A[j] * dq[j]; }
     const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
-    if (k <= 3) { vu[k] = T(0.5) * (uF + alu * uq); vl[k] = T(0.5) * (lF + all * lq); }
-    if (k >= 1) { vu[3 + k] = T(0.5) * (uF - alu * uq); vl[3 + k] = T(0.5) * (lF - all * lq); }
+    if (k <= 3) { vu[k] = uF + alu * uq; vl[k] = lF + all * lq; }
+    if (k >= 1) { vu[3 + k] = uF - alu * uq; vl[3 + k] = lF - all * lq; }
     sched_fence();
   }
 }
@@ -239,12 +270,12 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
   T vu[8], vl[8];
   // ---- fast pair (m = 1, 7)
   {
-    const T S[7] = {T(e.ha2 * (e.af * e.g1 * e.v2)), T(e.ha2 * (e.omg * e.af * e.vn)),
-                    T(e.ha2 * (e.omg * e.af * e.vt1)), T(e.ha2 * (e.omg * e.af * e.vt2)),
-                    T(e.ha2 * (e.omg * e.af * e.Bt1 + sra * e.as * e.by)),
-                    T(e.ha2 * (e.omg * e.af * e.Bt2 + sra * e.as * e.bz)), T(e.ha2 * (gm1 * e.af))};
-    const T A[4] = {T(e.ha2 * e.Gf), T(-e.ha2 * (e.af * e.cf)), T(e.ha2 * (e.csl * e.as * e.by * e.s)),
-                    T(e.ha2 * (e.csl * e.as * e.bz * e.s))};
+    const T S[7] = {T(e.qa2 * (e.af * e.g1 * e.v2)), T(e.qa2 * (e.omg * e.af * e.vn)),
+                    T(e.qa2 * (e.omg * e.af * e.vt1)), T(e.qa2 * (e.omg * e.af * e.vt2)),
+                    T(e.qa2 * (e.omg * e.af * e.Bt1 + sra * e.as * e.by)),
+                    T(e.qa2 * (e.omg * e.af * e.Bt2 + sra * e.as * e.bz)), T(e.qa2 * (gm1 * e.af))};
+    const T A[4] = {T(e.qa2 * e.Gf), T(-e.qa2 * (e.af * e.cf)), T(e.qa2 * (e.csl * e.as * e.by * e.s)),
+                    T(e.qa2 * (e.csl * e.as * e.bz * e.s))};
     split_pair(S, A, al[0], al[6], dl, vu, vl);
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
     const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
@@ -260,12 +291,12 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
   sched_fence();
   // ---- slow pair (m = 3, 5)
   {
-    const T S[7] = {T(e.ha2 * (e.as * e.g1 * e.v2)), T(e.ha2 * (e.omg * e.as * e.vn)),
-                    T(e.ha2 * (e.omg * e.as * e.vt1)), T(e.ha2 * (e.omg * e.as * e.vt2)),
-                    T(e.ha2 * (e.omg * e.as * e.Bt1 - sra * e.af * e.by)),
-                    T(e.ha2 * (e.omg * e.as * e.Bt2 - sra * e.af * e.bz)), T(e.ha2 * (gm1 * e.as))};
-    const T A[4] = {T(e.ha2 * e.Gs), T(-e.ha2 * (e.as * e.csl)), T(-e.ha2 * (e.cf * e.af * e.by * e.s)),
-                    T(-e.ha2 * (e.cf * e.af * e.bz * e.s))};
+    const T S[7] = {T(e.qa2 * (e.as * e.g1 * e.v2)), T(e.qa2 * (e.omg * e.as * e.vn)),
+                    T(e.qa2 * (e.omg * e.as * e.vt1)), T(e.qa2 * (e.omg * e.as * e.vt2)),
+                    T(e.qa2 * (e.omg * e.as * e.Bt1 - sra * e.af * e.by)),
+                    T(e.qa2 * (e.omg * e.as * e.Bt2 - sra * e.af * e.bz)), T(e.qa2 * (gm1 * e.as))};
+    const T A[4] = {T(e.qa2 * e.Gs), T(-e.qa2 * (e.as * e.csl)), T(-e.qa2 * (e.cf * e.af * e.by * e.s)),
+                    T(-e.qa2 * (e.cf * e.af * e.bz * e.s))};
     split_pair(S, A, al[2], al[4], dl, vu, vl);
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
     const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
@@ -281,8 +312,8 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
   sched_fence();
   // ---- Alfven pair (m = 2, 6): L = (Ga/2, 0, -bz s/2, by s/2, -+sr bz/2, +-sr by/2, 0)
   {
-    const T S0 = T(0.5 * e.Ga), S2 = T(-0.5 * e.bz * e.s), S3 = T(0.5 * e.by * e.s);
-    const T A4 = T(-0.5 * e.sr * e.bz), A5 = T(0.5 * e.sr * e.by);
+    const T S0 = T(0.25 * e.Ga), S2 = T(-0.25 * e.bz * e.s), S3 = T(0.25 * e.by * e.s);
+    const T A4 = T(-0.25 * e.sr * e.bz), A5 = T(0.25 * e.sr * e.by);
     const T alu = al[1], all = al[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -291,8 +322,8 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
       const T aF = A4 * dl(4, k) + A5 * dl(5, k);
       const T aq = A4 * dl(11, k) + A5 * dl(12, k);
       const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
-      if (k <= 3) { vu[k] = T(0.5) * (uF + alu * uq); vl[k] = T(0.5) * (lF + all * lq); }
-      if (k >= 1) { vu[3 + k] = T(0.5) * (uF - alu * uq); vl[3 + k] = T(0.5) * (lF - all * lq); }
+      if (k <= 3) { vu[k] = uF + alu * uq; vl[k] = lF + all * lq; }
+      if (k >= 1) { vu[3 + k] = uF - alu * uq; vl[3 + k] = lF - all * lq; }
       sched_fence();
     }
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
@@ -305,18 +336,19 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
     corr[6] += -e.Ga * sp;
   }
   sched_fence();
-  // ---- entropy (m = 4): L = (1 - tau v^2/2, tau v, tau B_t, -tau)
+  // ---- entropy (m = 4): L = (1 - tau v^2/2, tau v, tau B_t, -tau), times 1/2
   {
-    const T l[7] = {T(1.0 - 0.5 * e.tau * e.v2), T(e.tau * e.vn), T(e.tau * e.vt1), T(e.tau * e.vt2),
-                    T(e.tau * e.Bt1), T(e.tau * e.Bt2), T(-e.tau)};
+    const double ht = 0.5 * e.tau;
+    const T l[7] = {T(0.5 - 0.5 * ht * e.v2), T(ht * e.vn), T(ht * e.vt1), T(ht * e.vt2),
+                    T(ht * e.Bt1), T(ht * e.Bt2), T(-ht)};
     const T a4 = al[3];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       T sF = l[0] * dl(0, k), sq = l[0] * dl(7, k);
 #pragma unroll
       for (int j = 1; j < 7; ++j) { sF += l[j] * dl(j, k); sq += l[j] * dl(7 + j, k); }
-      if (k <= 3) vu[k] = T(0.5) * (sF + a4 * sq);
-      if (k >= 1) vu[3 + k] = T(0.5) * (sF - a4 * sq);
+      if (k <= 3) vu[k] = sF + a4 * sq;
+      if (k >= 1) vu[3 + k] = sF - a4 * sq;
       sched_fence();
     }
     const double f4 = double(weno_split<WENO_Z>(vu, eps, epsZ));

@@ -266,6 +266,8 @@ wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch,
   p->ph.eps_B = cfg->eps_B;
   p->ph.eps_Z = cfg->eps_Z;
   p->ph.weno_z = cfg->weights == WM_WENO_Z ? 1 : 0;
+  p->ph.g1 = 0.5 * (cfg->gamma - 1.0);
+  p->ph.g2 = (cfg->gamma - 2.0) / (cfg->gamma - 1.0);
   p->scratch = reinterpret_cast<char*>(scratch);
   p->lay = L;
   *out = p;
