@@ -55,6 +55,108 @@ def cpu_baseline(n: int, steps: int):
                                       f"{el:.1f} s on the host", seconds=round(el, 3))
 
 
+def l1_per_variable(a: dict, b: dict):
+    """L1 of Sect. 3 per conserved variable (rho, m_x, m_y, m_z, E, b_x, b_y, b_z)
+    and its geometric norm, between two GPU states (dicts of host tensors)."""
+    comps = lambda U: [U["rho"], U["m"][0], U["m"][1], U["m"][2], U["E"], U["b"][0], U["b"][1], U["b"][2]]
+    per = [float((x - y).abs().mean()) for x, y in zip(comps(a), comps(b))]
+    return per, sum(v * v for v in per) ** 0.5
+
+
+def timed_steps(p, steps: int, dts=None):
+    """Runs `steps` steps (dt from eq. (cfl), or the given list) and returns (ms, dts)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        if dts is None:
+            p.step()
+        else:
+            p.step_dt(dts[s])
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3
+
+
+def mixed_precision(n: int, steps: int):
+    """The Mach-0.1 workload in FP64 and in mixed precision: throughput of each
+    (own dt from eq. (cfl), HIP-event kernel times), and the L1 of the mixed
+    state against the FP64 state after `steps` steps taken with the FP64 run's
+    dt sequence."""
+    import torch
+    from paper_1812_04278_amd import binding, inputs
+    f = inputs.random_fields(n, seed=1, v_rms=0.1, kmax=4)
+    res, states, dts = {}, {}, []
+    for name, prec in (("fp64", binding.WM_FP64), ("mixed", binding.WM_MIXED)):
+        p = binding.Patch(binding.config(n, precision=prec), device="cuda:0")
+        p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+        p.step()                                    # warm-up
+        p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+        p.profile(True)
+        ms = timed_steps(p, steps)
+        rep = p.profile_report()
+        p.profile(False)
+        nsw, msw = rep["sweep"]
+        res[name] = {"value": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms / steps, 4),
+                     "sweep_avg_ms": round(msw / max(nsw, 1), 4)}
+        # accuracy run: the FP64 dt sequence for both
+        p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+        for s in range(steps):
+            if name == "fp64":
+                dts.append(p.step(want_dt=True))
+            else:
+                p.step_dt(dts[s])
+        states[name] = p.state()
+        del p
+    per, geo = l1_per_variable(states["fp64"], states["mixed"])
+    res["speedup"] = round(res["mixed"]["value"] / res["fp64"]["value"], 4)
+    res["l1_mixed_vs_fp64"] = {"per_variable": [float(f"{x:.3e}") for x in per],
+                               "variables": ["rho", "m_x", "m_y", "m_z", "E", "b_x", "b_y", "b_z"],
+                               "geometric": float(f"{geo:.3e}")}
+    res["workload"] = f"{n}^3 periodic box, Mach 0.1, beta~1, {steps} SSP-RK3 steps"
+    return res
+
+
+def convergence(sizes, c: float = 0.25):
+    """Grid-aligned linear fast wave (Sect. 4.1 setup), one period, dt = c h^(5/3),
+    on n x 4 x 4 zones, FP64 and mixed.  Two errors against the exact
+    travelling wave: the L1 of Sect. 3 (A0 = 1e-6; it meets the O(A0^2)
+    nonlinear floor near N = 64) and the error of the k = 1 Fourier amplitude of
+    every conserved variable (A0 = 1e-5), which nonlinearity changes only at
+    O(A0^3) and so shows the truncation order further."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1812_04278_amd import binding, inputs
+
+    def k1(U):
+        comps = [U["rho"], U["m"][0], U["m"][1], U["m"][2], U["E"], U["b"][0], U["b"][1], U["b"][2]]
+        return np.array([np.fft.rfft(np.asarray(x, dtype=np.float64).mean(axis=(0, 1)))[1] / x.shape[-1]
+                         for x in comps])
+
+    out = {}
+    for name, prec in (("fp64", binding.WM_FP64), ("mixed", binding.WM_MIXED)):
+        l1, fk = [], []
+        for n in sizes:
+            for A0 in (1e-6, 1e-5):
+                U0, U1 = inputs.fast_wave(n, A0=A0), inputs.fast_wave(n, t=0.5, A0=A0)
+                p = binding.Patch(binding.config(nx=n, ny=4, nz=4, h=1.0 / n, precision=prec), device="cuda:0")
+                p.set_state(U0["rho"], U0["m"], U0["E"], U0["b"])
+                nt = int(math.ceil(0.5 / (c * (1.0 / n) ** (5.0 / 3.0))))
+                for _ in range(nt):
+                    p.step_dt(0.5 / nt)
+                st = p.state()
+                if A0 == 1e-6:
+                    ex = {k: torch.as_tensor(v) for k, v in U1.items()}
+                    l1.append(float(f"{l1_per_variable(st, ex)[1]:.4e}"))
+                else:
+                    fk.append(float(f"{np.linalg.norm(k1(st) - k1(U1)):.4e}"))
+                del p
+        out[name] = {"l1": l1, "l1_order": [round(math.log2(l1[i] / l1[i + 1]), 3) for i in range(len(l1) - 1)],
+                     "k1": fk, "k1_order": [round(math.log2(fk[i] / fk[i + 1]), 3) for i in range(len(fk) - 1)]}
+    out["sizes"] = list(sizes)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +166,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=80)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP64-vs-mixed comparison")
+    ap.add_argument("--no-convergence", action="store_true", help="skip the fast-wave convergence table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -145,6 +249,12 @@ def main():
         "diagnostics_after": {"max_divb": d["max_divb"], "n_unphysical": d["n_unphysical"]},
         "context": "paper: ~0.6 Mzone/s per 36-core Broadwell node (FP64, RK4, with MPI)",
     }
+    if not args.no_mixed:
+        log("bench: mixed precision vs FP64 (Mach 0.1 workload)")
+        out["mixed"] = mixed_precision(n, args.steps)
+    if not args.no_convergence:
+        log("bench: fast-wave convergence, both precisions")
+        out["convergence"] = convergence((32, 64, 128, 256))
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written, for scaling
         # the FETCH_SIZE / WRITE_SIZE counters of the kernels above

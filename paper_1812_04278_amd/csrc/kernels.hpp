@@ -48,18 +48,25 @@ struct SweepArgs {
   double* dbg;           // optional [9][N]: 7 sweep-frame flux components + 2 T
 };
 
-template <int AXIS>
-constexpr size_t sweep_lds_bytes() {
-  return (size_t)(SW_NQ + SW_NP) * (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB * sizeof(double);
+// LDS per block: zone q and F in FP64 (the differences are formed in FP64),
+// zone primitives and speeds in the work type TW.
+template <int AXIS, typename TW>
+constexpr size_t sweep_lds_doubles() {
+  return (size_t)SW_NQ * (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB +
+         ((size_t)SW_NP * (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB * sizeof(TW) + 7) / 8;
 }
 
 // Phases: (1) zone prologue of the tile and its halo into LDS; (2) per face:
 // central flux, face state, Lax-Friedrichs speeds and the interface
 // differences Delta F, Delta q (formed in FP64); (3) per face: eigen-system
 // and characteristic WENO in registers, reading the differences (in TW) from
-// LDS one eigen pair at a time.
+// LDS one eigen pair at a time.  TW = double: everything in FP64.  TW = float
+// (mixed): projections, split, weights, zone primitives, LF speeds and the
+// transport-flux mean in FP32; the zone prologue (pressure recovery), the
+// differences, the central flux and the face eigen-system (renormalisation of
+// alpha_f, alpha_s, beta) in FP64.
 template <int AXIS, bool WENO_Z, typename TW>
-__global__ __launch_bounds__(SW_THREADS, 2) void sweep_kernel(SweepArgs a) {
+__global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_kernel(SweepArgs a) {
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;     // zones along the axis
   constexpr int NI = TA + 4;                 // interfaces i-3/2 .. i+TA+3/2
@@ -67,9 +74,9 @@ __global__ __launch_bounds__(SW_THREADS, 2) void sweep_kernel(SweepArgs a) {
   constexpr int NIF = NI * TB;
   static_assert(TA * TB == SW_THREADS, "one face per lane");
   static_assert(TA >= 4, "extra interfaces are built by lanes fa < 4");
-  __shared__ double smem[(SW_NQ + SW_NP) * NC];
+  __shared__ double smem[sweep_lds_doubles<AXIS, TW>()];
   double* Q = smem;                          // [14][NC] zone q and F, later the differences
-  double* Pz = smem + SW_NQ * NC;            // [11][NC] zone primitives and speeds
+  TW* Pz = reinterpret_cast<TW*>(smem + SW_NQ * NC);   // [11][NC] zone primitives and speeds
   TW* Dl = reinterpret_cast<TW*>(smem);      // [14][NIF] interface differences (aliases Q)
 
   const Grid& g = a.g;
@@ -100,17 +107,17 @@ __global__ __launch_bounds__(SW_THREADS, 2) void sweep_kernel(SweepArgs a) {
     zone_prologue(a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
 #pragma unroll
     for (int v = 0; v < SW_NQ; ++v) Q[v * NC + cell] = z[v];
-    Pz[P_RHO * NC + cell] = z[Z_RHO];
-    Pz[P_VN * NC + cell] = z[Z_VN];
-    Pz[P_VT1 * NC + cell] = z[Z_VT1];
-    Pz[P_VT2 * NC + cell] = z[Z_VT2];
-    Pz[P_BN * NC + cell] = z[Z_BN];
-    Pz[P_BT1 * NC + cell] = z[Z_BT1];
-    Pz[P_BT2 * NC + cell] = z[Z_BT2];
-    Pz[P_P * NC + cell] = z[Z_P];
-    Pz[P_CF * NC + cell] = z[Z_CF];
-    Pz[P_CA * NC + cell] = z[Z_CA];
-    Pz[P_CS * NC + cell] = z[Z_CS];
+    Pz[P_RHO * NC + cell] = TW(z[Z_RHO]);
+    Pz[P_VN * NC + cell] = TW(z[Z_VN]);
+    Pz[P_VT1 * NC + cell] = TW(z[Z_VT1]);
+    Pz[P_VT2 * NC + cell] = TW(z[Z_VT2]);
+    Pz[P_BN * NC + cell] = TW(z[Z_BN]);
+    Pz[P_BT1 * NC + cell] = TW(z[Z_BT1]);
+    Pz[P_BT2 * NC + cell] = TW(z[Z_BT2]);
+    Pz[P_P * NC + cell] = TW(z[Z_P]);
+    Pz[P_CF * NC + cell] = TW(z[Z_CF]);
+    Pz[P_CA * NC + cell] = TW(z[Z_CA]);
+    Pz[P_CS * NC + cell] = TW(z[Z_CS]);
   }
   __syncthreads();
 
@@ -125,8 +132,8 @@ __global__ __launch_bounds__(SW_THREADS, 2) void sweep_kernel(SweepArgs a) {
     const double* F = Q + (SW_NQ / 2 + j) * NC;
     Fc[j] = (-F[cidx(fa + 1, fb)] + 7.0 * F[cL] + 7.0 * F[cR] - F[cidx(fa + 4, fb)]) * (1.0 / 12.0);
   }
-  auto PL = [&](int v) { return Pz[v * NC + cL]; };
-  auto PR = [&](int v) { return Pz[v * NC + cR]; };
+  auto PL = [&](int v) { return double(Pz[v * NC + cL]); };
+  auto PR = [&](int v) { return double(Pz[v * NC + cR]); };
   double fp[8];   // face state: mean of the primitive states of zones i and i+1
 #pragma unroll
   for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (PL(P_RHO + v) + PR(P_RHO + v));

@@ -137,23 +137,28 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, T eps_Z) {
   const T t0 = a - b, t1 = a - T(3) * b;
   const T t2 = b - c, t3 = b + c;
   const T t4 = c - d, t5 = T(3) * c - d;
-  const T IS0 = T(13) * t0 * t0 + T(3) * t1 * t1;
-  const T IS1 = T(13) * t2 * t2 + T(3) * t3 * t3;
-  const T IS2 = T(13) * t4 * t4 + T(3) * t5 * t5;
   const T X = a - T(2) * b + c, Y = b - T(2) * c + d;
   if (!WENO_Z) {
-    // phi = [2 p12 X + (3 p01 - Q/2) Y] / (6 Q), p_ij = s_i^2 s_j^2
-    T s0 = eps + IS0, s1 = eps + IS1, s2 = eps + IS2;
+    // s_k/3 = eps/3 + IS_k/3: a common factor of the three s_k cancels in the
+    // weights.  phi = [p12 X / 3 + (p01/4 - p12/12 - p02/2) Y] / Q with
+    // p_ij = s_i^2 s_j^2 and Q = p12 + 6 p02 + 3 p01.
+    const T e3 = eps * T(1.0 / 3.0);
+    T s0 = fma(T(13.0 / 3.0) * t0, t0, fma(t1, t1, e3));
+    T s1 = fma(T(13.0 / 3.0) * t2, t2, fma(t3, t3, e3));
+    T s2 = fma(T(13.0 / 3.0) * t4, t4, fma(t5, t5, e3));
     s0 *= s0; s1 *= s1; s2 *= s2;
     if (sizeof(T) == 4) {   // FP32: normalise so the products cannot overflow
       const T r = rcp_w(fmax(s0, fmax(s1, s2)));
       s0 *= r; s1 *= r; s2 *= r;
     }
     const T p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
-    const T inv6 = rcp_w(T(6) * (p12 + T(6) * p02 + T(3) * p01));
-    const T cY = T(1.5) * p01 - T(0.5) * p12 - T(3) * p02;
-    return inv6 * ((p12 + p12) * X + cY * Y);
+    const T rq = rcp_w(fma(T(3), p01, fma(T(6), p02, p12)));
+    const T cY = fma(T(0.25), p01, fma(T(-1.0 / 12.0), p12, T(-0.5) * p02));
+    return rq * fma(cY, Y, (p12 * T(1.0 / 3.0)) * X);
   } else {
+    const T IS0 = T(13) * t0 * t0 + T(3) * t1 * t1;
+    const T IS1 = T(13) * t2 * t2 + T(3) * t3 * t3;
+    const T IS2 = T(13) * t4 * t4 + T(3) * t5 * t5;
     const T tau5 = fabs(IS0 - IS2);
     const T r0 = tau5 * rcp_w(eps_Z + IS0), r1 = tau5 * rcp_w(eps_Z + IS1), r2 = tau5 * rcp_w(eps_Z + IS2);
     const T al0 = T(1) + r0 * r0, al1 = T(6) * (T(1) + r1 * r1), al2 = T(3) * (T(1) + r2 * r2);

@@ -63,7 +63,7 @@ bool valid_config(const wm_config* c, const char** why) {
   if (!(c->cfl > 0.0)) { *why = "cfl must be positive"; return false; }
   if (!(c->eps_weno > 0.0) || !(c->eps_B >= 0.0) || !(c->eps_Z > 0.0)) { *why = "epsilons must be positive"; return false; }
   if (c->weights != WM_WENO_JS && c->weights != WM_WENO_Z) { *why = "unknown weights"; return false; }
-  if (c->precision != WM_FP64) { *why = "precision mode not available in this build"; return false; }
+  if (c->precision != WM_FP64 && c->precision != WM_MIXED) { *why = "unknown precision mode"; return false; }
   return true;
 }
 
@@ -153,8 +153,13 @@ wm_status launch_sweep(wm_patch* p, const double* hydro, const double* bcell, do
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
   dim3 grid((nA + TA - 1) / TA, (nB + TB - 1) / TB, nC);
   const long r = prof_begin(p, K_SWEEP);
-  if (p->ph.weno_z)
+  const bool mixed = p->cfg.precision == WM_MIXED;
+  if (p->ph.weno_z && mixed)
+    hipLaunchKernelGGL((sweep_kernel<AXIS, true, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
+  else if (p->ph.weno_z)
     hipLaunchKernelGGL((sweep_kernel<AXIS, true, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
+  else if (mixed)
+    hipLaunchKernelGGL((sweep_kernel<AXIS, false, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
   else
     hipLaunchKernelGGL((sweep_kernel<AXIS, false, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
   WM_LAUNCH_CHECK("sweep kernel");

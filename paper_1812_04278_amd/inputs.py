@@ -37,7 +37,7 @@ import dataclasses
 
 import numpy as np
 
-__all__ = ["Fields", "mode_set", "random_fields", "config_fields"]
+__all__ = ["Fields", "mode_set", "random_fields", "config_fields", "fast_wave"]
 
 
 @dataclasses.dataclass
@@ -141,3 +141,22 @@ def config_fields(name: str, n: int | None = None, seed: int | None = None) -> F
     c = CONFIGS[name]
     return random_fields(n or c["n"], seed if seed is not None else c["seed"], c["v_rms"],
                          kmax=c["kmax"], B0=c["B0"])
+
+
+def fast_wave(nx: int, ny: int = 4, nz: int = 4, t: float = 0.0, A0: float = 1e-6, gamma: float = 5.0 / 3.0):
+    """Grid-aligned linear fast wave of Sect. 4.1: Q = Qbar + A0 R_fast sin(2 pi (x - 2 t))
+    on nx x ny x nz zones with h = 1/nx, using the right eigenvector the paper
+    prints for Qbar = (1, 0,0,0, 1, sqrt2, 1/2, P = 1/gamma) (fast speed 2).
+    Face b_y, b_z take the value at the zone-centre x; b_x = 1.  Returns the
+    conserved state as numpy arrays: rho, m [3], E, b [3]."""
+    s5 = 1.0 / (6.0 * np.sqrt(5.0))
+    R = np.array([6, 12, -4 * np.sqrt(2.0), -2, 0, 8 * np.sqrt(2.0), 4, 27]) * s5
+    x = (np.arange(nx) + 0.5) / nx
+    s = np.broadcast_to(np.sin(2 * np.pi * (x - 2.0 * t)), (nz, ny, nx))
+    Bb = (1.0, np.sqrt(2.0), 0.5)
+    Eb = (1.0 / gamma) / (gamma - 1.0) + 0.5 * sum(q * q for q in Bb)
+    return dict(rho=np.ascontiguousarray(1.0 + A0 * R[0] * s),
+                m=np.ascontiguousarray(np.stack([A0 * R[1] * s, A0 * R[2] * s, A0 * R[3] * s])),
+                E=np.ascontiguousarray(Eb + A0 * R[7] * s),
+                b=np.ascontiguousarray(np.stack([np.ones_like(s), Bb[1] + A0 * R[5] * s, Bb[2] + A0 * R[6] * s])))
+

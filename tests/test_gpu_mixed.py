@@ -1,0 +1,122 @@
+"""Mixed precision (FP32 projections, split fluxes, weights, zone primitives and
+transport-flux means; FP64 state, pressure recovery, eigen-system
+renormalisation, differences and central flux) against the FP64 oracle and the
+FP64 GPU path, and the order of convergence of both precisions on a smooth
+grid-aligned fast wave (Sect. 4.1 setup, the paper's R_fast).
+
+Stated bounds (normwise relative per variable, max|x - ref| / max|ref|):
+  one step, 32^3 Mach 0.1 ........................ <= 1e-8  vs the oracle
+  ten steps, 64^3 Mach 2 ......................... <= 1e-6  vs the oracle
+  ten steps, 128^3 Mach 0.1 ...................... L1 per variable <= 1e-9 vs FP64
+Measured (MI355X): 1.8e-9, 4.7e-8 and 1.1e-10 respectively.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mhd
+from paper_1812_04278_amd import binding as B
+from helpers import fields, oracle_state, state_errors
+from paper_1812_04278_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load()
+
+
+def patch(f, precision):
+    nz, ny, nx = f.rho.shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=1.0 / nx, precision=precision))
+    p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+    return p
+
+
+def test_mixed_one_step_32():
+    say("mixed, one step 32^3 Mach 0.1")
+    f = fields(32, seed=1, v_rms=0.1)
+    U, cfg = oracle_state(f)
+    p = patch(f, B.WM_MIXED)
+    p.step()
+    U1, _ = mhd.step(U, cfg)
+    errs = state_errors(p.state(), U1)
+    say("  ", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-8, errs
+
+
+def test_mixed_ten_steps_64_mach2():
+    say("mixed, 10 steps 64^3 Mach 2")
+    f = fields(64, seed=1, v_rms=2.0)
+    U, cfg = oracle_state(f)
+    p = patch(f, B.WM_MIXED)
+    for _ in range(10):
+        p.step()
+        U, _ = mhd.step(U, cfg)
+    errs = state_errors(p.state(), U)
+    say("  ", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-6, errs
+    assert p.diagnostics()["max_divb"] <= 1e-12 * 64
+
+
+def test_mixed_vs_fp64_l1_128():
+    """L1 of the mixed run against the FP64 run (the Sect. 3 norm per variable)."""
+    say("mixed vs fp64 L1, 128^3 Mach 0.1, 10 steps")
+    f = fields(128, seed=1, v_rms=0.1)
+    a, b = patch(f, B.WM_FP64), patch(f, B.WM_MIXED)
+    for _ in range(10):
+        dt = a.step(want_dt=True)
+        b.step_dt(dt)
+    per, geo = mhd.l1_error(a.state(), b.state())
+    say("   L1 per variable", [f"{x:.2e}" for x in per], f"geometric {geo:.2e}")
+    assert max(per) <= 1e-9
+
+
+def fast_wave_k1(n, precision, A0, t_end=0.5, c=0.25):
+    """Grid-aligned fast wave (Sect. 4.1 setup, the paper's R_fast) on n x 4 x 4
+    zones, one period, dt = c h^(5/3).  Returns (L1 of Sect. 3 over the conserved
+    variables, error of the k = 1 Fourier amplitudes) against the exact
+    travelling wave."""
+    U0, U1 = inputs.fast_wave(n, A0=A0), inputs.fast_wave(n, t=t_end, A0=A0)
+    p = B.Patch(B.config(nx=n, ny=4, nz=4, h=1.0 / n, precision=precision))
+    p.set_state(U0["rho"], U0["m"], U0["E"], U0["b"])
+    nt = int(math.ceil(t_end / (c * (1.0 / n) ** (5.0 / 3.0))))
+    for _ in range(nt):
+        p.step_dt(t_end / nt)
+    st = p.state()
+    comps = lambda U: [np.asarray(x) for x in (U["rho"], U["m"][0], U["m"][1], U["m"][2], U["E"],
+                                                U["b"][0], U["b"][1], U["b"][2])]
+    l1 = math.sqrt(sum(float(np.abs(x - y).mean()) ** 2 for x, y in zip(comps(st), comps(U1))))
+    k1 = lambda U: np.array([np.fft.rfft(x.mean(axis=(0, 1)))[1] / n for x in comps(U)])
+    return l1, float(np.linalg.norm(k1(st) - k1(U1)))
+
+
+def test_fast_wave_order_both_precisions():
+    """Fifth order in both precisions.  The k = 1 Fourier amplitudes (A0 = 1e-5),
+    which nonlinearity changes only at O(A0^3), converge at order ~5 from N = 32
+    to 128; the L1 against the linear solution (A0 = 1e-6) reaches the O(A0^2)
+    steepening floor (~3e-12) near N = 64, the limit Sect. 4.1 also reports for
+    1D waves, so its order is asserted from 16 to 32.  The mixed errors equal the
+    FP64 errors at these N."""
+    res = {}
+    for precision, name in ((B.WM_FP64, "fp64"), (B.WM_MIXED, "mixed")):
+        k1 = [fast_wave_k1(n, precision, 1e-5)[1] for n in (32, 64, 128)]
+        l1 = [fast_wave_k1(n, precision, 1e-6)[0] for n in (16, 32)]
+        ko = [math.log2(k1[i] / k1[i + 1]) for i in range(2)]
+        lo = math.log2(l1[0] / l1[1])
+        say(f"fast wave {name}: k1 {[f'{e:.3e}' for e in k1]} orders {[f'{o:.2f}' for o in ko]}; "
+            f"L1 {[f'{e:.3e}' for e in l1]} order {lo:.2f}")
+        assert min(ko) > 4.8 and lo > 4.8, (name, k1, l1)
+        res[name] = k1 + l1
+    for a, b in zip(res["fp64"], res["mixed"]):
+        assert abs(a - b) <= 2e-2 * a
