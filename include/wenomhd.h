@@ -156,6 +156,43 @@ wm_status wm_debug_sweep(wm_patch* p, int axis, void* out);
  * d(b_x, b_y, b_z)/dt from the corner fluxes (Sect. 2.3). */
 wm_status wm_debug_rhs(wm_patch* p, void* out);
 
+/* ---- adjoint (vector-Jacobian products), FP64 ----------------------------
+ * The differentiated map is the step with a given dt (dt is held fixed: its
+ * dependence on the state through eq. (cfl) is not differentiated).  At the
+ * non-smooth points of the scheme the derivative of the branch the forward
+ * pass takes is used (max: the larger argument, ties the first; |x|: sign(x);
+ * clamps and the degenerate constants of Appendix A: zero).  Cotangent arrays
+ * have the layout of the state: lam_hydro [5][nz][ny][nx] (rho, m, E),
+ * lam_bface [3][nz][ny][nx].  The adjoint needs every grid size >= 3. */
+
+/* Bytes of device scratch the adjoint calls need (caller-owned, 256-aligned,
+ * reserved for one patch at a time).  0 for an invalid configuration. */
+size_t wm_adjoint_scratch_bytes(const wm_config* cfg);
+
+/* lam_out = (dL/dU)^T lam_k for the semi-discrete right-hand side L of the
+ * state U = (hydro, bface) (eq. num, eq. ox1-ox3 and the b equations of
+ * Sect. 2.3).  lam_k, lam_out: [8][nz][ny][nx] device arrays (rho, m_x, m_y,
+ * m_z, E, b_x, b_y, b_z); lam_out is overwritten. */
+wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const void* bface, const void* lam_k,
+                     void* lam_out);
+
+/* Adjoint of one SSP-RK3 step U^{n+1} = Phi(U^n; dt) (increment form): the
+ * stage states U1, U2 are recomputed from U^n into adj_scratch; lam_hydro,
+ * lam_bface hold dJ/dU^{n+1} on entry and dJ/dU^n on return. */
+wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface, double dt,
+                          void* lam_hydro, void* lam_bface);
+
+/* lam_bface += transpose of the zone interpolation B = interp4(b) applied to
+ * lam_bcell ([3][nz][ny][nx]): the cotangent of a loss on zone B. */
+wm_status wm_zone_field_vjp(wm_patch* p, const void* lam_bcell, void* lam_bface);
+
+/* Adjoint of wm_init_from_potential with respect to A_edge and v (rho, P0
+ * and B0 held fixed): given dJ/d(hydro, bface) of the initial state, writes
+ * g_A = dJ/dA_edge [3][..] and g_v = dJ/dv [3][..] (device arrays). */
+wm_status wm_init_adjoint(wm_patch* p, void* adj_scratch, const double* rho, const double* v, const double* A_edge,
+                          const double B0[3], const void* lam_hydro, const void* lam_bface, double* g_A,
+                          double* g_v);
+
 /* Kernel timing with HIP events recorded on the patch's stream around every
  * launch (for measurement; adds two event records per launch).  enable = 1
  * starts a session (discarding earlier records), 0 stops it.  Records up to
@@ -165,7 +202,7 @@ wm_status wm_profile(wm_patch* p, int enable);
 /* Synchronises the stream and reports the session: out[2*c] = number of
  * launches and out[2*c+1] = summed milliseconds of kernel class c, with
  * c = 0 sweeps, 1 update (divergence + CT + RK), 2 zone-B interpolation,
- * 3 time-step reduction, 4 other.  n_out must be >= 10. */
+ * 3 time-step reduction, 4 other (adjoint kernels).  n_out must be >= 10. */
 wm_status wm_profile_report(wm_patch* p, double* out, int n_out);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -21,7 +21,8 @@ WM_WENO_JS, WM_WENO_Z = 0, 1
 SYMBOLS = [
     "wm_config_default", "wm_scratch_bytes", "wm_patch_create", "wm_patch_destroy", "wm_bind_state",
     "wm_init_from_potential", "wm_refresh_zone_field", "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics",
-    "wm_debug_sweep", "wm_debug_rhs", "wm_profile", "wm_profile_report", "wm_last_error",
+    "wm_debug_sweep", "wm_debug_rhs", "wm_adjoint_scratch_bytes", "wm_rhs_vjp", "wm_adjoint_step",
+    "wm_zone_field_vjp", "wm_init_adjoint", "wm_profile", "wm_profile_report", "wm_last_error",
 ]
 KERNEL_CLASSES = ["sweep", "update", "bcell", "dt", "other"]
 
@@ -73,6 +74,12 @@ def load(path: str = LIB_PATH):
     lib.wm_diagnostics.argtypes = [P, ctypes.POINTER(WmDiag)]
     lib.wm_debug_sweep.argtypes = [P, ctypes.c_int, P]
     lib.wm_debug_rhs.argtypes = [P, P]
+    lib.wm_adjoint_scratch_bytes.argtypes = [C]
+    lib.wm_adjoint_scratch_bytes.restype = ctypes.c_size_t
+    lib.wm_rhs_vjp.argtypes = [P, P, P, P, P, P]
+    lib.wm_adjoint_step.argtypes = [P, P, P, P, ctypes.c_double, P, P]
+    lib.wm_zone_field_vjp.argtypes = [P, P, P]
+    lib.wm_init_adjoint.argtypes = [P, P, P, P, P, D, P, P, P, P]
     lib.wm_profile.argtypes = [P, ctypes.c_int]
     lib.wm_profile_report.argtypes = [P, D, ctypes.c_int]
     lib.wm_last_error.argtypes = []
@@ -80,6 +87,7 @@ def load(path: str = LIB_PATH):
     for name in ("wm_patch_create", "wm_patch_destroy", "wm_bind_state", "wm_init_from_potential",
                  "wm_refresh_zone_field",
                  "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics", "wm_debug_sweep", "wm_debug_rhs",
+                 "wm_rhs_vjp", "wm_adjoint_step", "wm_zone_field_vjp", "wm_init_adjoint",
                  "wm_profile", "wm_profile_report"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -221,3 +229,39 @@ class Patch:
         out = (ctypes.c_double * 10)()
         _check(self.lib.wm_profile_report(self.handle, out, 10))
         return {name: (int(out[2 * c]), float(out[2 * c + 1])) for c, name in enumerate(KERNEL_CLASSES)}
+
+    # ---- adjoint
+    def _adj(self):
+        if getattr(self, "adj_scratch", None) is None:
+            nbytes = self.lib.wm_adjoint_scratch_bytes(ctypes.byref(self.cfg))
+            self.adj_scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.adj_scratch
+
+    def rhs_vjp(self, hydro, bface, lam_k):
+        """(dL/dU)^T lam_k at U = (hydro, bface); lam_k [8, nz, ny, nx]."""
+        out = torch.empty((8,) + self.shape, dtype=torch.float64, device=self.device)
+        h, b, l = hydro.contiguous(), bface.contiguous(), lam_k.contiguous()
+        _check(self.lib.wm_rhs_vjp(self.handle, _ptr(self._adj()), _ptr(h), _ptr(b), _ptr(l), _ptr(out)))
+        return out
+
+    def adjoint_step(self, Un_hydro, Un_bface, dt: float, lam_hydro, lam_bface):
+        """In place: (lam_hydro, lam_bface) <- adjoint of one step from U^n with dt."""
+        _check(self.lib.wm_adjoint_step(self.handle, _ptr(self._adj()), _ptr(Un_hydro), _ptr(Un_bface),
+                                        float(dt), _ptr(lam_hydro), _ptr(lam_bface)))
+
+    def zone_field_vjp(self, lam_bcell, lam_bface):
+        _check(self.lib.wm_zone_field_vjp(self.handle, _ptr(lam_bcell.contiguous()), _ptr(lam_bface)))
+
+    def init_adjoint(self, rho, v, A, B0, lam_hydro, lam_bface):
+        """Gradients (g_A, g_v) of the initial-state map for cotangents of the state."""
+        dev = lambda x: torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
+        r, vv, AA = dev(rho), dev(v), dev(A)
+        gA = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        gv = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        b0 = (ctypes.c_double * 3)(*[float(x) for x in B0])
+        _check(self.lib.wm_init_adjoint(self.handle, _ptr(self._adj()), _ptr(r), _ptr(vv), _ptr(AA), b0,
+                                        _ptr(lam_hydro.contiguous()), _ptr(lam_bface.contiguous()), _ptr(gA),
+                                        _ptr(gv)))
+        self.stream.synchronize()
+        return gA, gv
+

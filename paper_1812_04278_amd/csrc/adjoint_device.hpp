@@ -1,0 +1,486 @@
+// Reverse-mode (vector-Jacobian) counterparts of the per-zone and per-face
+// computations of the WENO5-CT sweep, FP64, for the adjoint of a stage.
+//
+// Each *_vjp function recomputes what it needs of the forward pass and
+// propagates a cotangent backwards through it.  Non-smooth points take the
+// derivative of the branch the forward pass takes: max() of the Lax-Friedrichs
+// speed follows the larger argument (ties: the first), |x| its sign (0 at 0),
+// the clamps of alpha_f^2, alpha_s^2 and the degenerate constants of Appendix A
+// (beta, sgn(B_n), alpha_f = alpha_s = 1/sqrt2) have zero derivative, and
+// sqrt(0) contributes nothing.
+#pragma once
+#include "mhd_device.hpp"
+
+namespace wm {
+
+// ---------------------------------------------------------------------------
+// phi_N: gradient with respect to its four arguments (Sect. 2.2), Jiang-Shu
+// weights.  With s_k = eps + IS_k, alpha_k = d_k/s_k^2, omega = alpha/sum,
+// g = X/3, h = Y/6 (X = a-2b+c, Y = b-2c+d) and W = g omega_0 + h omega_2:
+//   dphi/ds_0 = (2 omega_0/s_0)(W - g), dphi/ds_1 = (2 omega_1/s_1) W,
+//   dphi/ds_2 = (2 omega_2/s_2)(W - h).
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ void phiN_grad(double a, double b, double c, double d, double eps,
+                                                   double gr[4]) {
+  const double t0 = a - b, t1 = a - 3.0 * b;
+  const double t2 = b - c, t3 = b + c;
+  const double t4 = c - d, t5 = 3.0 * c - d;
+  const double s0 = eps + 13.0 * t0 * t0 + 3.0 * t1 * t1;
+  const double s1 = eps + 13.0 * t2 * t2 + 3.0 * t3 * t3;
+  const double s2 = eps + 13.0 * t4 * t4 + 3.0 * t5 * t5;
+  const double i0 = 1.0 / s0, i1 = 1.0 / s1, i2 = 1.0 / s2;
+  const double al0 = i0 * i0, al1 = 6.0 * i1 * i1, al2 = 3.0 * i2 * i2;
+  const double isum = 1.0 / (al0 + al1 + al2);
+  const double w0 = al0 * isum, w1 = al1 * isum, w2 = al2 * isum;
+  const double X = a - 2.0 * b + c, Y = b - 2.0 * c + d;
+  const double g = X * (1.0 / 3.0), h = Y * (1.0 / 6.0);
+  const double W = g * w0 + h * w2;
+  const double l0 = 2.0 * w0 * i0 * (W - g);   // dphi/dIS_0
+  const double l1 = 2.0 * w1 * i1 * W;         // dphi/dIS_1
+  const double l2 = 2.0 * w2 * i2 * (W - h);   // dphi/dIS_2
+  const double cX = w0 * (1.0 / 3.0), cY = (w2 - 0.5) * (1.0 / 6.0);
+  // dIS_0/da = 26 t0 + 6 t1, dIS_0/db = -26 t0 - 18 t1
+  // dIS_1/db = 26 t2 + 6 t3, dIS_1/dc = -26 t2 + 6 t3
+  // dIS_2/dc = 26 t4 + 18 t5, dIS_2/dd = -26 t4 - 6 t5
+  gr[0] = cX + l0 * (26.0 * t0 + 6.0 * t1);
+  gr[1] = -2.0 * cX + cY + l0 * (-26.0 * t0 - 18.0 * t1) + l1 * (26.0 * t2 + 6.0 * t3);
+  gr[2] = cX - 2.0 * cY + l1 * (-26.0 * t2 + 6.0 * t3) + l2 * (26.0 * t4 + 18.0 * t5);
+  gr[3] = cY + l2 * (-26.0 * t4 - 6.0 * t5);
+}
+
+// ---------------------------------------------------------------------------
+// face eigen-system scalars: cotangents of the FaceEig members -> face state
+// ---------------------------------------------------------------------------
+struct FaceEigBar {
+  double vn, vt1, vt2, Bt1, Bt2;
+  double a2, cs, sr, isr, cf, cf2, csl, csl2;
+  double by, bz, af, as;
+  double v2, Gf, Ga, Gs, qa2, tau;
+  __host__ __device__ void zero() {
+    vn = vt1 = vt2 = Bt1 = Bt2 = a2 = cs = sr = isr = cf = cf2 = csl = csl2 = 0.0;
+    by = bz = af = as = v2 = Gf = Ga = Gs = qa2 = tau = 0.0;
+  }
+};
+
+// Reverse of face_eig: out[0..7] += d/d(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P).
+__host__ __device__ inline void face_eig_vjp(const double fp[8], const Phys& ph, const FaceEig& e, FaceEigBar eb,
+                                             double out[8]) {
+  const double rho = fp[0], vn = fp[1], vt1 = fp[2], vt2 = fp[3], Bn = fp[4], Bt1 = fp[5], Bt2 = fp[6], P = fp[7];
+  const double gamma = ph.gamma;
+  const double isr = 1.0 / sqrt(rho);
+  const double irho = isr * isr;
+  const double a2 = e.a2;
+  const double ia2 = 1.0 / a2;
+  const double Bp2 = Bt1 * Bt1 + Bt2 * Bt2;
+  const double b2 = (Bn * Bn + Bp2) * irho;
+  const double dab = a2 - b2;
+  const double Q = dab * dab + 4.0 * a2 * Bp2 * irho;
+  const double D = sqrt(Q);
+  const double cf2 = 0.5 * (a2 + b2 + D);
+  const double bv = e.by * vt1 + e.bz * vt2;
+  const double s = e.s;
+  double l_vn = eb.vn, l_vt1 = eb.vt1, l_vt2 = eb.vt2, l_Bt1 = eb.Bt1, l_Bt2 = eb.Bt2;
+  double l_a2 = eb.a2, l_cf = eb.cf, l_cf2 = eb.cf2, l_csl = eb.csl, l_csl2 = eb.csl2;
+  double l_by = eb.by, l_bz = eb.bz, l_af = eb.af, l_as = eb.as, l_v2 = eb.v2;
+  double l_isr = eb.isr, l_sr = eb.sr, l_cs = eb.cs;
+  double l_bv = 0.0, l_ia2 = 0.0, l_Bp2 = 0.0, l_b2 = 0.0, l_dab = 0.0, l_D = 0.0, l_irho = 0.0;
+  double l_rho = 0.0, l_Bn = 0.0, l_P = 0.0;
+  // Gs = as csl vn + af cf s bv
+  l_as += eb.Gs * e.csl * vn; l_csl += eb.Gs * e.as * vn; l_vn += eb.Gs * e.as * e.csl;
+  l_af += eb.Gs * e.cf * s * bv; l_cf += eb.Gs * e.af * s * bv; l_bv += eb.Gs * e.af * e.cf * s;
+  // Ga = s (bz vt1 - by vt2)
+  l_bz += eb.Ga * s * vt1; l_vt1 += eb.Ga * s * e.bz; l_by -= eb.Ga * s * vt2; l_vt2 -= eb.Ga * s * e.by;
+  // Gf = af cf vn - as csl s bv
+  l_af += eb.Gf * e.cf * vn; l_cf += eb.Gf * e.af * vn; l_vn += eb.Gf * e.af * e.cf;
+  l_as -= eb.Gf * e.csl * s * bv; l_csl -= eb.Gf * e.as * s * bv; l_bv -= eb.Gf * e.as * e.csl * s;
+  // bv = by vt1 + bz vt2
+  l_by += l_bv * vt1; l_vt1 += l_bv * e.by; l_bz += l_bv * vt2; l_vt2 += l_bv * e.bz;
+  // v2
+  l_vn += 2.0 * vn * l_v2; l_vt1 += 2.0 * vt1 * l_v2; l_vt2 += 2.0 * vt2 * l_v2;
+  // qa2 = ia2/4, tau = (gamma-1) ia2
+  l_ia2 += 0.25 * eb.qa2 + (gamma - 1.0) * eb.tau;
+  // alpha_f, alpha_s (non-degenerate branch, unclamped interior)
+  if (D >= ph.eps_B * ph.eps_B) {
+    const double r = dab / D;
+    const double cfa = 0.5 * (1.0 + r), csa = 0.5 * (1.0 - r);
+    double l_r = 0.0;
+    if (cfa > 0.0 && cfa < 1.0 && e.af > 0.0) l_r += l_af * 0.5 / e.af * 0.5;
+    if (csa > 0.0 && csa < 1.0 && e.as > 0.0) l_r -= l_as * 0.5 / e.as * 0.5;
+    l_dab += l_r / D;
+    l_D -= l_r * r / D;
+  }
+  // beta
+  if (Bp2 > ph.eps_B) {
+    const double ib = 1.0 / sqrt(Bp2);
+    l_Bt1 += l_by * ib;
+    l_Bt2 += l_bz * ib;
+    l_Bp2 -= 0.5 * ib * ib * ib * (l_by * Bt1 + l_bz * Bt2);
+  }
+  // csl = sqrt(csl2)
+  if (e.csl > 0.0) l_csl2 += l_csl * 0.5 / e.csl;
+  // csl2 = a2 Bn^2 irho / cf2
+  if (cf2 > 0.0) {
+    const double lN = l_csl2 / cf2;
+    l_cf2 -= l_csl2 * e.csl2 / cf2;
+    l_a2 += lN * Bn * Bn * irho;
+    l_Bn += lN * 2.0 * a2 * Bn * irho;
+    l_irho += lN * a2 * Bn * Bn;
+  }
+  // cf = sqrt(cf2)
+  if (e.cf > 0.0) l_cf2 += l_cf * 0.5 / e.cf;
+  // cf2 = (a2 + b2 + D)/2
+  l_a2 += 0.5 * l_cf2; l_b2 += 0.5 * l_cf2; l_D += 0.5 * l_cf2;
+  // D = sqrt(dab^2 + 4 a2 Bp2 irho)
+  if (D > 0.0) {
+    const double lQ = l_D * 0.5 / D;
+    l_dab += 2.0 * dab * lQ;
+    l_a2 += 4.0 * Bp2 * irho * lQ;
+    l_Bp2 += 4.0 * a2 * irho * lQ;
+    l_irho += 4.0 * a2 * Bp2 * lQ;
+  }
+  // dab = a2 - b2
+  l_a2 += l_dab; l_b2 -= l_dab;
+  // b2 = (Bn^2 + Bp2) irho
+  l_Bn += 2.0 * Bn * irho * l_b2; l_Bp2 += irho * l_b2; l_irho += (Bn * Bn + Bp2) * l_b2;
+  // Bp2
+  l_Bt1 += 2.0 * Bt1 * l_Bp2; l_Bt2 += 2.0 * Bt2 * l_Bp2;
+  // ia2 = 1/a2, cs = sqrt(a2)
+  l_a2 -= ia2 * ia2 * l_ia2;
+  if (e.cs > 0.0) l_a2 += l_cs * 0.5 / e.cs;
+  // a2 = gamma P irho
+  l_P += gamma * irho * l_a2; l_irho += gamma * P * l_a2;
+  // irho = isr^2, sr = rho isr, isr = rho^(-1/2)
+  l_isr += 2.0 * isr * l_irho;
+  l_rho += isr * l_sr; l_isr += rho * l_sr;
+  l_rho -= 0.5 * isr * isr * isr * l_isr;
+  out[0] += l_rho; out[1] += l_vn; out[2] += l_vt1; out[3] += l_vt2;
+  out[4] += l_Bn; out[5] += l_Bt1; out[6] += l_Bt2; out[7] += l_P;
+}
+
+// ---------------------------------------------------------------------------
+// one eigen pair: forward recompute + reverse
+// ---------------------------------------------------------------------------
+// Forward of a pair with left rows S + A (upper) and S - A (lower), A nonzero
+// in components 0..3, as split_pair/weno_split compute it, then the reverse
+// for cotangents lfu, lfl of f_upper = phi^- - phi^+ and f_lower.  Produces the
+// cotangents of S, A, the LF speeds, and calls emit(k, lD[14]) with the
+// cotangent of interface difference k (j = 0..6 Delta F, 7..13 Delta q).
+template <class DL, class EMIT>
+__host__ __device__ __forceinline__ void pair_vjp(const double S[7], const double A[4], double alu, double all,
+                                                  DL dl, double eps, double& fu, double& fl, double lfu, double lfl,
+                                                  bool backward, double lS[7], double lA[4], double& lalu,
+                                                  double& lall, EMIT emit) {
+  double uF[5], uq[5], lF[5], lq[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double sF = 0.0, sq = 0.0, aF = 0.0, aq = 0.0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) { sF += S[j] * dl(j, k); sq += S[j] * dl(7 + j, k); }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { aF += A[j] * dl(j, k); aq += A[j] * dl(7 + j, k); }
+    uF[k] = sF + aF; uq[k] = sq + aq; lF[k] = sF - aF; lq[k] = sq - aq;
+  }
+  double vu[8], vl[8];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { vu[k] = uF[k] + alu * uq[k]; vl[k] = lF[k] + all * lq[k]; }
+#pragma unroll
+  for (int k = 1; k < 5; ++k) { vu[3 + k] = uF[k] - alu * uq[k]; vl[3 + k] = lF[k] - all * lq[k]; }
+  fu = weno_split<false>(vu, eps, 0.0);
+  fl = weno_split<false>(vl, eps, 0.0);
+  if (!backward) return;
+  // f = phi(v7, v6, v5, v4) - phi(v0, v1, v2, v3)
+  double gu[8], gl[8], g4[4];
+  phiN_grad(vu[7], vu[6], vu[5], vu[4], eps, g4);
+  gu[7] = g4[0] * lfu; gu[6] = g4[1] * lfu; gu[5] = g4[2] * lfu; gu[4] = g4[3] * lfu;
+  phiN_grad(vu[0], vu[1], vu[2], vu[3], eps, g4);
+  gu[0] = -g4[0] * lfu; gu[1] = -g4[1] * lfu; gu[2] = -g4[2] * lfu; gu[3] = -g4[3] * lfu;
+  phiN_grad(vl[7], vl[6], vl[5], vl[4], eps, g4);
+  gl[7] = g4[0] * lfl; gl[6] = g4[1] * lfl; gl[5] = g4[2] * lfl; gl[4] = g4[3] * lfl;
+  phiN_grad(vl[0], vl[1], vl[2], vl[3], eps, g4);
+  gl[0] = -g4[0] * lfl; gl[1] = -g4[1] * lfl; gl[2] = -g4[2] * lfl; gl[3] = -g4[3] * lfl;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double pu = k <= 3 ? gu[k] : 0.0, mu = k >= 1 ? gu[3 + k] : 0.0;
+    const double pl = k <= 3 ? gl[k] : 0.0, ml = k >= 1 ? gl[3 + k] : 0.0;
+    const double luF = pu + mu, luq = alu * (pu - mu);
+    const double llF = pl + ml, llq = all * (pl - ml);
+    lalu += uq[k] * (pu - mu);
+    lall += lq[k] * (pl - ml);
+    // uF = (S + A).dF, lF = (S - A).dF
+    const double sFb = luF + llF, aFb = luF - llF, sqb = luq + llq, aqb = luq - llq;
+    double lD[14];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      lS[j] += sFb * dl(j, k) + sqb * dl(7 + j, k);
+      lD[j] = S[j] * sFb;
+      lD[7 + j] = S[j] * sqb;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      lA[j] += aFb * dl(j, k) + aqb * dl(7 + j, k);
+      lD[j] += A[j] * aFb;
+      lD[7 + j] += A[j] * aqb;
+    }
+    emit(k, lD);
+  }
+}
+
+// Full reverse of face_corr (FP64): given the face state fp, LF speeds al,
+// differences dl and the cotangent lam[7] of corr, accumulates the cotangents
+// of the face state (lfp[8]), of the LF speeds (lal[7]) and, via emit, of the
+// interface differences.
+template <class DL, class EMIT>
+__host__ __device__ inline void face_corr_vjp(const double fp[8], const double al[7], DL dl, const Phys& ph,
+                                              const double lam[7], double lfp[8], double lal[7], EMIT emit) {
+  FaceEig e;
+  face_eig(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], fp[6], fp[7], ph, e);
+  FaceEigBar eb;
+  eb.zero();
+  const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs;
+  const double s = e.s;
+  double fu, fl;
+  // ---------------- fast pair (m = 1, 7)
+  {
+    const double t[7] = {e.af * e.g1 * e.v2, omg * e.af * e.vn, omg * e.af * e.vt1, omg * e.af * e.vt2,
+                         omg * e.af * e.Bt1 + sra * e.as * e.by, omg * e.af * e.Bt2 + sra * e.as * e.bz, gm1 * e.af};
+    const double u[4] = {e.Gf, -(e.af * e.cf), e.csl * e.as * e.by * s, e.csl * e.as * e.bz * s};
+    double S[7], A[4];
+    for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
+    for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
+    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
+    pair_vjp(S, A, al[0], al[6], dl, ph.eps, fu, fl, 0.0, 0.0, false, lS, lA, lal[0], lal[6], emit);
+    const double sp = fu + fl, sm = fu - fl;
+    const double Rs6 = e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2);
+    // corr[0..6] = af sp; af vn sp - af cf sm; af vt1 sp + csl as by s sm; af vt2 sp + csl as bz s sm;
+    //              cs as by isr sp; cs as bz isr sp; Rs6 sp - Gf sm
+    const double lsp = e.af * lam[0] + e.af * e.vn * lam[1] + e.af * e.vt1 * lam[2] + e.af * e.vt2 * lam[3] +
+                       e.cs * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
+    const double lsm = -e.af * e.cf * lam[1] + e.csl * e.as * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gf * lam[6];
+    eb.af += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
+                   (0.5 * e.v2 + e.cf2 - e.g2 * e.a2) * lam[6]) - sm * e.cf * lam[1];
+    eb.vn += e.af * sp * lam[1]; eb.vt1 += e.af * sp * lam[2]; eb.vt2 += e.af * sp * lam[3];
+    eb.cf -= e.af * sm * lam[1];
+    eb.cf2 += e.af * sp * lam[6]; eb.v2 += 0.5 * e.af * sp * lam[6]; eb.a2 -= e.g2 * e.af * sp * lam[6];
+    eb.csl += sm * e.as * s * (e.by * lam[2] + e.bz * lam[3]);
+    eb.as += sm * e.csl * s * (e.by * lam[2] + e.bz * lam[3]) + sp * e.cs * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+    eb.by += sm * e.csl * e.as * s * lam[2] + sp * e.cs * e.as * e.isr * lam[4];
+    eb.bz += sm * e.csl * e.as * s * lam[3] + sp * e.cs * e.as * e.isr * lam[5];
+    eb.cs += sp * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+    eb.isr += sp * e.cs * e.as * (e.by * lam[4] + e.bz * lam[5]);
+    eb.Gf -= sm * lam[6];
+    const double lfu = lsp + lsm, lfl = lsp - lsm;
+    pair_vjp(S, A, al[0], al[6], dl, ph.eps, fu, fl, lfu, lfl, true, lS, lA, lal[0], lal[6], emit);
+    // rows S = qa2 t, A = qa2 u
+    double lt[7], lu[4];
+    for (int j = 0; j < 7; ++j) { eb.qa2 += lS[j] * t[j]; lt[j] = qa2 * lS[j]; }
+    for (int j = 0; j < 4; ++j) { eb.qa2 += lA[j] * u[j]; lu[j] = qa2 * lA[j]; }
+    eb.af += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
+                                          lt[5] * e.Bt2) + gm1 * lt[6];
+    eb.v2 += lt[0] * e.af * e.g1;
+    eb.vn += lt[1] * omg * e.af; eb.vt1 += lt[2] * omg * e.af; eb.vt2 += lt[3] * omg * e.af;
+    eb.Bt1 += lt[4] * omg * e.af; eb.Bt2 += lt[5] * omg * e.af;
+    eb.sr += e.cs * e.as * (lt[4] * e.by + lt[5] * e.bz);
+    eb.cs += e.sr * e.as * (lt[4] * e.by + lt[5] * e.bz);
+    eb.as += sra * (lt[4] * e.by + lt[5] * e.bz);
+    eb.by += sra * e.as * lt[4]; eb.bz += sra * e.as * lt[5];
+    eb.Gf += lu[0];
+    eb.af -= lu[1] * e.cf; eb.cf -= lu[1] * e.af;
+    eb.csl += e.as * s * (lu[2] * e.by + lu[3] * e.bz);
+    eb.as += e.csl * s * (lu[2] * e.by + lu[3] * e.bz);
+    eb.by += e.csl * e.as * s * lu[2]; eb.bz += e.csl * e.as * s * lu[3];
+  }
+  // ---------------- slow pair (m = 3, 5)
+  {
+    const double t[7] = {e.as * e.g1 * e.v2, omg * e.as * e.vn, omg * e.as * e.vt1, omg * e.as * e.vt2,
+                         omg * e.as * e.Bt1 - sra * e.af * e.by, omg * e.as * e.Bt2 - sra * e.af * e.bz, gm1 * e.as};
+    const double u[4] = {e.Gs, -(e.as * e.csl), -(e.cf * e.af * e.by * s), -(e.cf * e.af * e.bz * s)};
+    double S[7], A[4];
+    for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
+    for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
+    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
+    pair_vjp(S, A, al[2], al[4], dl, ph.eps, fu, fl, 0.0, 0.0, false, lS, lA, lal[2], lal[4], emit);
+    const double sp = fu + fl, sm = fu - fl;
+    const double Rs6 = e.as * (0.5 * e.v2 + e.csl2 - e.g2 * e.a2);
+    // corr += as sp; as vn sp - as csl sm; as vt1 sp - cf af by s sm; as vt2 sp - cf af bz s sm;
+    //         -cs af by isr sp; -cs af bz isr sp; Rs6 sp - Gs sm
+    const double lsp = e.as * lam[0] + e.as * e.vn * lam[1] + e.as * e.vt1 * lam[2] + e.as * e.vt2 * lam[3] -
+                       e.cs * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
+    const double lsm = -e.as * e.csl * lam[1] - e.cf * e.af * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gs * lam[6];
+    eb.as += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
+                   (0.5 * e.v2 + e.csl2 - e.g2 * e.a2) * lam[6]) - sm * e.csl * lam[1];
+    eb.vn += e.as * sp * lam[1]; eb.vt1 += e.as * sp * lam[2]; eb.vt2 += e.as * sp * lam[3];
+    eb.csl -= e.as * sm * lam[1];
+    eb.csl2 += e.as * sp * lam[6]; eb.v2 += 0.5 * e.as * sp * lam[6]; eb.a2 -= e.g2 * e.as * sp * lam[6];
+    eb.cf -= sm * e.af * s * (e.by * lam[2] + e.bz * lam[3]);
+    eb.af -= sm * e.cf * s * (e.by * lam[2] + e.bz * lam[3]) + sp * e.cs * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+    eb.by -= sm * e.cf * e.af * s * lam[2] + sp * e.cs * e.af * e.isr * lam[4];
+    eb.bz -= sm * e.cf * e.af * s * lam[3] + sp * e.cs * e.af * e.isr * lam[5];
+    eb.cs -= sp * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+    eb.isr -= sp * e.cs * e.af * (e.by * lam[4] + e.bz * lam[5]);
+    eb.Gs -= sm * lam[6];
+    const double lfu = lsp + lsm, lfl = lsp - lsm;
+    pair_vjp(S, A, al[2], al[4], dl, ph.eps, fu, fl, lfu, lfl, true, lS, lA, lal[2], lal[4], emit);
+    double lt[7], lu[4];
+    for (int j = 0; j < 7; ++j) { eb.qa2 += lS[j] * t[j]; lt[j] = qa2 * lS[j]; }
+    for (int j = 0; j < 4; ++j) { eb.qa2 += lA[j] * u[j]; lu[j] = qa2 * lA[j]; }
+    eb.as += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
+                                          lt[5] * e.Bt2) + gm1 * lt[6];
+    eb.v2 += lt[0] * e.as * e.g1;
+    eb.vn += lt[1] * omg * e.as; eb.vt1 += lt[2] * omg * e.as; eb.vt2 += lt[3] * omg * e.as;
+    eb.Bt1 += lt[4] * omg * e.as; eb.Bt2 += lt[5] * omg * e.as;
+    eb.sr -= e.cs * e.af * (lt[4] * e.by + lt[5] * e.bz);
+    eb.cs -= e.sr * e.af * (lt[4] * e.by + lt[5] * e.bz);
+    eb.af -= sra * (lt[4] * e.by + lt[5] * e.bz);
+    eb.by -= sra * e.af * lt[4]; eb.bz -= sra * e.af * lt[5];
+    eb.Gs += lu[0];
+    eb.as -= lu[1] * e.csl; eb.csl -= lu[1] * e.as;
+    eb.cf -= e.af * s * (lu[2] * e.by + lu[3] * e.bz);
+    eb.af -= e.cf * s * (lu[2] * e.by + lu[3] * e.bz);
+    eb.by -= e.cf * e.af * s * lu[2]; eb.bz -= e.cf * e.af * s * lu[3];
+  }
+  // ---------------- Alfven pair (m = 2, 6): S = (Ga/4, 0, -bz s/4, by s/4, 0, 0, 0),
+  //                  A = (0, 0, 0, 0, -sr bz/4, sr by/4) (A on components 4, 5)
+  {
+    const double S[7] = {0.25 * e.Ga, 0.0, -0.25 * e.bz * s, 0.25 * e.by * s, 0.0, 0.0, 0.0};
+    const double A45[2] = {-0.25 * e.sr * e.bz, 0.25 * e.sr * e.by};
+    // forward in the same form as face_corr (A on 4, 5): reuse pair_vjp with A folded into S
+    // of two separate rows (upper = S + A, lower = S - A, full 7-vectors, A part zero on 0..3)
+    double Su[7], Sl[7];
+    for (int j = 0; j < 7; ++j) { Su[j] = S[j]; Sl[j] = S[j]; }
+    Su[4] += A45[0]; Su[5] += A45[1]; Sl[4] -= A45[0]; Sl[5] -= A45[1];
+    const double Z4[4] = {0.0, 0.0, 0.0, 0.0};
+    double lSu[7] = {0, 0, 0, 0, 0, 0, 0}, lSl[7] = {0, 0, 0, 0, 0, 0, 0}, lz[4] = {0, 0, 0, 0};
+    double f1, f2, dummy;
+    pair_vjp(Su, Z4, al[1], al[1], dl, ph.eps, fu, f1, 0.0, 0.0, false, lSu, lz, dummy, dummy, emit);
+    pair_vjp(Sl, Z4, al[5], al[5], dl, ph.eps, fl, f2, 0.0, 0.0, false, lSl, lz, dummy, dummy, emit);
+    const double sp = fu + fl, sm = fu - fl;
+    // corr += (0, 0, -bz s sp, by s sp, -bz isr sm, by isr sm, -Ga sp)
+    const double lsp = -e.bz * s * lam[2] + e.by * s * lam[3] - e.Ga * lam[6];
+    const double lsm = -e.bz * e.isr * lam[4] + e.by * e.isr * lam[5];
+    eb.bz += -s * sp * lam[2] - e.isr * sm * lam[4];
+    eb.by += s * sp * lam[3] + e.isr * sm * lam[5];
+    eb.isr += sm * (-e.bz * lam[4] + e.by * lam[5]);
+    eb.Ga -= sp * lam[6];
+    const double lfu = lsp + lsm, lfl = lsp - lsm;
+    double lal_dummy = 0.0;
+    pair_vjp(Su, Z4, al[1], al[1], dl, ph.eps, fu, f1, lfu, 0.0, true, lSu, lz, lal[1], lal_dummy, emit);
+    pair_vjp(Sl, Z4, al[5], al[5], dl, ph.eps, fl, f2, lfl, 0.0, true, lSl, lz, lal[5], lal_dummy, emit);
+    const double lS0 = lSu[0] + lSl[0], lS2 = lSu[2] + lSl[2], lS3 = lSu[3] + lSl[3];
+    const double lA4 = lSu[4] - lSl[4], lA5 = lSu[5] - lSl[5];
+    eb.Ga += 0.25 * lS0;
+    eb.bz += -0.25 * s * lS2 - 0.25 * e.sr * lA4;
+    eb.by += 0.25 * s * lS3 + 0.25 * e.sr * lA5;
+    eb.sr += -0.25 * e.bz * lA4 + 0.25 * e.by * lA5;
+  }
+  // ---------------- entropy (m = 4): L/2 = (1/2 - tau v^2/4, tau vn/2, tau vt1/2, tau vt2/2, tau Bt1/2, tau Bt2/2, -tau/2)
+  {
+    const double ht = 0.5 * e.tau;
+    const double l[7] = {0.5 - 0.5 * ht * e.v2, ht * e.vn, ht * e.vt1, ht * e.vt2, ht * e.Bt1, ht * e.Bt2, -ht};
+    const double Z4[4] = {0.0, 0.0, 0.0, 0.0};
+    double ll[7] = {0, 0, 0, 0, 0, 0, 0}, lz[4] = {0, 0, 0, 0};
+    double f4, f5, dummy = 0.0;
+    pair_vjp(l, Z4, al[3], al[3], dl, ph.eps, f4, f5, 0.0, 0.0, false, ll, lz, dummy, dummy, emit);
+    // corr += (f4, vn f4, vt1 f4, vt2 f4, 0, 0, v2/2 f4)
+    const double lf4 = lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] + 0.5 * e.v2 * lam[6];
+    eb.vn += f4 * lam[1]; eb.vt1 += f4 * lam[2]; eb.vt2 += f4 * lam[3]; eb.v2 += 0.5 * f4 * lam[6];
+    double lal_dummy = 0.0;
+    pair_vjp(l, Z4, al[3], al[3], dl, ph.eps, f4, f5, lf4, 0.0, true, ll, lz, lal[3], lal_dummy, emit);
+    const double lht = -0.5 * e.v2 * ll[0] + e.vn * ll[1] + e.vt1 * ll[2] + e.vt2 * ll[3] + e.Bt1 * ll[4] +
+                       e.Bt2 * ll[5] - ll[6];
+    eb.v2 -= 0.5 * ht * ll[0];
+    eb.vn += ht * ll[1]; eb.vt1 += ht * ll[2]; eb.vt2 += ht * ll[3]; eb.Bt1 += ht * ll[4]; eb.Bt2 += ht * ll[5];
+    eb.tau += 0.5 * lht;
+  }
+  // pass-through members of FaceEig that are face-state components
+  // (vn, vt1, vt2, Bt1, Bt2 are fp[1], fp[2], fp[3], fp[5], fp[6])
+  face_eig_vjp(fp, ph, e, eb, lfp);
+}
+
+// ---------------------------------------------------------------------------
+// zone prologue: cotangents of (q, F, primitives, speeds) -> zone inputs
+// ---------------------------------------------------------------------------
+// Inputs in the sweep frame: u = (rho, m_n, m_t1, m_t2, E, B_n, B_t1, B_t2).
+// lz[Z_NVAR] are the cotangents of the prologue outputs; out[8] += d/du.
+__host__ __device__ inline void zone_prologue_vjp(const double u[8], double gamma, const double lz[Z_NVAR],
+                                                  double out[8]) {
+  const double rho = u[0], mn = u[1], mt1 = u[2], mt2 = u[3], E = u[4], Bn = u[5], Bt1 = u[6], Bt2 = u[7];
+  const double irho = 1.0 / rho;
+  const double vn = mn * irho, vt1 = mt1 * irho, vt2 = mt2 * irho;
+  const double Bp2 = Bt1 * Bt1 + Bt2 * Bt2;
+  const double B2 = Bn * Bn + Bp2;
+  const double P = (gamma - 1.0) * (E - 0.5 * ((mn * vn + mt1 * vt1 + mt2 * vt2) + B2));
+  const double Pstar = P + 0.5 * B2;
+  const double vB = vn * Bn + vt1 * Bt1 + vt2 * Bt2;
+  const double a2 = gamma * P * irho, b2 = B2 * irho, bn2 = Bn * Bn * irho;
+  const double dab = a2 - b2;
+  const double D = sqrt(dab * dab + 4.0 * a2 * (Bp2 * irho));
+  const double cf2 = 0.5 * (a2 + b2 + D);
+  const double cs2 = cf2 > 0.0 ? a2 * bn2 / cf2 : 0.0;
+  const double cf = sqrt(cf2), cA = sqrt(bn2), cs = sqrt(cs2);
+  double l_rho = lz[Z_RHO], l_mn = lz[Z_MN], l_mt1 = lz[Z_MT1], l_mt2 = lz[Z_MT2];
+  double l_Bt1 = lz[Z_BT1], l_Bt2 = lz[Z_BT2], l_E = lz[Z_E];
+  double l_vn = lz[Z_VN], l_vt1 = lz[Z_VT1], l_vt2 = lz[Z_VT2], l_Bn = lz[Z_BN], l_P = lz[Z_P];
+  double l_cf2 = 0.0, l_cs2 = 0.0, l_bn2 = 0.0, l_a2 = 0.0, l_b2 = 0.0, l_D = 0.0, l_dab = 0.0;
+  double l_irho = 0.0, l_Bp2 = 0.0, l_B2 = 0.0, l_Pstar = 0.0, l_vB = 0.0;
+  // speeds
+  if (cf > 0.0) l_cf2 += lz[Z_CF] * 0.5 / cf;
+  if (cA > 0.0) l_bn2 += lz[Z_CA] * 0.5 / cA;
+  if (cs > 0.0) l_cs2 += lz[Z_CS] * 0.5 / cs;
+  if (cf2 > 0.0) {
+    l_a2 += l_cs2 * bn2 / cf2;
+    l_bn2 += l_cs2 * a2 / cf2;
+    l_cf2 -= l_cs2 * cs2 / cf2;
+  }
+  l_a2 += 0.5 * l_cf2; l_b2 += 0.5 * l_cf2; l_D += 0.5 * l_cf2;
+  if (D > 0.0) {
+    const double lQ = l_D * 0.5 / D;
+    l_dab += 2.0 * dab * lQ;
+    l_a2 += 4.0 * Bp2 * irho * lQ;
+    l_Bp2 += 4.0 * a2 * irho * lQ;
+    l_irho += 4.0 * a2 * Bp2 * lQ;
+  }
+  l_a2 += l_dab; l_b2 -= l_dab;
+  l_Bn += 2.0 * Bn * irho * l_bn2; l_irho += Bn * Bn * l_bn2;
+  l_B2 += irho * l_b2; l_irho += B2 * l_b2;
+  l_P += gamma * irho * l_a2; l_irho += gamma * P * l_a2;
+  // fluxes
+  const double F0 = lz[Z_F0], F1 = lz[Z_F1], F2 = lz[Z_F2], F3 = lz[Z_F3], F4 = lz[Z_F4], F5 = lz[Z_F5], F6 = lz[Z_F6];
+  // F0 = rho vn
+  l_rho += F0 * vn; l_vn += F0 * rho;
+  // F1 = rho vn vn + Pstar - Bn Bn
+  l_rho += F1 * vn * vn; l_vn += F1 * 2.0 * rho * vn; l_Pstar += F1; l_Bn -= F1 * 2.0 * Bn;
+  // F2 = rho vn vt1 - Bn Bt1, F3 = rho vn vt2 - Bn Bt2
+  l_rho += F2 * vn * vt1 + F3 * vn * vt2;
+  l_vn += F2 * rho * vt1 + F3 * rho * vt2;
+  l_vt1 += F2 * rho * vn; l_vt2 += F3 * rho * vn;
+  l_Bn -= F2 * Bt1 + F3 * Bt2; l_Bt1 -= F2 * Bn; l_Bt2 -= F3 * Bn;
+  // F4 = Bt1 vn - Bn vt1, F5 = Bt2 vn - Bn vt2
+  l_Bt1 += F4 * vn; l_vn += F4 * Bt1 + F5 * Bt2; l_Bn -= F4 * vt1 + F5 * vt2; l_vt1 -= F4 * Bn;
+  l_Bt2 += F5 * vn; l_vt2 -= F5 * Bn;
+  // F6 = (E + Pstar) vn - Bn vB
+  l_E += F6 * vn; l_Pstar += F6 * vn; l_vn += F6 * (E + Pstar); l_Bn -= F6 * vB; l_vB -= F6 * Bn;
+  // vB = vn Bn + vt1 Bt1 + vt2 Bt2
+  l_vn += l_vB * Bn; l_Bn += l_vB * vn; l_vt1 += l_vB * Bt1; l_Bt1 += l_vB * vt1; l_vt2 += l_vB * Bt2;
+  l_Bt2 += l_vB * vt2;
+  // Pstar = P + B2/2
+  l_P += l_Pstar; l_B2 += 0.5 * l_Pstar;
+  // P = (gamma-1)(E - (mn vn + mt1 vt1 + mt2 vt2 + B2)/2)
+  const double gm = gamma - 1.0;
+  l_E += gm * l_P;
+  l_mn -= 0.5 * gm * l_P * vn; l_vn -= 0.5 * gm * l_P * mn;
+  l_mt1 -= 0.5 * gm * l_P * vt1; l_vt1 -= 0.5 * gm * l_P * mt1;
+  l_mt2 -= 0.5 * gm * l_P * vt2; l_vt2 -= 0.5 * gm * l_P * mt2;
+  l_B2 -= 0.5 * gm * l_P;
+  // B2 = Bn^2 + Bp2, Bp2 = Bt1^2 + Bt2^2
+  l_Bn += 2.0 * Bn * l_B2; l_Bp2 += l_B2;
+  l_Bt1 += 2.0 * Bt1 * l_Bp2; l_Bt2 += 2.0 * Bt2 * l_Bp2;
+  // v = m irho
+  l_mn += l_vn * irho; l_mt1 += l_vt1 * irho; l_mt2 += l_vt2 * irho;
+  l_irho += l_vn * mn + l_vt1 * mt1 + l_vt2 * mt2;
+  // irho = 1/rho
+  l_rho -= irho * irho * l_irho;
+  out[0] += l_rho; out[1] += l_mn; out[2] += l_mt1; out[3] += l_mt2;
+  out[4] += l_E; out[5] += l_Bn; out[6] += l_Bt1; out[7] += l_Bt2;
+}
+
+}  // namespace wm

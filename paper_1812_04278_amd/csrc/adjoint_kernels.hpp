@@ -1,0 +1,410 @@
+// HIP kernels of the adjoint (vector-Jacobian product) of the semi-discrete
+// right-hand side and of the SSP-RK3 stage map, FP64.
+//
+//   adj_emf_kernel       cotangent of the face-b right-hand side -> cotangents
+//                        of the six transport fluxes (transposes of the b
+//                        equations of Sect. 2.3 and of eq. ox1-ox3)
+//   adj_sweep_kernel     one direction: recomputes the tile's forward data,
+//                        runs the per-face reverse (adjoint_device.hpp) and
+//                        the per-zone prologue reverse.  Full tiles add the
+//                        cotangents of their own zones to `main` and write
+//                        those of the halo zones owned by neighbouring tiles
+//                        to `spillL` / `spillR` (two and three zones; for full
+//                        tiles every entry has exactly one writer).  A ragged
+//                        last tile behind full tiles runs as a separate launch
+//                        afterwards and adds all of its zones into `main`
+//                        directly: when it is shorter than three zones, the
+//                        wrapped halos of the first and last tiles would
+//                        otherwise share entries.
+//   adj_combine_kernel   main += spillL + spillR, spills cleared
+//   adj_bcell_kernel     face-b cotangent += transpose of the fourth-order
+//                        zone interpolation
+//   adj_axpy kernels     the RK3 stage combinations
+//   init_adj kernels     transpose of the initial-state map (curl_h A, m, E)
+// Accumulation orders are fixed (LDS sub-rounds separated by barriers, no
+// atomics), so results are bitwise reproducible.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "adjoint_device.hpp"
+#include "kernels.hpp"
+
+namespace wm {
+
+// ---------------------------------------------------------------------------
+// b equations and corner fluxes, transposed
+// ---------------------------------------------------------------------------
+// Forward (update_kernel): rhs_bx = -(Ez - Ez[j-1])/h + (Ey - Ey[k-1])/h,
+// rhs_by = -(Ex - Ex[k-1])/h + (Ez - Ez[i-1])/h, rhs_bz = -(Ey - Ey[i-1])/h +
+// (Ex - Ex[j-1])/h with Ez = (Tyx + Tyx[i+1])/2 - (Txy + Txy[j+1])/2,
+// Ex = (Tzy + Tzy[j+1])/2 - (Tyz + Tyz[k+1])/2, Ey = (Txz + Txz[k+1])/2 - (Tzx + Tzx[i+1])/2.
+__global__ __launch_bounds__(256) void adj_emf_kernel(Grid g, double inv_h, const double* lam_k, double* lam_T) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const size_t N = g.N;
+  const double* lbx = lam_k + 5 * N;
+  const double* lby = lam_k + 6 * N;
+  const double* lbz = lam_k + 7 * N;
+  const int im = wrap(i - 1, g.nx), ip = wrap(i + 1, g.nx);
+  const int jm = wrap(j - 1, g.ny), jp = wrap(j + 1, g.ny);
+  const int km = wrap(k - 1, g.nz), kp = wrap(k + 1, g.nz);
+  // cotangents of the corner fluxes at edge index (ii, jj, kk)
+  auto lEz = [&](int ii, int jj, int kk) {
+    const int jjp = wrap(jj + 1, g.ny), iip = wrap(ii + 1, g.nx);
+    return (-lbx[g.at(ii, jj, kk)] + lbx[g.at(ii, jjp, kk)] + lby[g.at(ii, jj, kk)] - lby[g.at(iip, jj, kk)]) * inv_h;
+  };
+  auto lEx = [&](int ii, int jj, int kk) {
+    const int kkp = wrap(kk + 1, g.nz), jjp = wrap(jj + 1, g.ny);
+    return (-lby[g.at(ii, jj, kk)] + lby[g.at(ii, jj, kkp)] + lbz[g.at(ii, jj, kk)] - lbz[g.at(ii, jjp, kk)]) * inv_h;
+  };
+  auto lEy = [&](int ii, int jj, int kk) {
+    const int kkp = wrap(kk + 1, g.nz), iip = wrap(ii + 1, g.nx);
+    return (lbx[g.at(ii, jj, kk)] - lbx[g.at(ii, jj, kkp)] - lbz[g.at(ii, jj, kk)] + lbz[g.at(iip, jj, kk)]) * inv_h;
+  };
+  (void)ip; (void)jp; (void)kp;
+  const size_t c0 = g.at(i, j, k);
+  const double ez = lEz(i, j, k), ex = lEx(i, j, k), ey = lEy(i, j, k);
+  // T layout: [0] Txy, [1] Txz, [2] Tyz, [3] Tyx, [4] Tzx, [5] Tzy
+  lam_T[0 * N + c0] = -0.5 * (ez + lEz(i, jm, k));   // Txy feeds Ez(j) and Ez(j-1)
+  lam_T[1 * N + c0] = 0.5 * (ey + lEy(i, j, km));    // Txz feeds Ey(k) and Ey(k-1)
+  lam_T[2 * N + c0] = -0.5 * (ex + lEx(i, j, km));   // Tyz feeds Ex(k) and Ex(k-1)
+  lam_T[3 * N + c0] = 0.5 * (ez + lEz(im, j, k));    // Tyx feeds Ez(i) and Ez(i-1)
+  lam_T[4 * N + c0] = -0.5 * (ey + lEy(im, j, k));   // Tzx feeds Ey(i) and Ey(i-1)
+  lam_T[5 * N + c0] = 0.5 * (ex + lEx(i, jm, k));    // Tzy feeds Ex(j) and Ex(j-1)
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of one directional sweep
+// ---------------------------------------------------------------------------
+struct AdjSweepArgs {
+  Grid g;
+  Phys ph;
+  double inv_h;
+  const double* hydro;   // forward state [5][N]
+  const double* bcell;   // its zone B [3][N]
+  const double* lam_k;   // [8][N] cotangent of the right-hand side (hydro part used)
+  const double* lam_T;   // [2][N] cotangent of this sweep's transport fluxes T^n_t1, T^n_t2
+  double* lam_main;      // [8][N] += zone cotangents: rho, m_x, m_y, m_z, E, B_x, B_y, B_z
+  double* spillL;        // [8][N] zone cotangents of the two zones left of a tile
+  double* spillR;        // [8][N] zone cotangents of the three zones right of a tile
+  int tile0;             // index of the first tile of this launch along the axis
+  int direct;            // 1: add every zone's cotangent into lam_main (a launch of one tile column)
+};
+
+constexpr int ADJ_NP = 11;   // cotangents of zone primitives and speeds (P_* order)
+
+template <int AXIS>
+__global__ __launch_bounds__(SW_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a) {
+  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  constexpr int NA = TA + SW_HL + SW_HR;
+  constexpr int NI = TA + 4;
+  constexpr int NC = NA * TB;
+  constexpr int NIF = NI * TB;
+  constexpr int NF = TA * TB;
+  // LDS: zone q/F (later the differences) | primitives (later their cotangents)
+  //      | interface cotangents | face cotangents of the flux (central term)
+  __shared__ double Q[SW_NQ * NC];
+  __shared__ double Pz[SW_NP * NC];
+  __shared__ double LD[SW_NQ * NIF];
+  __shared__ double LF[7 * NF];
+  const Grid& g = a.g;
+  const int nA = AXIS == 0 ? g.nx : (AXIS == 1 ? g.ny : g.nz);
+  const int nB = AXIS == 0 ? g.ny : g.nx;
+  const int a0 = (a.tile0 + blockIdx.x) * TA;
+  const int b0 = blockIdx.y * TB;
+  const int c = blockIdx.z;
+  const int tav = min(TA, nA - a0);            // valid faces (and own zones) along the axis
+  constexpr int CN = AXIS, CT1 = (AXIS + 1) % 3, CT2 = (AXIS + 2) % 3;
+  auto cidx = [](int aa, int bb) { return AXIS == 0 ? bb * NA + aa : aa * TB + bb; };
+  auto iidx = [](int ia, int bb) { return AXIS == 0 ? bb * NI + ia : ia * TB + bb; };
+  auto fidx = [](int fa, int bb) { return AXIS == 0 ? bb * TA + fa : fa * TB + bb; };
+  auto gindex = [&](int aa_global, int bb_global) {
+    int i, j, k;
+    if (AXIS == 0)      { i = aa_global; j = bb_global; k = c; }
+    else if (AXIS == 1) { i = bb_global; j = aa_global; k = c; }
+    else                { i = bb_global; j = c;         k = aa_global; }
+    return g.at(i, j, k);
+  };
+
+  // ---- (1) forward zone prologue into LDS
+  for (int cell = threadIdx.x; cell < NC; cell += SW_THREADS) {
+    int aa, bb;
+    if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
+    else           { bb = cell % TB; aa = cell / TB; }
+    const size_t gi = gindex(wrap(a0 - SW_HL + aa, nA), min(b0 + bb, nB - 1));
+    const double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
+    const double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
+    double z[Z_NVAR];
+    zone_prologue(a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
+#pragma unroll
+    for (int v = 0; v < SW_NQ; ++v) Q[v * NC + cell] = z[v];
+    const int pv[SW_NP] = {Z_RHO, Z_VN, Z_VT1, Z_VT2, Z_BN, Z_BT1, Z_BT2, Z_P, Z_CF, Z_CA, Z_CS};
+#pragma unroll
+    for (int v = 0; v < SW_NP; ++v) Pz[v * NC + cell] = z[pv[v]];
+  }
+  __syncthreads();
+
+  // ---- (2) per face: face state, LF speeds, zone values for the reverse,
+  //          own interface differences, incoming flux cotangents
+  int fa, fb;
+  if (AXIS == 0) { fa = threadIdx.x % TA; fb = threadIdx.x / TA; }
+  else           { fb = threadIdx.x % TB; fa = threadIdx.x / TB; }
+  const bool valid = fa < tav && b0 + fb < nB;
+  const int cL = cidx(fa + 2, fb), cR = cidx(fa + 3, fb);
+  double fp[8], al[7];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (Pz[v * NC + cL] + Pz[v * NC + cR]);
+  const double vL = Pz[P_VN * NC + cL], vR = Pz[P_VN * NC + cR];
+  const double spL[3] = {Pz[P_CF * NC + cL], Pz[P_CA * NC + cL], Pz[P_CS * NC + cL]};
+  const double spR[3] = {Pz[P_CF * NC + cR], Pz[P_CA * NC + cR], Pz[P_CS * NC + cR]};
+  const double BnL = Pz[P_BN * NC + cL], BnR = Pz[P_BN * NC + cR];
+  const double t1L = Pz[P_VT1 * NC + cL], t1R = Pz[P_VT1 * NC + cR];
+  const double t2L = Pz[P_VT2 * NC + cL], t2R = Pz[P_VT2 * NC + cR];
+  // LF speed of field m: max(|v_L + sg c_L|, |v_R + sg c_R|); c index: fast 0, Alfven 1, slow 2, none (entropy)
+  const int sgm[7] = {-1, -1, -1, 0, 1, 1, 1};
+  const int spi[7] = {0, 1, 2, 0, 2, 1, 0};
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    const double xl = sgm[m] == 0 ? vL : vL + sgm[m] * spL[spi[m]];
+    const double xr = sgm[m] == 0 ? vR : vR + sgm[m] * spR[spi[m]];
+    al[m] = fmax(fabs(xl), fabs(xr));
+  }
+  double d0[SW_NQ], d1[SW_NQ];
+  {
+    const int c0 = cidx(fa, fb), c1 = cidx(fa + 1, fb);
+#pragma unroll
+    for (int v = 0; v < SW_NQ; ++v) d0[v] = Q[v * NC + c1] - Q[v * NC + c0];
+    if (fa < 4) {
+      const int c2 = cidx(TA + fa, fb), c3 = cidx(TA + fa + 1, fb);
+#pragma unroll
+      for (int v = 0; v < SW_NQ; ++v) d1[v] = Q[v * NC + c3] - Q[v * NC + c2];
+    }
+  }
+  // incoming cotangents: flux divergence transposed, lam_F_v(face i+1/2) = (lam_k_v(i+1) - lam_k_v(i))/h,
+  // in the sweep frame; the B_t components carry the transport-flux cotangents
+  double lam[7], ltc1, ltc2;
+  {
+    const int ia = wrap(a0 + fa, nA), ia1 = wrap(a0 + fa + 1, nA);
+    const int ib = min(b0 + fb, nB - 1);
+    const size_t g0 = gindex(ia, ib), g1 = gindex(ia1, ib);
+    double lg[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) lg[v] = (a.lam_k[v * g.N + g1] - a.lam_k[v * g.N + g0]) * a.inv_h;
+    const double lm[3] = {lg[1], lg[2], lg[3]};
+    const double msk = valid ? 1.0 : 0.0;
+    ltc1 = msk * a.lam_T[g0];
+    ltc2 = msk * a.lam_T[g.N + g0];
+    lam[0] = msk * lg[0];
+    lam[1] = msk * lm[CN];
+    lam[2] = msk * lm[CT1];
+    lam[3] = msk * lm[CT2];
+    lam[4] = ltc1;
+    lam[5] = ltc2;
+    lam[6] = msk * lg[4];
+  }
+  __syncthreads();
+  // differences (Delta F, Delta q) into the q/F area; cotangent areas cleared
+#pragma unroll
+  for (int v = 0; v < 7; ++v) {
+    Q[v * NIF + iidx(fa, fb)] = d0[7 + v];
+    Q[(7 + v) * NIF + iidx(fa, fb)] = d0[v];
+  }
+  if (fa < 4) {
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      Q[v * NIF + iidx(TA + fa, fb)] = d1[7 + v];
+      Q[(7 + v) * NIF + iidx(TA + fa, fb)] = d1[v];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 7; ++v) LF[v * NF + fidx(fa, fb)] = lam[v];
+  for (int t = threadIdx.x; t < SW_NQ * NIF; t += SW_THREADS) LD[t] = 0.0;
+  for (int t = threadIdx.x; t < SW_NP * NC; t += SW_THREADS) Pz[t] = 0.0;
+  __syncthreads();
+
+  // ---- (3) per-face reverse; interface cotangents in barrier-separated sub-rounds
+  auto dl = [&](int j, int k) -> double { return Q[j * NIF + iidx(fa + k, fb)]; };
+  auto emit = [&](int k, const double* v) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SW_NQ; ++j) LD[j * NIF + iidx(fa + k, fb)] += v[j];
+  };
+  double lfp[8] = {0, 0, 0, 0, 0, 0, 0, 0}, lal[7] = {0, 0, 0, 0, 0, 0, 0};
+  face_corr_vjp(fp, al, dl, a.ph, lam, lfp, lal, emit);
+  // zone-primitive cotangents of zones L (i) and R (i+1): face-state means,
+  // LF speeds (branch of the larger argument; ties -> L) and transport-flux means
+  double pl[ADJ_NP], pr[ADJ_NP];
+#pragma unroll
+  for (int v = 0; v < ADJ_NP; ++v) { pl[v] = v < 8 ? 0.5 * lfp[v] : 0.0; pr[v] = pl[v]; }
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    const double xl = sgm[m] == 0 ? vL : vL + sgm[m] * spL[spi[m]];
+    const double xr = sgm[m] == 0 ? vR : vR + sgm[m] * spR[spi[m]];
+    const bool left = fabs(xl) >= fabs(xr);
+    const double x = left ? xl : xr;
+    const double sx = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
+    double* t = left ? pl : pr;
+    t[P_VN] += lal[m] * sx;
+    if (sgm[m] != 0) t[P_CF + spi[m]] += lal[m] * sx * sgm[m];
+  }
+  pl[P_BN] += 0.5 * (ltc1 * t1L + ltc2 * t2L);
+  pr[P_BN] += 0.5 * (ltc1 * t1R + ltc2 * t2R);
+  pl[P_VT1] += 0.5 * ltc1 * BnL; pr[P_VT1] += 0.5 * ltc1 * BnR;
+  pl[P_VT2] += 0.5 * ltc2 * BnL; pr[P_VT2] += 0.5 * ltc2 * BnR;
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < ADJ_NP; ++v) Pz[v * NC + cL] += pl[v];
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < ADJ_NP; ++v) Pz[v * NC + cR] += pr[v];
+  __syncthreads();
+
+  // ---- (4) per zone: gather, prologue reverse, write
+  for (int cell = threadIdx.x; cell < NC; cell += SW_THREADS) {
+    int aa, bb;
+    if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
+    else           { bb = cell % TB; aa = cell / TB; }
+    if (aa >= tav + 5 || b0 + bb >= nB) continue;   // no valid face touches this zone
+    double lz[Z_NVAR];
+#pragma unroll
+    for (int v = 0; v < Z_NVAR; ++v) lz[v] = 0.0;
+    // interface differences: D(ia) = X(ia+1) - X(ia)
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      double lFj = 0.0, lqj = 0.0;
+      if (aa >= 1) { lFj += LD[j * NIF + iidx(aa - 1, bb)]; lqj += LD[(7 + j) * NIF + iidx(aa - 1, bb)]; }
+      if (aa < NI) { lFj -= LD[j * NIF + iidx(aa, bb)]; lqj -= LD[(7 + j) * NIF + iidx(aa, bb)]; }
+      // central term: face f (local) uses zones f+1 (-1/12), f+2 (7/12), f+3 (7/12), f+4 (-1/12)
+      const int f1 = aa - 1, f2 = aa - 2, f3 = aa - 3, f4 = aa - 4;
+      if (f1 >= 0 && f1 < TA) lFj -= LF[j * NF + fidx(f1, bb)] * (1.0 / 12.0);
+      if (f2 >= 0 && f2 < TA) lFj += LF[j * NF + fidx(f2, bb)] * (7.0 / 12.0);
+      if (f3 >= 0 && f3 < TA) lFj += LF[j * NF + fidx(f3, bb)] * (7.0 / 12.0);
+      if (f4 >= 0 && f4 < TA) lFj -= LF[j * NF + fidx(f4, bb)] * (1.0 / 12.0);
+      lz[Z_F0 + j] = lFj;
+      lz[Z_RHO + j] = lqj;
+    }
+    lz[Z_RHO] += Pz[P_RHO * NC + cell];
+    lz[Z_VN] += Pz[P_VN * NC + cell];
+    lz[Z_VT1] += Pz[P_VT1 * NC + cell];
+    lz[Z_VT2] += Pz[P_VT2 * NC + cell];
+    lz[Z_BN] += Pz[P_BN * NC + cell];
+    lz[Z_BT1] += Pz[P_BT1 * NC + cell];
+    lz[Z_BT2] += Pz[P_BT2 * NC + cell];
+    lz[Z_P] += Pz[P_P * NC + cell];
+    lz[Z_CF] += Pz[P_CF * NC + cell];
+    lz[Z_CA] += Pz[P_CA * NC + cell];
+    lz[Z_CS] += Pz[P_CS * NC + cell];
+    const int gaa = wrap(a0 - SW_HL + aa, nA);
+    const size_t gi = gindex(gaa, b0 + bb);
+    const double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
+    const double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
+    const double u[8] = {a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2]};
+    double lu[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    zone_prologue_vjp(u, a.ph.gamma, lz, lu);
+    double out[8];
+    out[0] = lu[0];
+    out[1 + CN] = lu[1]; out[1 + CT1] = lu[2]; out[1 + CT2] = lu[3];
+    out[4] = lu[4];
+    out[5 + CN] = lu[5]; out[5 + CT1] = lu[6]; out[5 + CT2] = lu[7];
+    if (a.direct) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) a.lam_main[v * g.N + gi] += out[v];
+    } else if (aa < SW_HL) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) a.spillL[v * g.N + gi] = out[v];
+    } else if (aa < SW_HL + tav) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) a.lam_main[v * g.N + gi] += out[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) a.spillR[v * g.N + gi] = out[v];
+    }
+  }
+}
+
+// main += spillL + spillR; spills cleared for the next sweep
+__global__ __launch_bounds__(256) void adj_combine_kernel(size_t n8, double* lam_main, double* spillL, double* spillR) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n8) return;
+  lam_main[c] += spillL[c] + spillR[c];
+  spillL[c] = 0.0;
+  spillR[c] = 0.0;
+}
+
+// face b cotangent += transpose of B_i = (-b_{i-2} + 9 b_{i-1} + 9 b_i - b_{i+1})/16:
+// lam_b_j += (-lam_B_{j+2} + 9 lam_B_{j+1} + 9 lam_B_j - lam_B_{j-1})/16
+__global__ __launch_bounds__(256) void adj_bcell_kernel(Grid g, const double* lam_B, double* lam_b) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const size_t N = g.N, c0 = g.at(i, j, k);
+  const double* Lx = lam_B;
+  const double* Ly = lam_B + N;
+  const double* Lz = lam_B + 2 * N;
+  lam_b[c0] += (-Lx[g.at(wrap(i + 2, g.nx), j, k)] + 9.0 * Lx[g.at(wrap(i + 1, g.nx), j, k)] + 9.0 * Lx[c0] -
+                Lx[g.at(wrap(i - 1, g.nx), j, k)]) * (1.0 / 16.0);
+  lam_b[N + c0] += (-Ly[g.at(i, wrap(j + 2, g.ny), k)] + 9.0 * Ly[g.at(i, wrap(j + 1, g.ny), k)] + 9.0 * Ly[c0] -
+                    Ly[g.at(i, wrap(j - 1, g.ny), k)]) * (1.0 / 16.0);
+  lam_b[2 * N + c0] += (-Lz[g.at(i, j, wrap(k + 2, g.nz))] + 9.0 * Lz[g.at(i, j, wrap(k + 1, g.nz))] + 9.0 * Lz[c0] -
+                        Lz[g.at(i, j, wrap(k - 1, g.nz))]) * (1.0 / 16.0);
+}
+
+// y = a x (n doubles)
+__global__ __launch_bounds__(256) void scale_kernel(size_t n, double a, const double* x, double* y) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < n) y[c] = a * x[c];
+}
+// y = a x + b z (n doubles)
+__global__ __launch_bounds__(256) void axpby_kernel(size_t n, double a, const double* x, double b, const double* z,
+                                                    double* y) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < n) y[c] = a * x[c] + b * z[c];
+}
+// y += x (n doubles)
+__global__ __launch_bounds__(256) void add_kernel(size_t n, const double* x, double* y) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < n) y[c] += x[c];
+}
+__global__ __launch_bounds__(256) void fill_kernel(size_t n, double v, double* y) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < n) y[c] = v;
+}
+
+// Initial-state map transposed, per zone: m = rho v, E = P0/(gamma-1) + (rho v^2 + B^2)/2
+// with B the zone interpolation of b:  lam_v = rho lam_m + rho v lam_E,  lam_B = B lam_E.
+__global__ __launch_bounds__(256) void init_adj_zone_kernel(size_t N, const double* rho, const double* v,
+                                                            const double* B, const double* lam_h, double* g_v,
+                                                            double* lam_B) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  const double r = rho[c], lE = lam_h[4 * N + c];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g_v[d * N + c] = r * lam_h[(1 + d) * N + c] + r * v[d * N + c] * lE;
+    lam_B[d * N + c] = B[d * N + c] * lE;
+  }
+}
+
+// curl_h transposed: b_x = (Az - Az[j-1] - Ay + Ay[k-1])/h, b_y = (Ax - Ax[k-1] - Az + Az[i-1])/h,
+// b_z = (Ay - Ay[i-1] - Ax + Ax[j-1])/h  =>  per edge value of A:
+// g_Ax = (lby - lby[k+1] - lbz + lbz[j+1])/h, g_Ay = (lbz - lbz[i+1] - lbx + lbx[k+1])/h,
+// g_Az = (lbx - lbx[j+1] - lby + lby[i+1])/h
+__global__ __launch_bounds__(256) void curl_adj_kernel(Grid g, double inv_h, const double* lam_b, double* g_A) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const size_t N = g.N, c0 = g.at(i, j, k);
+  const double* lbx = lam_b;
+  const double* lby = lam_b + N;
+  const double* lbz = lam_b + 2 * N;
+  const int ip = wrap(i + 1, g.nx), jp = wrap(j + 1, g.ny), kp = wrap(k + 1, g.nz);
+  g_A[c0] = (lby[c0] - lby[g.at(i, j, kp)] - lbz[c0] + lbz[g.at(i, jp, k)]) * inv_h;
+  g_A[N + c0] = (lbz[c0] - lbz[g.at(ip, j, k)] - lbx[c0] + lbx[g.at(i, j, kp)]) * inv_h;
+  g_A[2 * N + c0] = (lbx[c0] - lbx[g.at(i, jp, k)] - lby[c0] + lby[g.at(ip, j, k)]) * inv_h;
+}
+
+}  // namespace wm

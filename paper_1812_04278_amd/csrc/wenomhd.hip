@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/wenomhd.h"
-#include "kernels.hpp"
+#include "adjoint_kernels.hpp"
 
 using namespace wm;
 
@@ -77,6 +77,18 @@ Layout layout(const wm_config* c) {
   L.red = off;   off = align_up(off + kRedDoubles * sizeof(double));
   L.total = off;
   return L;
+}
+
+// adjoint scratch (doubles, N each unless noted): U1 (11), U2 (11), zone B of
+// the linearisation state (3), transport-flux cotangents (6), zone cotangents
+// main / spillL / spillR (8 each), rhs cotangent (8), stage cotangents lamU2,
+// lamU1 (8 each), work (8), then the dt slot.
+enum AdjOff { A_U1 = 0, A_U2 = 11, A_BZ = 22, A_LT = 25, A_MAIN = 31, A_SPL = 39, A_SPR = 47, A_LK = 55,
+              A_LU2 = 63, A_LU1 = 71, A_WORK = 79, A_NARR = 87 };
+
+size_t adjoint_bytes(const wm_config* c) {
+  const size_t N = (size_t)c->nx * c->ny * c->nz;
+  return align_up(A_NARR * N * sizeof(double) + 256);
 }
 
 }  // namespace
@@ -223,6 +235,118 @@ int red_blocks(const Grid& g) {
 wm_status check_bound(wm_patch* p) {
   if (!p) return fail(WM_ERR_ARG, "null patch");
   if (!p->hydro || !p->bface || !p->bcell) return fail(WM_ERR_STATE, "state not bound (wm_bind_state)");
+  return WM_OK;
+}
+
+dim3 lin_grid(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+template <int AXIS>
+wm_status launch_adj_sweep(wm_patch* p, const double* hydro, const double* bcell, const double* lam_k,
+                           const double* lam_T, double* main, double* spl, double* spr) {
+  AdjSweepArgs a;
+  a.g = p->g;
+  a.ph = p->ph;
+  a.inv_h = 1.0 / p->cfg.h;
+  a.hydro = hydro;
+  a.bcell = bcell;
+  a.lam_k = lam_k;
+  a.lam_T = lam_T;
+  a.lam_main = main;
+  a.spillL = spl;
+  a.spillR = spr;
+  const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
+  const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
+  const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
+  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  // Spill mode for every tile except a ragged last one behind at least one full
+  // tile: with fewer than three zones it would share spill entries with the
+  // first tile (their halos wrap onto the same zones), so it runs afterwards
+  // and adds straight into main.  Its own zone range (rem + 5 <= nA zones) does
+  // not wrap onto itself; a single tile (nA <= TA) keeps the spill mode, whose
+  // buffers hold two and three distinct zones for nA >= 3.
+  const int nfull = nA / TA, rem = nA % TA;
+  const int nspill = (nfull > 0 && rem > 0) ? nfull : (nA + TA - 1) / TA;
+  const long r = prof_begin(p, K_OTHER);
+  a.tile0 = 0;
+  a.direct = 0;
+  hipLaunchKernelGGL((adj_sweep_kernel<AXIS>), dim3(nspill, (nB + TB - 1) / TB, nC), dim3(SW_THREADS), 0,
+                     p->stream, a);
+  WM_LAUNCH_CHECK("adjoint sweep kernel");
+  if (nspill * TA < nA) {
+    a.tile0 = nspill;
+    a.direct = 1;
+    hipLaunchKernelGGL((adj_sweep_kernel<AXIS>), dim3(1, (nB + TB - 1) / TB, nC), dim3(SW_THREADS), 0, p->stream,
+                       a);
+    WM_LAUNCH_CHECK("adjoint sweep kernel");
+  }
+  prof_end(p, r);
+  hipLaunchKernelGGL(adj_combine_kernel, lin_grid(8 * p->g.N), dim3(256), 0, p->stream, 8 * p->g.N, main, spl, spr);
+  WM_LAUNCH_CHECK("adjoint combine kernel");
+  return WM_OK;
+}
+
+wm_status check_adjoint(wm_patch* p, void* adj) {
+  if (!p) return fail(WM_ERR_ARG, "null patch");
+  if (!adj || reinterpret_cast<uintptr_t>(adj) % kAlign) return fail(WM_ERR_ARG, "adjoint scratch null or misaligned");
+  if (p->cfg.nx < 3 || p->cfg.ny < 3 || p->cfg.nz < 3) return fail(WM_ERR_ARG, "the adjoint needs grid sizes >= 3");
+  return WM_OK;
+}
+
+// (dL/dU)^T lam_k at U = (hydro, bface) -> out (hydro 5, bface 3); A = adjoint scratch base
+wm_status rhs_vjp(wm_patch* p, double* A, const double* hydro, const double* bface, const double* lam_k,
+                  double* out) {
+  const size_t N = p->g.N;
+  wm_status s;
+  double* Bz = A + A_BZ * N;
+  double* lT = A + A_LT * N;
+  double* main = A + A_MAIN * N;
+  double* spl = A + A_SPL * N;
+  double* spr = A + A_SPR * N;
+  if ((s = launch_bcell(p, bface, Bz)) != WM_OK) return s;
+  hipLaunchKernelGGL(adj_emf_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, lam_k, lT);
+  WM_LAUNCH_CHECK("adjoint emf kernel");
+  hipLaunchKernelGGL(fill_kernel, lin_grid(24 * N), dim3(256), 0, p->stream, 24 * N, 0.0, main);  // main, spills
+  WM_LAUNCH_CHECK("fill kernel");
+  if ((s = launch_adj_sweep<0>(p, hydro, Bz, lam_k, lT, main, spl, spr)) != WM_OK) return s;
+  if ((s = launch_adj_sweep<1>(p, hydro, Bz, lam_k, lT + 2 * N, main, spl, spr)) != WM_OK) return s;
+  if ((s = launch_adj_sweep<2>(p, hydro, Bz, lam_k, lT + 4 * N, main, spl, spr)) != WM_OK) return s;
+  // hydro cotangents as they are; face b from the zone-B cotangent
+  hipLaunchKernelGGL(scale_kernel, lin_grid(5 * N), dim3(256), 0, p->stream, 5 * N, 1.0, main, out);
+  WM_LAUNCH_CHECK("copy kernel");
+  hipLaunchKernelGGL(fill_kernel, lin_grid(3 * N), dim3(256), 0, p->stream, 3 * N, 0.0, out + 5 * N);
+  WM_LAUNCH_CHECK("fill kernel");
+  hipLaunchKernelGGL(adj_bcell_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, main + 5 * N, out + 5 * N);
+  WM_LAUNCH_CHECK("adjoint bcell kernel");
+  return WM_OK;
+}
+
+// forward stages U1, U2 from U^n with the dt in *dtp (device); U1, U2 = [hydro 5, b 3, bcell 3]
+wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double* Bz, const double* dtp, double* U1,
+                         double* U2, double* acc) {
+  const size_t N = p->g.N;
+  wm_status s;
+  if ((s = launch_bcell(p, Ub, Bz)) != WM_OK) return s;
+  for (int st = 0; st < 2; ++st) {
+    const double* hin = st == 0 ? Uh : U1;
+    const double* bcin = st == 0 ? Bz : U1 + 8 * N;
+    if ((s = sweeps(p, hin, bcin)) != WM_OK) return s;
+    UpdateArgs a;
+    a.g = p->g;
+    a.inv_h = 1.0 / p->cfg.h;
+    a.faces = p->faces();
+    a.Un = Uh;
+    a.bn = Ub;
+    a.acc = acc;
+    a.rhs_out = nullptr;
+    a.dt = dtp;
+    double* out = st == 0 ? U1 : U2;
+    a.hyd_out = out;
+    a.b_out = out + 5 * N;
+    if (st == 0) hipLaunchKernelGGL(update_kernel<0>, zone_grid(p->g), dim3(256), 0, p->stream, a);
+    else hipLaunchKernelGGL(update_kernel<1>, zone_grid(p->g), dim3(256), 0, p->stream, a);
+    WM_LAUNCH_CHECK("update kernel");
+    if ((s = launch_bcell(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
+  }
   return WM_OK;
 }
 
@@ -440,6 +564,113 @@ wm_status wm_debug_rhs(wm_patch* p, void* out) {
   if (!out) return fail(WM_ERR_ARG, "null output");
   if ((s = sweeps(p, p->hydro, p->bcell)) != WM_OK) return s;
   return launch_update(p, 0, reinterpret_cast<double*>(out));
+}
+
+size_t wm_adjoint_scratch_bytes(const wm_config* cfg) {
+  const char* why = "";
+  if (!valid_config(cfg, &why)) return 0;
+  return adjoint_bytes(cfg);
+}
+
+wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const void* bface, const void* lam_k,
+                     void* lam_out) {
+  wm_status s = check_adjoint(p, adj_scratch);
+  if (s != WM_OK) return s;
+  if (!hydro || !bface || !lam_k || !lam_out) return fail(WM_ERR_ARG, "null pointer");
+  return rhs_vjp(p, reinterpret_cast<double*>(adj_scratch), reinterpret_cast<const double*>(hydro),
+                 reinterpret_cast<const double*>(bface), reinterpret_cast<const double*>(lam_k),
+                 reinterpret_cast<double*>(lam_out));
+}
+
+wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface, double dt,
+                          void* lam_hydro, void* lam_bface) {
+  wm_status s = check_adjoint(p, adj_scratch);
+  if (s != WM_OK) return s;
+  if (!Un_hydro || !Un_bface || !lam_hydro || !lam_bface) return fail(WM_ERR_ARG, "null pointer");
+  if (!std::isfinite(dt)) return fail(WM_ERR_ARG, "dt is not finite");
+  const size_t N = p->g.N;
+  double* A = reinterpret_cast<double*>(adj_scratch);
+  double* dtp = A + A_NARR * N;
+  const double* Uh = reinterpret_cast<const double*>(Un_hydro);
+  const double* Ub = reinterpret_cast<const double*>(Un_bface);
+  double* lh = reinterpret_cast<double*>(lam_hydro);
+  double* lb = reinterpret_cast<double*>(lam_bface);
+  double* U1 = A + A_U1 * N;
+  double* U2 = A + A_U2 * N;
+  double* lk = A + A_LK * N;
+  double* lU2 = A + A_LU2 * N;
+  double* lU1 = A + A_LU1 * N;
+  double* w = A + A_WORK * N;
+  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
+  WM_LAUNCH_CHECK("set dt");
+  // the stage accumulator of the forward scratch is free outside wm_step
+  if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, U1, U2, p->acc())) != WM_OK) return s;
+  const dim3 g8 = lin_grid(8 * N), g5 = lin_grid(5 * N), g3 = lin_grid(3 * N);
+  // lam3 = (lh, lb) gathered into w
+  hipLaunchKernelGGL(scale_kernel, g5, dim3(256), 0, p->stream, 5 * N, 1.0, lh, w);
+  hipLaunchKernelGGL(scale_kernel, g3, dim3(256), 0, p->stream, 3 * N, 1.0, lb, w + 5 * N);
+  WM_LAUNCH_CHECK("copy kernel");
+  // k2 = L(U2), weight 4 dt/6
+  hipLaunchKernelGGL(scale_kernel, g8, dim3(256), 0, p->stream, 8 * N, 4.0 * dt / 6.0, w, lk);
+  WM_LAUNCH_CHECK("scale kernel");
+  if ((s = rhs_vjp(p, A, U2, U2 + 5 * N, lk, lU2)) != WM_OK) return s;
+  // k1 = L(U1): dt/6 lam3 + dt/4 lamU2
+  hipLaunchKernelGGL(axpby_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 6.0, w, 0.25 * dt, lU2, lk);
+  WM_LAUNCH_CHECK("axpby kernel");
+  if ((s = rhs_vjp(p, A, U1, U1 + 5 * N, lk, lU1)) != WM_OK) return s;
+  // k0 = L(U^n): dt/6 lam3 + dt/4 lamU2 + dt lamU1
+  hipLaunchKernelGGL(axpby_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 6.0, w, 0.25 * dt, lU2, lk);
+  hipLaunchKernelGGL(axpby_kernel, g8, dim3(256), 0, p->stream, 8 * N, 1.0, lk, dt, lU1, lk);
+  WM_LAUNCH_CHECK("axpby kernel");
+  // lam^n = lam3 + lamU2 + lamU1 + (dL/dU^n)^T lam_k0 (the rhs VJP result goes to lU2's slot after use)
+  hipLaunchKernelGGL(add_kernel, g8, dim3(256), 0, p->stream, 8 * N, lU2, w);
+  hipLaunchKernelGGL(add_kernel, g8, dim3(256), 0, p->stream, 8 * N, lU1, w);
+  WM_LAUNCH_CHECK("add kernel");
+  if ((s = rhs_vjp(p, A, Uh, Ub, lk, lU1)) != WM_OK) return s;
+  hipLaunchKernelGGL(add_kernel, g8, dim3(256), 0, p->stream, 8 * N, lU1, w);
+  WM_LAUNCH_CHECK("add kernel");
+  hipLaunchKernelGGL(scale_kernel, g5, dim3(256), 0, p->stream, 5 * N, 1.0, w, lh);
+  hipLaunchKernelGGL(scale_kernel, g3, dim3(256), 0, p->stream, 3 * N, 1.0, w + 5 * N, lb);
+  WM_LAUNCH_CHECK("copy kernel");
+  return WM_OK;
+}
+
+wm_status wm_zone_field_vjp(wm_patch* p, const void* lam_bcell, void* lam_bface) {
+  if (!p) return fail(WM_ERR_ARG, "null patch");
+  if (!lam_bcell || !lam_bface) return fail(WM_ERR_ARG, "null pointer");
+  hipLaunchKernelGGL(adj_bcell_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g,
+                     reinterpret_cast<const double*>(lam_bcell), reinterpret_cast<double*>(lam_bface));
+  WM_LAUNCH_CHECK("adjoint bcell kernel");
+  return WM_OK;
+}
+
+wm_status wm_init_adjoint(wm_patch* p, void* adj_scratch, const double* rho, const double* v, const double* A_edge,
+                          const double B0[3], const void* lam_hydro, const void* lam_bface, double* g_A,
+                          double* g_v) {
+  wm_status s = check_adjoint(p, adj_scratch);
+  if (s != WM_OK) return s;
+  if (!rho || !v || !A_edge || !B0 || !lam_hydro || !lam_bface || !g_A || !g_v) return fail(WM_ERR_ARG, "null pointer");
+  const size_t N = p->g.N;
+  double* A = reinterpret_cast<double*>(adj_scratch);
+  double* b0 = A + A_U1 * N;          // initial face field
+  double* B0z = A + A_U1 * N + 3 * N; // its zone interpolation
+  double* lB = A + A_WORK * N;        // zone-B cotangent
+  double* lb = A + A_WORK * N + 3 * N;  // total face-b cotangent
+  hipLaunchKernelGGL(init_b_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, A_edge, B0[0],
+                     B0[1], B0[2], b0);
+  WM_LAUNCH_CHECK("init_b kernel");
+  if ((s = launch_bcell(p, b0, B0z)) != WM_OK) return s;
+  hipLaunchKernelGGL(init_adj_zone_kernel, lin_grid(N), dim3(256), 0, p->stream, N, rho, v, B0z,
+                     reinterpret_cast<const double*>(lam_hydro), g_v, lB);
+  WM_LAUNCH_CHECK("init adjoint kernel");
+  hipLaunchKernelGGL(scale_kernel, lin_grid(3 * N), dim3(256), 0, p->stream, 3 * N, 1.0,
+                     reinterpret_cast<const double*>(lam_bface), lb);
+  WM_LAUNCH_CHECK("copy kernel");
+  hipLaunchKernelGGL(adj_bcell_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, lB, lb);
+  WM_LAUNCH_CHECK("adjoint bcell kernel");
+  hipLaunchKernelGGL(curl_adj_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, lb, g_A);
+  WM_LAUNCH_CHECK("curl adjoint kernel");
+  return WM_OK;
 }
 
 wm_status wm_profile(wm_patch* p, int enable) {

@@ -1,0 +1,69 @@
+"""Differentiable rollout: n SSP-RK3 steps from an initial vector potential and
+velocity, as a ``torch.autograd.Function`` whose backward runs the hand-written
+adjoint of the HIP library (``wm_adjoint_step``, ``wm_init_adjoint``).
+
+Memory: the forward keeps a checkpoint of the state every ``ckpt_every`` steps;
+the backward re-runs each segment forward from its checkpoint, keeping that
+segment's states, and walks it in reverse.  The time steps of the forward pass
+are recorded and held fixed in the backward (dt is not differentiated).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+class Rollout(torch.autograd.Function):
+    """outputs = (hydro_T [5, ...], bface_T [3, ...], bcell_T [3, ...]) after
+    ``nsteps`` steps from init_from_potential(rho, v, A, P0, B0)."""
+
+    @staticmethod
+    def forward(ctx, A, v, rho, patch: B.Patch, nsteps: int, ckpt_every: int, P0: float, B0):
+        with torch.no_grad():
+            patch.init_from_potential(rho, v, A, P0, B0)
+            ckpts, dts = [], []
+            for n in range(nsteps):
+                if n % ckpt_every == 0:
+                    ckpts.append((patch.hydro.clone(), patch.bface.clone()))
+                dts.append(patch.step(want_dt=True))
+            out = (patch.hydro.clone(), patch.bface.clone(), patch.bcell.clone())
+        ctx.patch, ctx.nsteps, ctx.ckpt_every = patch, nsteps, ckpt_every
+        ctx.ckpts, ctx.dts, ctx.P0, ctx.B0 = ckpts, dts, P0, B0
+        ctx.save_for_backward(A, v, rho)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_hydro, g_bface, g_bcell):
+        A, v, rho = ctx.saved_tensors
+        p = ctx.patch
+        shape = p.shape
+        dev = p.device
+        with torch.no_grad():
+            lam_h = (g_hydro if g_hydro is not None else torch.zeros((5,) + shape, dtype=torch.float64, device=dev))
+            lam_b = (g_bface if g_bface is not None else torch.zeros((3,) + shape, dtype=torch.float64, device=dev))
+            lam_h = lam_h.to(dev, torch.float64).contiguous().clone()
+            lam_b = lam_b.to(dev, torch.float64).contiguous().clone()
+            if g_bcell is not None:
+                p.zone_field_vjp(g_bcell.to(dev, torch.float64), lam_b)
+            n_seg = len(ctx.ckpts)
+            for sgi in range(n_seg - 1, -1, -1):
+                n0 = sgi * ctx.ckpt_every
+                n1 = min(n0 + ctx.ckpt_every, ctx.nsteps)
+                h0, b0 = ctx.ckpts[sgi]
+                # recompute the segment's states from its checkpoint with the recorded dts
+                p.set_state(h0[0], h0[1:4], h0[4], b0)
+                states = []
+                for n in range(n0, n1):
+                    states.append((p.hydro.clone(), p.bface.clone()))
+                    if n + 1 < n1:
+                        p.step_dt(ctx.dts[n])
+                for n in range(n1 - 1, n0 - 1, -1):
+                    Uh, Ub = states[n - n0]
+                    p.adjoint_step(Uh, Ub, ctx.dts[n], lam_h, lam_b)
+            gA, gv = p.init_adjoint(rho, v, A, ctx.B0, lam_h, lam_b)
+        return gA, gv, None, None, None, None, None, None
+
+
+def rollout(A, v, rho, patch: B.Patch, nsteps: int, ckpt_every: int = 5, P0: float = 0.6, B0=(1.0, 0.5, 0.0)):
+    return Rollout.apply(A, v, rho, patch, nsteps, ckpt_every, P0, B0)
