@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwenomhd.so")
 SOURCES = [os.path.join(CSRC, "wenomhd.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "mhd_device.hpp")] + [
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "mhd_device.hpp", "adjoint_device.hpp", "adjoint_kernels.hpp")] + [
     os.path.join(os.path.dirname(HERE), "include", "wenomhd.h")]
 
 # Packed FP32 instructions are disabled for all device code; FMA contraction

@@ -51,6 +51,26 @@ __host__ __device__ __forceinline__ void phiN_grad(double a, double b, double c,
 // ---------------------------------------------------------------------------
 // face eigen-system scalars: cotangents of the FaceEig members -> face state
 // ---------------------------------------------------------------------------
+// Materialises x in a register at this point of the program: the compiler may
+// not sink the computation of x past it (without this, the terms of the
+// cotangent sums below are kept live until their final use and spill).
+__host__ __device__ __forceinline__ void pin(double& x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  asm volatile("" : "+v"(x));
+#else
+  (void)x;
+#endif
+}
+
+// Compiler-level memory clobber: loads after it are not merged with loads
+// before it (re-reading the differences from LDS is cheaper than keeping them
+// live in registers).
+__host__ __device__ __forceinline__ void reload_fence() {
+#ifdef __HIP_DEVICE_COMPILE__
+  asm volatile("" ::: "memory");
+#endif
+}
+
 struct FaceEigBar {
   double vn, vt1, vt2, Bt1, Bt2;
   double a2, cs, sr, isr, cf, cf2, csl, csl2;
@@ -60,11 +80,22 @@ struct FaceEigBar {
     vn = vt1 = vt2 = Bt1 = Bt2 = a2 = cs = sr = isr = cf = cf2 = csl = csl2 = 0.0;
     by = bz = af = as = v2 = Gf = Ga = Gs = qa2 = tau = 0.0;
   }
+  // pin_*: the members that the reverse of one pair writes
+  __host__ __device__ __forceinline__ void pin_fast_slow_common() {
+    pin(vn); pin(vt1); pin(vt2); pin(Bt1); pin(Bt2); pin(a2); pin(cs); pin(sr); pin(isr); pin(cf); pin(csl);
+    pin(by); pin(bz); pin(af); pin(as); pin(v2); pin(qa2);
+  }
+  __host__ __device__ __forceinline__ void pin_fast() { pin_fast_slow_common(); pin(cf2); pin(Gf); }
+  __host__ __device__ __forceinline__ void pin_slow() { pin_fast_slow_common(); pin(csl2); pin(Gs); }
+  __host__ __device__ __forceinline__ void pin_alfven() { pin(bz); pin(by); pin(isr); pin(Ga); pin(sr); }
+  __host__ __device__ __forceinline__ void pin_entropy() {
+    pin(vn); pin(vt1); pin(vt2); pin(v2); pin(Bt1); pin(Bt2); pin(tau);
+  }
 };
 
 // Reverse of face_eig: out[0..7] += d/d(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P).
-__host__ __device__ inline void face_eig_vjp(const double fp[8], const Phys& ph, const FaceEig& e, FaceEigBar eb,
-                                             double out[8]) {
+__host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const Phys& ph, const FaceEig& e,
+                                                      FaceEigBar eb, double out[8]) {
   const double rho = fp[0], vn = fp[1], vt1 = fp[2], vt2 = fp[3], Bn = fp[4], Bt1 = fp[5], Bt2 = fp[6], P = fp[7];
   const double gamma = ph.gamma;
   const double isr = 1.0 / sqrt(rho);
@@ -158,104 +189,186 @@ __host__ __device__ inline void face_eig_vjp(const double fp[8], const Phys& ph,
 }
 
 // ---------------------------------------------------------------------------
-// one eigen pair: forward recompute + reverse
+// phi_N with its gradient (same quantities as phiN_grad, plus the value
+// phi = omega_0 X/3 + (omega_2 - 1/2) Y/6)
 // ---------------------------------------------------------------------------
-// Forward of a pair with left rows S + A (upper) and S - A (lower), A nonzero
-// in components 0..3, as split_pair/weno_split compute it, then the reverse
-// for cotangents lfu, lfl of f_upper = phi^- - phi^+ and f_lower.  Produces the
-// cotangents of S, A, the LF speeds, and calls emit(k, lD[14]) with the
-// cotangent of interface difference k (j = 0..6 Delta F, 7..13 Delta q).
-template <class DL, class EMIT>
-__host__ __device__ __forceinline__ void pair_vjp(const double S[7], const double A[4], double alu, double all,
-                                                  DL dl, double eps, double& fu, double& fl, double lfu, double lfl,
-                                                  bool backward, double lS[7], double lA[4], double& lalu,
+__host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, double c, double d, double eps,
+                                                       double& val, double gr[4]) {
+  const double t0 = a - b, t1 = a - 3.0 * b;
+  const double t2 = b - c, t3 = b + c;
+  const double t4 = c - d, t5 = 3.0 * c - d;
+  const double s0 = eps + 13.0 * t0 * t0 + 3.0 * t1 * t1;
+  const double s1 = eps + 13.0 * t2 * t2 + 3.0 * t3 * t3;
+  const double s2 = eps + 13.0 * t4 * t4 + 3.0 * t5 * t5;
+  // 1/s_k from one reciprocal of s0 s1 s2 (s_k >= eps, so the product stays normal)
+  const double s12 = s1 * s2, r = rcp_w(s0 * s12);
+  const double i0 = s12 * r, i1 = s0 * s2 * r, i2 = s0 * s1 * r;
+  const double al0 = i0 * i0, al1 = 6.0 * i1 * i1, al2 = 3.0 * i2 * i2;
+  const double isum = rcp_w(al0 + al1 + al2);
+  const double w0 = al0 * isum, w1 = al1 * isum, w2 = al2 * isum;
+  const double X = a - 2.0 * b + c, Y = b - 2.0 * c + d;
+  const double g = X * (1.0 / 3.0), h = Y * (1.0 / 6.0);
+  const double W = g * w0 + h * w2;
+  const double l0 = 2.0 * w0 * i0 * (W - g);
+  const double l1 = 2.0 * w1 * i1 * W;
+  const double l2 = 2.0 * w2 * i2 * (W - h);
+  const double cX = w0 * (1.0 / 3.0), cY = (w2 - 0.5) * (1.0 / 6.0);
+  val = cX * X + cY * Y;
+  gr[0] = cX + l0 * (26.0 * t0 + 6.0 * t1);
+  gr[1] = -2.0 * cX + cY + l0 * (-26.0 * t0 - 18.0 * t1) + l1 * (26.0 * t2 + 6.0 * t3);
+  gr[2] = cX - 2.0 * cY + l1 * (-26.0 * t2 + 6.0 * t3) + l2 * (26.0 * t4 + 18.0 * t5);
+  gr[3] = cY + l2 * (-26.0 * t4 - 6.0 * t5);
+}
+
+// ---------------------------------------------------------------------------
+// one eigen pair, forward and reverse in a single pass
+// ---------------------------------------------------------------------------
+// Rows: upper S + A, lower S - A, where A is nonzero on components
+// A0 .. A0+NA-1 and S on the components set in SMASK (TWO = false: the upper
+// row S alone).  Split values as in
+// split_pair, f = phi(v7, v6, v5, v4) - phi(v0, v1, v2, v3) per row.  The
+// cotangents lfu, lfl of the two f are known beforehand (they only involve the
+// right eigenvectors), so the pass computes f (returned for the right-vector
+// cotangents), adds the cotangents of S, A and of the two Lax-Friedrichs
+// speeds, and hands emit(k, lD[14]) the cotangent of interface difference k
+// (j = 0..6 Delta F, 7..13 Delta q).
+template <int A0, int NA, bool TWO, int SMASK, class DL, class EMIT>
+__host__ __device__ __forceinline__ void pair_rev(const double S[7], const double A[4], double alu, double all,
+                                                  double lfu, double lfl, DL dl, double eps, double& fu,
+                                                  double& fl, double lS[7], double lA[4], double& lalu,
                                                   double& lall, EMIT emit) {
-  double uF[5], uq[5], lF[5], lq[5];
+  double vu[8], vl[8], uq[5], lq[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     double sF = 0.0, sq = 0.0, aF = 0.0, aq = 0.0;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) { sF += S[j] * dl(j, k); sq += S[j] * dl(7 + j, k); }
+    for (int j = 0; j < 7; ++j)
+      if (SMASK & (1 << j)) { sF += S[j] * dl(j, k); sq += S[j] * dl(7 + j, k); }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) { aF += A[j] * dl(j, k); aq += A[j] * dl(7 + j, k); }
-    uF[k] = sF + aF; uq[k] = sq + aq; lF[k] = sF - aF; lq[k] = sq - aq;
+    for (int j = 0; j < NA; ++j) { aF += A[j] * dl(A0 + j, k); aq += A[j] * dl(7 + A0 + j, k); }
+    const double uF = sF + aF, lF = sF - aF;
+    uq[k] = sq + aq;
+    lq[k] = sq - aq;
+    if (k <= 3) { vu[k] = uF + alu * uq[k]; vl[k] = lF + all * lq[k]; }
+    if (k >= 1) { vu[3 + k] = uF - alu * uq[k]; vl[3 + k] = lF - all * lq[k]; }
   }
-  double vu[8], vl[8];
+  double lPu[5], lQu[5], lPl[5], lQl[5];
+  {
+    double gu[8], g4[4], pa, pb;
+    phiN_val_grad(vu[7], vu[6], vu[5], vu[4], eps, pa, g4);
+    gu[7] = g4[0] * lfu; gu[6] = g4[1] * lfu; gu[5] = g4[2] * lfu; gu[4] = g4[3] * lfu;
+    phiN_val_grad(vu[0], vu[1], vu[2], vu[3], eps, pb, g4);
+    gu[0] = -g4[0] * lfu; gu[1] = -g4[1] * lfu; gu[2] = -g4[2] * lfu; gu[3] = -g4[3] * lfu;
+    fu = pa - pb;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) { vu[k] = uF[k] + alu * uq[k]; vl[k] = lF[k] + all * lq[k]; }
+    for (int k = 0; k < 5; ++k) {
+      const double pk = k <= 3 ? gu[k] : 0.0, mk = k >= 1 ? gu[3 + k] : 0.0;
+      lPu[k] = pk + mk;
+      lQu[k] = alu * (pk - mk);
+      lalu += uq[k] * (pk - mk);
+    }
+  }
+  if (TWO) {
+    double gl[8], g4[4], pa, pb;
+    phiN_val_grad(vl[7], vl[6], vl[5], vl[4], eps, pa, g4);
+    gl[7] = g4[0] * lfl; gl[6] = g4[1] * lfl; gl[5] = g4[2] * lfl; gl[4] = g4[3] * lfl;
+    phiN_val_grad(vl[0], vl[1], vl[2], vl[3], eps, pb, g4);
+    gl[0] = -g4[0] * lfl; gl[1] = -g4[1] * lfl; gl[2] = -g4[2] * lfl; gl[3] = -g4[3] * lfl;
+    fl = pa - pb;
 #pragma unroll
-  for (int k = 1; k < 5; ++k) { vu[3 + k] = uF[k] - alu * uq[k]; vl[3 + k] = lF[k] - all * lq[k]; }
-  fu = weno_split<false>(vu, eps, 0.0);
-  fl = weno_split<false>(vl, eps, 0.0);
-  if (!backward) return;
-  // f = phi(v7, v6, v5, v4) - phi(v0, v1, v2, v3)
-  double gu[8], gl[8], g4[4];
-  phiN_grad(vu[7], vu[6], vu[5], vu[4], eps, g4);
-  gu[7] = g4[0] * lfu; gu[6] = g4[1] * lfu; gu[5] = g4[2] * lfu; gu[4] = g4[3] * lfu;
-  phiN_grad(vu[0], vu[1], vu[2], vu[3], eps, g4);
-  gu[0] = -g4[0] * lfu; gu[1] = -g4[1] * lfu; gu[2] = -g4[2] * lfu; gu[3] = -g4[3] * lfu;
-  phiN_grad(vl[7], vl[6], vl[5], vl[4], eps, g4);
-  gl[7] = g4[0] * lfl; gl[6] = g4[1] * lfl; gl[5] = g4[2] * lfl; gl[4] = g4[3] * lfl;
-  phiN_grad(vl[0], vl[1], vl[2], vl[3], eps, g4);
-  gl[0] = -g4[0] * lfl; gl[1] = -g4[1] * lfl; gl[2] = -g4[2] * lfl; gl[3] = -g4[3] * lfl;
+    for (int k = 0; k < 5; ++k) {
+      const double pk = k <= 3 ? gl[k] : 0.0, mk = k >= 1 ? gl[3 + k] : 0.0;
+      lPl[k] = pk + mk;
+      lQl[k] = all * (pk - mk);
+      lall += lq[k] * (pk - mk);
+    }
+  } else {
+    fl = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { lPl[k] = 0.0; lQl[k] = 0.0; }
+  }
+  // cotangents of the rows (reads of the differences, no synchronisation) ...
+  reload_fence();
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double pu = k <= 3 ? gu[k] : 0.0, mu = k >= 1 ? gu[3 + k] : 0.0;
-    const double pl = k <= 3 ? gl[k] : 0.0, ml = k >= 1 ? gl[3 + k] : 0.0;
-    const double luF = pu + mu, luq = alu * (pu - mu);
-    const double llF = pl + ml, llq = all * (pl - ml);
-    lalu += uq[k] * (pu - mu);
-    lall += lq[k] * (pl - ml);
-    // uF = (S + A).dF, lF = (S - A).dF
-    const double sFb = luF + llF, aFb = luF - llF, sqb = luq + llq, aqb = luq - llq;
+    const double sFb = lPu[k] + lPl[k], aFb = lPu[k] - lPl[k];
+    const double sqb = lQu[k] + lQl[k], aqb = lQu[k] - lQl[k];
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+      if (SMASK & (1 << j)) lS[j] += sFb * dl(j, k) + sqb * dl(7 + j, k);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) lA[j] += aFb * dl(A0 + j, k) + aqb * dl(7 + A0 + j, k);
+    sched_fence();
+  }
+#pragma unroll
+  for (int j = 0; j < 7; ++j)
+    if (SMASK & (1 << j)) pin(lS[j]);
+#pragma unroll
+  for (int j = 0; j < NA; ++j) pin(lA[j]);
+  // ... then those of the interface differences, one barrier-separated round per k
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double sFb = lPu[k] + lPl[k], aFb = lPu[k] - lPl[k];
+    const double sqb = lQu[k] + lQl[k], aqb = lQu[k] - lQl[k];
     double lD[14];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-      lS[j] += sFb * dl(j, k) + sqb * dl(7 + j, k);
-      lD[j] = S[j] * sFb;
-      lD[7 + j] = S[j] * sqb;
+      lD[j] = (SMASK & (1 << j)) ? S[j] * sFb : 0.0;
+      lD[7 + j] = (SMASK & (1 << j)) ? S[j] * sqb : 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      lA[j] += aFb * dl(j, k) + aqb * dl(7 + j, k);
-      lD[j] += A[j] * aFb;
-      lD[7 + j] += A[j] * aqb;
+    for (int j = 0; j < NA; ++j) {
+      lD[A0 + j] += A[j] * aFb;
+      lD[7 + A0 + j] += A[j] * aqb;
     }
     emit(k, lD);
   }
 }
 
-// Full reverse of face_corr (FP64): given the face state fp, LF speeds al,
-// differences dl and the cotangent lam[7] of corr, accumulates the cotangents
-// of the face state (lfp[8]), of the LF speeds (lal[7]) and, via emit, of the
-// interface differences.
-template <class DL, class EMIT>
-__host__ __device__ inline void face_corr_vjp(const double fp[8], const double al[7], DL dl, const Phys& ph,
-                                              const double lam[7], double lfp[8], double lal[7], EMIT emit) {
-  FaceEig e;
-  face_eig(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], fp[6], fp[7], ph, e);
-  FaceEigBar eb;
-  eb.zero();
-  const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs;
-  const double s = e.s;
-  double fu, fl;
+// Reverse of face_corr (FP64) at one face: given the eigen scalars e, the
+// Lax-Friedrichs speeds alf(m), the differences dl and the cotangent lamf(j)
+// of corr, accumulates the cotangents of the eigen scalars (eb), of the LF
+// speeds (lal[7]) and, via emit, of the interface differences.  The face-state
+// cotangents follow from face_eig_vjp(eb).  PAIRS selects the eigen pairs
+// (bits: 1 fast, 2 slow, 4 Alfven, 8 entropy); the contributions of disjoint
+// selections add up to the full reverse, since corr is a sum over the pairs.
+// The eigen scalars are not kept live across a pair's reverse: reeig()
+// recomputes them from the face state after it (register pressure), and e
+// holds them on return.
+template <int PAIRS, class EIG, class ALF, class LAM, class DL, class EMIT>
+__host__ __device__ __forceinline__ void face_corr_vjp(FaceEig& e, EIG reeig, ALF alf, LAM lamf, DL dl,
+                                                       const Phys& ph, FaceEigBar& eb, double lal[7], EMIT emit) {
   // ---------------- fast pair (m = 1, 7)
-  {
+  if (PAIRS & 1) {
+    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
+    double fu, fl;
+    {
+      const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
+      const double t[7] = {e.af * e.g1 * e.v2, omg * e.af * e.vn, omg * e.af * e.vt1, omg * e.af * e.vt2,
+                           omg * e.af * e.Bt1 + sra * e.as * e.by, omg * e.af * e.Bt2 + sra * e.as * e.bz, gm1 * e.af};
+      const double u[4] = {e.Gf, -(e.af * e.cf), e.csl * e.as * e.by * s, e.csl * e.as * e.bz * s};
+      double S[7], A[4];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
+      const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
+      const double Rs6 = e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2);
+      // corr[0..6] = af sp; af vn sp - af cf sm; af vt1 sp + csl as by s sm; af vt2 sp + csl as bz s sm;
+      //              cs as by isr sp; cs as bz isr sp; Rs6 sp - Gf sm
+      const double lsp = e.af * lam[0] + e.af * e.vn * lam[1] + e.af * e.vt1 * lam[2] + e.af * e.vt2 * lam[3] +
+                         e.cs * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
+      const double lsm = -e.af * e.cf * lam[1] + e.csl * e.as * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gf * lam[6];
+      pair_rev<0, 4, true, 127>(S, A, alf(0), alf(6), lsp + lsm, lsp - lsm, dl, ph.eps, fu, fl, lS, lA, lal[0],
+                                lal[6], emit);
+    }
+    e = reeig();
+    const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
     const double t[7] = {e.af * e.g1 * e.v2, omg * e.af * e.vn, omg * e.af * e.vt1, omg * e.af * e.vt2,
                          omg * e.af * e.Bt1 + sra * e.as * e.by, omg * e.af * e.Bt2 + sra * e.as * e.bz, gm1 * e.af};
     const double u[4] = {e.Gf, -(e.af * e.cf), e.csl * e.as * e.by * s, e.csl * e.as * e.bz * s};
-    double S[7], A[4];
-    for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
-    for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
-    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
-    pair_vjp(S, A, al[0], al[6], dl, ph.eps, fu, fl, 0.0, 0.0, false, lS, lA, lal[0], lal[6], emit);
+    const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
     const double sp = fu + fl, sm = fu - fl;
-    const double Rs6 = e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2);
-    // corr[0..6] = af sp; af vn sp - af cf sm; af vt1 sp + csl as by s sm; af vt2 sp + csl as bz s sm;
-    //              cs as by isr sp; cs as bz isr sp; Rs6 sp - Gf sm
-    const double lsp = e.af * lam[0] + e.af * e.vn * lam[1] + e.af * e.vt1 * lam[2] + e.af * e.vt2 * lam[3] +
-                       e.cs * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
-    const double lsm = -e.af * e.cf * lam[1] + e.csl * e.as * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gf * lam[6];
     eb.af += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
                    (0.5 * e.v2 + e.cf2 - e.g2 * e.a2) * lam[6]) - sm * e.cf * lam[1];
     eb.vn += e.af * sp * lam[1]; eb.vt1 += e.af * sp * lam[2]; eb.vt2 += e.af * sp * lam[3];
@@ -268,11 +381,11 @@ __host__ __device__ inline void face_corr_vjp(const double fp[8], const double a
     eb.cs += sp * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]);
     eb.isr += sp * e.cs * e.as * (e.by * lam[4] + e.bz * lam[5]);
     eb.Gf -= sm * lam[6];
-    const double lfu = lsp + lsm, lfl = lsp - lsm;
-    pair_vjp(S, A, al[0], al[6], dl, ph.eps, fu, fl, lfu, lfl, true, lS, lA, lal[0], lal[6], emit);
     // rows S = qa2 t, A = qa2 u
     double lt[7], lu[4];
+#pragma unroll
     for (int j = 0; j < 7; ++j) { eb.qa2 += lS[j] * t[j]; lt[j] = qa2 * lS[j]; }
+#pragma unroll
     for (int j = 0; j < 4; ++j) { eb.qa2 += lA[j] * u[j]; lu[j] = qa2 * lA[j]; }
     eb.af += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
                                           lt[5] * e.Bt2) + gm1 * lt[6];
@@ -289,23 +402,40 @@ __host__ __device__ inline void face_corr_vjp(const double fp[8], const double a
     eb.as += e.csl * s * (lu[2] * e.by + lu[3] * e.bz);
     eb.by += e.csl * e.as * s * lu[2]; eb.bz += e.csl * e.as * s * lu[3];
   }
+  if (PAIRS & 1) eb.pin_fast();
+  if (PAIRS & 1) { pin(lal[0]); pin(lal[6]); }
+  sched_fence();
   // ---------------- slow pair (m = 3, 5)
-  {
+  if (PAIRS & 2) {
+    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
+    double fu, fl;
+    {
+      const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
+      const double t[7] = {e.as * e.g1 * e.v2, omg * e.as * e.vn, omg * e.as * e.vt1, omg * e.as * e.vt2,
+                           omg * e.as * e.Bt1 - sra * e.af * e.by, omg * e.as * e.Bt2 - sra * e.af * e.bz, gm1 * e.as};
+      const double u[4] = {e.Gs, -(e.as * e.csl), -(e.cf * e.af * e.by * s), -(e.cf * e.af * e.bz * s)};
+      double S[7], A[4];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
+      const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
+      const double Rs6 = e.as * (0.5 * e.v2 + e.csl2 - e.g2 * e.a2);
+      // corr += as sp; as vn sp - as csl sm; as vt1 sp - cf af by s sm; as vt2 sp - cf af bz s sm;
+      //         -cs af by isr sp; -cs af bz isr sp; Rs6 sp - Gs sm
+      const double lsp = e.as * lam[0] + e.as * e.vn * lam[1] + e.as * e.vt1 * lam[2] + e.as * e.vt2 * lam[3] -
+                         e.cs * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
+      const double lsm = -e.as * e.csl * lam[1] - e.cf * e.af * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gs * lam[6];
+      pair_rev<0, 4, true, 127>(S, A, alf(2), alf(4), lsp + lsm, lsp - lsm, dl, ph.eps, fu, fl, lS, lA, lal[2],
+                                lal[4], emit);
+    }
+    e = reeig();
+    const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
     const double t[7] = {e.as * e.g1 * e.v2, omg * e.as * e.vn, omg * e.as * e.vt1, omg * e.as * e.vt2,
                          omg * e.as * e.Bt1 - sra * e.af * e.by, omg * e.as * e.Bt2 - sra * e.af * e.bz, gm1 * e.as};
     const double u[4] = {e.Gs, -(e.as * e.csl), -(e.cf * e.af * e.by * s), -(e.cf * e.af * e.bz * s)};
-    double S[7], A[4];
-    for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
-    for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
-    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
-    pair_vjp(S, A, al[2], al[4], dl, ph.eps, fu, fl, 0.0, 0.0, false, lS, lA, lal[2], lal[4], emit);
+    const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
     const double sp = fu + fl, sm = fu - fl;
-    const double Rs6 = e.as * (0.5 * e.v2 + e.csl2 - e.g2 * e.a2);
-    // corr += as sp; as vn sp - as csl sm; as vt1 sp - cf af by s sm; as vt2 sp - cf af bz s sm;
-    //         -cs af by isr sp; -cs af bz isr sp; Rs6 sp - Gs sm
-    const double lsp = e.as * lam[0] + e.as * e.vn * lam[1] + e.as * e.vt1 * lam[2] + e.as * e.vt2 * lam[3] -
-                       e.cs * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
-    const double lsm = -e.as * e.csl * lam[1] - e.cf * e.af * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gs * lam[6];
     eb.as += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
                    (0.5 * e.v2 + e.csl2 - e.g2 * e.a2) * lam[6]) - sm * e.csl * lam[1];
     eb.vn += e.as * sp * lam[1]; eb.vt1 += e.as * sp * lam[2]; eb.vt2 += e.as * sp * lam[3];
@@ -318,10 +448,10 @@ __host__ __device__ inline void face_corr_vjp(const double fp[8], const double a
     eb.cs -= sp * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]);
     eb.isr -= sp * e.cs * e.af * (e.by * lam[4] + e.bz * lam[5]);
     eb.Gs -= sm * lam[6];
-    const double lfu = lsp + lsm, lfl = lsp - lsm;
-    pair_vjp(S, A, al[2], al[4], dl, ph.eps, fu, fl, lfu, lfl, true, lS, lA, lal[2], lal[4], emit);
     double lt[7], lu[4];
+#pragma unroll
     for (int j = 0; j < 7; ++j) { eb.qa2 += lS[j] * t[j]; lt[j] = qa2 * lS[j]; }
+#pragma unroll
     for (int j = 0; j < 4; ++j) { eb.qa2 += lA[j] * u[j]; lu[j] = qa2 * lA[j]; }
     eb.as += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
                                           lt[5] * e.Bt2) + gm1 * lt[6];
@@ -338,62 +468,65 @@ __host__ __device__ inline void face_corr_vjp(const double fp[8], const double a
     eb.af -= e.cf * s * (lu[2] * e.by + lu[3] * e.bz);
     eb.by -= e.cf * e.af * s * lu[2]; eb.bz -= e.cf * e.af * s * lu[3];
   }
+  if (PAIRS & 2) eb.pin_slow();
+  if (PAIRS & 2) { pin(lal[2]); pin(lal[4]); }
+  sched_fence();
   // ---------------- Alfven pair (m = 2, 6): S = (Ga/4, 0, -bz s/4, by s/4, 0, 0, 0),
-  //                  A = (0, 0, 0, 0, -sr bz/4, sr by/4) (A on components 4, 5)
-  {
-    const double S[7] = {0.25 * e.Ga, 0.0, -0.25 * e.bz * s, 0.25 * e.by * s, 0.0, 0.0, 0.0};
-    const double A45[2] = {-0.25 * e.sr * e.bz, 0.25 * e.sr * e.by};
-    // forward in the same form as face_corr (A on 4, 5): reuse pair_vjp with A folded into S
-    // of two separate rows (upper = S + A, lower = S - A, full 7-vectors, A part zero on 0..3)
-    double Su[7], Sl[7];
-    for (int j = 0; j < 7; ++j) { Su[j] = S[j]; Sl[j] = S[j]; }
-    Su[4] += A45[0]; Su[5] += A45[1]; Sl[4] -= A45[0]; Sl[5] -= A45[1];
-    const double Z4[4] = {0.0, 0.0, 0.0, 0.0};
-    double lSu[7] = {0, 0, 0, 0, 0, 0, 0}, lSl[7] = {0, 0, 0, 0, 0, 0, 0}, lz[4] = {0, 0, 0, 0};
-    double f1, f2, dummy;
-    pair_vjp(Su, Z4, al[1], al[1], dl, ph.eps, fu, f1, 0.0, 0.0, false, lSu, lz, dummy, dummy, emit);
-    pair_vjp(Sl, Z4, al[5], al[5], dl, ph.eps, fl, f2, 0.0, 0.0, false, lSl, lz, dummy, dummy, emit);
+  //                  A = (-sr bz/4, sr by/4) on components 4, 5
+  if (PAIRS & 4) {
+    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
+    double fu, fl;
+    {
+      const double s = e.s;
+      const double S[7] = {0.25 * e.Ga, 0.0, -0.25 * e.bz * s, 0.25 * e.by * s, 0.0, 0.0, 0.0};
+      const double A[4] = {-0.25 * e.sr * e.bz, 0.25 * e.sr * e.by, 0.0, 0.0};
+      const double lam2 = lamf(2), lam3 = lamf(3), lam4 = lamf(4), lam5 = lamf(5), lam6 = lamf(6);
+      // corr += (0, 0, -bz s sp, by s sp, -bz isr sm, by isr sm, -Ga sp)
+      const double lsp = -e.bz * s * lam2 + e.by * s * lam3 - e.Ga * lam6;
+      const double lsm = -e.bz * e.isr * lam4 + e.by * e.isr * lam5;
+      pair_rev<4, 2, true, 13>(S, A, alf(1), alf(5), lsp + lsm, lsp - lsm, dl, ph.eps, fu, fl, lS, lA, lal[1],
+                               lal[5], emit);
+    }
+    e = reeig();
+    const double s = e.s;
+    const double lam2 = lamf(2), lam3 = lamf(3), lam4 = lamf(4), lam5 = lamf(5), lam6 = lamf(6);
     const double sp = fu + fl, sm = fu - fl;
-    // corr += (0, 0, -bz s sp, by s sp, -bz isr sm, by isr sm, -Ga sp)
-    const double lsp = -e.bz * s * lam[2] + e.by * s * lam[3] - e.Ga * lam[6];
-    const double lsm = -e.bz * e.isr * lam[4] + e.by * e.isr * lam[5];
-    eb.bz += -s * sp * lam[2] - e.isr * sm * lam[4];
-    eb.by += s * sp * lam[3] + e.isr * sm * lam[5];
-    eb.isr += sm * (-e.bz * lam[4] + e.by * lam[5]);
-    eb.Ga -= sp * lam[6];
-    const double lfu = lsp + lsm, lfl = lsp - lsm;
-    double lal_dummy = 0.0;
-    pair_vjp(Su, Z4, al[1], al[1], dl, ph.eps, fu, f1, lfu, 0.0, true, lSu, lz, lal[1], lal_dummy, emit);
-    pair_vjp(Sl, Z4, al[5], al[5], dl, ph.eps, fl, f2, lfl, 0.0, true, lSl, lz, lal[5], lal_dummy, emit);
-    const double lS0 = lSu[0] + lSl[0], lS2 = lSu[2] + lSl[2], lS3 = lSu[3] + lSl[3];
-    const double lA4 = lSu[4] - lSl[4], lA5 = lSu[5] - lSl[5];
-    eb.Ga += 0.25 * lS0;
-    eb.bz += -0.25 * s * lS2 - 0.25 * e.sr * lA4;
-    eb.by += 0.25 * s * lS3 + 0.25 * e.sr * lA5;
-    eb.sr += -0.25 * e.bz * lA4 + 0.25 * e.by * lA5;
+    eb.bz += -s * sp * lam2 - e.isr * sm * lam4;
+    eb.by += s * sp * lam3 + e.isr * sm * lam5;
+    eb.isr += sm * (-e.bz * lam4 + e.by * lam5);
+    eb.Ga -= sp * lam6;
+    eb.Ga += 0.25 * lS[0];
+    eb.bz += -0.25 * s * lS[2] - 0.25 * e.sr * lA[0];
+    eb.by += 0.25 * s * lS[3] + 0.25 * e.sr * lA[1];
+    eb.sr += -0.25 * e.bz * lA[0] + 0.25 * e.by * lA[1];
   }
+  if (PAIRS & 4) eb.pin_alfven();
+  if (PAIRS & 4) { pin(lal[1]); pin(lal[5]); }
+  sched_fence();
   // ---------------- entropy (m = 4): L/2 = (1/2 - tau v^2/4, tau vn/2, tau vt1/2, tau vt2/2, tau Bt1/2, tau Bt2/2, -tau/2)
-  {
-    const double ht = 0.5 * e.tau;
-    const double l[7] = {0.5 - 0.5 * ht * e.v2, ht * e.vn, ht * e.vt1, ht * e.vt2, ht * e.Bt1, ht * e.Bt2, -ht};
-    const double Z4[4] = {0.0, 0.0, 0.0, 0.0};
+  if (PAIRS & 8) {
     double ll[7] = {0, 0, 0, 0, 0, 0, 0}, lz[4] = {0, 0, 0, 0};
     double f4, f5, dummy = 0.0;
-    pair_vjp(l, Z4, al[3], al[3], dl, ph.eps, f4, f5, 0.0, 0.0, false, ll, lz, dummy, dummy, emit);
-    // corr += (f4, vn f4, vt1 f4, vt2 f4, 0, 0, v2/2 f4)
-    const double lf4 = lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] + 0.5 * e.v2 * lam[6];
-    eb.vn += f4 * lam[1]; eb.vt1 += f4 * lam[2]; eb.vt2 += f4 * lam[3]; eb.v2 += 0.5 * f4 * lam[6];
-    double lal_dummy = 0.0;
-    pair_vjp(l, Z4, al[3], al[3], dl, ph.eps, f4, f5, lf4, 0.0, true, ll, lz, lal[3], lal_dummy, emit);
+    {
+      const double ht = 0.5 * e.tau;
+      const double l[7] = {0.5 - 0.5 * ht * e.v2, ht * e.vn, ht * e.vt1, ht * e.vt2, ht * e.Bt1, ht * e.Bt2, -ht};
+      const double Z4[4] = {0.0, 0.0, 0.0, 0.0};
+      // corr += (f4, vn f4, vt1 f4, vt2 f4, 0, 0, v2/2 f4)
+      const double lf4 = lamf(0) + e.vn * lamf(1) + e.vt1 * lamf(2) + e.vt2 * lamf(3) + 0.5 * e.v2 * lamf(6);
+      pair_rev<0, 0, false, 127>(l, Z4, alf(3), alf(3), lf4, 0.0, dl, ph.eps, f4, f5, ll, lz, lal[3], dummy, emit);
+    }
+    e = reeig();
+    const double ht = 0.5 * e.tau;
+    const double lam1 = lamf(1), lam2 = lamf(2), lam3 = lamf(3), lam6 = lamf(6);
+    eb.vn += f4 * lam1; eb.vt1 += f4 * lam2; eb.vt2 += f4 * lam3; eb.v2 += 0.5 * f4 * lam6;
     const double lht = -0.5 * e.v2 * ll[0] + e.vn * ll[1] + e.vt1 * ll[2] + e.vt2 * ll[3] + e.Bt1 * ll[4] +
                        e.Bt2 * ll[5] - ll[6];
     eb.v2 -= 0.5 * ht * ll[0];
     eb.vn += ht * ll[1]; eb.vt1 += ht * ll[2]; eb.vt2 += ht * ll[3]; eb.Bt1 += ht * ll[4]; eb.Bt2 += ht * ll[5];
     eb.tau += 0.5 * lht;
   }
-  // pass-through members of FaceEig that are face-state components
-  // (vn, vt1, vt2, Bt1, Bt2 are fp[1], fp[2], fp[3], fp[5], fp[6])
-  face_eig_vjp(fp, ph, e, eb, lfp);
+  if (PAIRS & 8) eb.pin_entropy();
+  if (PAIRS & 8) pin(lal[3]);
 }
 
 // ---------------------------------------------------------------------------

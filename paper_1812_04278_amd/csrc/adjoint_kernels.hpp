@@ -6,17 +6,10 @@
 //                        equations of Sect. 2.3 and of eq. ox1-ox3)
 //   adj_sweep_kernel     one direction: recomputes the tile's forward data,
 //                        runs the per-face reverse (adjoint_device.hpp) and
-//                        the per-zone prologue reverse.  Full tiles add the
-//                        cotangents of their own zones to `main` and write
-//                        those of the halo zones owned by neighbouring tiles
-//                        to `spillL` / `spillR` (two and three zones; for full
-//                        tiles every entry has exactly one writer).  A ragged
-//                        last tile behind full tiles runs as a separate launch
-//                        afterwards and adds all of its zones into `main`
-//                        directly: when it is shorter than three zones, the
-//                        wrapped halos of the first and last tiles would
-//                        otherwise share entries.
-//   adj_combine_kernel   main += spillL + spillR, spills cleared
+//                        the per-zone prologue reverse, and adds the zone
+//                        cotangents of every zone its faces touch (own zones
+//                        and the halo zones of the neighbouring tiles); the
+//                        tiles of one launch touch disjoint zones
 //   adj_bcell_kernel     face-b cotangent += transpose of the fourth-order
 //                        zone interpolation
 //   adj_axpy kernels     the RK3 stage combinations
@@ -87,32 +80,52 @@ struct AdjSweepArgs {
   const double* lam_k;   // [8][N] cotangent of the right-hand side (hydro part used)
   const double* lam_T;   // [2][N] cotangent of this sweep's transport fluxes T^n_t1, T^n_t2
   double* lam_main;      // [8][N] += zone cotangents: rho, m_x, m_y, m_z, E, B_x, B_y, B_z
-  double* spillL;        // [8][N] zone cotangents of the two zones left of a tile
-  double* spillR;        // [8][N] zone cotangents of the three zones right of a tile
-  int tile0;             // index of the first tile of this launch along the axis
-  int direct;            // 1: add every zone's cotangent into lam_main (a launch of one tile column)
+  int tile0;             // tile index along the axis of block 0 of this launch
+  int tstride;           // tile index step between consecutive blocks along the axis
 };
 
 constexpr int ADJ_NP = 11;   // cotangents of zone primitives and speeds (P_* order)
+// Threads per face (ADJ_ROLES): with 2, waves 0-3 (role 0) reverse the fast
+// and Alfven pairs and waves 4-7 (role 1) the slow pair and the entropy field;
+// with 1, every thread reverses all four.
+#ifndef ADJ_ROLES
+#define ADJ_ROLES 1
+#endif
+constexpr int ADJ_THREADS = ADJ_ROLES * SW_THREADS;
 
 template <int AXIS>
-__global__ __launch_bounds__(SW_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a) {
+struct AdjLds {
+  static constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  static constexpr int NC = (TA + SW_HL + SW_HR) * TB, NIF = (TA + 4) * TB, NF = TA * TB;
+  static constexpr size_t bytes = sizeof(double) * (size_t)(SW_NQ * NC + SW_NP * NC + ADJ_NP * NC + SW_NQ * NIF + 7 * NF);
+};
+
+// One block: TA x TB faces of one plane.  Every zone that a face of the tile
+// touches (positions 0 .. tav+4 along the axis) gets its cotangent added to
+// lam_main by exactly one thread of the block; positions that wrap onto the
+// same zone (a tile that spans the whole axis) are summed first.  Blocks of
+// one launch touch disjoint zones (the host launches the tiles of an axis in
+// conflict-free classes), so the additions need no atomics and the order of
+// accumulation is fixed.
+template <int AXIS>
+__global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSweepArgs a) {
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;
   constexpr int NI = TA + 4;
   constexpr int NC = NA * TB;
   constexpr int NIF = NI * TB;
   constexpr int NF = TA * TB;
-  // LDS: zone q/F (later the differences) | primitives (later their cotangents)
-  //      | interface cotangents | face cotangents of the flux (central term)
+  // LDS: zone q/F (later the differences) | zone primitives and speeds | their
+  //      cotangents | interface-difference cotangents | face flux cotangents
   __shared__ double Q[SW_NQ * NC];
   __shared__ double Pz[SW_NP * NC];
+  __shared__ double PB[ADJ_NP * NC];
   __shared__ double LD[SW_NQ * NIF];
   __shared__ double LF[7 * NF];
   const Grid& g = a.g;
   const int nA = AXIS == 0 ? g.nx : (AXIS == 1 ? g.ny : g.nz);
   const int nB = AXIS == 0 ? g.ny : g.nx;
-  const int a0 = (a.tile0 + blockIdx.x) * TA;
+  const int a0 = (a.tile0 + blockIdx.x * a.tstride) * TA;
   const int b0 = blockIdx.y * TB;
   const int c = blockIdx.z;
   const int tav = min(TA, nA - a0);            // valid faces (and own zones) along the axis
@@ -128,16 +141,49 @@ __global__ __launch_bounds__(SW_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a
     return g.at(i, j, k);
   };
 
-  // ---- (1) forward zone prologue into LDS
-  for (int cell = threadIdx.x; cell < NC; cell += SW_THREADS) {
+  const int role = threadIdx.x / SW_THREADS;     // wave-uniform
+  const int tid = threadIdx.x % SW_THREADS;      // face of this thread
+  // ---- (0) global loads first: the states of this thread's cells (the same
+  //          cells it handles in (4), kept in registers) and the right-hand-side
+  //          cotangents of its face, so that the latencies overlap
+  int fa, fb;
+  if (AXIS == 0) { fa = tid % TA; fb = tid / TA; }
+  else           { fb = tid % TB; fa = tid / TB; }
+  const bool valid = fa < tav && b0 + fb < nB;
+  constexpr int NCELL = (NC + ADJ_THREADS - 1) / ADJ_THREADS;
+  double uz[NCELL][8];   // sweep frame: rho, m_n, m_t1, m_t2, E, B_n, B_t1, B_t2
+#pragma unroll
+  for (int k = 0; k < NCELL; ++k) {
+    const int cell = min(threadIdx.x + k * ADJ_THREADS, (unsigned)NC - 1);
     int aa, bb;
     if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
     else           { bb = cell % TB; aa = cell / TB; }
     const size_t gi = gindex(wrap(a0 - SW_HL + aa, nA), min(b0 + bb, nB - 1));
     const double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
     const double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
+    double* u = uz[k];
+    u[0] = a.hydro[gi]; u[1] = m[CN]; u[2] = m[CT1]; u[3] = m[CT2]; u[4] = a.hydro[4 * g.N + gi];
+    u[5] = B[CN]; u[6] = B[CT1]; u[7] = B[CT2];
+  }
+  double lk0[5], lk1[5], lT[2];
+  if (role == 0) {
+    const int ia = wrap(a0 + fa, nA), ia1 = wrap(a0 + fa + 1, nA);
+    const int ib = min(b0 + fb, nB - 1);
+    const size_t g0 = gindex(ia, ib), g1 = gindex(ia1, ib);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { lk0[v] = a.lam_k[v * g.N + g0]; lk1[v] = a.lam_k[v * g.N + g1]; }
+    lT[0] = a.lam_T[g0];
+    lT[1] = a.lam_T[g.N + g0];
+  }
+
+  // ---- (1) forward zone prologue into LDS
+#pragma unroll
+  for (int k = 0; k < NCELL; ++k) {
+    const int cell = threadIdx.x + k * ADJ_THREADS;
+    if (cell >= NC) break;
+    const double* u = uz[k];
     double z[Z_NVAR];
-    zone_prologue(a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
+    zone_prologue(u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7], a.ph.gamma, z);
 #pragma unroll
     for (int v = 0; v < SW_NQ; ++v) Q[v * NC + cell] = z[v];
     const int pv[SW_NP] = {Z_RHO, Z_VN, Z_VT1, Z_VT2, Z_BN, Z_BT1, Z_BT2, Z_P, Z_CF, Z_CA, Z_CS};
@@ -146,93 +192,108 @@ __global__ __launch_bounds__(SW_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a
   }
   __syncthreads();
 
-  // ---- (2) per face: face state, LF speeds, zone values for the reverse,
-  //          own interface differences, incoming flux cotangents
-  int fa, fb;
-  if (AXIS == 0) { fa = threadIdx.x % TA; fb = threadIdx.x / TA; }
-  else           { fb = threadIdx.x % TB; fa = threadIdx.x / TB; }
-  const bool valid = fa < tav && b0 + fb < nB;
+  // ---- (2) per face: own interface differences (role 0: Delta F, role 1:
+  //          Delta q), incoming flux cotangents (role 0)
   const int cL = cidx(fa + 2, fb), cR = cidx(fa + 3, fb);
-  double fp[8], al[7];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (Pz[v * NC + cL] + Pz[v * NC + cR]);
-  const double vL = Pz[P_VN * NC + cL], vR = Pz[P_VN * NC + cR];
-  const double spL[3] = {Pz[P_CF * NC + cL], Pz[P_CA * NC + cL], Pz[P_CS * NC + cL]};
-  const double spR[3] = {Pz[P_CF * NC + cR], Pz[P_CA * NC + cR], Pz[P_CS * NC + cR]};
-  const double BnL = Pz[P_BN * NC + cL], BnR = Pz[P_BN * NC + cR];
-  const double t1L = Pz[P_VT1 * NC + cL], t1R = Pz[P_VT1 * NC + cR];
-  const double t2L = Pz[P_VT2 * NC + cL], t2R = Pz[P_VT2 * NC + cR];
-  // LF speed of field m: max(|v_L + sg c_L|, |v_R + sg c_R|); c index: fast 0, Alfven 1, slow 2, none (entropy)
-  const int sgm[7] = {-1, -1, -1, 0, 1, 1, 1};
-  const int spi[7] = {0, 1, 2, 0, 2, 1, 0};
-#pragma unroll
-  for (int m = 0; m < 7; ++m) {
-    const double xl = sgm[m] == 0 ? vL : vL + sgm[m] * spL[spi[m]];
-    const double xr = sgm[m] == 0 ? vR : vR + sgm[m] * spR[spi[m]];
-    al[m] = fmax(fabs(xl), fabs(xr));
-  }
-  double d0[SW_NQ], d1[SW_NQ];
   {
-    const int c0 = cidx(fa, fb), c1 = cidx(fa + 1, fb);
+    // zone variables: q in Q rows 0..6, F in rows 7..13; differences: Delta F
+    // in rows 0..6, Delta q in rows 7..13 (two roles: one half each)
+    constexpr int NV = SW_NQ / ADJ_ROLES;
+    auto src_row = [&](int v) { const int w = role * NV + v; return w < 7 ? w + 7 : w - 7; };
+    auto dst_row = [&](int v) { return role * NV + v; };
+    double d0[NV], d1[NV];
+    {
+      const int c0 = cidx(fa, fb), c1 = cidx(fa + 1, fb);
 #pragma unroll
-    for (int v = 0; v < SW_NQ; ++v) d0[v] = Q[v * NC + c1] - Q[v * NC + c0];
+      for (int v = 0; v < NV; ++v) d0[v] = Q[src_row(v) * NC + c1] - Q[src_row(v) * NC + c0];
+      if (fa < 4) {
+        const int c2 = cidx(TA + fa, fb), c3 = cidx(TA + fa + 1, fb);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) d1[v] = Q[src_row(v) * NC + c3] - Q[src_row(v) * NC + c2];
+      }
+    }
+    // incoming cotangents: flux divergence transposed, lam_F_v(face i+1/2) = (lam_k_v(i+1) - lam_k_v(i))/h,
+    // in the sweep frame; the B_t components carry the transport-flux cotangents
+    double lam[7];
+    if (role == 0) {
+      double lg[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) lg[v] = (lk1[v] - lk0[v]) * a.inv_h;
+      const double lm[3] = {lg[1], lg[2], lg[3]};
+      const double msk = valid ? 1.0 : 0.0;
+      lam[0] = msk * lg[0];
+      lam[1] = msk * lm[CN];
+      lam[2] = msk * lm[CT1];
+      lam[3] = msk * lm[CT2];
+      lam[4] = msk * lT[0];
+      lam[5] = msk * lT[1];
+      lam[6] = msk * lg[4];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Q[dst_row(v) * NIF + iidx(fa, fb)] = d0[v];
     if (fa < 4) {
-      const int c2 = cidx(TA + fa, fb), c3 = cidx(TA + fa + 1, fb);
 #pragma unroll
-      for (int v = 0; v < SW_NQ; ++v) d1[v] = Q[v * NC + c3] - Q[v * NC + c2];
+      for (int v = 0; v < NV; ++v) Q[dst_row(v) * NIF + iidx(TA + fa, fb)] = d1[v];
+    }
+    if (role == 0) {
+#pragma unroll
+      for (int v = 0; v < 7; ++v) LF[v * NF + fidx(fa, fb)] = lam[v];
     }
   }
-  // incoming cotangents: flux divergence transposed, lam_F_v(face i+1/2) = (lam_k_v(i+1) - lam_k_v(i))/h,
-  // in the sweep frame; the B_t components carry the transport-flux cotangents
-  double lam[7], ltc1, ltc2;
-  {
-    const int ia = wrap(a0 + fa, nA), ia1 = wrap(a0 + fa + 1, nA);
-    const int ib = min(b0 + fb, nB - 1);
-    const size_t g0 = gindex(ia, ib), g1 = gindex(ia1, ib);
-    double lg[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) lg[v] = (a.lam_k[v * g.N + g1] - a.lam_k[v * g.N + g0]) * a.inv_h;
-    const double lm[3] = {lg[1], lg[2], lg[3]};
-    const double msk = valid ? 1.0 : 0.0;
-    ltc1 = msk * a.lam_T[g0];
-    ltc2 = msk * a.lam_T[g.N + g0];
-    lam[0] = msk * lg[0];
-    lam[1] = msk * lm[CN];
-    lam[2] = msk * lm[CT1];
-    lam[3] = msk * lm[CT2];
-    lam[4] = ltc1;
-    lam[5] = ltc2;
-    lam[6] = msk * lg[4];
-  }
-  __syncthreads();
-  // differences (Delta F, Delta q) into the q/F area; cotangent areas cleared
-#pragma unroll
-  for (int v = 0; v < 7; ++v) {
-    Q[v * NIF + iidx(fa, fb)] = d0[7 + v];
-    Q[(7 + v) * NIF + iidx(fa, fb)] = d0[v];
-  }
-  if (fa < 4) {
-#pragma unroll
-    for (int v = 0; v < 7; ++v) {
-      Q[v * NIF + iidx(TA + fa, fb)] = d1[7 + v];
-      Q[(7 + v) * NIF + iidx(TA + fa, fb)] = d1[v];
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < 7; ++v) LF[v * NF + fidx(fa, fb)] = lam[v];
-  for (int t = threadIdx.x; t < SW_NQ * NIF; t += SW_THREADS) LD[t] = 0.0;
-  for (int t = threadIdx.x; t < SW_NP * NC; t += SW_THREADS) Pz[t] = 0.0;
+  for (int t = threadIdx.x; t < SW_NQ * NIF; t += ADJ_THREADS) LD[t] = 0.0;
+  for (int t = threadIdx.x; t < ADJ_NP * NC; t += ADJ_THREADS) PB[t] = 0.0;
   __syncthreads();
 
   // ---- (3) per-face reverse; interface cotangents in barrier-separated sub-rounds
-  auto dl = [&](int j, int k) -> double { return Q[j * NIF + iidx(fa + k, fb)]; };
-  auto emit = [&](int k, const double* v) {
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < SW_NQ; ++j) LD[j * NIF + iidx(fa + k, fb)] += v[j];
+  // LF speed of field m: max(|v_L + sg c_L|, |v_R + sg c_R|); c index: fast 0, Alfven 1, slow 2, none (entropy)
+  // sign and speed index of field m: m < 3 minus, m = 3 none, m > 3 plus
+  auto sgm = [](int m) { return m < 3 ? -1 : (m == 3 ? 0 : 1); };
+  auto spi = [](int m) { return (m == 0 || m == 6) ? 0 : ((m == 1 || m == 5) ? 1 : 2); };
+  auto xarg = [&](int m, int cz) {
+    const double v = Pz[P_VN * NC + cz];
+    return sgm(m) == 0 ? v : v + sgm(m) * Pz[(P_CF + spi(m)) * NC + cz];
   };
-  double lfp[8] = {0, 0, 0, 0, 0, 0, 0, 0}, lal[7] = {0, 0, 0, 0, 0, 0, 0};
-  face_corr_vjp(fp, al, dl, a.ph, lam, lfp, lal, emit);
+  auto alf = [&](int m) { return fmax(fabs(xarg(m, cL)), fabs(xarg(m, cR))); };
+  auto lamf = [&](int j) { return LF[j * NF + fidx(fa, fb)]; };
+  auto dl = [&](int j, int k) -> double { return Q[j * NIF + iidx(fa + k, fb)]; };
+  // every role emits five times per pair; role 0 adds first, then role 1
+  auto emit = [&](int k, const double* v) {
+#pragma unroll
+    for (int r = 0; r < ADJ_ROLES; ++r) {
+      __syncthreads();
+      if (role == r) {
+#pragma unroll
+        for (int j = 0; j < SW_NQ; ++j) LD[j * NIF + iidx(fa + k, fb)] += v[j];
+      }
+    }
+  };
+  double lal[7] = {0, 0, 0, 0, 0, 0, 0};
+  double lfp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  {
+    // eigen scalars of the face state (the mean of the two zones' primitives)
+    auto eig = [&]() {
+      double fp[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (Pz[v * NC + cL] + Pz[v * NC + cR]);
+      FaceEig e;
+      face_eig(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], fp[6], fp[7], a.ph, e);
+      return e;
+    };
+    FaceEig e = eig();
+    // two roles (256 registers per thread): recompute after each pair's reverse
+    // instead of keeping the scalars live; one role (512): keep them
+    auto reeig = [&]() { return ADJ_ROLES == 1 ? e : eig(); };
+    FaceEigBar eb;
+    eb.zero();
+    if (ADJ_ROLES == 1)  face_corr_vjp<1 | 2 | 4 | 8>(e, reeig, alf, lamf, dl, a.ph, eb, lal, emit);
+    else if (role == 0)  face_corr_vjp<1 | 4>(e, reeig, alf, lamf, dl, a.ph, eb, lal, emit);
+    else                 face_corr_vjp<2 | 8>(e, reeig, alf, lamf, dl, a.ph, eb, lal, emit);
+    double fp[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (Pz[v * NC + cL] + Pz[v * NC + cR]);
+    face_eig_vjp(fp, a.ph, e, eb, lfp);   // linear in eb: the two roles' parts add up
+  }
   // zone-primitive cotangents of zones L (i) and R (i+1): face-state means,
   // LF speeds (branch of the larger argument; ties -> L) and transport-flux means
   double pl[ADJ_NP], pr[ADJ_NP];
@@ -240,40 +301,59 @@ __global__ __launch_bounds__(SW_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a
   for (int v = 0; v < ADJ_NP; ++v) { pl[v] = v < 8 ? 0.5 * lfp[v] : 0.0; pr[v] = pl[v]; }
 #pragma unroll
   for (int m = 0; m < 7; ++m) {
-    const double xl = sgm[m] == 0 ? vL : vL + sgm[m] * spL[spi[m]];
-    const double xr = sgm[m] == 0 ? vR : vR + sgm[m] * spR[spi[m]];
+    const double xl = xarg(m, cL), xr = xarg(m, cR);
     const bool left = fabs(xl) >= fabs(xr);
     const double x = left ? xl : xr;
     const double sx = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
     double* t = left ? pl : pr;
     t[P_VN] += lal[m] * sx;
-    if (sgm[m] != 0) t[P_CF + spi[m]] += lal[m] * sx * sgm[m];
+    if (sgm(m) != 0) t[P_CF + spi(m)] += lal[m] * sx * sgm(m);
   }
-  pl[P_BN] += 0.5 * (ltc1 * t1L + ltc2 * t2L);
-  pr[P_BN] += 0.5 * (ltc1 * t1R + ltc2 * t2R);
-  pl[P_VT1] += 0.5 * ltc1 * BnL; pr[P_VT1] += 0.5 * ltc1 * BnR;
-  pl[P_VT2] += 0.5 * ltc2 * BnL; pr[P_VT2] += 0.5 * ltc2 * BnR;
-  __syncthreads();
+  if (role == 0) {
+    const double ltc1 = lamf(4), ltc2 = lamf(5);
+    const double BnL = Pz[P_BN * NC + cL], BnR = Pz[P_BN * NC + cR];
+    pl[P_BN] += 0.5 * (ltc1 * Pz[P_VT1 * NC + cL] + ltc2 * Pz[P_VT2 * NC + cL]);
+    pr[P_BN] += 0.5 * (ltc1 * Pz[P_VT1 * NC + cR] + ltc2 * Pz[P_VT2 * NC + cR]);
+    pl[P_VT1] += 0.5 * ltc1 * BnL; pr[P_VT1] += 0.5 * ltc1 * BnR;
+    pl[P_VT2] += 0.5 * ltc2 * BnL; pr[P_VT2] += 0.5 * ltc2 * BnR;
+  }
+  // cotangent sums of this thread's cells in (4), loaded ahead of the sub-rounds
+  const int span = tav + SW_HL + SW_HR;          // positions touched by the valid faces
+  const int nz_own = min(span, nA);              // distinct zones among them
+  double lm[NCELL][8];
+  size_t gcell[NCELL];
+  bool own[NCELL];
 #pragma unroll
-  for (int v = 0; v < ADJ_NP; ++v) Pz[v * NC + cL] += pl[v];
-  __syncthreads();
-#pragma unroll
-  for (int v = 0; v < ADJ_NP; ++v) Pz[v * NC + cR] += pr[v];
-  __syncthreads();
-
-  // ---- (4) per zone: gather, prologue reverse, write
-  for (int cell = threadIdx.x; cell < NC; cell += SW_THREADS) {
+  for (int k = 0; k < NCELL; ++k) {
+    const int cell = threadIdx.x + k * ADJ_THREADS;
     int aa, bb;
     if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
     else           { bb = cell % TB; aa = cell / TB; }
-    if (aa >= tav + 5 || b0 + bb >= nB) continue;   // no valid face touches this zone
-    double lz[Z_NVAR];
+    own[k] = cell < NC && aa < nz_own && b0 + bb < nB;
+    gcell[k] = own[k] ? gindex(wrap(a0 - SW_HL + aa, nA), b0 + bb) : 0;
 #pragma unroll
-    for (int v = 0; v < Z_NVAR; ++v) lz[v] = 0.0;
-    // interface differences: D(ia) = X(ia+1) - X(ia)
+    for (int v = 0; v < 8; ++v) lm[k][v] = own[k] ? a.lam_main[v * g.N + gcell[k]] : 0.0;
+  }
+  // sub-rounds: zone L from role 0, then role 1; zone R likewise
+#pragma unroll
+  for (int r = 0; r < 2 * ADJ_ROLES; ++r) {
+    __syncthreads();
+    if (role == r % ADJ_ROLES) {
+      double* dst = PB + (r < ADJ_ROLES ? cL : cR);
+      const double* src = r < ADJ_ROLES ? pl : pr;
+#pragma unroll
+      for (int v = 0; v < ADJ_NP; ++v) dst[v * NC] += src[v];
+    }
+  }
+  __syncthreads();
+
+  // ---- (4) per zone: gather, prologue reverse, add
+  // cotangents of the prologue outputs at tile position aa (lz += ...)
+  auto gather = [&](int aa, int bb, double* lz) {
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
       double lFj = 0.0, lqj = 0.0;
+      // interface differences: D(ia) = X(ia+1) - X(ia)
       if (aa >= 1) { lFj += LD[j * NIF + iidx(aa - 1, bb)]; lqj += LD[(7 + j) * NIF + iidx(aa - 1, bb)]; }
       if (aa < NI) { lFj -= LD[j * NIF + iidx(aa, bb)]; lqj -= LD[(7 + j) * NIF + iidx(aa, bb)]; }
       // central term: face f (local) uses zones f+1 (-1/12), f+2 (7/12), f+3 (7/12), f+4 (-1/12)
@@ -282,55 +362,43 @@ __global__ __launch_bounds__(SW_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a
       if (f2 >= 0 && f2 < TA) lFj += LF[j * NF + fidx(f2, bb)] * (7.0 / 12.0);
       if (f3 >= 0 && f3 < TA) lFj += LF[j * NF + fidx(f3, bb)] * (7.0 / 12.0);
       if (f4 >= 0 && f4 < TA) lFj -= LF[j * NF + fidx(f4, bb)] * (1.0 / 12.0);
-      lz[Z_F0 + j] = lFj;
-      lz[Z_RHO + j] = lqj;
+      lz[Z_F0 + j] += lFj;
+      lz[Z_RHO + j] += lqj;
     }
-    lz[Z_RHO] += Pz[P_RHO * NC + cell];
-    lz[Z_VN] += Pz[P_VN * NC + cell];
-    lz[Z_VT1] += Pz[P_VT1 * NC + cell];
-    lz[Z_VT2] += Pz[P_VT2 * NC + cell];
-    lz[Z_BN] += Pz[P_BN * NC + cell];
-    lz[Z_BT1] += Pz[P_BT1 * NC + cell];
-    lz[Z_BT2] += Pz[P_BT2 * NC + cell];
-    lz[Z_P] += Pz[P_P * NC + cell];
-    lz[Z_CF] += Pz[P_CF * NC + cell];
-    lz[Z_CA] += Pz[P_CA * NC + cell];
-    lz[Z_CS] += Pz[P_CS * NC + cell];
-    const int gaa = wrap(a0 - SW_HL + aa, nA);
-    const size_t gi = gindex(gaa, b0 + bb);
-    const double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
-    const double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
-    const double u[8] = {a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2]};
+    const int cz = cidx(aa, bb);
+    lz[Z_RHO] += PB[P_RHO * NC + cz];
+    lz[Z_VN] += PB[P_VN * NC + cz];
+    lz[Z_VT1] += PB[P_VT1 * NC + cz];
+    lz[Z_VT2] += PB[P_VT2 * NC + cz];
+    lz[Z_BN] += PB[P_BN * NC + cz];
+    lz[Z_BT1] += PB[P_BT1 * NC + cz];
+    lz[Z_BT2] += PB[P_BT2 * NC + cz];
+    lz[Z_P] += PB[P_P * NC + cz];
+    lz[Z_CF] += PB[P_CF * NC + cz];
+    lz[Z_CA] += PB[P_CA * NC + cz];
+    lz[Z_CS] += PB[P_CS * NC + cz];
+  };
+#pragma unroll
+  for (int k = 0; k < NCELL; ++k) {
+    if (!own[k]) continue;
+    const int cell = threadIdx.x + k * ADJ_THREADS;
+    int aa, bb;
+    if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
+    else           { bb = cell % TB; aa = cell / TB; }
+    double lz[Z_NVAR];
+#pragma unroll
+    for (int v = 0; v < Z_NVAR; ++v) lz[v] = 0.0;
+    for (int q = aa; q < span; q += nA) gather(q, bb, lz);   // positions of the same zone
     double lu[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    zone_prologue_vjp(u, a.ph.gamma, lz, lu);
+    zone_prologue_vjp(uz[k], a.ph.gamma, lz, lu);
     double out[8];
     out[0] = lu[0];
     out[1 + CN] = lu[1]; out[1 + CT1] = lu[2]; out[1 + CT2] = lu[3];
     out[4] = lu[4];
     out[5 + CN] = lu[5]; out[5 + CT1] = lu[6]; out[5 + CT2] = lu[7];
-    if (a.direct) {
 #pragma unroll
-      for (int v = 0; v < 8; ++v) a.lam_main[v * g.N + gi] += out[v];
-    } else if (aa < SW_HL) {
-#pragma unroll
-      for (int v = 0; v < 8; ++v) a.spillL[v * g.N + gi] = out[v];
-    } else if (aa < SW_HL + tav) {
-#pragma unroll
-      for (int v = 0; v < 8; ++v) a.lam_main[v * g.N + gi] += out[v];
-    } else {
-#pragma unroll
-      for (int v = 0; v < 8; ++v) a.spillR[v * g.N + gi] = out[v];
-    }
+    for (int v = 0; v < 8; ++v) a.lam_main[v * g.N + gcell[k]] = lm[k][v] + out[v];
   }
-}
-
-// main += spillL + spillR; spills cleared for the next sweep
-__global__ __launch_bounds__(256) void adj_combine_kernel(size_t n8, double* lam_main, double* spillL, double* spillR) {
-  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= n8) return;
-  lam_main[c] += spillL[c] + spillR[c];
-  spillL[c] = 0.0;
-  spillR[c] = 0.0;
 }
 
 // face b cotangent += transpose of B_i = (-b_{i-2} + 9 b_{i-1} + 9 b_i - b_{i+1})/16:

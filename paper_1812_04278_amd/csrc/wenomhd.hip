@@ -3,6 +3,7 @@
 // scratch layout, and stream-ordered kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -81,10 +82,69 @@ Layout layout(const wm_config* c) {
 
 // adjoint scratch (doubles, N each unless noted): U1 (11), U2 (11), zone B of
 // the linearisation state (3), transport-flux cotangents (6), zone cotangents
-// main / spillL / spillR (8 each), rhs cotangent (8), stage cotangents lamU2,
-// lamU1 (8 each), work (8), then the dt slot.
-enum AdjOff { A_U1 = 0, A_U2 = 11, A_BZ = 22, A_LT = 25, A_MAIN = 31, A_SPL = 39, A_SPR = 47, A_LK = 55,
-              A_LU2 = 63, A_LU1 = 71, A_WORK = 79, A_NARR = 87 };
+// (8), rhs cotangent (8), stage cotangents lamU2, lamU1 (8 each), work (8),
+// then the dt slot.
+enum AdjOff { A_U1 = 0, A_U2 = 11, A_BZ = 22, A_LT = 25, A_MAIN = 31, A_LK = 39, A_LU2 = 47, A_LU1 = 55,
+              A_WORK = 63, A_NARR = 71 };
+
+// Launch classes of the adjoint sweep along one axis: n zones in tiles of TA
+// faces; tile t adds into the zones t*TA - 2 .. t*TA + tav + 2 (periodic).
+// Neighbouring tiles on the ring share zones, and so do tiles 0 and nt-2 when
+// the last tile has at most 4 zones (their halos reach into it from both
+// sides).  Classes: even tiles, odd tiles, and the tile left over (nt odd:
+// the last; nt even with a short last tile: tile nt-2).
+struct TileRun { int first, stride, count; };
+struct TilePlan { TileRun run[4]; int n; };
+
+bool plan_disjoint(int n, int TA, const TilePlan& pl) {
+  std::vector<int> stamp(n, -1);
+  for (int r = 0; r < pl.n; ++r) {
+    const TileRun& t = pl.run[r];
+    for (int i = 0; i < t.count; ++i) {
+      const int tile = t.first + i * t.stride;
+      const int tav = std::min(TA, n - tile * TA);
+      if (tav <= 0) return false;
+      const int span = std::min(tav + SW_HL + SW_HR, n);   // distinct zones (wrapped positions are summed)
+      for (int q = 0; q < span; ++q) {
+        const int z = ((tile * TA - SW_HL + q) % n + n) % n;
+        if (stamp[z] == r * 1000000 + tile) continue;
+        if (stamp[z] >= r * 1000000) return false;       // another tile of the same class
+        stamp[z] = r * 1000000 + tile;
+      }
+    }
+  }
+  // every tile in exactly one class
+  std::vector<int> seen((n + TA - 1) / TA, 0);
+  for (int r = 0; r < pl.n; ++r)
+    for (int i = 0; i < pl.run[r].count; ++i) ++seen[pl.run[r].first + i * pl.run[r].stride];
+  for (int v : seen)
+    if (v != 1) return false;
+  return true;
+}
+
+TilePlan plan_tiles(int n, int TA) {
+  TilePlan pl{};
+  const int nt = (n + TA - 1) / TA;
+  const int last = n - (nt - 1) * TA;
+  auto add = [&](int first, int stride, int count) {
+    if (count > 0) pl.run[pl.n++] = TileRun{first, stride, count};
+  };
+  if (nt == 1) {
+    add(0, 1, 1);
+  } else if (nt % 2 == 1) {
+    add(0, 2, (nt - 1) / 2);
+    add(1, 2, (nt - 1) / 2);
+    add(nt - 1, 1, 1);
+  } else if (nt == 2 || last > SW_HL + SW_HR - 1) {
+    add(0, 2, nt / 2);
+    add(1, 2, nt / 2);
+  } else {
+    add(0, 2, nt / 2 - 1);
+    add(1, 2, nt / 2);
+    add(nt - 2, 1, 1);
+  }
+  return pl;
+}
 
 size_t adjoint_bytes(const wm_config* c) {
   const size_t N = (size_t)c->nx * c->ny * c->nz;
@@ -105,6 +165,7 @@ struct wm_patch {
   double* bcell = nullptr;
   int stage_done = -1;       // last completed stage of the current step (-1: none)
   bool dt_valid = false;
+  TilePlan adj_plan[3];      // adjoint sweep launch classes per axis (grid sizes >= 3)
   // event timing (wm_profile)
   bool prof = false;
   std::vector<hipEvent_t> ev;       // pool, 2 per record
@@ -242,7 +303,7 @@ dim3 lin_grid(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 template <int AXIS>
 wm_status launch_adj_sweep(wm_patch* p, const double* hydro, const double* bcell, const double* lam_k,
-                           const double* lam_T, double* main, double* spl, double* spr) {
+                           const double* lam_T, double* main) {
   AdjSweepArgs a;
   a.g = p->g;
   a.ph = p->ph;
@@ -252,36 +313,19 @@ wm_status launch_adj_sweep(wm_patch* p, const double* hydro, const double* bcell
   a.lam_k = lam_k;
   a.lam_T = lam_T;
   a.lam_main = main;
-  a.spillL = spl;
-  a.spillR = spr;
-  const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
   const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
   const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
-  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
-  // Spill mode for every tile except a ragged last one behind at least one full
-  // tile: with fewer than three zones it would share spill entries with the
-  // first tile (their halos wrap onto the same zones), so it runs afterwards
-  // and adds straight into main.  Its own zone range (rem + 5 <= nA zones) does
-  // not wrap onto itself; a single tile (nA <= TA) keeps the spill mode, whose
-  // buffers hold two and three distinct zones for nA >= 3.
-  const int nfull = nA / TA, rem = nA % TA;
-  const int nspill = (nfull > 0 && rem > 0) ? nfull : (nA + TA - 1) / TA;
+  constexpr int TB = SweepTile<AXIS>::TB;
+  const TilePlan& pl = p->adj_plan[AXIS];
   const long r = prof_begin(p, K_OTHER);
-  a.tile0 = 0;
-  a.direct = 0;
-  hipLaunchKernelGGL((adj_sweep_kernel<AXIS>), dim3(nspill, (nB + TB - 1) / TB, nC), dim3(SW_THREADS), 0,
-                     p->stream, a);
-  WM_LAUNCH_CHECK("adjoint sweep kernel");
-  if (nspill * TA < nA) {
-    a.tile0 = nspill;
-    a.direct = 1;
-    hipLaunchKernelGGL((adj_sweep_kernel<AXIS>), dim3(1, (nB + TB - 1) / TB, nC), dim3(SW_THREADS), 0, p->stream,
-                       a);
+  for (int c = 0; c < pl.n; ++c) {   // classes in order: each launch adds into disjoint zones
+    a.tile0 = pl.run[c].first;
+    a.tstride = pl.run[c].stride;
+    hipLaunchKernelGGL((adj_sweep_kernel<AXIS>), dim3(pl.run[c].count, (nB + TB - 1) / TB, nC), dim3(ADJ_THREADS), 0,
+                       p->stream, a);
     WM_LAUNCH_CHECK("adjoint sweep kernel");
   }
   prof_end(p, r);
-  hipLaunchKernelGGL(adj_combine_kernel, lin_grid(8 * p->g.N), dim3(256), 0, p->stream, 8 * p->g.N, main, spl, spr);
-  WM_LAUNCH_CHECK("adjoint combine kernel");
   return WM_OK;
 }
 
@@ -300,16 +344,14 @@ wm_status rhs_vjp(wm_patch* p, double* A, const double* hydro, const double* bfa
   double* Bz = A + A_BZ * N;
   double* lT = A + A_LT * N;
   double* main = A + A_MAIN * N;
-  double* spl = A + A_SPL * N;
-  double* spr = A + A_SPR * N;
   if ((s = launch_bcell(p, bface, Bz)) != WM_OK) return s;
   hipLaunchKernelGGL(adj_emf_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, lam_k, lT);
   WM_LAUNCH_CHECK("adjoint emf kernel");
-  hipLaunchKernelGGL(fill_kernel, lin_grid(24 * N), dim3(256), 0, p->stream, 24 * N, 0.0, main);  // main, spills
+  hipLaunchKernelGGL(fill_kernel, lin_grid(8 * N), dim3(256), 0, p->stream, 8 * N, 0.0, main);
   WM_LAUNCH_CHECK("fill kernel");
-  if ((s = launch_adj_sweep<0>(p, hydro, Bz, lam_k, lT, main, spl, spr)) != WM_OK) return s;
-  if ((s = launch_adj_sweep<1>(p, hydro, Bz, lam_k, lT + 2 * N, main, spl, spr)) != WM_OK) return s;
-  if ((s = launch_adj_sweep<2>(p, hydro, Bz, lam_k, lT + 4 * N, main, spl, spr)) != WM_OK) return s;
+  if ((s = launch_adj_sweep<0>(p, hydro, Bz, lam_k, lT, main)) != WM_OK) return s;
+  if ((s = launch_adj_sweep<1>(p, hydro, Bz, lam_k, lT + 2 * N, main)) != WM_OK) return s;
+  if ((s = launch_adj_sweep<2>(p, hydro, Bz, lam_k, lT + 4 * N, main)) != WM_OK) return s;
   // hydro cotangents as they are; face b from the zone-B cotangent
   hipLaunchKernelGGL(scale_kernel, lin_grid(5 * N), dim3(256), 0, p->stream, 5 * N, 1.0, main, out);
   WM_LAUNCH_CHECK("copy kernel");
@@ -399,6 +441,17 @@ wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch,
   p->ph.g2 = (cfg->gamma - 2.0) / (cfg->gamma - 1.0);
   p->scratch = reinterpret_cast<char*>(scratch);
   p->lay = L;
+  if (cfg->nx >= 3 && cfg->ny >= 3 && cfg->nz >= 3) {
+    const int n3[3] = {cfg->nx, cfg->ny, cfg->nz};
+    const int ta[3] = {SweepTile<0>::TA, SweepTile<1>::TA, SweepTile<2>::TA};
+    for (int d = 0; d < 3; ++d) {
+      p->adj_plan[d] = plan_tiles(n3[d], ta[d]);
+      if (!plan_disjoint(n3[d], ta[d], p->adj_plan[d])) {
+        delete p;
+        return fail(WM_ERR_ARG, "internal: adjoint tile classes overlap");
+      }
+    }
+  }
   *out = p;
   g_err[0] = 0;
   return WM_OK;
