@@ -176,11 +176,19 @@ size_t wm_adjoint_scratch_bytes(const wm_config* cfg);
 wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const void* bface, const void* lam_k,
                      void* lam_out);
 
-/* Adjoint of one SSP-RK3 step U^{n+1} = Phi(U^n; dt) (increment form): the
- * stage states U1, U2 are recomputed from U^n into adj_scratch; lam_hydro,
- * lam_bface hold dJ/dU^{n+1} on entry and dJ/dU^n on return. */
-wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface, double dt,
-                          void* lam_hydro, void* lam_bface);
+/* Adjoint of one SSP-RK3 step U^{n+1} = Phi(U^n; dt) (increment form, dt
+ * held fixed): lam_hydro [5][..], lam_bface [3][..] hold dJ/dU^{n+1} on entry
+ * and dJ/dU^n on return.  U1_stage, U2_stage: the step's two intermediate
+ * stage states as wm_step_record stores them ([8][..]: hydro then face b), or
+ * both NULL to recompute them from U^n into adj_scratch. */
+wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface,
+                          const void* U1_stage, const void* U2_stage, double dt, void* lam_hydro, void* lam_bface);
+
+/* One SSP-RK3 step of the bound state with the given dt (as wm_rk_stage
+ * 0, 1, 2), also copying the two intermediate stage states to U1_out and
+ * U2_out ([8][nz][ny][nx] device arrays each: rho, m_x, m_y, m_z, E, b_x, b_y,
+ * b_z), for a later wm_adjoint_step. */
+wm_status wm_step_record(wm_patch* p, double dt, void* U1_out, void* U2_out);
 
 /* lam_bface += transpose of the zone interpolation B = interp4(b) applied to
  * lam_bcell ([3][nz][ny][nx]): the cotangent of a loss on zone B. */

@@ -22,7 +22,7 @@ SYMBOLS = [
     "wm_config_default", "wm_scratch_bytes", "wm_patch_create", "wm_patch_destroy", "wm_bind_state",
     "wm_init_from_potential", "wm_refresh_zone_field", "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics",
     "wm_debug_sweep", "wm_debug_rhs", "wm_adjoint_scratch_bytes", "wm_rhs_vjp", "wm_adjoint_step",
-    "wm_zone_field_vjp", "wm_init_adjoint", "wm_profile", "wm_profile_report", "wm_last_error",
+    "wm_step_record", "wm_zone_field_vjp", "wm_init_adjoint", "wm_profile", "wm_profile_report", "wm_last_error",
 ]
 KERNEL_CLASSES = ["sweep", "update", "bcell", "dt", "other"]
 
@@ -77,7 +77,8 @@ def load(path: str = LIB_PATH):
     lib.wm_adjoint_scratch_bytes.argtypes = [C]
     lib.wm_adjoint_scratch_bytes.restype = ctypes.c_size_t
     lib.wm_rhs_vjp.argtypes = [P, P, P, P, P, P]
-    lib.wm_adjoint_step.argtypes = [P, P, P, P, ctypes.c_double, P, P]
+    lib.wm_adjoint_step.argtypes = [P, P, P, P, P, P, ctypes.c_double, P, P]
+    lib.wm_step_record.argtypes = [P, ctypes.c_double, P, P]
     lib.wm_zone_field_vjp.argtypes = [P, P, P]
     lib.wm_init_adjoint.argtypes = [P, P, P, P, P, D, P, P, P, P]
     lib.wm_profile.argtypes = [P, ctypes.c_int]
@@ -87,7 +88,7 @@ def load(path: str = LIB_PATH):
     for name in ("wm_patch_create", "wm_patch_destroy", "wm_bind_state", "wm_init_from_potential",
                  "wm_refresh_zone_field",
                  "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics", "wm_debug_sweep", "wm_debug_rhs",
-                 "wm_rhs_vjp", "wm_adjoint_step", "wm_zone_field_vjp", "wm_init_adjoint",
+                 "wm_rhs_vjp", "wm_adjoint_step", "wm_step_record", "wm_zone_field_vjp", "wm_init_adjoint",
                  "wm_profile", "wm_profile_report"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -244,10 +245,26 @@ class Patch:
         _check(self.lib.wm_rhs_vjp(self.handle, _ptr(self._adj()), _ptr(h), _ptr(b), _ptr(l), _ptr(out)))
         return out
 
-    def adjoint_step(self, Un_hydro, Un_bface, dt: float, lam_hydro, lam_bface):
-        """In place: (lam_hydro, lam_bface) <- adjoint of one step from U^n with dt."""
+    def adjoint_step(self, Un_hydro, Un_bface, dt: float, lam_hydro, lam_bface, U1=None, U2=None):
+        """In place: (lam_hydro, lam_bface) <- adjoint of one step from U^n with dt.
+        U1, U2: the step's stage states from step_record ([8, nz, ny, nx]), or
+        None to recompute them."""
+        if (U1 is None) != (U2 is None):
+            raise ValueError("give both stage states or neither")
         _check(self.lib.wm_adjoint_step(self.handle, _ptr(self._adj()), _ptr(Un_hydro), _ptr(Un_bface),
+                                        _ptr(U1) if U1 is not None else None,
+                                        _ptr(U2) if U2 is not None else None,
                                         float(dt), _ptr(lam_hydro), _ptr(lam_bface)))
+
+    def step_record(self, dt: float, U1=None, U2=None):
+        """One step of the bound state with dt; returns its two stage states
+        ([8, nz, ny, nx] each, written into U1/U2 when given)."""
+        if U1 is None:
+            U1 = torch.empty((8,) + self.shape, dtype=torch.float64, device=self.device)
+        if U2 is None:
+            U2 = torch.empty((8,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.wm_step_record(self.handle, float(dt), _ptr(U1), _ptr(U2)))
+        return U1, U2
 
     def zone_field_vjp(self, lam_bcell, lam_bface):
         _check(self.lib.wm_zone_field_vjp(self.handle, _ptr(lam_bcell.contiguous()), _ptr(lam_bface)))

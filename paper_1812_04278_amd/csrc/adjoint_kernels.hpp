@@ -12,7 +12,7 @@
 //                        tiles of one launch touch disjoint zones
 //   adj_bcell_kernel     face-b cotangent += transpose of the fourth-order
 //                        zone interpolation
-//   adj_axpy kernels     the RK3 stage combinations
+//   adj_glue kernels     the RK3 stage combinations
 //   init_adj kernels     transpose of the initial-state map (curl_h A, m, E)
 // Accumulation orders are fixed (LDS sub-rounds separated by barriers, no
 // atomics), so results are bitwise reproducible.
@@ -79,7 +79,8 @@ struct AdjSweepArgs {
   const double* bcell;   // its zone B [3][N]
   const double* lam_k;   // [8][N] cotangent of the right-hand side (hydro part used)
   const double* lam_T;   // [2][N] cotangent of this sweep's transport fluxes T^n_t1, T^n_t2
-  double* lam_main;      // [8][N] += zone cotangents: rho, m_x, m_y, m_z, E, B_x, B_y, B_z
+  double* lam_h;         // [5][N] += zone cotangents of rho, m_x, m_y, m_z, E
+  double* lam_Bz;        // [3][N] += zone cotangents of the zone field B_x, B_y, B_z
   int tile0;             // tile index along the axis of block 0 of this launch
   int tstride;           // tile index step between consecutive blocks along the axis
 };
@@ -102,7 +103,7 @@ struct AdjLds {
 
 // One block: TA x TB faces of one plane.  Every zone that a face of the tile
 // touches (positions 0 .. tav+4 along the axis) gets its cotangent added to
-// lam_main by exactly one thread of the block; positions that wrap onto the
+// lam_h / lam_Bz by exactly one thread of the block; positions that wrap onto the
 // same zone (a tile that spans the whole axis) are summed first.  Blocks of
 // one launch touch disjoint zones (the host launches the tiles of an axis in
 // conflict-free classes), so the additions need no atomics and the order of
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
     own[k] = cell < NC && aa < nz_own && b0 + bb < nB;
     gcell[k] = own[k] ? gindex(wrap(a0 - SW_HL + aa, nA), b0 + bb) : 0;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) lm[k][v] = own[k] ? a.lam_main[v * g.N + gcell[k]] : 0.0;
+    for (int v = 0; v < 8; ++v) lm[k][v] = own[k] ? (v < 5 ? a.lam_h : a.lam_Bz - 5 * g.N)[v * g.N + gcell[k]] : 0.0;
   }
   // sub-rounds: zone L from role 0, then role 1; zone R likewise
 #pragma unroll
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
     out[4] = lu[4];
     out[5 + CN] = lu[5]; out[5 + CT1] = lu[6]; out[5 + CT2] = lu[7];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) a.lam_main[v * g.N + gcell[k]] = lm[k][v] + out[v];
+    for (int v = 0; v < 8; ++v) (v < 5 ? a.lam_h : a.lam_Bz - 5 * g.N)[v * g.N + gcell[k]] = lm[k][v] + out[v];
   }
 }
 
@@ -425,20 +426,42 @@ __global__ __launch_bounds__(256) void scale_kernel(size_t n, double a, const do
   const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (c < n) y[c] = a * x[c];
 }
-// y = a x + b z (n doubles)
-__global__ __launch_bounds__(256) void axpby_kernel(size_t n, double a, const double* x, double b, const double* z,
-                                                    double* y) {
-  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (c < n) y[c] = a * x[c] + b * z[c];
-}
-// y += x (n doubles)
-__global__ __launch_bounds__(256) void add_kernel(size_t n, const double* x, double* y) {
-  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (c < n) y[c] += x[c];
-}
 __global__ __launch_bounds__(256) void fill_kernel(size_t n, double v, double* y) {
   const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (c < n) y[c] = v;
+}
+
+// The RK3 stage combinations of the adjoint step over the 8N cotangent
+// entries (hydro [5][N] then face b [3][N]; lam3 split over lh, lb):
+//   glue_a: w = lam3, lk = c lam3, z = 0
+//   glue_b: lk = a w + b x, z = 0
+//   glue_c: lk = a w + b x + c y, (lh, lb) = w + x + y
+__global__ __launch_bounds__(256) void adj_glue_a_kernel(size_t N, double c, const double* lh, const double* lb,
+                                                         double* w, double* lk, double* z) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= 8 * N) return;
+  const double l3 = i < 5 * N ? lh[i] : lb[i - 5 * N];
+  w[i] = l3;
+  lk[i] = c * l3;
+  z[i] = 0.0;
+}
+__global__ __launch_bounds__(256) void adj_glue_b_kernel(size_t n8, double a, const double* w, double b,
+                                                         const double* x, double* lk, double* z) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n8) return;
+  lk[i] = a * w[i] + b * x[i];
+  z[i] = 0.0;
+}
+__global__ __launch_bounds__(256) void adj_glue_c_kernel(size_t N, double a, const double* w, double b,
+                                                         const double* x, double c, const double* y, double* lk,
+                                                         double* lh, double* lb) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= 8 * N) return;
+  const double wi = w[i], xi = x[i], yi = y[i];
+  lk[i] = a * wi + b * xi + c * yi;
+  const double s = wi + xi + yi;
+  if (i < 5 * N) lh[i] = s;
+  else lb[i - 5 * N] = s;
 }
 
 // Initial-state map transposed, per zone: m = rho v, E = P0/(gamma-1) + (rho v^2 + B^2)/2

@@ -80,12 +80,12 @@ Layout layout(const wm_config* c) {
   return L;
 }
 
-// adjoint scratch (doubles, N each unless noted): U1 (11), U2 (11), zone B of
-// the linearisation state (3), transport-flux cotangents (6), zone cotangents
-// (8), rhs cotangent (8), stage cotangents lamU2, lamU1 (8 each), work (8),
-// then the dt slot.
-enum AdjOff { A_U1 = 0, A_U2 = 11, A_BZ = 22, A_LT = 25, A_MAIN = 31, A_LK = 39, A_LU2 = 47, A_LU1 = 55,
-              A_WORK = 63, A_NARR = 71 };
+// adjoint scratch (doubles, N each unless noted): recomputed stage states U1,
+// U2 (11 each: hydro, face b, zone B), zone B of the linearisation state (3),
+// transport-flux cotangents (6), zone-B cotangent (3), rhs cotangent (8), stage
+// cotangents lamU2, lamU1 (8 each), lam3 (8), then the dt slot.
+enum AdjOff { A_U1 = 0, A_U2 = 11, A_BZ = 22, A_LT = 25, A_LBZ = 31, A_LK = 34, A_LU2 = 42, A_LU1 = 50,
+              A_WORK = 58, A_NARR = 66 };
 
 // Launch classes of the adjoint sweep along one axis: n zones in tiles of TA
 // faces; tile t adds into the zones t*TA - 2 .. t*TA + tav + 2 (periodic).
@@ -303,7 +303,7 @@ dim3 lin_grid(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 template <int AXIS>
 wm_status launch_adj_sweep(wm_patch* p, const double* hydro, const double* bcell, const double* lam_k,
-                           const double* lam_T, double* main) {
+                           const double* lam_T, double* acc_h, double* lam_Bz) {
   AdjSweepArgs a;
   a.g = p->g;
   a.ph = p->ph;
@@ -312,7 +312,8 @@ wm_status launch_adj_sweep(wm_patch* p, const double* hydro, const double* bcell
   a.bcell = bcell;
   a.lam_k = lam_k;
   a.lam_T = lam_T;
-  a.lam_main = main;
+  a.lam_h = acc_h;
+  a.lam_Bz = lam_Bz;
   const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
   const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
   constexpr int TB = SweepTile<AXIS>::TB;
@@ -337,27 +338,24 @@ wm_status check_adjoint(wm_patch* p, void* adj) {
 }
 
 // (dL/dU)^T lam_k at U = (hydro, bface) -> out (hydro 5, bface 3); A = adjoint scratch base
-wm_status rhs_vjp(wm_patch* p, double* A, const double* hydro, const double* bface, const double* lam_k,
-                  double* out) {
+// (acc_h, acc_b) += (dL/dU)^T lam_k at U = (hydro, bface)
+wm_status rhs_vjp_acc(wm_patch* p, double* A, const double* hydro, const double* bface, const double* lam_k,
+                      double* acc_h, double* acc_b) {
   const size_t N = p->g.N;
   wm_status s;
   double* Bz = A + A_BZ * N;
   double* lT = A + A_LT * N;
-  double* main = A + A_MAIN * N;
+  double* lBz = A + A_LBZ * N;
   if ((s = launch_bcell(p, bface, Bz)) != WM_OK) return s;
   hipLaunchKernelGGL(adj_emf_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, lam_k, lT);
   WM_LAUNCH_CHECK("adjoint emf kernel");
-  hipLaunchKernelGGL(fill_kernel, lin_grid(8 * N), dim3(256), 0, p->stream, 8 * N, 0.0, main);
+  hipLaunchKernelGGL(fill_kernel, lin_grid(3 * N), dim3(256), 0, p->stream, 3 * N, 0.0, lBz);
   WM_LAUNCH_CHECK("fill kernel");
-  if ((s = launch_adj_sweep<0>(p, hydro, Bz, lam_k, lT, main)) != WM_OK) return s;
-  if ((s = launch_adj_sweep<1>(p, hydro, Bz, lam_k, lT + 2 * N, main)) != WM_OK) return s;
-  if ((s = launch_adj_sweep<2>(p, hydro, Bz, lam_k, lT + 4 * N, main)) != WM_OK) return s;
-  // hydro cotangents as they are; face b from the zone-B cotangent
-  hipLaunchKernelGGL(scale_kernel, lin_grid(5 * N), dim3(256), 0, p->stream, 5 * N, 1.0, main, out);
-  WM_LAUNCH_CHECK("copy kernel");
-  hipLaunchKernelGGL(fill_kernel, lin_grid(3 * N), dim3(256), 0, p->stream, 3 * N, 0.0, out + 5 * N);
-  WM_LAUNCH_CHECK("fill kernel");
-  hipLaunchKernelGGL(adj_bcell_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, main + 5 * N, out + 5 * N);
+  if ((s = launch_adj_sweep<0>(p, hydro, Bz, lam_k, lT, acc_h, lBz)) != WM_OK) return s;
+  if ((s = launch_adj_sweep<1>(p, hydro, Bz, lam_k, lT + 2 * N, acc_h, lBz)) != WM_OK) return s;
+  if ((s = launch_adj_sweep<2>(p, hydro, Bz, lam_k, lT + 4 * N, acc_h, lBz)) != WM_OK) return s;
+  // face b from the zone-B cotangent
+  hipLaunchKernelGGL(adj_bcell_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, lBz, acc_b);
   WM_LAUNCH_CHECK("adjoint bcell kernel");
   return WM_OK;
 }
@@ -630,62 +628,75 @@ wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const vo
   wm_status s = check_adjoint(p, adj_scratch);
   if (s != WM_OK) return s;
   if (!hydro || !bface || !lam_k || !lam_out) return fail(WM_ERR_ARG, "null pointer");
-  return rhs_vjp(p, reinterpret_cast<double*>(adj_scratch), reinterpret_cast<const double*>(hydro),
-                 reinterpret_cast<const double*>(bface), reinterpret_cast<const double*>(lam_k),
-                 reinterpret_cast<double*>(lam_out));
+  const size_t N = p->g.N;
+  double* out = reinterpret_cast<double*>(lam_out);
+  hipLaunchKernelGGL(fill_kernel, lin_grid(8 * N), dim3(256), 0, p->stream, 8 * N, 0.0, out);
+  WM_LAUNCH_CHECK("fill kernel");
+  return rhs_vjp_acc(p, reinterpret_cast<double*>(adj_scratch), reinterpret_cast<const double*>(hydro),
+                     reinterpret_cast<const double*>(bface), reinterpret_cast<const double*>(lam_k), out,
+                     out + 5 * N);
 }
 
-wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface, double dt,
-                          void* lam_hydro, void* lam_bface) {
+wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface,
+                          const void* U1_stage, const void* U2_stage, double dt, void* lam_hydro, void* lam_bface) {
   wm_status s = check_adjoint(p, adj_scratch);
   if (s != WM_OK) return s;
   if (!Un_hydro || !Un_bface || !lam_hydro || !lam_bface) return fail(WM_ERR_ARG, "null pointer");
+  if ((U1_stage == nullptr) != (U2_stage == nullptr)) return fail(WM_ERR_ARG, "give both stage states or neither");
   if (!std::isfinite(dt)) return fail(WM_ERR_ARG, "dt is not finite");
   const size_t N = p->g.N;
   double* A = reinterpret_cast<double*>(adj_scratch);
-  double* dtp = A + A_NARR * N;
   const double* Uh = reinterpret_cast<const double*>(Un_hydro);
   const double* Ub = reinterpret_cast<const double*>(Un_bface);
   double* lh = reinterpret_cast<double*>(lam_hydro);
   double* lb = reinterpret_cast<double*>(lam_bface);
-  double* U1 = A + A_U1 * N;
-  double* U2 = A + A_U2 * N;
+  const double* U1 = reinterpret_cast<const double*>(U1_stage);
+  const double* U2 = reinterpret_cast<const double*>(U2_stage);
+  if (!U1) {   // recompute the stage states from U^n
+    double* dtp = A + A_NARR * N;
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
+    WM_LAUNCH_CHECK("set dt");
+    // the stage accumulator of the forward scratch is free outside wm_step
+    if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N, p->acc())) != WM_OK) return s;
+    U1 = A + A_U1 * N;
+    U2 = A + A_U2 * N;
+  }
   double* lk = A + A_LK * N;
   double* lU2 = A + A_LU2 * N;
   double* lU1 = A + A_LU1 * N;
   double* w = A + A_WORK * N;
-  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
-  WM_LAUNCH_CHECK("set dt");
-  // the stage accumulator of the forward scratch is free outside wm_step
-  if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, U1, U2, p->acc())) != WM_OK) return s;
-  const dim3 g8 = lin_grid(8 * N), g5 = lin_grid(5 * N), g3 = lin_grid(3 * N);
-  // lam3 = (lh, lb) gathered into w
-  hipLaunchKernelGGL(scale_kernel, g5, dim3(256), 0, p->stream, 5 * N, 1.0, lh, w);
-  hipLaunchKernelGGL(scale_kernel, g3, dim3(256), 0, p->stream, 3 * N, 1.0, lb, w + 5 * N);
-  WM_LAUNCH_CHECK("copy kernel");
+  const dim3 g8 = lin_grid(8 * N);
   // k2 = L(U2), weight 4 dt/6
-  hipLaunchKernelGGL(scale_kernel, g8, dim3(256), 0, p->stream, 8 * N, 4.0 * dt / 6.0, w, lk);
-  WM_LAUNCH_CHECK("scale kernel");
-  if ((s = rhs_vjp(p, A, U2, U2 + 5 * N, lk, lU2)) != WM_OK) return s;
+  hipLaunchKernelGGL(adj_glue_a_kernel, g8, dim3(256), 0, p->stream, N, 4.0 * dt / 6.0, lh, lb, w, lk, lU2);
+  WM_LAUNCH_CHECK("adjoint glue kernel");
+  if ((s = rhs_vjp_acc(p, A, U2, U2 + 5 * N, lk, lU2, lU2 + 5 * N)) != WM_OK) return s;
   // k1 = L(U1): dt/6 lam3 + dt/4 lamU2
-  hipLaunchKernelGGL(axpby_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 6.0, w, 0.25 * dt, lU2, lk);
-  WM_LAUNCH_CHECK("axpby kernel");
-  if ((s = rhs_vjp(p, A, U1, U1 + 5 * N, lk, lU1)) != WM_OK) return s;
-  // k0 = L(U^n): dt/6 lam3 + dt/4 lamU2 + dt lamU1
-  hipLaunchKernelGGL(axpby_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 6.0, w, 0.25 * dt, lU2, lk);
-  hipLaunchKernelGGL(axpby_kernel, g8, dim3(256), 0, p->stream, 8 * N, 1.0, lk, dt, lU1, lk);
-  WM_LAUNCH_CHECK("axpby kernel");
-  // lam^n = lam3 + lamU2 + lamU1 + (dL/dU^n)^T lam_k0 (the rhs VJP result goes to lU2's slot after use)
-  hipLaunchKernelGGL(add_kernel, g8, dim3(256), 0, p->stream, 8 * N, lU2, w);
-  hipLaunchKernelGGL(add_kernel, g8, dim3(256), 0, p->stream, 8 * N, lU1, w);
-  WM_LAUNCH_CHECK("add kernel");
-  if ((s = rhs_vjp(p, A, Uh, Ub, lk, lU1)) != WM_OK) return s;
-  hipLaunchKernelGGL(add_kernel, g8, dim3(256), 0, p->stream, 8 * N, lU1, w);
-  WM_LAUNCH_CHECK("add kernel");
-  hipLaunchKernelGGL(scale_kernel, g5, dim3(256), 0, p->stream, 5 * N, 1.0, w, lh);
-  hipLaunchKernelGGL(scale_kernel, g3, dim3(256), 0, p->stream, 3 * N, 1.0, w + 5 * N, lb);
-  WM_LAUNCH_CHECK("copy kernel");
-  return WM_OK;
+  hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 6.0, w, 0.25 * dt, lU2, lk, lU1);
+  WM_LAUNCH_CHECK("adjoint glue kernel");
+  if ((s = rhs_vjp_acc(p, A, U1, U1 + 5 * N, lk, lU1, lU1 + 5 * N)) != WM_OK) return s;
+  // k0 = L(U^n): dt/6 lam3 + dt/4 lamU2 + dt lamU1; lam^n = lam3 + lamU2 + lamU1 + (dL/dU^n)^T lam_k0
+  hipLaunchKernelGGL(adj_glue_c_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, w, 0.25 * dt, lU2, dt, lU1, lk,
+                     lh, lb);
+  WM_LAUNCH_CHECK("adjoint glue kernel");
+  return rhs_vjp_acc(p, A, Uh, Ub, lk, lh, lb);
+}
+
+wm_status wm_step_record(wm_patch* p, double dt, void* U1_out, void* U2_out) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  if (!U1_out || !U2_out) return fail(WM_ERR_ARG, "null pointer");
+  if (!std::isfinite(dt)) return fail(WM_ERR_ARG, "dt is not finite");
+  const size_t bytes = 8 * p->g.N * sizeof(double);
+  p->stage_done = -1;
+  if ((s = wm_rk_stage(p, 0, &dt)) != WM_OK) return s;
+  if ((s = hip_check(hipMemcpyAsync(U1_out, p->us(), bytes, hipMemcpyDeviceToDevice, p->stream), "stage copy")) !=
+      WM_OK)
+    return s;
+  if ((s = wm_rk_stage(p, 1, nullptr)) != WM_OK) return s;
+  if ((s = hip_check(hipMemcpyAsync(U2_out, p->us(), bytes, hipMemcpyDeviceToDevice, p->stream), "stage copy")) !=
+      WM_OK)
+    return s;
+  return wm_rk_stage(p, 2, nullptr);
 }
 
 wm_status wm_zone_field_vjp(wm_patch* p, const void* lam_bcell, void* lam_bface) {

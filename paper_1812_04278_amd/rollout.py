@@ -4,8 +4,11 @@ adjoint of the HIP library (``wm_adjoint_step``, ``wm_init_adjoint``).
 
 Memory: the forward keeps a checkpoint of the state every ``ckpt_every`` steps;
 the backward re-runs each segment forward from its checkpoint, keeping that
-segment's states, and walks it in reverse.  The time steps of the forward pass
-are recorded and held fixed in the backward (dt is not differentiated).
+segment's states (and, with ``store_stages``, the two intermediate RK stages of
+every step, so the adjoint step does not recompute them: 3 states of 8 fields
+per step of the segment), and walks it in reverse.  The time steps of the
+forward pass are recorded and held fixed in the backward (dt is not
+differentiated).
 """
 from __future__ import annotations
 
@@ -19,7 +22,7 @@ class Rollout(torch.autograd.Function):
     ``nsteps`` steps from init_from_potential(rho, v, A, P0, B0)."""
 
     @staticmethod
-    def forward(ctx, A, v, rho, patch: B.Patch, nsteps: int, ckpt_every: int, P0: float, B0):
+    def forward(ctx, A, v, rho, patch: B.Patch, nsteps: int, ckpt_every: int, P0: float, B0, store_stages=True):
         with torch.no_grad():
             patch.init_from_potential(rho, v, A, P0, B0)
             ckpts, dts = [], []
@@ -30,6 +33,7 @@ class Rollout(torch.autograd.Function):
             out = (patch.hydro.clone(), patch.bface.clone(), patch.bcell.clone())
         ctx.patch, ctx.nsteps, ctx.ckpt_every = patch, nsteps, ckpt_every
         ctx.ckpts, ctx.dts, ctx.P0, ctx.B0 = ckpts, dts, P0, B0
+        ctx.store_stages = store_stages
         ctx.save_for_backward(A, v, rho)
         return out
 
@@ -55,15 +59,22 @@ class Rollout(torch.autograd.Function):
                 p.set_state(h0[0], h0[1:4], h0[4], b0)
                 states = []
                 for n in range(n0, n1):
-                    states.append((p.hydro.clone(), p.bface.clone()))
-                    if n + 1 < n1:
-                        p.step_dt(ctx.dts[n])
+                    Uh, Ub = p.hydro.clone(), p.bface.clone()
+                    if ctx.store_stages:
+                        U1, U2 = p.step_record(ctx.dts[n])
+                    else:
+                        U1 = U2 = None
+                        if n + 1 < n1:
+                            p.step_dt(ctx.dts[n])
+                    states.append((Uh, Ub, U1, U2))
                 for n in range(n1 - 1, n0 - 1, -1):
-                    Uh, Ub = states[n - n0]
-                    p.adjoint_step(Uh, Ub, ctx.dts[n], lam_h, lam_b)
+                    Uh, Ub, U1, U2 = states[n - n0]
+                    p.adjoint_step(Uh, Ub, ctx.dts[n], lam_h, lam_b, U1, U2)
+                del states
             gA, gv = p.init_adjoint(rho, v, A, ctx.B0, lam_h, lam_b)
-        return gA, gv, None, None, None, None, None, None
+        return gA, gv, None, None, None, None, None, None, None
 
 
-def rollout(A, v, rho, patch: B.Patch, nsteps: int, ckpt_every: int = 5, P0: float = 0.6, B0=(1.0, 0.5, 0.0)):
-    return Rollout.apply(A, v, rho, patch, nsteps, ckpt_every, P0, B0)
+def rollout(A, v, rho, patch: B.Patch, nsteps: int, ckpt_every: int = 5, P0: float = 0.6, B0=(1.0, 0.5, 0.0),
+            store_stages: bool = True):
+    return Rollout.apply(A, v, rho, patch, nsteps, ckpt_every, P0, B0, store_stages)

@@ -103,6 +103,30 @@ def test_adjoint_step_vs_oracle():
     check8(torch.cat([lh.cpu(), lb.cpu()]), ref, "adjoint step")
 
 
+def test_adjoint_step_recorded_stages():
+    """Stage states recorded by step_record give the same adjoint step as the
+    recomputed ones, and step_record advances the state like step_dt."""
+    say("adjoint step with recorded stages 20x18x16")
+    f = fields(24, seed=13, v_rms=1.0, crop=(20, 18, 16))
+    U, cfg = oracle_state(f)
+    dt = 0.8 * mhd.compute_dt(U, cfg)
+    nz, ny, nx = U["rho"].shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h))
+    h, b = to_gpu_state(U)
+    p.set_state(h[0], h[1:4], h[4], b)
+    U1, U2 = p.step_record(dt)
+    h1, b1 = p.hydro.clone(), p.bface.clone()
+    p.set_state(h[0], h[1:4], h[4], b)
+    p.step_dt(dt)
+    assert torch.equal(h1, p.hydro) and torch.equal(b1, p.bface)
+    lam = torch.randn((8,) + U["rho"].shape, generator=torch.Generator().manual_seed(9), dtype=torch.float64).cuda()
+    lh1, lb1 = lam[:5].clone(), lam[5:].clone()
+    lh2, lb2 = lam[:5].clone(), lam[5:].clone()
+    p.adjoint_step(h, b, dt, lh1, lb1)
+    p.adjoint_step(h, b, dt, lh2, lb2, U1, U2)
+    assert torch.equal(lh1, lh2) and torch.equal(lb1, lb2)
+
+
 def test_init_adjoint_vs_oracle():
     say("init adjoint 16^3")
     f = fields(16, seed=14, v_rms=1.0)
@@ -152,9 +176,11 @@ def gpu_forward_fixed(p, f, A, v, dts):
     return p.hydro.clone(), p.bcell.clone()
 
 
-def test_rollout_gradient_vs_oracle():
+@pytest.mark.parametrize("store_stages", [True, False])
+def test_rollout_gradient_vs_oracle(store_stages):
     """Gradient of the rollout loss w.r.t. (A, v): GPU adjoint with checkpoints
-    against autograd through the oracle, 12^3, 6 steps, checkpoints every 4."""
+    against autograd through the oracle, 12^3, 6 steps, checkpoints every 4,
+    with recorded and with recomputed stage states."""
     n, nsteps = 12, 6
     f = fields(n, seed=1, v_rms=1.0, kmax=4)
     rho_t, e_t = targets(n)
@@ -162,7 +188,8 @@ def test_rollout_gradient_vs_oracle():
     p = B.Patch(B.config(n))
     A = torch.as_tensor(f.A).cuda().requires_grad_(True)
     v = torch.as_tensor(f.v).cuda().requires_grad_(True)
-    hyd, bf, bc = R.rollout(A, v, torch.as_tensor(f.rho).cuda(), p, nsteps, ckpt_every=4, P0=f.P0, B0=f.B0)
+    hyd, bf, bc = R.rollout(A, v, torch.as_tensor(f.rho).cuda(), p, nsteps, ckpt_every=4, P0=f.P0, B0=f.B0,
+                            store_stages=store_stages)
     J = loss_from(hyd, bc, rho_t.cuda(), e_t.cuda(), h)
     gA, gv = torch.autograd.grad(J, [A, v])
     # oracle: autograd through the same steps with the dt sequence held fixed
@@ -178,8 +205,8 @@ def test_rollout_gradient_vs_oracle():
     for dt in dts:
         Uo, _ = mhd.step(Uo, cfg, dt)
     Jo = loss_from(flat8(Uo)[:5], mhd.zone_B(Uo["b"]), rho_t, e_t, h)
-    say(f"rollout loss: gpu {float(J):.15e} oracle {float(Jo):.15e}")
-    assert abs(float(J) - float(Jo)) <= 1e-12 * abs(float(Jo))
+    say(f"rollout loss: gpu {float(J.detach()):.15e} oracle {float(Jo.detach()):.15e}")
+    assert abs(float(J.detach()) - float(Jo.detach())) <= 1e-12 * abs(float(Jo.detach()))
     gAo2, gvo2 = torch.autograd.grad(Jo, [Ao, vo])
     for c in range(3):
         ea, ev = rel_err(gA[c].cpu(), gAo2[c]), rel_err(gv[c].cpu(), gvo2[c])
