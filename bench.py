@@ -157,6 +157,55 @@ def convergence(sizes, c: float = 0.25):
     return out
 
 
+def adjoint_cost(n: int = 128, steps: int = 20, ckpt: int = 5):
+    """The adjoint workload: gradient of J = h^3 sum[(rho_T - rho*)^2 + (|B_T|^2/2
+    - e*)^2] (targets: the initial density and magnetic energy density of the
+    seed-2 fields) with respect to the initial vector potential and velocity, n^3
+    Mach-1 inputs (seed 1), `steps` FP64 steps, checkpoints every `ckpt` steps,
+    each segment recomputed in the backward pass with its stage states recorded.
+    Times: the plain forward (same steps, dt from eq. (cfl)), the checkpointing
+    forward and the backward; the cost ratio is backward / plain forward."""
+    import torch
+    from paper_1812_04278_amd import binding, inputs, rollout
+    f = inputs.random_fields(n, seed=1, v_rms=1.0, kmax=4)
+    f2 = inputs.random_fields(n, seed=2, v_rms=1.0, kmax=4)
+    p = binding.Patch(binding.config(n), device="cuda:0")
+    p.init_from_potential(f2.rho, f2.v, f2.A, f2.P0, f2.B0)
+    rho_t = p.hydro[0].clone()
+    e_t = 0.5 * (p.bcell * p.bcell).sum(0)
+    h3 = (1.0 / n) ** 3
+    A0 = torch.as_tensor(f.A).to("cuda:0")
+    v0 = torch.as_tensor(f.v).to("cuda:0")
+    rho = torch.as_tensor(f.rho).to("cuda:0")
+
+    def run():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.init_from_potential(rho, v0, A0, f.P0, f.B0)
+        for _ in range(steps):
+            p.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        A = A0.clone().requires_grad_(True)
+        v = v0.clone().requires_grad_(True)
+        hyd, bf, bc = rollout.rollout(A, v, rho, p, steps, ckpt_every=ckpt, P0=f.P0, B0=f.B0)
+        J = h3 * (((hyd[0] - rho_t) ** 2).sum() + ((0.5 * (bc * bc).sum(0) - e_t) ** 2).sum())
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        gA, gv = torch.autograd.grad(J, [A, v])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return (t1 - t0) * 1e3, (t2 - t1) * 1e3, (t3 - t2) * 1e3, float(J.detach()), gA, gv
+
+    run()                                           # warm-up (allocations, first launches)
+    fwd, ck, bwd, J, gA, gv = run()
+    return {"workload": f"{n}^3 periodic box, Mach 1, {steps} FP64 SSP-RK3 steps, checkpoints every {ckpt}, "
+                        f"loss: L2 mismatch of final density and magnetic energy density vs a seed-2 target",
+            "forward_ms": round(fwd, 2), "checkpointed_forward_ms": round(ck, 2), "backward_ms": round(bwd, 2),
+            "ratio_backward_to_forward": round(bwd / fwd, 3), "ratio_total_to_forward": round((ck + bwd) / fwd, 3),
+            "loss": J, "grad_norm_A": float(gA.norm()), "grad_norm_v": float(gv.norm())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +217,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64-vs-mixed comparison")
     ap.add_argument("--no-convergence", action="store_true", help="skip the fast-wave convergence table")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -255,6 +305,9 @@ def main():
     if not args.no_convergence:
         log("bench: fast-wave convergence, both precisions")
         out["convergence"] = convergence((32, 64, 128, 256))
+    if not args.no_adjoint:
+        log("bench: adjoint cost (128^3, 20 steps, checkpoints every 5)")
+        out["adjoint"] = adjoint_cost()
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written, for scaling
         # the FETCH_SIZE / WRITE_SIZE counters of the kernels above

@@ -221,312 +221,368 @@ __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, doubl
 }
 
 // ---------------------------------------------------------------------------
-// one eigen pair, forward and reverse in a single pass
+// eigen pairs: forward and reverse in a single pass
 // ---------------------------------------------------------------------------
-// Rows: upper S + A, lower S - A, where A is nonzero on components
-// A0 .. A0+NA-1 and S on the components set in SMASK (TWO = false: the upper
-// row S alone).  Split values as in
-// split_pair, f = phi(v7, v6, v5, v4) - phi(v0, v1, v2, v3) per row.  The
-// cotangents lfu, lfl of the two f are known beforehand (they only involve the
-// right eigenvectors), so the pass computes f (returned for the right-vector
-// cotangents), adds the cotangents of S, A and of the two Lax-Friedrichs
-// speeds, and hands emit(k, lD[14]) the cotangent of interface difference k
-// (j = 0..6 Delta F, 7..13 Delta q).
-template <int A0, int NA, bool TWO, int SMASK, class DL, class EMIT>
-__host__ __device__ __forceinline__ void pair_rev(const double S[7], const double A[4], double alu, double all,
-                                                  double lfu, double lfl, DL dl, double eps, double& fu,
-                                                  double& fl, double lS[7], double lA[4], double& lalu,
-                                                  double& lall, EMIT emit) {
-  double vu[8], vl[8], uq[5], lq[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
+// A pair has the left rows S + A (upper) and S - A (lower) with the
+// Lax-Friedrichs speeds alu, all; S is nonzero on the components in SM, A on
+// A0 .. A0+NA-1 (TWO = false: the single row S).  Split values as in
+// split_pair; f = phi(v7, v6, v5, v4) - phi(v0, v1, v2, v3) per row.  The
+// cotangents lfu, lfl of the two f only involve the right eigenvectors, so they
+// are known before the pass, which computes f (needed for the right-vector
+// cotangents) and the cotangents of S, A, the two speeds and the interface
+// differences.
+struct PairRows {
+  double S[7], A[4];
+  double alu, all;   // Lax-Friedrichs speeds of the upper / lower row
+  double lfu, lfl;   // cotangents of f_upper, f_lower
+};
+struct PairCot {
+  double fu = 0.0, fl = 0.0;                       // forward values
+  double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
+  double lalu = 0.0, lall = 0.0;                   // cotangents of the speeds
+};
+
+template <int A0, int NA, bool TWO, int SM>
+struct PairShape {
+  // projections of the rows at one interface: d[0..6] Delta F, d[7..13] Delta q
+  __host__ __device__ static __forceinline__ void proj(const PairRows& r, const double d[14], double& uF, double& uq,
+                                                       double& lF, double& lq) {
     double sF = 0.0, sq = 0.0, aF = 0.0, aq = 0.0;
 #pragma unroll
     for (int j = 0; j < 7; ++j)
-      if (SMASK & (1 << j)) { sF += S[j] * dl(j, k); sq += S[j] * dl(7 + j, k); }
+      if (SM & (1 << j)) { sF += r.S[j] * d[j]; sq += r.S[j] * d[7 + j]; }
 #pragma unroll
-    for (int j = 0; j < NA; ++j) { aF += A[j] * dl(A0 + j, k); aq += A[j] * dl(7 + A0 + j, k); }
-    const double uF = sF + aF, lF = sF - aF;
-    uq[k] = sq + aq;
-    lq[k] = sq - aq;
-    if (k <= 3) { vu[k] = uF + alu * uq[k]; vl[k] = lF + all * lq[k]; }
-    if (k >= 1) { vu[3 + k] = uF - alu * uq[k]; vl[3 + k] = lF - all * lq[k]; }
+    for (int j = 0; j < NA; ++j) { aF += r.A[j] * d[A0 + j]; aq += r.A[j] * d[7 + A0 + j]; }
+    uF = sF + aF; uq = sq + aq; lF = sF - aF; lq = sq - aq;
   }
-  double lPu[5], lQu[5], lPl[5], lQl[5];
-  {
-    double gu[8], g4[4], pa, pb;
-    phiN_val_grad(vu[7], vu[6], vu[5], vu[4], eps, pa, g4);
-    gu[7] = g4[0] * lfu; gu[6] = g4[1] * lfu; gu[5] = g4[2] * lfu; gu[4] = g4[3] * lfu;
-    phiN_val_grad(vu[0], vu[1], vu[2], vu[3], eps, pb, g4);
-    gu[0] = -g4[0] * lfu; gu[1] = -g4[1] * lfu; gu[2] = -g4[2] * lfu; gu[3] = -g4[3] * lfu;
-    fu = pa - pb;
+  // cotangents of S, A from one interface (sFb = lP_u + lP_l, aFb = lP_u - lP_l, ...)
+  __host__ __device__ static __forceinline__ void rowcot(const double d[14], double sFb, double aFb, double sqb,
+                                                         double aqb, PairCot& c) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double pk = k <= 3 ? gu[k] : 0.0, mk = k >= 1 ? gu[3 + k] : 0.0;
-      lPu[k] = pk + mk;
-      lQu[k] = alu * (pk - mk);
-      lalu += uq[k] * (pk - mk);
-    }
+    for (int j = 0; j < 7; ++j)
+      if (SM & (1 << j)) c.lS[j] += sFb * d[j] + sqb * d[7 + j];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) c.lA[j] += aFb * d[A0 + j] + aqb * d[7 + A0 + j];
   }
-  if (TWO) {
-    double gl[8], g4[4], pa, pb;
-    phiN_val_grad(vl[7], vl[6], vl[5], vl[4], eps, pa, g4);
-    gl[7] = g4[0] * lfl; gl[6] = g4[1] * lfl; gl[5] = g4[2] * lfl; gl[4] = g4[3] * lfl;
-    phiN_val_grad(vl[0], vl[1], vl[2], vl[3], eps, pb, g4);
-    gl[0] = -g4[0] * lfl; gl[1] = -g4[1] * lfl; gl[2] = -g4[2] * lfl; gl[3] = -g4[3] * lfl;
-    fl = pa - pb;
+  // cotangent of the interface differences: lD += (S + A) lP_u + (S - A) lP_l (F and q parts)
+  __host__ __device__ static __forceinline__ void difcot(const PairRows& r, double sFb, double aFb, double sqb,
+                                                         double aqb, double lD[14]) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double pk = k <= 3 ? gl[k] : 0.0, mk = k >= 1 ? gl[3 + k] : 0.0;
-      lPl[k] = pk + mk;
-      lQl[k] = all * (pk - mk);
-      lall += lq[k] * (pk - mk);
-    }
-  } else {
-    fl = 0.0;
+    for (int j = 0; j < 7; ++j)
+      if (SM & (1 << j)) { lD[j] += r.S[j] * sFb; lD[7 + j] += r.S[j] * sqb; }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) { lPl[k] = 0.0; lQl[k] = 0.0; }
+    for (int j = 0; j < NA; ++j) { lD[A0 + j] += r.A[j] * aFb; lD[7 + A0 + j] += r.A[j] * aqb; }
   }
-  // cotangents of the rows (reads of the differences, no synchronisation) ...
+};
+
+// Split values, phi and its gradient for one row: from the projections uF, uq
+// (interfaces 0..4) to f and the cotangents lP (of uF), lQ (of uq) and of alpha.
+__host__ __device__ __forceinline__ void row_split_grad(const double uF[5], const double uq[5], double al, double lf,
+                                                        double eps, double& f, double lP[5], double lQ[5],
+                                                        double& lal) {
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = uF[k] + al * uq[k];
+#pragma unroll
+  for (int k = 1; k < 5; ++k) v[3 + k] = uF[k] - al * uq[k];
+  double g[8], g4[4], pa, pb;
+  phiN_val_grad(v[7], v[6], v[5], v[4], eps, pa, g4);
+  g[7] = g4[0] * lf; g[6] = g4[1] * lf; g[5] = g4[2] * lf; g[4] = g4[3] * lf;
+  phiN_val_grad(v[0], v[1], v[2], v[3], eps, pb, g4);
+  g[0] = -g4[0] * lf; g[1] = -g4[1] * lf; g[2] = -g4[2] * lf; g[3] = -g4[3] * lf;
+  f = pa - pb;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double pk = k <= 3 ? g[k] : 0.0, mk = k >= 1 ? g[3 + k] : 0.0;
+    lP[k] = pk + mk;
+    lQ[k] = al * (pk - mk);
+    lal += uq[k] * (pk - mk);
+  }
+}
+
+// Forward and reverse of two pairs at once: one read of the differences per
+// interface serves both, and one barrier round per interface carries both
+// pairs' cotangents (emit(k, lD[14])).
+template <class PA, bool TWOA, class PB, bool TWOB, class DL, class EMIT>
+__host__ __device__ __forceinline__ void pair2_rev(const PairRows& ra, const PairRows& rb, DL dl, double eps,
+                                                   PairCot& ca, PairCot& cb, EMIT emit) {
+  double uFa[5], uqa[5], lFa[5], lqa[5], uFb[5], uqb[5], lFb[5], lqb[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double d[14];
+#pragma unroll
+    for (int j = 0; j < 14; ++j) d[j] = dl(j, k);
+    PA::proj(ra, d, uFa[k], uqa[k], lFa[k], lqa[k]);
+    PB::proj(rb, d, uFb[k], uqb[k], lFb[k], lqb[k]);
+    sched_fence();
+  }
+  double lPua[5], lQua[5], lPla[5], lQla[5], lPub[5], lQub[5], lPlb[5], lQlb[5];
+  row_split_grad(uFa, uqa, ra.alu, ra.lfu, eps, ca.fu, lPua, lQua, ca.lalu);
+  if (TWOA) row_split_grad(lFa, lqa, ra.all, ra.lfl, eps, ca.fl, lPla, lQla, ca.lall);
+  row_split_grad(uFb, uqb, rb.alu, rb.lfu, eps, cb.fu, lPub, lQub, cb.lalu);
+  if (TWOB) row_split_grad(lFb, lqb, rb.all, rb.lfl, eps, cb.fl, lPlb, lQlb, cb.lall);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    if (!TWOA) { lPla[k] = 0.0; lQla[k] = 0.0; }
+    if (!TWOB) { lPlb[k] = 0.0; lQlb[k] = 0.0; }
+  }
+  // cotangents of the rows (a second read of the differences, no synchronisation) ...
   reload_fence();
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double sFb = lPu[k] + lPl[k], aFb = lPu[k] - lPl[k];
-    const double sqb = lQu[k] + lQl[k], aqb = lQu[k] - lQl[k];
+    double d[14];
 #pragma unroll
-    for (int j = 0; j < 7; ++j)
-      if (SMASK & (1 << j)) lS[j] += sFb * dl(j, k) + sqb * dl(7 + j, k);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) lA[j] += aFb * dl(A0 + j, k) + aqb * dl(7 + A0 + j, k);
+    for (int j = 0; j < 14; ++j) d[j] = dl(j, k);
+    PA::rowcot(d, lPua[k] + lPla[k], lPua[k] - lPla[k], lQua[k] + lQla[k], lQua[k] - lQla[k], ca);
+    PB::rowcot(d, lPub[k] + lPlb[k], lPub[k] - lPlb[k], lQub[k] + lQlb[k], lQub[k] - lQlb[k], cb);
     sched_fence();
   }
 #pragma unroll
-  for (int j = 0; j < 7; ++j)
-    if (SMASK & (1 << j)) pin(lS[j]);
+  for (int j = 0; j < 7; ++j) { pin(ca.lS[j]); pin(cb.lS[j]); }
 #pragma unroll
-  for (int j = 0; j < NA; ++j) pin(lA[j]);
+  for (int j = 0; j < 4; ++j) { pin(ca.lA[j]); pin(cb.lA[j]); }
   // ... then those of the interface differences, one barrier-separated round per k
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double sFb = lPu[k] + lPl[k], aFb = lPu[k] - lPl[k];
-    const double sqb = lQu[k] + lQl[k], aqb = lQu[k] - lQl[k];
     double lD[14];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-      lD[j] = (SMASK & (1 << j)) ? S[j] * sFb : 0.0;
-      lD[7 + j] = (SMASK & (1 << j)) ? S[j] * sqb : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      lD[A0 + j] += A[j] * aFb;
-      lD[7 + A0 + j] += A[j] * aqb;
-    }
+    for (int j = 0; j < 14; ++j) lD[j] = 0.0;
+    PA::difcot(ra, lPua[k] + lPla[k], lPua[k] - lPla[k], lQua[k] + lQla[k], lQua[k] - lQla[k], lD);
+    PB::difcot(rb, lPub[k] + lPlb[k], lPub[k] - lPlb[k], lQub[k] + lQlb[k], lQub[k] - lQlb[k], lD);
     emit(k, lD);
   }
 }
 
+// ---------------------------------------------------------------------------
+// rows and right-vector cotangents of each pair (Appendix A), with the
+// reverse of the row construction into the eigen-scalar cotangents eb
+// ---------------------------------------------------------------------------
+// fast pair (m = 1, 7): S = qa2 t, A = qa2 u
+template <class ALF, class LAM>
+__host__ __device__ __forceinline__ void fast_rows(const FaceEig& e, ALF alf, LAM lamf, PairRows& r) {
+  const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
+  const double t[7] = {e.af * e.g1 * e.v2, omg * e.af * e.vn, omg * e.af * e.vt1, omg * e.af * e.vt2,
+                       omg * e.af * e.Bt1 + sra * e.as * e.by, omg * e.af * e.Bt2 + sra * e.as * e.bz, gm1 * e.af};
+  const double u[4] = {e.Gf, -(e.af * e.cf), e.csl * e.as * e.by * s, e.csl * e.as * e.bz * s};
+#pragma unroll
+  for (int j = 0; j < 7; ++j) r.S[j] = qa2 * t[j];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r.A[j] = qa2 * u[j];
+  const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
+  const double Rs6 = e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2);
+  // corr[0..6] = af sp; af vn sp - af cf sm; af vt1 sp + csl as by s sm; af vt2 sp + csl as bz s sm;
+  //              cs as by isr sp; cs as bz isr sp; Rs6 sp - Gf sm   (sp = fu + fl, sm = fu - fl)
+  const double lsp = e.af * lam[0] + e.af * e.vn * lam[1] + e.af * e.vt1 * lam[2] + e.af * e.vt2 * lam[3] +
+                     e.cs * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
+  const double lsm = -e.af * e.cf * lam[1] + e.csl * e.as * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gf * lam[6];
+  r.lfu = lsp + lsm;
+  r.lfl = lsp - lsm;
+  r.alu = alf(0);
+  r.all = alf(6);
+}
+template <class LAM>
+__host__ __device__ __forceinline__ void fast_post(const FaceEig& e, LAM lamf, const PairCot& c, FaceEigBar& eb) {
+  const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
+  const double t[7] = {e.af * e.g1 * e.v2, omg * e.af * e.vn, omg * e.af * e.vt1, omg * e.af * e.vt2,
+                       omg * e.af * e.Bt1 + sra * e.as * e.by, omg * e.af * e.Bt2 + sra * e.as * e.bz, gm1 * e.af};
+  const double u[4] = {e.Gf, -(e.af * e.cf), e.csl * e.as * e.by * s, e.csl * e.as * e.bz * s};
+  const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
+  const double sp = c.fu + c.fl, sm = c.fu - c.fl;
+  eb.af += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
+                 (0.5 * e.v2 + e.cf2 - e.g2 * e.a2) * lam[6]) - sm * e.cf * lam[1];
+  eb.vn += e.af * sp * lam[1]; eb.vt1 += e.af * sp * lam[2]; eb.vt2 += e.af * sp * lam[3];
+  eb.cf -= e.af * sm * lam[1];
+  eb.cf2 += e.af * sp * lam[6]; eb.v2 += 0.5 * e.af * sp * lam[6]; eb.a2 -= e.g2 * e.af * sp * lam[6];
+  eb.csl += sm * e.as * s * (e.by * lam[2] + e.bz * lam[3]);
+  eb.as += sm * e.csl * s * (e.by * lam[2] + e.bz * lam[3]) + sp * e.cs * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+  eb.by += sm * e.csl * e.as * s * lam[2] + sp * e.cs * e.as * e.isr * lam[4];
+  eb.bz += sm * e.csl * e.as * s * lam[3] + sp * e.cs * e.as * e.isr * lam[5];
+  eb.cs += sp * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+  eb.isr += sp * e.cs * e.as * (e.by * lam[4] + e.bz * lam[5]);
+  eb.Gf -= sm * lam[6];
+  // rows S = qa2 t, A = qa2 u
+  double lt[7], lu[4];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) { eb.qa2 += c.lS[j] * t[j]; lt[j] = qa2 * c.lS[j]; }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) { eb.qa2 += c.lA[j] * u[j]; lu[j] = qa2 * c.lA[j]; }
+  eb.af += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
+                                        lt[5] * e.Bt2) + gm1 * lt[6];
+  eb.v2 += lt[0] * e.af * e.g1;
+  eb.vn += lt[1] * omg * e.af; eb.vt1 += lt[2] * omg * e.af; eb.vt2 += lt[3] * omg * e.af;
+  eb.Bt1 += lt[4] * omg * e.af; eb.Bt2 += lt[5] * omg * e.af;
+  eb.sr += e.cs * e.as * (lt[4] * e.by + lt[5] * e.bz);
+  eb.cs += e.sr * e.as * (lt[4] * e.by + lt[5] * e.bz);
+  eb.as += sra * (lt[4] * e.by + lt[5] * e.bz);
+  eb.by += sra * e.as * lt[4]; eb.bz += sra * e.as * lt[5];
+  eb.Gf += lu[0];
+  eb.af -= lu[1] * e.cf; eb.cf -= lu[1] * e.af;
+  eb.csl += e.as * s * (lu[2] * e.by + lu[3] * e.bz);
+  eb.as += e.csl * s * (lu[2] * e.by + lu[3] * e.bz);
+  eb.by += e.csl * e.as * s * lu[2]; eb.bz += e.csl * e.as * s * lu[3];
+}
+
+// slow pair (m = 3, 5): S = qa2 t, A = qa2 u
+template <class ALF, class LAM>
+__host__ __device__ __forceinline__ void slow_rows(const FaceEig& e, ALF alf, LAM lamf, PairRows& r) {
+  const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
+  const double t[7] = {e.as * e.g1 * e.v2, omg * e.as * e.vn, omg * e.as * e.vt1, omg * e.as * e.vt2,
+                       omg * e.as * e.Bt1 - sra * e.af * e.by, omg * e.as * e.Bt2 - sra * e.af * e.bz, gm1 * e.as};
+  const double u[4] = {e.Gs, -(e.as * e.csl), -(e.cf * e.af * e.by * s), -(e.cf * e.af * e.bz * s)};
+#pragma unroll
+  for (int j = 0; j < 7; ++j) r.S[j] = qa2 * t[j];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r.A[j] = qa2 * u[j];
+  const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
+  const double Rs6 = e.as * (0.5 * e.v2 + e.csl2 - e.g2 * e.a2);
+  // corr += as sp; as vn sp - as csl sm; as vt1 sp - cf af by s sm; as vt2 sp - cf af bz s sm;
+  //         -cs af by isr sp; -cs af bz isr sp; Rs6 sp - Gs sm
+  const double lsp = e.as * lam[0] + e.as * e.vn * lam[1] + e.as * e.vt1 * lam[2] + e.as * e.vt2 * lam[3] -
+                     e.cs * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
+  const double lsm = -e.as * e.csl * lam[1] - e.cf * e.af * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gs * lam[6];
+  r.lfu = lsp + lsm;
+  r.lfl = lsp - lsm;
+  r.alu = alf(2);
+  r.all = alf(4);
+}
+template <class LAM>
+__host__ __device__ __forceinline__ void slow_post(const FaceEig& e, LAM lamf, const PairCot& c, FaceEigBar& eb) {
+  const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
+  const double t[7] = {e.as * e.g1 * e.v2, omg * e.as * e.vn, omg * e.as * e.vt1, omg * e.as * e.vt2,
+                       omg * e.as * e.Bt1 - sra * e.af * e.by, omg * e.as * e.Bt2 - sra * e.af * e.bz, gm1 * e.as};
+  const double u[4] = {e.Gs, -(e.as * e.csl), -(e.cf * e.af * e.by * s), -(e.cf * e.af * e.bz * s)};
+  const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
+  const double sp = c.fu + c.fl, sm = c.fu - c.fl;
+  eb.as += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
+                 (0.5 * e.v2 + e.csl2 - e.g2 * e.a2) * lam[6]) - sm * e.csl * lam[1];
+  eb.vn += e.as * sp * lam[1]; eb.vt1 += e.as * sp * lam[2]; eb.vt2 += e.as * sp * lam[3];
+  eb.csl -= e.as * sm * lam[1];
+  eb.csl2 += e.as * sp * lam[6]; eb.v2 += 0.5 * e.as * sp * lam[6]; eb.a2 -= e.g2 * e.as * sp * lam[6];
+  eb.cf -= sm * e.af * s * (e.by * lam[2] + e.bz * lam[3]);
+  eb.af -= sm * e.cf * s * (e.by * lam[2] + e.bz * lam[3]) + sp * e.cs * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+  eb.by -= sm * e.cf * e.af * s * lam[2] + sp * e.cs * e.af * e.isr * lam[4];
+  eb.bz -= sm * e.cf * e.af * s * lam[3] + sp * e.cs * e.af * e.isr * lam[5];
+  eb.cs -= sp * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]);
+  eb.isr -= sp * e.cs * e.af * (e.by * lam[4] + e.bz * lam[5]);
+  eb.Gs -= sm * lam[6];
+  double lt[7], lu[4];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) { eb.qa2 += c.lS[j] * t[j]; lt[j] = qa2 * c.lS[j]; }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) { eb.qa2 += c.lA[j] * u[j]; lu[j] = qa2 * c.lA[j]; }
+  eb.as += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
+                                        lt[5] * e.Bt2) + gm1 * lt[6];
+  eb.v2 += lt[0] * e.as * e.g1;
+  eb.vn += lt[1] * omg * e.as; eb.vt1 += lt[2] * omg * e.as; eb.vt2 += lt[3] * omg * e.as;
+  eb.Bt1 += lt[4] * omg * e.as; eb.Bt2 += lt[5] * omg * e.as;
+  eb.sr -= e.cs * e.af * (lt[4] * e.by + lt[5] * e.bz);
+  eb.cs -= e.sr * e.af * (lt[4] * e.by + lt[5] * e.bz);
+  eb.af -= sra * (lt[4] * e.by + lt[5] * e.bz);
+  eb.by -= sra * e.af * lt[4]; eb.bz -= sra * e.af * lt[5];
+  eb.Gs += lu[0];
+  eb.as -= lu[1] * e.csl; eb.csl -= lu[1] * e.as;
+  eb.cf -= e.af * s * (lu[2] * e.by + lu[3] * e.bz);
+  eb.af -= e.cf * s * (lu[2] * e.by + lu[3] * e.bz);
+  eb.by -= e.cf * e.af * s * lu[2]; eb.bz -= e.cf * e.af * s * lu[3];
+}
+
+// Alfven pair (m = 2, 6): S = (Ga/4, 0, -bz s/4, by s/4, 0, 0, 0), A = (-sr bz/4, sr by/4) on components 4, 5
+template <class ALF, class LAM>
+__host__ __device__ __forceinline__ void alfven_rows(const FaceEig& e, ALF alf, LAM lamf, PairRows& r) {
+  const double s = e.s;
+  r.S[0] = 0.25 * e.Ga; r.S[1] = 0.0; r.S[2] = -0.25 * e.bz * s; r.S[3] = 0.25 * e.by * s;
+  r.S[4] = 0.0; r.S[5] = 0.0; r.S[6] = 0.0;
+  r.A[0] = -0.25 * e.sr * e.bz; r.A[1] = 0.25 * e.sr * e.by; r.A[2] = 0.0; r.A[3] = 0.0;
+  // corr += (0, 0, -bz s sp, by s sp, -bz isr sm, by isr sm, -Ga sp)
+  const double lsp = -e.bz * s * lamf(2) + e.by * s * lamf(3) - e.Ga * lamf(6);
+  const double lsm = -e.bz * e.isr * lamf(4) + e.by * e.isr * lamf(5);
+  r.lfu = lsp + lsm;
+  r.lfl = lsp - lsm;
+  r.alu = alf(1);
+  r.all = alf(5);
+}
+template <class LAM>
+__host__ __device__ __forceinline__ void alfven_post(const FaceEig& e, LAM lamf, const PairCot& c, FaceEigBar& eb) {
+  const double s = e.s;
+  const double lam2 = lamf(2), lam3 = lamf(3), lam4 = lamf(4), lam5 = lamf(5), lam6 = lamf(6);
+  const double sp = c.fu + c.fl, sm = c.fu - c.fl;
+  eb.bz += -s * sp * lam2 - e.isr * sm * lam4;
+  eb.by += s * sp * lam3 + e.isr * sm * lam5;
+  eb.isr += sm * (-e.bz * lam4 + e.by * lam5);
+  eb.Ga -= sp * lam6;
+  eb.Ga += 0.25 * c.lS[0];
+  eb.bz += -0.25 * s * c.lS[2] - 0.25 * e.sr * c.lA[0];
+  eb.by += 0.25 * s * c.lS[3] + 0.25 * e.sr * c.lA[1];
+  eb.sr += -0.25 * e.bz * c.lA[0] + 0.25 * e.by * c.lA[1];
+}
+
+// entropy (m = 4): the single row L/2 = (1/2 - tau v^2/4, tau vn/2, tau vt1/2, tau vt2/2, tau Bt1/2, tau Bt2/2, -tau/2)
+template <class ALF, class LAM>
+__host__ __device__ __forceinline__ void entropy_rows(const FaceEig& e, ALF alf, LAM lamf, PairRows& r) {
+  const double ht = 0.5 * e.tau;
+  r.S[0] = 0.5 - 0.5 * ht * e.v2; r.S[1] = ht * e.vn; r.S[2] = ht * e.vt1; r.S[3] = ht * e.vt2;
+  r.S[4] = ht * e.Bt1; r.S[5] = ht * e.Bt2; r.S[6] = -ht;
+  r.A[0] = r.A[1] = r.A[2] = r.A[3] = 0.0;
+  // corr += (f4, vn f4, vt1 f4, vt2 f4, 0, 0, v2/2 f4)
+  r.lfu = lamf(0) + e.vn * lamf(1) + e.vt1 * lamf(2) + e.vt2 * lamf(3) + 0.5 * e.v2 * lamf(6);
+  r.lfl = 0.0;
+  r.alu = alf(3);
+  r.all = r.alu;
+}
+template <class LAM>
+__host__ __device__ __forceinline__ void entropy_post(const FaceEig& e, LAM lamf, const PairCot& c, FaceEigBar& eb) {
+  const double ht = 0.5 * e.tau;
+  const double f4 = c.fu;
+  eb.vn += f4 * lamf(1); eb.vt1 += f4 * lamf(2); eb.vt2 += f4 * lamf(3); eb.v2 += 0.5 * f4 * lamf(6);
+  const double lht = -0.5 * e.v2 * c.lS[0] + e.vn * c.lS[1] + e.vt1 * c.lS[2] + e.vt2 * c.lS[3] +
+                     e.Bt1 * c.lS[4] + e.Bt2 * c.lS[5] - c.lS[6];
+  eb.v2 -= 0.5 * ht * c.lS[0];
+  eb.vn += ht * c.lS[1]; eb.vt1 += ht * c.lS[2]; eb.vt2 += ht * c.lS[3]; eb.Bt1 += ht * c.lS[4];
+  eb.Bt2 += ht * c.lS[5];
+  eb.tau += 0.5 * lht;
+}
+
+using FastShape = PairShape<0, 4, true, 127>;
+using SlowShape = PairShape<0, 4, true, 127>;
+using AlfvenShape = PairShape<4, 2, true, 13>;
+using EntropyShape = PairShape<0, 0, false, 127>;
+
 // Reverse of face_corr (FP64) at one face: given the eigen scalars e, the
 // Lax-Friedrichs speeds alf(m), the differences dl and the cotangent lamf(j)
 // of corr, accumulates the cotangents of the eigen scalars (eb), of the LF
-// speeds (lal[7]) and, via emit, of the interface differences.  The face-state
-// cotangents follow from face_eig_vjp(eb).  PAIRS selects the eigen pairs
-// (bits: 1 fast, 2 slow, 4 Alfven, 8 entropy); the contributions of disjoint
-// selections add up to the full reverse, since corr is a sum over the pairs.
-// The eigen scalars are not kept live across a pair's reverse: reeig()
-// recomputes them from the face state after it (register pressure), and e
-// holds them on return.
-template <int PAIRS, class EIG, class ALF, class LAM, class DL, class EMIT>
-__host__ __device__ __forceinline__ void face_corr_vjp(FaceEig& e, EIG reeig, ALF alf, LAM lamf, DL dl,
-                                                       const Phys& ph, FaceEigBar& eb, double lal[7], EMIT emit) {
-  // ---------------- fast pair (m = 1, 7)
-  if (PAIRS & 1) {
-    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
-    double fu, fl;
-    {
-      const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
-      const double t[7] = {e.af * e.g1 * e.v2, omg * e.af * e.vn, omg * e.af * e.vt1, omg * e.af * e.vt2,
-                           omg * e.af * e.Bt1 + sra * e.as * e.by, omg * e.af * e.Bt2 + sra * e.as * e.bz, gm1 * e.af};
-      const double u[4] = {e.Gf, -(e.af * e.cf), e.csl * e.as * e.by * s, e.csl * e.as * e.bz * s};
-      double S[7], A[4];
-#pragma unroll
-      for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
-      const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
-      const double Rs6 = e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2);
-      // corr[0..6] = af sp; af vn sp - af cf sm; af vt1 sp + csl as by s sm; af vt2 sp + csl as bz s sm;
-      //              cs as by isr sp; cs as bz isr sp; Rs6 sp - Gf sm
-      const double lsp = e.af * lam[0] + e.af * e.vn * lam[1] + e.af * e.vt1 * lam[2] + e.af * e.vt2 * lam[3] +
-                         e.cs * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
-      const double lsm = -e.af * e.cf * lam[1] + e.csl * e.as * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gf * lam[6];
-      pair_rev<0, 4, true, 127>(S, A, alf(0), alf(6), lsp + lsm, lsp - lsm, dl, ph.eps, fu, fl, lS, lA, lal[0],
-                                lal[6], emit);
-    }
-    e = reeig();
-    const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
-    const double t[7] = {e.af * e.g1 * e.v2, omg * e.af * e.vn, omg * e.af * e.vt1, omg * e.af * e.vt2,
-                         omg * e.af * e.Bt1 + sra * e.as * e.by, omg * e.af * e.Bt2 + sra * e.as * e.bz, gm1 * e.af};
-    const double u[4] = {e.Gf, -(e.af * e.cf), e.csl * e.as * e.by * s, e.csl * e.as * e.bz * s};
-    const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
-    const double sp = fu + fl, sm = fu - fl;
-    eb.af += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
-                   (0.5 * e.v2 + e.cf2 - e.g2 * e.a2) * lam[6]) - sm * e.cf * lam[1];
-    eb.vn += e.af * sp * lam[1]; eb.vt1 += e.af * sp * lam[2]; eb.vt2 += e.af * sp * lam[3];
-    eb.cf -= e.af * sm * lam[1];
-    eb.cf2 += e.af * sp * lam[6]; eb.v2 += 0.5 * e.af * sp * lam[6]; eb.a2 -= e.g2 * e.af * sp * lam[6];
-    eb.csl += sm * e.as * s * (e.by * lam[2] + e.bz * lam[3]);
-    eb.as += sm * e.csl * s * (e.by * lam[2] + e.bz * lam[3]) + sp * e.cs * e.isr * (e.by * lam[4] + e.bz * lam[5]);
-    eb.by += sm * e.csl * e.as * s * lam[2] + sp * e.cs * e.as * e.isr * lam[4];
-    eb.bz += sm * e.csl * e.as * s * lam[3] + sp * e.cs * e.as * e.isr * lam[5];
-    eb.cs += sp * e.as * e.isr * (e.by * lam[4] + e.bz * lam[5]);
-    eb.isr += sp * e.cs * e.as * (e.by * lam[4] + e.bz * lam[5]);
-    eb.Gf -= sm * lam[6];
-    // rows S = qa2 t, A = qa2 u
-    double lt[7], lu[4];
-#pragma unroll
-    for (int j = 0; j < 7; ++j) { eb.qa2 += lS[j] * t[j]; lt[j] = qa2 * lS[j]; }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) { eb.qa2 += lA[j] * u[j]; lu[j] = qa2 * lA[j]; }
-    eb.af += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
-                                          lt[5] * e.Bt2) + gm1 * lt[6];
-    eb.v2 += lt[0] * e.af * e.g1;
-    eb.vn += lt[1] * omg * e.af; eb.vt1 += lt[2] * omg * e.af; eb.vt2 += lt[3] * omg * e.af;
-    eb.Bt1 += lt[4] * omg * e.af; eb.Bt2 += lt[5] * omg * e.af;
-    eb.sr += e.cs * e.as * (lt[4] * e.by + lt[5] * e.bz);
-    eb.cs += e.sr * e.as * (lt[4] * e.by + lt[5] * e.bz);
-    eb.as += sra * (lt[4] * e.by + lt[5] * e.bz);
-    eb.by += sra * e.as * lt[4]; eb.bz += sra * e.as * lt[5];
-    eb.Gf += lu[0];
-    eb.af -= lu[1] * e.cf; eb.cf -= lu[1] * e.af;
-    eb.csl += e.as * s * (lu[2] * e.by + lu[3] * e.bz);
-    eb.as += e.csl * s * (lu[2] * e.by + lu[3] * e.bz);
-    eb.by += e.csl * e.as * s * lu[2]; eb.bz += e.csl * e.as * s * lu[3];
+// speeds (lal[7]) and, via emit (five rounds per group), of the interface
+// differences.  The face-state cotangents follow from face_eig_vjp(eb).  The
+// pairs run in two groups, fast with slow and Alfven with entropy.
+template <class ALF, class LAM, class DL, class EMIT>
+__host__ __device__ __forceinline__ void face_corr_vjp(const FaceEig& e, ALF alf, LAM lamf, DL dl, const Phys& ph,
+                                                       FaceEigBar& eb, double lal[7], EMIT emit) {
+  {
+    PairRows rf, rs;
+    fast_rows(e, alf, lamf, rf);
+    slow_rows(e, alf, lamf, rs);
+    PairCot cf, cs;
+    pair2_rev<FastShape, true, SlowShape, true>(rf, rs, dl, ph.eps, cf, cs, emit);
+    fast_post(e, lamf, cf, eb);
+    slow_post(e, lamf, cs, eb);
+    lal[0] += cf.lalu; lal[6] += cf.lall; lal[2] += cs.lalu; lal[4] += cs.lall;
   }
-  if (PAIRS & 1) eb.pin_fast();
-  if (PAIRS & 1) { pin(lal[0]); pin(lal[6]); }
+  eb.pin_fast();
+  eb.pin_slow();
+  pin(lal[0]); pin(lal[6]); pin(lal[2]); pin(lal[4]);
   sched_fence();
-  // ---------------- slow pair (m = 3, 5)
-  if (PAIRS & 2) {
-    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
-    double fu, fl;
-    {
-      const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
-      const double t[7] = {e.as * e.g1 * e.v2, omg * e.as * e.vn, omg * e.as * e.vt1, omg * e.as * e.vt2,
-                           omg * e.as * e.Bt1 - sra * e.af * e.by, omg * e.as * e.Bt2 - sra * e.af * e.bz, gm1 * e.as};
-      const double u[4] = {e.Gs, -(e.as * e.csl), -(e.cf * e.af * e.by * s), -(e.cf * e.af * e.bz * s)};
-      double S[7], A[4];
-#pragma unroll
-      for (int j = 0; j < 7; ++j) S[j] = qa2 * t[j];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) A[j] = qa2 * u[j];
-      const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
-      const double Rs6 = e.as * (0.5 * e.v2 + e.csl2 - e.g2 * e.a2);
-      // corr += as sp; as vn sp - as csl sm; as vt1 sp - cf af by s sm; as vt2 sp - cf af bz s sm;
-      //         -cs af by isr sp; -cs af bz isr sp; Rs6 sp - Gs sm
-      const double lsp = e.as * lam[0] + e.as * e.vn * lam[1] + e.as * e.vt1 * lam[2] + e.as * e.vt2 * lam[3] -
-                         e.cs * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]) + Rs6 * lam[6];
-      const double lsm = -e.as * e.csl * lam[1] - e.cf * e.af * s * (e.by * lam[2] + e.bz * lam[3]) - e.Gs * lam[6];
-      pair_rev<0, 4, true, 127>(S, A, alf(2), alf(4), lsp + lsm, lsp - lsm, dl, ph.eps, fu, fl, lS, lA, lal[2],
-                                lal[4], emit);
-    }
-    e = reeig();
-    const double gm1 = -e.omg, omg = e.omg, qa2 = e.qa2, sra = e.sr * e.cs, s = e.s;
-    const double t[7] = {e.as * e.g1 * e.v2, omg * e.as * e.vn, omg * e.as * e.vt1, omg * e.as * e.vt2,
-                         omg * e.as * e.Bt1 - sra * e.af * e.by, omg * e.as * e.Bt2 - sra * e.af * e.bz, gm1 * e.as};
-    const double u[4] = {e.Gs, -(e.as * e.csl), -(e.cf * e.af * e.by * s), -(e.cf * e.af * e.bz * s)};
-    const double lam[7] = {lamf(0), lamf(1), lamf(2), lamf(3), lamf(4), lamf(5), lamf(6)};
-    const double sp = fu + fl, sm = fu - fl;
-    eb.as += sp * (lam[0] + e.vn * lam[1] + e.vt1 * lam[2] + e.vt2 * lam[3] +
-                   (0.5 * e.v2 + e.csl2 - e.g2 * e.a2) * lam[6]) - sm * e.csl * lam[1];
-    eb.vn += e.as * sp * lam[1]; eb.vt1 += e.as * sp * lam[2]; eb.vt2 += e.as * sp * lam[3];
-    eb.csl -= e.as * sm * lam[1];
-    eb.csl2 += e.as * sp * lam[6]; eb.v2 += 0.5 * e.as * sp * lam[6]; eb.a2 -= e.g2 * e.as * sp * lam[6];
-    eb.cf -= sm * e.af * s * (e.by * lam[2] + e.bz * lam[3]);
-    eb.af -= sm * e.cf * s * (e.by * lam[2] + e.bz * lam[3]) + sp * e.cs * e.isr * (e.by * lam[4] + e.bz * lam[5]);
-    eb.by -= sm * e.cf * e.af * s * lam[2] + sp * e.cs * e.af * e.isr * lam[4];
-    eb.bz -= sm * e.cf * e.af * s * lam[3] + sp * e.cs * e.af * e.isr * lam[5];
-    eb.cs -= sp * e.af * e.isr * (e.by * lam[4] + e.bz * lam[5]);
-    eb.isr -= sp * e.cs * e.af * (e.by * lam[4] + e.bz * lam[5]);
-    eb.Gs -= sm * lam[6];
-    double lt[7], lu[4];
-#pragma unroll
-    for (int j = 0; j < 7; ++j) { eb.qa2 += lS[j] * t[j]; lt[j] = qa2 * lS[j]; }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) { eb.qa2 += lA[j] * u[j]; lu[j] = qa2 * lA[j]; }
-    eb.as += lt[0] * e.g1 * e.v2 + omg * (lt[1] * e.vn + lt[2] * e.vt1 + lt[3] * e.vt2 + lt[4] * e.Bt1 +
-                                          lt[5] * e.Bt2) + gm1 * lt[6];
-    eb.v2 += lt[0] * e.as * e.g1;
-    eb.vn += lt[1] * omg * e.as; eb.vt1 += lt[2] * omg * e.as; eb.vt2 += lt[3] * omg * e.as;
-    eb.Bt1 += lt[4] * omg * e.as; eb.Bt2 += lt[5] * omg * e.as;
-    eb.sr -= e.cs * e.af * (lt[4] * e.by + lt[5] * e.bz);
-    eb.cs -= e.sr * e.af * (lt[4] * e.by + lt[5] * e.bz);
-    eb.af -= sra * (lt[4] * e.by + lt[5] * e.bz);
-    eb.by -= sra * e.af * lt[4]; eb.bz -= sra * e.af * lt[5];
-    eb.Gs += lu[0];
-    eb.as -= lu[1] * e.csl; eb.csl -= lu[1] * e.as;
-    eb.cf -= e.af * s * (lu[2] * e.by + lu[3] * e.bz);
-    eb.af -= e.cf * s * (lu[2] * e.by + lu[3] * e.bz);
-    eb.by -= e.cf * e.af * s * lu[2]; eb.bz -= e.cf * e.af * s * lu[3];
+  {
+    PairRows ra, rn;
+    alfven_rows(e, alf, lamf, ra);
+    entropy_rows(e, alf, lamf, rn);
+    PairCot ca, cn;
+    pair2_rev<AlfvenShape, true, EntropyShape, false>(ra, rn, dl, ph.eps, ca, cn, emit);
+    alfven_post(e, lamf, ca, eb);
+    entropy_post(e, lamf, cn, eb);
+    lal[1] += ca.lalu; lal[5] += ca.lall; lal[3] += cn.lalu;
   }
-  if (PAIRS & 2) eb.pin_slow();
-  if (PAIRS & 2) { pin(lal[2]); pin(lal[4]); }
-  sched_fence();
-  // ---------------- Alfven pair (m = 2, 6): S = (Ga/4, 0, -bz s/4, by s/4, 0, 0, 0),
-  //                  A = (-sr bz/4, sr by/4) on components 4, 5
-  if (PAIRS & 4) {
-    double lS[7] = {0, 0, 0, 0, 0, 0, 0}, lA[4] = {0, 0, 0, 0};
-    double fu, fl;
-    {
-      const double s = e.s;
-      const double S[7] = {0.25 * e.Ga, 0.0, -0.25 * e.bz * s, 0.25 * e.by * s, 0.0, 0.0, 0.0};
-      const double A[4] = {-0.25 * e.sr * e.bz, 0.25 * e.sr * e.by, 0.0, 0.0};
-      const double lam2 = lamf(2), lam3 = lamf(3), lam4 = lamf(4), lam5 = lamf(5), lam6 = lamf(6);
-      // corr += (0, 0, -bz s sp, by s sp, -bz isr sm, by isr sm, -Ga sp)
-      const double lsp = -e.bz * s * lam2 + e.by * s * lam3 - e.Ga * lam6;
-      const double lsm = -e.bz * e.isr * lam4 + e.by * e.isr * lam5;
-      pair_rev<4, 2, true, 13>(S, A, alf(1), alf(5), lsp + lsm, lsp - lsm, dl, ph.eps, fu, fl, lS, lA, lal[1],
-                               lal[5], emit);
-    }
-    e = reeig();
-    const double s = e.s;
-    const double lam2 = lamf(2), lam3 = lamf(3), lam4 = lamf(4), lam5 = lamf(5), lam6 = lamf(6);
-    const double sp = fu + fl, sm = fu - fl;
-    eb.bz += -s * sp * lam2 - e.isr * sm * lam4;
-    eb.by += s * sp * lam3 + e.isr * sm * lam5;
-    eb.isr += sm * (-e.bz * lam4 + e.by * lam5);
-    eb.Ga -= sp * lam6;
-    eb.Ga += 0.25 * lS[0];
-    eb.bz += -0.25 * s * lS[2] - 0.25 * e.sr * lA[0];
-    eb.by += 0.25 * s * lS[3] + 0.25 * e.sr * lA[1];
-    eb.sr += -0.25 * e.bz * lA[0] + 0.25 * e.by * lA[1];
-  }
-  if (PAIRS & 4) eb.pin_alfven();
-  if (PAIRS & 4) { pin(lal[1]); pin(lal[5]); }
-  sched_fence();
-  // ---------------- entropy (m = 4): L/2 = (1/2 - tau v^2/4, tau vn/2, tau vt1/2, tau vt2/2, tau Bt1/2, tau Bt2/2, -tau/2)
-  if (PAIRS & 8) {
-    double ll[7] = {0, 0, 0, 0, 0, 0, 0}, lz[4] = {0, 0, 0, 0};
-    double f4, f5, dummy = 0.0;
-    {
-      const double ht = 0.5 * e.tau;
-      const double l[7] = {0.5 - 0.5 * ht * e.v2, ht * e.vn, ht * e.vt1, ht * e.vt2, ht * e.Bt1, ht * e.Bt2, -ht};
-      const double Z4[4] = {0.0, 0.0, 0.0, 0.0};
-      // corr += (f4, vn f4, vt1 f4, vt2 f4, 0, 0, v2/2 f4)
-      const double lf4 = lamf(0) + e.vn * lamf(1) + e.vt1 * lamf(2) + e.vt2 * lamf(3) + 0.5 * e.v2 * lamf(6);
-      pair_rev<0, 0, false, 127>(l, Z4, alf(3), alf(3), lf4, 0.0, dl, ph.eps, f4, f5, ll, lz, lal[3], dummy, emit);
-    }
-    e = reeig();
-    const double ht = 0.5 * e.tau;
-    const double lam1 = lamf(1), lam2 = lamf(2), lam3 = lamf(3), lam6 = lamf(6);
-    eb.vn += f4 * lam1; eb.vt1 += f4 * lam2; eb.vt2 += f4 * lam3; eb.v2 += 0.5 * f4 * lam6;
-    const double lht = -0.5 * e.v2 * ll[0] + e.vn * ll[1] + e.vt1 * ll[2] + e.vt2 * ll[3] + e.Bt1 * ll[4] +
-                       e.Bt2 * ll[5] - ll[6];
-    eb.v2 -= 0.5 * ht * ll[0];
-    eb.vn += ht * ll[1]; eb.vt1 += ht * ll[2]; eb.vt2 += ht * ll[3]; eb.Bt1 += ht * ll[4]; eb.Bt2 += ht * ll[5];
-    eb.tau += 0.5 * lht;
-  }
-  if (PAIRS & 8) eb.pin_entropy();
-  if (PAIRS & 8) pin(lal[3]);
+  eb.pin_alfven();
+  eb.pin_entropy();
+  pin(lal[1]); pin(lal[5]); pin(lal[3]);
 }
 
 // ---------------------------------------------------------------------------

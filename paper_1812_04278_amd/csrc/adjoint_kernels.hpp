@@ -86,13 +86,9 @@ struct AdjSweepArgs {
 };
 
 constexpr int ADJ_NP = 11;   // cotangents of zone primitives and speeds (P_* order)
-// Threads per face (ADJ_ROLES): with 2, waves 0-3 (role 0) reverse the fast
-// and Alfven pairs and waves 4-7 (role 1) the slow pair and the entropy field;
-// with 1, every thread reverses all four.
-#ifndef ADJ_ROLES
-#define ADJ_ROLES 1
-#endif
-constexpr int ADJ_THREADS = ADJ_ROLES * SW_THREADS;
+// One thread per face; one 256-face tile per CU (LDS), so one wave per SIMD
+// with up to 512 registers per thread.
+constexpr int ADJ_THREADS = SW_THREADS;
 
 template <int AXIS>
 struct AdjLds {
@@ -109,7 +105,7 @@ struct AdjLds {
 // conflict-free classes), so the additions need no atomics and the order of
 // accumulation is fixed.
 template <int AXIS>
-__global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSweepArgs a) {
+__global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a) {
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;
   constexpr int NI = TA + 4;
@@ -142,8 +138,7 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
     return g.at(i, j, k);
   };
 
-  const int role = threadIdx.x / SW_THREADS;     // wave-uniform
-  const int tid = threadIdx.x % SW_THREADS;      // face of this thread
+  const int tid = threadIdx.x;                   // face of this thread
   // ---- (0) global loads first: the states of this thread's cells (the same
   //          cells it handles in (4), kept in registers) and the right-hand-side
   //          cotangents of its face, so that the latencies overlap
@@ -167,7 +162,7 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
     u[5] = B[CN]; u[6] = B[CT1]; u[7] = B[CT2];
   }
   double lk0[5], lk1[5], lT[2];
-  if (role == 0) {
+  {
     const int ia = wrap(a0 + fa, nA), ia1 = wrap(a0 + fa + 1, nA);
     const int ib = min(b0 + fb, nB - 1);
     const size_t g0 = gindex(ia, ib), g1 = gindex(ia1, ib);
@@ -193,15 +188,14 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
   }
   __syncthreads();
 
-  // ---- (2) per face: own interface differences (role 0: Delta F, role 1:
-  //          Delta q), incoming flux cotangents (role 0)
+  // ---- (2) per face: own interface differences, incoming flux cotangents
   const int cL = cidx(fa + 2, fb), cR = cidx(fa + 3, fb);
   {
     // zone variables: q in Q rows 0..6, F in rows 7..13; differences: Delta F
-    // in rows 0..6, Delta q in rows 7..13 (two roles: one half each)
-    constexpr int NV = SW_NQ / ADJ_ROLES;
-    auto src_row = [&](int v) { const int w = role * NV + v; return w < 7 ? w + 7 : w - 7; };
-    auto dst_row = [&](int v) { return role * NV + v; };
+    // in rows 0..6, Delta q in rows 7..13
+    constexpr int NV = SW_NQ;
+    auto src_row = [](int v) { return v < 7 ? v + 7 : v - 7; };
+    auto dst_row = [](int v) { return v; };
     double d0[NV], d1[NV];
     {
       const int c0 = cidx(fa, fb), c1 = cidx(fa + 1, fb);
@@ -216,7 +210,7 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
     // incoming cotangents: flux divergence transposed, lam_F_v(face i+1/2) = (lam_k_v(i+1) - lam_k_v(i))/h,
     // in the sweep frame; the B_t components carry the transport-flux cotangents
     double lam[7];
-    if (role == 0) {
+    {
       double lg[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) lg[v] = (lk1[v] - lk0[v]) * a.inv_h;
@@ -237,10 +231,8 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
 #pragma unroll
       for (int v = 0; v < NV; ++v) Q[dst_row(v) * NIF + iidx(TA + fa, fb)] = d1[v];
     }
-    if (role == 0) {
 #pragma unroll
-      for (int v = 0; v < 7; ++v) LF[v * NF + fidx(fa, fb)] = lam[v];
-    }
+    for (int v = 0; v < 7; ++v) LF[v * NF + fidx(fa, fb)] = lam[v];
   }
   for (int t = threadIdx.x; t < SW_NQ * NIF; t += ADJ_THREADS) LD[t] = 0.0;
   for (int t = threadIdx.x; t < ADJ_NP * NC; t += ADJ_THREADS) PB[t] = 0.0;
@@ -258,16 +250,11 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
   auto alf = [&](int m) { return fmax(fabs(xarg(m, cL)), fabs(xarg(m, cR))); };
   auto lamf = [&](int j) { return LF[j * NF + fidx(fa, fb)]; };
   auto dl = [&](int j, int k) -> double { return Q[j * NIF + iidx(fa + k, fb)]; };
-  // every role emits five times per pair; role 0 adds first, then role 1
+  // round k: every face adds its cotangent of interface difference fa + k
   auto emit = [&](int k, const double* v) {
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < ADJ_ROLES; ++r) {
-      __syncthreads();
-      if (role == r) {
-#pragma unroll
-        for (int j = 0; j < SW_NQ; ++j) LD[j * NIF + iidx(fa + k, fb)] += v[j];
-      }
-    }
+    for (int j = 0; j < SW_NQ; ++j) LD[j * NIF + iidx(fa + k, fb)] += v[j];
   };
   double lal[7] = {0, 0, 0, 0, 0, 0, 0};
   double lfp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -281,19 +268,14 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
       face_eig(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], fp[6], fp[7], a.ph, e);
       return e;
     };
-    FaceEig e = eig();
-    // two roles (256 registers per thread): recompute after each pair's reverse
-    // instead of keeping the scalars live; one role (512): keep them
-    auto reeig = [&]() { return ADJ_ROLES == 1 ? e : eig(); };
+    const FaceEig e = eig();
     FaceEigBar eb;
     eb.zero();
-    if (ADJ_ROLES == 1)  face_corr_vjp<1 | 2 | 4 | 8>(e, reeig, alf, lamf, dl, a.ph, eb, lal, emit);
-    else if (role == 0)  face_corr_vjp<1 | 4>(e, reeig, alf, lamf, dl, a.ph, eb, lal, emit);
-    else                 face_corr_vjp<2 | 8>(e, reeig, alf, lamf, dl, a.ph, eb, lal, emit);
+    face_corr_vjp(e, alf, lamf, dl, a.ph, eb, lal, emit);
     double fp[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (Pz[v * NC + cL] + Pz[v * NC + cR]);
-    face_eig_vjp(fp, a.ph, e, eb, lfp);   // linear in eb: the two roles' parts add up
+    face_eig_vjp(fp, a.ph, e, eb, lfp);
   }
   // zone-primitive cotangents of zones L (i) and R (i+1): face-state means,
   // LF speeds (branch of the larger argument; ties -> L) and transport-flux means
@@ -310,7 +292,7 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
     t[P_VN] += lal[m] * sx;
     if (sgm(m) != 0) t[P_CF + spi(m)] += lal[m] * sx * sgm(m);
   }
-  if (role == 0) {
+  {
     const double ltc1 = lamf(4), ltc2 = lamf(5);
     const double BnL = Pz[P_BN * NC + cL], BnR = Pz[P_BN * NC + cR];
     pl[P_BN] += 0.5 * (ltc1 * Pz[P_VT1 * NC + cL] + ltc2 * Pz[P_VT2 * NC + cL]);
@@ -335,17 +317,13 @@ __global__ __launch_bounds__(ADJ_THREADS, ADJ_ROLES) void adj_sweep_kernel(AdjSw
 #pragma unroll
     for (int v = 0; v < 8; ++v) lm[k][v] = own[k] ? (v < 5 ? a.lam_h : a.lam_Bz - 5 * g.N)[v * g.N + gcell[k]] : 0.0;
   }
-  // sub-rounds: zone L from role 0, then role 1; zone R likewise
+  // two sub-rounds: zone L, then zone R
+  __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 2 * ADJ_ROLES; ++r) {
-    __syncthreads();
-    if (role == r % ADJ_ROLES) {
-      double* dst = PB + (r < ADJ_ROLES ? cL : cR);
-      const double* src = r < ADJ_ROLES ? pl : pr;
+  for (int v = 0; v < ADJ_NP; ++v) PB[v * NC + cL] += pl[v];
+  __syncthreads();
 #pragma unroll
-      for (int v = 0; v < ADJ_NP; ++v) dst[v * NC] += src[v];
-    }
-  }
+  for (int v = 0; v < ADJ_NP; ++v) PB[v * NC + cR] += pr[v];
   __syncthreads();
 
   // ---- (4) per zone: gather, prologue reverse, add
