@@ -98,15 +98,15 @@ __host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const 
                                                       FaceEigBar eb, double out[8]) {
   const double rho = fp[0], vn = fp[1], vt1 = fp[2], vt2 = fp[3], Bn = fp[4], Bt1 = fp[5], Bt2 = fp[6], P = fp[7];
   const double gamma = ph.gamma;
-  const double isr = 1.0 / sqrt(rho);
+  const double isr = rsq_nr(rho);
   const double irho = isr * isr;
   const double a2 = e.a2;
-  const double ia2 = 1.0 / a2;
+  const double ia2 = rcp_w(a2);
   const double Bp2 = Bt1 * Bt1 + Bt2 * Bt2;
   const double b2 = (Bn * Bn + Bp2) * irho;
   const double dab = a2 - b2;
   const double Q = dab * dab + 4.0 * a2 * Bp2 * irho;
-  const double D = sqrt(Q);
+  const double D = sqrt_nr(Q);
   const double cf2 = 0.5 * (a2 + b2 + D);
   const double bv = e.by * vt1 + e.bz * vt2;
   const double s = e.s;
@@ -132,38 +132,40 @@ __host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const 
   l_ia2 += 0.25 * eb.qa2 + (gamma - 1.0) * eb.tau;
   // alpha_f, alpha_s (non-degenerate branch, unclamped interior)
   if (D >= ph.eps_B * ph.eps_B) {
-    const double r = dab / D;
+    const double iD = rcp_w(D);
+    const double r = dab * iD;
     const double cfa = 0.5 * (1.0 + r), csa = 0.5 * (1.0 - r);
     double l_r = 0.0;
-    if (cfa > 0.0 && cfa < 1.0 && e.af > 0.0) l_r += l_af * 0.5 / e.af * 0.5;
-    if (csa > 0.0 && csa < 1.0 && e.as > 0.0) l_r -= l_as * 0.5 / e.as * 0.5;
-    l_dab += l_r / D;
-    l_D -= l_r * r / D;
+    if (cfa > 0.0 && cfa < 1.0 && e.af > 0.0) l_r += l_af * 0.25 * rcp_w(e.af);
+    if (csa > 0.0 && csa < 1.0 && e.as > 0.0) l_r -= l_as * 0.25 * rcp_w(e.as);
+    l_dab += l_r * iD;
+    l_D -= l_r * r * iD;
   }
   // beta
   if (Bp2 > ph.eps_B) {
-    const double ib = 1.0 / sqrt(Bp2);
+    const double ib = rsq_nr(Bp2);
     l_Bt1 += l_by * ib;
     l_Bt2 += l_bz * ib;
     l_Bp2 -= 0.5 * ib * ib * ib * (l_by * Bt1 + l_bz * Bt2);
   }
   // csl = sqrt(csl2)
-  if (e.csl > 0.0) l_csl2 += l_csl * 0.5 / e.csl;
+  if (e.csl > 0.0) l_csl2 += l_csl * 0.5 * rcp_w(e.csl);
   // csl2 = a2 Bn^2 irho / cf2
   if (cf2 > 0.0) {
-    const double lN = l_csl2 / cf2;
-    l_cf2 -= l_csl2 * e.csl2 / cf2;
+    const double icf2 = rcp_w(cf2);
+    const double lN = l_csl2 * icf2;
+    l_cf2 -= l_csl2 * e.csl2 * icf2;
     l_a2 += lN * Bn * Bn * irho;
     l_Bn += lN * 2.0 * a2 * Bn * irho;
     l_irho += lN * a2 * Bn * Bn;
   }
   // cf = sqrt(cf2)
-  if (e.cf > 0.0) l_cf2 += l_cf * 0.5 / e.cf;
+  if (e.cf > 0.0) l_cf2 += l_cf * 0.5 * rcp_w(e.cf);
   // cf2 = (a2 + b2 + D)/2
   l_a2 += 0.5 * l_cf2; l_b2 += 0.5 * l_cf2; l_D += 0.5 * l_cf2;
   // D = sqrt(dab^2 + 4 a2 Bp2 irho)
   if (D > 0.0) {
-    const double lQ = l_D * 0.5 / D;
+    const double lQ = l_D * 0.5 * rcp_w(D);
     l_dab += 2.0 * dab * lQ;
     l_a2 += 4.0 * Bp2 * irho * lQ;
     l_Bp2 += 4.0 * a2 * irho * lQ;
@@ -177,7 +179,7 @@ __host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const 
   l_Bt1 += 2.0 * Bt1 * l_Bp2; l_Bt2 += 2.0 * Bt2 * l_Bp2;
   // ia2 = 1/a2, cs = sqrt(a2)
   l_a2 -= ia2 * ia2 * l_ia2;
-  if (e.cs > 0.0) l_a2 += l_cs * 0.5 / e.cs;
+  if (e.cs > 0.0) l_a2 += l_cs * 0.5 * rcp_w(e.cs);
   // a2 = gamma P irho
   l_P += gamma * irho * l_a2; l_irho += gamma * P * l_a2;
   // irho = isr^2, sr = rho isr, isr = rho^(-1/2)
@@ -590,10 +592,10 @@ __host__ __device__ __forceinline__ void face_corr_vjp(const FaceEig& e, ALF alf
 // ---------------------------------------------------------------------------
 // Inputs in the sweep frame: u = (rho, m_n, m_t1, m_t2, E, B_n, B_t1, B_t2).
 // lz[Z_NVAR] are the cotangents of the prologue outputs; out[8] += d/du.
-__host__ __device__ inline void zone_prologue_vjp(const double u[8], double gamma, const double lz[Z_NVAR],
+__host__ __device__ __forceinline__ void zone_prologue_vjp(const double u[8], double gamma, const double lz[Z_NVAR],
                                                   double out[8]) {
   const double rho = u[0], mn = u[1], mt1 = u[2], mt2 = u[3], E = u[4], Bn = u[5], Bt1 = u[6], Bt2 = u[7];
-  const double irho = 1.0 / rho;
+  const double irho = rcp_w(rho);
   const double vn = mn * irho, vt1 = mt1 * irho, vt2 = mt2 * irho;
   const double Bp2 = Bt1 * Bt1 + Bt2 * Bt2;
   const double B2 = Bn * Bn + Bp2;
@@ -602,27 +604,28 @@ __host__ __device__ inline void zone_prologue_vjp(const double u[8], double gamm
   const double vB = vn * Bn + vt1 * Bt1 + vt2 * Bt2;
   const double a2 = gamma * P * irho, b2 = B2 * irho, bn2 = Bn * Bn * irho;
   const double dab = a2 - b2;
-  const double D = sqrt(dab * dab + 4.0 * a2 * (Bp2 * irho));
+  const double D = sqrt_nr(dab * dab + 4.0 * a2 * (Bp2 * irho));
   const double cf2 = 0.5 * (a2 + b2 + D);
-  const double cs2 = cf2 > 0.0 ? a2 * bn2 / cf2 : 0.0;
-  const double cf = sqrt(cf2), cA = sqrt(bn2), cs = sqrt(cs2);
+  const double icf2 = cf2 > 0.0 ? rcp_w(cf2) : 0.0;
+  const double cs2 = a2 * bn2 * icf2;
+  const double cf = sqrt_nr(cf2), cA = sqrt_nr(bn2), cs = sqrt_nr(cs2);
   double l_rho = lz[Z_RHO], l_mn = lz[Z_MN], l_mt1 = lz[Z_MT1], l_mt2 = lz[Z_MT2];
   double l_Bt1 = lz[Z_BT1], l_Bt2 = lz[Z_BT2], l_E = lz[Z_E];
   double l_vn = lz[Z_VN], l_vt1 = lz[Z_VT1], l_vt2 = lz[Z_VT2], l_Bn = lz[Z_BN], l_P = lz[Z_P];
   double l_cf2 = 0.0, l_cs2 = 0.0, l_bn2 = 0.0, l_a2 = 0.0, l_b2 = 0.0, l_D = 0.0, l_dab = 0.0;
   double l_irho = 0.0, l_Bp2 = 0.0, l_B2 = 0.0, l_Pstar = 0.0, l_vB = 0.0;
   // speeds
-  if (cf > 0.0) l_cf2 += lz[Z_CF] * 0.5 / cf;
-  if (cA > 0.0) l_bn2 += lz[Z_CA] * 0.5 / cA;
-  if (cs > 0.0) l_cs2 += lz[Z_CS] * 0.5 / cs;
+  if (cf > 0.0) l_cf2 += lz[Z_CF] * 0.5 * rcp_w(cf);
+  if (cA > 0.0) l_bn2 += lz[Z_CA] * 0.5 * rcp_w(cA);
+  if (cs > 0.0) l_cs2 += lz[Z_CS] * 0.5 * rcp_w(cs);
   if (cf2 > 0.0) {
-    l_a2 += l_cs2 * bn2 / cf2;
-    l_bn2 += l_cs2 * a2 / cf2;
-    l_cf2 -= l_cs2 * cs2 / cf2;
+    l_a2 += l_cs2 * bn2 * icf2;
+    l_bn2 += l_cs2 * a2 * icf2;
+    l_cf2 -= l_cs2 * cs2 * icf2;
   }
   l_a2 += 0.5 * l_cf2; l_b2 += 0.5 * l_cf2; l_D += 0.5 * l_cf2;
   if (D > 0.0) {
-    const double lQ = l_D * 0.5 / D;
+    const double lQ = l_D * 0.5 * rcp_w(D);
     l_dab += 2.0 * dab * lQ;
     l_a2 += 4.0 * Bp2 * irho * lQ;
     l_Bp2 += 4.0 * a2 * irho * lQ;

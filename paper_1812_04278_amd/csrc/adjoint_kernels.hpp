@@ -288,9 +288,15 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs 
     const bool left = fabs(xl) >= fabs(xr);
     const double x = left ? xl : xr;
     const double sx = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
-    double* t = left ? pl : pr;
-    t[P_VN] += lal[m] * sx;
-    if (sgm(m) != 0) t[P_CF + spi(m)] += lal[m] * sx * sgm(m);
+    // to the zone of the larger argument (weights instead of a pointer select,
+    // which would move pl, pr to scratch memory)
+    const double gl = left ? lal[m] * sx : 0.0, gr = left ? 0.0 : lal[m] * sx;
+    pl[P_VN] += gl;
+    pr[P_VN] += gr;
+    if (sgm(m) != 0) {
+      pl[P_CF + spi(m)] += gl * sgm(m);
+      pr[P_CF + spi(m)] += gr * sgm(m);
+    }
   }
   {
     const double ltc1 = lamf(4), ltc2 = lamf(5);
