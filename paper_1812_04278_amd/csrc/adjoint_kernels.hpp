@@ -174,9 +174,8 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs 
 
   // ---- (1) forward zone prologue into LDS
 #pragma unroll
-  for (int k = 0; k < NCELL; ++k) {
-    const int cell = threadIdx.x + k * ADJ_THREADS;
-    if (cell >= NC) break;
+  for (int k = 0; k < NCELL; ++k) {   // branch-free: surplus threads repeat the last cell (equal values)
+    const int cell = min(threadIdx.x + k * ADJ_THREADS, (unsigned)NC - 1);
     const double* u = uz[k];
     double z[Z_NVAR];
     zone_prologue(u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7], a.ph.gamma, z);
@@ -364,16 +363,17 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs 
     lz[Z_CS] += PB[P_CS * NC + cz];
   };
 #pragma unroll
-  for (int k = 0; k < NCELL; ++k) {
-    if (!own[k]) continue;
-    const int cell = threadIdx.x + k * ADJ_THREADS;
+  for (int k = 0; k < NCELL; ++k) {   // branch-free over the cells (the stores are predicated)
+    const int cell = min(threadIdx.x + k * ADJ_THREADS, (unsigned)NC - 1);
     int aa, bb;
     if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
     else           { bb = cell % TB; aa = cell / TB; }
     double lz[Z_NVAR];
 #pragma unroll
     for (int v = 0; v < Z_NVAR; ++v) lz[v] = 0.0;
-    for (int q = aa; q < span; q += nA) gather(q, bb, lz);   // positions of the same zone
+    gather(aa, bb, lz);
+    if (span > nA)   // a tile that wraps onto itself: other positions of the same zone
+      for (int q = aa + nA; q < span; q += nA) gather(q, bb, lz);
     double lu[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     zone_prologue_vjp(uz[k], a.ph.gamma, lz, lu);
     double out[8];
@@ -381,8 +381,10 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs 
     out[1 + CN] = lu[1]; out[1 + CT1] = lu[2]; out[1 + CT2] = lu[3];
     out[4] = lu[4];
     out[5 + CN] = lu[5]; out[5 + CT1] = lu[6]; out[5 + CT2] = lu[7];
+    if (own[k]) {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) (v < 5 ? a.lam_h : a.lam_Bz - 5 * g.N)[v * g.N + gcell[k]] = lm[k][v] + out[v];
+      for (int v = 0; v < 8; ++v) (v < 5 ? a.lam_h : a.lam_Bz - 5 * g.N)[v * g.N + gcell[k]] = lm[k][v] + out[v];
+    }
   }
 }
 
