@@ -31,6 +31,10 @@ FLOPS_PER_FACE = 2060
 # writes the stage state (8) and the accumulator (8, stages 0-1).
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per sweep dispatch on the 256^3 FP64 workload, averaged over the
+# three axes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain copy of
+# known size gives), profiles/fp64_step_256cube_pmc_traffic.md.
+SWEEP_TRAFFIC_BYTES_256 = 2.417e9
 
 
 def log(*a):
@@ -289,7 +293,8 @@ def main():
         "config": {"workload": f"{n}^3 periodic MHD box, Mach 2, beta~1, WENO5-JS + CT, SSP-RK3 CFL 0.4, FP64",
                    "grid": n, "steps": args.steps, "precision": "fp64", "seed": 1},
         "roofline": {"kernel": "sweep", "bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                     "traffic": SWEEP_TRAFFIC_BYTES_256 if n == 256 else None,
                      "avg_ms": round(sweep_ms, 4), "launches": nsw, "flops_per_launch": flops},
         "roofline_update": {"kernel": "update", "bound": "hbm",
                             "achieved": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,

@@ -7,6 +7,11 @@
 * With epsilon -> infinity the weights become the linear ones and the flux is the
   linear fifth-order upwind flux (2, -13, 47, 27, -3)/60.
 * A 1D scalar advection run with the oracle's split flux converges at 5th order.
+* WENO-Z (reading R13: alpha_k = d_k (1 + (tau_5 / (eps_Z + IS_k))^2)) equals the
+  textbook WENO-Z reconstruction of Borges, Carmona, Costa & Don (2008) with the
+  exponent 2 and eps_Z/12 (the ratio tau_5/IS_k is unchanged by the factor 12),
+  written here from its own definition; with eps_Z -> infinity it is the linear
+  upwind flux; and it advects at 5th order.
 """
 import math
 
@@ -28,6 +33,23 @@ def textbook_js_plus(f, eps):
     b1 = 13 / 12 * (fm1 - 2 * f0 + fp1) ** 2 + 0.25 * (fm1 - fp1) ** 2
     b2 = 13 / 12 * (f0 - 2 * fp1 + fp2) ** 2 + 0.25 * (3 * f0 - 4 * fp1 + fp2) ** 2
     a0, a1, a2 = 0.1 / (eps + b0) ** 2, 0.6 / (eps + b1) ** 2, 0.3 / (eps + b2) ** 2
+    s = a0 + a1 + a2
+    return (a0 * q0 + a1 * q1 + a2 * q2) / s
+
+
+def textbook_z_plus(f, eps):
+    """Left-biased WENO5-Z value at i+1/2 from f_{i-2..i+2} (Borges et al. 2008, exponent 2)."""
+    fm2, fm1, f0, fp1, fp2 = f
+    q0 = (2 * fm2 - 7 * fm1 + 11 * f0) / 6
+    q1 = (-fm1 + 5 * f0 + 2 * fp1) / 6
+    q2 = (2 * f0 + 5 * fp1 - fp2) / 6
+    b0 = 13 / 12 * (fm2 - 2 * fm1 + f0) ** 2 + 0.25 * (fm2 - 4 * fm1 + 3 * f0) ** 2
+    b1 = 13 / 12 * (fm1 - 2 * f0 + fp1) ** 2 + 0.25 * (fm1 - fp1) ** 2
+    b2 = 13 / 12 * (f0 - 2 * fp1 + fp2) ** 2 + 0.25 * (3 * f0 - 4 * fp1 + fp2) ** 2
+    tau = (b0 - b2).abs()
+    a0 = 0.1 * (1 + (tau / (b0 + eps)) ** 2)
+    a1 = 0.6 * (1 + (tau / (b1 + eps)) ** 2)
+    a2 = 0.3 * (1 + (tau / (b2 + eps)) ** 2)
     s = a0 + a1 + a2
     return (a0 * q0 + a1 * q1 + a2 * q2) / s
 
@@ -69,9 +91,9 @@ def test_linear_limit_is_upwind5():
     np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=1e-14)
 
 
-def _advect(n, t_end, cfl=0.4):
+def _advect(n, t_end, cfl=0.4, weights="js"):
     """u_t + u_x = 0 on [0,1), f(u) = u, alpha = 1, SSP-RK3, dt ~ h^(5/3)."""
-    cfg = mhd.Config(n, 1, 1, 1.0 / n)
+    cfg = mhd.Config(n, 1, 1, 1.0 / n, weights=weights)
     h = 1.0 / n
     x = (torch.arange(n, dtype=T64) + 0.5) * h
     u0 = torch.sin(2 * math.pi * x)
@@ -108,3 +130,41 @@ def test_lax_friedrichs_speed_bounds_both_zones():
         nxt = mhd.at(lam.movedim(-1, 0), 1, axis).movedim(0, -1)
         assert bool((a >= lam.abs()).all()) and bool((a >= nxt.abs()).all())
         assert bool(((a == lam.abs()) | (a == nxt.abs())).all())
+
+
+def test_phiN_wenoz_equals_textbook_z():
+    cfg = mhd.Config(4, 4, 4, 0.25, weights="z", eps_Z=1e-12)
+    for smooth in (False, True):
+        fp = split_values(11, 5000, smooth)
+        fmv = split_values(12, 5000, smooth)
+        Fs = [fp[k] + fmv[k] for k in range(6)]
+        qs = [fp[k] - fmv[k] for k in range(6)]
+        got = mhd.weno_split_flux(Fs, qs, torch.ones(()), cfg)
+        ref = textbook_z_plus([fp[k] for k in range(0, 5)], cfg.eps_Z / 12) + \
+            textbook_z_plus([fmv[k] for k in range(5, 0, -1)], cfg.eps_Z / 12)
+        np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=2e-14 * (1 + float(ref.abs().max())))
+    # and with the paper's eps_Z = 1e-40, including constant stencils (tau_5 = IS_k = 0)
+    cfg = mhd.Config(4, 4, 4, 0.25, weights="z")
+    f = split_values(13, 2000, True)
+    f[:, :100] = 0.7
+    Fs = [f[k] for k in range(6)]
+    got = mhd.weno_split_flux(Fs, Fs, torch.ones(()), cfg)
+    ref = textbook_z_plus([f[k] for k in range(0, 5)], cfg.eps_Z / 12)
+    assert bool(torch.isfinite(got).all())
+    np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=2e-14 * (1 + float(ref.abs().max())))
+
+
+def test_wenoz_linear_limit_is_upwind5():
+    cfg = mhd.Config(4, 4, 4, 0.25, weights="z", eps_Z=1e30)
+    g = torch.Generator().manual_seed(14)
+    f = torch.randn(6, 1000, generator=g, dtype=T64)
+    Fs = [f[k] for k in range(6)]
+    got = mhd.weno_split_flux(Fs, Fs, torch.ones(()), cfg)
+    ref = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60
+    np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=1e-14)
+
+
+def test_wenoz_scalar_advection_fifth_order():
+    e = [_advect(n, 0.5, weights="z") for n in (20, 40, 80)]
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert orders[-1] > 4.6, (e, orders)
