@@ -131,9 +131,11 @@ __host__ __device__ __forceinline__ void zone_prologue(double rho, double mn, do
 // Jiang-Shu weights alpha_k = d_k / s_k^2 give
 //   omega_0 = s1^2 s2^2 / Q,  omega_2 = 3 s0^2 s1^2 / Q,
 //   Q = s1^2 s2^2 + 6 s0^2 s2^2 + 3 s0^2 s1^2,
-// one reciprocal instead of four divisions.  WENO-Z: alpha_k = d_k (1 + (tau_5/(eps_Z + IS_k))^2).
+// one reciprocal instead of four divisions.  WENO-Z: alpha_k = d_k (1 + (tau_5/(eps_Z + IS_k))^2),
+// always evaluated in FP64: eps_Z (1e-40 in the paper) lies below the FP32 range, and
+// 1/(eps_Z + IS_k) of a constant stencil would overflow there.
 template <bool WENO_Z, typename T>
-__host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, T eps_Z) {
+__host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps_Z) {
   const T t0 = a - b, t1 = a - T(3) * b;
   const T t2 = b - c, t3 = b + c;
   const T t4 = c - d, t5 = T(3) * c - d;
@@ -156,6 +158,8 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, T eps_Z) {
     const T cY = fma(T(0.25), p01, fma(T(-1.0 / 12.0), p12, T(-0.5) * p02));
     return rq * fma(cY, Y, (p12 * T(1.0 / 3.0)) * X);
   } else {
+    if constexpr (sizeof(T) == 4)
+      return T(phiN<true, double>(double(a), double(b), double(c), double(d), double(eps), eps_Z));
     const T IS0 = T(13) * t0 * t0 + T(3) * t1 * t1;
     const T IS1 = T(13) * t2 * t2 + T(3) * t3 * t3;
     const T IS2 = T(13) * t4 * t4 + T(3) * t5 * t5;
@@ -170,7 +174,7 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, T eps_Z) {
 // phi^- - phi^+ of eq. (FWENO) from the split values of one characteristic
 // field: v[0..3] = Delta F^+ at i-3/2 .. i+3/2, v[4..7] = Delta F^- at i-1/2 .. i+5/2.
 template <bool WENO_Z, typename T>
-__host__ __device__ __forceinline__ T weno_split(const T v[8], T eps, T eps_Z) {
+__host__ __device__ __forceinline__ T weno_split(const T v[8], T eps, double eps_Z) {
   return phiN<WENO_Z>(v[7], v[6], v[5], v[4], eps, eps_Z) - phiN<WENO_Z>(v[0], v[1], v[2], v[3], eps, eps_Z);
 }
 
@@ -269,7 +273,8 @@ __host__ __device__ __forceinline__ void split_pair(const T S[7], const T A[4], 
 template <bool WENO_Z, typename T, class DL>
 __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[7], DL dl, const Phys& ph,
                                                    double corr[7]) {
-  const T eps = T(ph.eps), epsZ = T(ph.eps_Z);
+  const T eps = T(ph.eps);
+  const double epsZ = ph.eps_Z;
   const double gm1 = -e.omg;
   const double sra = e.sr * e.cs;
   T vu[8], vl[8];

@@ -334,6 +334,7 @@ wm_status check_adjoint(wm_patch* p, void* adj) {
   if (!p) return fail(WM_ERR_ARG, "null patch");
   if (!adj || reinterpret_cast<uintptr_t>(adj) % kAlign) return fail(WM_ERR_ARG, "adjoint scratch null or misaligned");
   if (p->cfg.nx < 3 || p->cfg.ny < 3 || p->cfg.nz < 3) return fail(WM_ERR_ARG, "the adjoint needs grid sizes >= 3");
+  if (p->cfg.weights != WM_WENO_JS) return fail(WM_ERR_ARG, "the adjoint differentiates the Jiang-Shu weights only");
   return WM_OK;
 }
 

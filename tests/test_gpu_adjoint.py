@@ -192,6 +192,17 @@ def test_full_size_sampled_rhs_vjp_128():
     assert float(out[:, ~near].abs().max()) == 0.0
 
 
+def test_adjoint_rejects_wenoz():
+    """The adjoint linearises the Jiang-Shu weights only: other weights are an error."""
+    f = fields(12, seed=15, v_rms=1.0)
+    U, cfg = oracle_state(f)
+    h, b = to_gpu_state(U)
+    p = B.Patch(B.config(12, weights=B.WM_WENO_Z))
+    lam = torch.zeros((8, 12, 12, 12), dtype=torch.float64).cuda()
+    with pytest.raises(B.WmError):
+        p.rhs_vjp(h, b, lam)
+
+
 def test_adjoint_deterministic():
     f = fields(24, seed=15, v_rms=1.0)
     U, cfg = oracle_state(f)

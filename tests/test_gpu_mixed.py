@@ -55,6 +55,30 @@ def test_mixed_one_step_32():
     assert max(errs.values()) <= 1e-8, errs
 
 
+def test_mixed_wenoz_one_step_32():
+    """Mixed precision with WENO-Z weights (evaluated in FP64: eps_Z = 1e-40 lies
+    below the FP32 range), including a region of constant state where every
+    smoothness indicator is zero."""
+    import dataclasses
+    say("mixed WENO-Z, one step 32^3 Mach 0.1 with a constant block")
+    f = fields(32, seed=1, v_rms=0.1)
+    f.v[:, 8:20, 8:20, :] = 0.0
+    f.rho[8:20, 8:20, :] = 1.0
+    f.A[:, 6:22, 6:22, :] = 0.0
+    U, cfg = oracle_state(f)
+    cfg = dataclasses.replace(cfg, weights="z")
+    nz, ny, nx = f.rho.shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=1.0 / nx, precision=B.WM_MIXED, weights=B.WM_WENO_Z))
+    p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+    p.step()
+    U1, _ = mhd.step(U, cfg)
+    st = p.state()
+    assert all(bool(torch.isfinite(torch.as_tensor(st[k])).all()) for k in st)
+    errs = state_errors(st, U1)
+    say("  ", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-8, errs
+
+
 def test_mixed_ten_steps_64_mach2():
     say("mixed, 10 steps 64^3 Mach 2")
     f = fields(64, seed=1, v_rms=2.0)
