@@ -210,6 +210,71 @@ def adjoint_cost(n: int = 128, steps: int = 20, ckpt: int = 5):
             "loss": J, "grad_norm_A": float(gA.norm()), "grad_norm_v": float(gv.norm())}
 
 
+def c5(steps: int = 10, ckpt: int = 5, n: int = 512):
+    """The 512^3 workload: Mach 5 (v_rms 5, |k| <= 8), beta 0.5.  Throughput of
+    the FP32-state mixed form (WM_MIXED_F32STATE) over `steps` steps with the
+    update kernel's HBM rate, then the checkpointed FP64 adjoint of the same
+    steps (stage states recomputed: memory) and its cost ratio to the FP64
+    forward."""
+    import math
+    import torch
+    from paper_1812_04278_amd import binding, inputs, rollout
+    B0 = tuple(math.sqrt(2.4 / 1.25) * x for x in (1.0, 0.5, 0.0))
+    log(f"bench c5: generating {n}^3 inputs")
+    f = inputs.random_fields(n, seed=1, v_rms=5.0, kmax=8, B0=B0)
+    out = {"workload": f"{n}^3 periodic box, Mach 5, |k| <= 8, beta 0.5, {steps} SSP-RK3 steps"}
+    rho = torch.as_tensor(f.rho).to("cuda:0")
+    v0 = torch.as_tensor(f.v).to("cuda:0")
+    A0 = torch.as_tensor(f.A).to("cuda:0")
+    del f.rho, f.v, f.A
+    p = binding.Patch(binding.config(n, precision=binding.WM_MIXED_F32STATE), device="cuda:0")
+    p.init_from_potential(rho, v0, A0, 0.6, B0)
+    p.step()
+    p.init_from_potential(rho, v0, A0, 0.6, B0)
+    p.profile(True)
+    ms = timed_steps(p, steps)
+    rep = p.profile_report()
+    p.profile(False)
+    d = p.diagnostics(raise_unphysical=False)
+    nup, msup = rep["update"]
+    upd_ms = msup / max(nup, 1)
+    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * 4 * float(n) ** 3
+    out["f32state"] = {"value": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 3), "unit": "Mzone-updates/s",
+                       "ms_per_step": round(ms / steps, 3),
+                       "sweep_avg_ms": round(rep["sweep"][1] / max(rep["sweep"][0], 1), 4),
+                       "update_avg_ms": round(upd_ms, 4),
+                       "update_hbm_gbs": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1),
+                       "update_hbm_frac": round(upd_bytes / (upd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                       "max_divb": d["max_divb"], "n_unphysical": d["n_unphysical"], "min_p": d["min_p"]}
+    del p
+    torch.cuda.empty_cache()
+    log("bench c5: FP64 forward and checkpointed adjoint")
+    p = binding.Patch(binding.config(n), device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.init_from_potential(rho, v0, A0, 0.6, B0)
+    for _ in range(steps):
+        p.step()
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) * 1e3
+    A = A0.clone().requires_grad_(True)
+    v = v0.clone().requires_grad_(True)
+    t1 = time.perf_counter()
+    hyd, bf, bc = rollout.rollout(A, v, rho, p, steps, ckpt_every=ckpt, P0=0.6, B0=B0, store_stages=False)
+    J = (1.0 / n) ** 3 * ((hyd[0] - 1.0) ** 2).sum()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gA, gv = torch.autograd.grad(J, [A, v])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out["adjoint_fp64"] = {"forward_ms": round(fwd, 1), "checkpointed_forward_ms": round((t2 - t1) * 1e3, 1),
+                           "backward_ms": round((t3 - t2) * 1e3, 1),
+                           "ratio_backward_to_forward": round((t3 - t2) * 1e3 / fwd, 3),
+                           "loss": "h^3 sum (rho_T - 1)^2", "stage_states": "recomputed",
+                           "grad_finite": bool(torch.isfinite(gA).all() and torch.isfinite(gv).all())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +287,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64-vs-mixed comparison")
     ap.add_argument("--no-convergence", action="store_true", help="skip the fast-wave convergence table")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
+    ap.add_argument("--c5", action="store_true",
+                    help="also run the 512^3 Mach-5 workload (FP32 state, FP64 adjoint); several minutes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -313,6 +380,8 @@ def main():
     if not args.no_adjoint:
         log("bench: adjoint cost (128^3, 20 steps, checkpoints every 5)")
         out["adjoint"] = adjoint_cost()
+    if args.c5:
+        out["c5"] = c5()
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written, for scaling
         # the FETCH_SIZE / WRITE_SIZE counters of the kernels above

@@ -12,8 +12,10 @@
  * Grid: nx * ny * nz zones, periodic in all three directions, one zone size h
  * for every direction (Sect. 2.3 divides every difference by the same Delta x).
  * Every array is structure-of-arrays, [component][z][y][x] with x contiguous,
- * double precision, in device memory of the GPU that is current when the
- * patch is created.  Conventions of the field components:
+ * in device memory of the GPU that is current when the patch is created, and
+ * double precision -- except the bound state (hydro, bface, bcell) and the
+ * stage states of wm_step_record, which hold floats when the configuration's
+ * precision is WM_MIXED_F32STATE.  Conventions of the field components:
  *   hydro  [5][nz][ny][nx]  rho, m_x, m_y, m_z, E            (zone centred)
  *   bface  [3][nz][ny][nx]  b_x at (i+1/2, j, k), b_y at (i, j+1/2, k),
  *                           b_z at (i, j, k+1/2)              (face centred)
@@ -54,10 +56,15 @@ typedef enum {
 
 typedef enum {
   WM_FP64 = 0,              /* everything in double precision                */
-  WM_MIXED = 1              /* FP64 state, pressure recovery, eigenvector
+  WM_MIXED = 1,             /* FP64 state, pressure recovery, eigenvector
                                renormalisation and central flux; FP32
                                characteristic projections, WENO weights and
                                split fluxes                                   */
+  WM_MIXED_F32STATE = 2     /* the WM_MIXED arithmetic with the state (hydro,
+                               bface, bcell), the stage states, the RK
+                               accumulator and the face fluxes stored in FP32
+                               (float arrays); increments and divergences are
+                               formed in FP64 before rounding to the state    */
 } wm_precision;
 
 typedef enum {
@@ -107,8 +114,9 @@ wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch,
                           size_t scratch_bytes, wm_patch** out);
 wm_status wm_patch_destroy(wm_patch* p);
 
-/* Binds the caller's state arrays (layouts above).  hydro and bface are
- * read and advanced in place by wm_rk_stage(2) / wm_step; bcell is written. */
+/* Binds the caller's state arrays (layouts above; element type double, or
+ * float for WM_MIXED_F32STATE).  hydro and bface are read and advanced in
+ * place by wm_rk_stage(2) / wm_step; bcell is written. */
 wm_status wm_bind_state(wm_patch* p, void* hydro, void* bface, void* bcell);
 
 /* Initial state from primitive fields and an edge vector potential

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwenomhd.so")
 
 WM_OK, WM_ERR_ARG, WM_ERR_HIP, WM_ERR_UNPHYSICAL, WM_ERR_STATE = 0, -1, -2, -3, -4
-WM_FP64, WM_MIXED = 0, 1
+WM_FP64, WM_MIXED, WM_MIXED_F32STATE = 0, 1, 2
 WM_WENO_JS, WM_WENO_Z = 0, 1
 
 SYMBOLS = [
@@ -123,8 +123,8 @@ def _ptr(t: torch.Tensor):
 class Patch:
     """A periodic box on one GPU: state tensors, scratch and the C patch handle.
 
-    State (float64, on ``device``): ``hydro`` [5, nz, ny, nx] (rho, m, E),
-    ``bface`` [3, nz, ny, nx], ``bcell`` [3, nz, ny, nx]."""
+    State (on ``device``; float64, or float32 for WM_MIXED_F32STATE): ``hydro``
+    [5, nz, ny, nx] (rho, m, E), ``bface`` [3, nz, ny, nx], ``bcell`` [3, nz, ny, nx]."""
 
     def __init__(self, cfg: WmConfig, device="cuda", stream: torch.cuda.Stream | None = None):
         self.lib = load()
@@ -136,9 +136,10 @@ class Patch:
         if nbytes == 0:
             raise WmError(WM_ERR_ARG, "invalid configuration")
         self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.hydro = torch.zeros((5,) + shape, dtype=torch.float64, device=self.device)
-        self.bface = torch.zeros((3,) + shape, dtype=torch.float64, device=self.device)
-        self.bcell = torch.zeros((3,) + shape, dtype=torch.float64, device=self.device)
+        self.dtype = torch.float32 if cfg.precision == WM_MIXED_F32STATE else torch.float64
+        self.hydro = torch.zeros((5,) + shape, dtype=self.dtype, device=self.device)
+        self.bface = torch.zeros((3,) + shape, dtype=self.dtype, device=self.device)
+        self.bcell = torch.zeros((3,) + shape, dtype=self.dtype, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.wm_patch_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -176,9 +177,9 @@ class Patch:
         _check(self.lib.wm_refresh_zone_field(self.handle))
 
     def state(self):
-        """Host copy as the oracle's dict (rho, m, E, b)."""
-        h = self.hydro.cpu()
-        return dict(rho=h[0], m=h[1:4].clone(), E=h[4], b=self.bface.cpu())
+        """Host copy (float64) as the oracle's dict (rho, m, E, b)."""
+        h = self.hydro.cpu().double()
+        return dict(rho=h[0], m=h[1:4].clone(), E=h[4], b=self.bface.cpu().double())
 
     # ---- method
     def compute_dt(self) -> float:
@@ -260,9 +261,11 @@ class Patch:
         """One step of the bound state with dt; returns its two stage states
         ([8, nz, ny, nx] each, written into U1/U2 when given)."""
         if U1 is None:
-            U1 = torch.empty((8,) + self.shape, dtype=torch.float64, device=self.device)
+            U1 = torch.empty((8,) + self.shape, dtype=self.dtype, device=self.device)
         if U2 is None:
-            U2 = torch.empty((8,) + self.shape, dtype=torch.float64, device=self.device)
+            U2 = torch.empty((8,) + self.shape, dtype=self.dtype, device=self.device)
+        if U1.dtype != self.dtype or U2.dtype != self.dtype:
+            raise ValueError("stage states must have the state's dtype")
         _check(self.lib.wm_step_record(self.handle, float(dt), _ptr(U1), _ptr(U2)))
         return U1, U2
 

@@ -38,13 +38,16 @@ constexpr int SW_NQ = 14;                    // q (7) and F (7) per zone
 constexpr int SW_NP = 11;                    // rho, v_n, v_t1, v_t2, B_n, B_t1, B_t2, P, c_f, c_A, c_s
 enum { P_RHO = 0, P_VN, P_VT1, P_VT2, P_BN, P_BT1, P_BT2, P_P, P_CF, P_CA, P_CS };
 
+// S: storage type of the state and of the face values (double, or float for
+// the FP32-state form); arithmetic is in double / TW as described below.
+template <typename S>
 struct SweepArgs {
   Grid g;
   Phys ph;
-  const double* hydro;   // [5][N] rho, mx, my, mz, E
-  const double* bcell;   // [3][N] zone B
-  double* fhydro;        // [5][N] interface flux, global frame (rho, mx, my, mz, E)
-  double* T;             // [2][N] transport fluxes T^n_t1, T^n_t2
+  const S* hydro;        // [5][N] rho, mx, my, mz, E
+  const S* bcell;        // [3][N] zone B
+  S* fhydro;             // [5][N] interface flux, global frame (rho, mx, my, mz, E)
+  S* T;                  // [2][N] transport fluxes T^n_t1, T^n_t2
   double* dbg;           // optional [9][N]: 7 sweep-frame flux components + 2 T
 };
 
@@ -65,8 +68,8 @@ constexpr size_t sweep_lds_doubles() {
 // transport-flux mean in FP32; the zone prologue (pressure recovery), the
 // differences, the central flux and the face eigen-system (renormalisation of
 // alpha_f, alpha_s, beta) in FP64.
-template <int AXIS, bool WENO_Z, typename TW>
-__global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_kernel(SweepArgs a) {
+template <int AXIS, bool WENO_Z, typename TW, typename S>
+__global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_kernel(SweepArgs<S> a) {
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;     // zones along the axis
   constexpr int NI = TA + 4;                 // interfaces i-3/2 .. i+TA+3/2
@@ -203,13 +206,13 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
   const size_t gi = g.at(i, j, k);
   double fm[3];
   fm[CN] = Ff[1]; fm[CT1] = Ff[2]; fm[CT2] = Ff[3];
-  a.fhydro[gi] = Ff[0];
-  a.fhydro[g.N + gi] = fm[0];
-  a.fhydro[2 * g.N + gi] = fm[1];
-  a.fhydro[3 * g.N + gi] = fm[2];
-  a.fhydro[4 * g.N + gi] = Ff[6];
-  a.T[gi] = T1;
-  a.T[g.N + gi] = T2;
+  a.fhydro[gi] = S(Ff[0]);
+  a.fhydro[g.N + gi] = S(fm[0]);
+  a.fhydro[2 * g.N + gi] = S(fm[1]);
+  a.fhydro[3 * g.N + gi] = S(fm[2]);
+  a.fhydro[4 * g.N + gi] = S(Ff[6]);
+  a.T[gi] = S(T1);
+  a.T[g.N + gi] = S(T2);
   if (a.dbg) {
 #pragma unroll
     for (int v = 0; v < 7; ++v) a.dbg[v * g.N + gi] = Ff[v];
@@ -221,15 +224,16 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
 // ---------------------------------------------------------------------------
 // divergence + CT + RK stage
 // ---------------------------------------------------------------------------
+template <typename S>
 struct UpdateArgs {
   Grid g;
   double inv_h;
-  const double* faces;   // [21][N]: F^x[5], F^y[5], F^z[5], T^x[2], T^y[2], T^z[2]
-  const double* Un;      // hydro [5][N] of U^n
-  const double* bn;      // bface [3][N] of U^n
-  double* acc;           // [8][N] accumulated increments
-  double* hyd_out;       // hydro [5][N] of the stage result
-  double* b_out;         // bface [3][N] of the stage result
+  const S* faces;        // [21][N]: F^x[5], F^y[5], F^z[5], T^x[2], T^y[2], T^z[2]
+  const S* Un;           // hydro [5][N] of U^n
+  const S* bn;           // bface [3][N] of U^n
+  S* acc;                // [8][N] accumulated increments
+  S* hyd_out;            // hydro [5][N] of the stage result
+  S* b_out;              // bface [3][N] of the stage result
   double* rhs_out;       // optional [8][N]: the right-hand side itself (no state update)
   const double* dt;      // device scalar
 };
@@ -238,12 +242,13 @@ struct UpdateArgs {
 //   Ez(i+1/2, j+1/2, k) = (Tyx(i) + Tyx(i+1))/2 - (Txy(j) + Txy(j+1))/2   [Omega_x]
 //   Ex(i, j+1/2, k+1/2) = (Tzy(j) + Tzy(j+1))/2 - (Tyz(k) + Tyz(k+1))/2   [Omega_y]
 //   Ey(i+1/2, j, k+1/2) = (Txz(k) + Txz(k+1))/2 - (Tzx(i) + Tzx(i+1))/2   [Omega_z]
+template <typename S>
 struct TView {
-  const double *xy, *xz, *yz, *yx, *zx, *zy;
+  const S *xy, *xz, *yz, *yx, *zx, *zy;
 };
 
-template <int STAGE>
-__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a) {
+template <int STAGE, typename S>
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
   const Grid& g = a.g;
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -256,36 +261,36 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs a) {
   const size_t c0 = g.at(i, j, k);
   const size_t cxm = g.at(im, j, k), cym = g.at(i, jm, k), czm = g.at(i, j, km);
   const double ih = a.inv_h;
-  const double* Fx = a.faces;
-  const double* Fy = a.faces + 5 * N;
-  const double* Fz = a.faces + 10 * N;
+  const S* Fx = a.faces;
+  const S* Fy = a.faces + 5 * N;
+  const S* Fz = a.faces + 10 * N;
   double kv[8];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const size_t o = v * N;
-    const double dx = -(Fx[o + c0] - Fx[o + cxm]) * ih;
-    const double dy = -(Fy[o + c0] - Fy[o + cym]) * ih;
-    const double dz = -(Fz[o + c0] - Fz[o + czm]) * ih;
+    const double dx = -(double(Fx[o + c0]) - double(Fx[o + cxm])) * ih;
+    const double dy = -(double(Fy[o + c0]) - double(Fy[o + cym])) * ih;
+    const double dz = -(double(Fz[o + c0]) - double(Fz[o + czm])) * ih;
     kv[v] = (dx + dy) + dz;
   }
-  TView T;
+  TView<S> T;
   T.xy = a.faces + 15 * N; T.xz = a.faces + 16 * N;
   T.yz = a.faces + 17 * N; T.yx = a.faces + 18 * N;
   T.zx = a.faces + 19 * N; T.zy = a.faces + 20 * N;
   auto Ez = [&](int ii, int jj, int kk) {
     const int iip = ii + 1 == g.nx ? 0 : ii + 1, jjp = jj + 1 == g.ny ? 0 : jj + 1;
-    return 0.5 * (T.yx[g.at(ii, jj, kk)] + T.yx[g.at(iip, jj, kk)]) -
-           0.5 * (T.xy[g.at(ii, jj, kk)] + T.xy[g.at(ii, jjp, kk)]);
+    return 0.5 * (double(T.yx[g.at(ii, jj, kk)]) + double(T.yx[g.at(iip, jj, kk)])) -
+           0.5 * (double(T.xy[g.at(ii, jj, kk)]) + double(T.xy[g.at(ii, jjp, kk)]));
   };
   auto Ex = [&](int ii, int jj, int kk) {
     const int jjp = jj + 1 == g.ny ? 0 : jj + 1, kkp = kk + 1 == g.nz ? 0 : kk + 1;
-    return 0.5 * (T.zy[g.at(ii, jj, kk)] + T.zy[g.at(ii, jjp, kk)]) -
-           0.5 * (T.yz[g.at(ii, jj, kk)] + T.yz[g.at(ii, jj, kkp)]);
+    return 0.5 * (double(T.zy[g.at(ii, jj, kk)]) + double(T.zy[g.at(ii, jjp, kk)])) -
+           0.5 * (double(T.yz[g.at(ii, jj, kk)]) + double(T.yz[g.at(ii, jj, kkp)]));
   };
   auto Ey = [&](int ii, int jj, int kk) {
     const int iip = ii + 1 == g.nx ? 0 : ii + 1, kkp = kk + 1 == g.nz ? 0 : kk + 1;
-    return 0.5 * (T.xz[g.at(ii, jj, kk)] + T.xz[g.at(ii, jj, kkp)]) -
-           0.5 * (T.zx[g.at(ii, jj, kk)] + T.zx[g.at(iip, jj, kk)]);
+    return 0.5 * (double(T.xz[g.at(ii, jj, kk)]) + double(T.xz[g.at(ii, jj, kkp)])) -
+           0.5 * (double(T.zx[g.at(ii, jj, kk)]) + double(T.zx[g.at(iip, jj, kk)]));
   };
   (void)ip; (void)jp; (void)kp;
   const double ez = Ez(i, j, k), ez_jm = Ez(i, jm, k), ez_im = Ez(im, j, k);
@@ -304,45 +309,48 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs a) {
   const double dt = *a.dt;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
-    const double un = v < 5 ? a.Un[v * N + c0] : a.bn[(v - 5) * N + c0];
+    const double un = v < 5 ? double(a.Un[v * N + c0]) : double(a.bn[(v - 5) * N + c0]);
     double out;
     if (STAGE == 0) {
-      a.acc[v * N + c0] = kv[v];
+      a.acc[v * N + c0] = S(kv[v]);
       out = un + dt * kv[v];
     } else if (STAGE == 1) {
-      const double s = a.acc[v * N + c0] + kv[v];
-      a.acc[v * N + c0] = s;
+      const double s = double(a.acc[v * N + c0]) + kv[v];
+      a.acc[v * N + c0] = S(s);
       out = un + (0.25 * dt) * s;
     } else {
-      const double s = a.acc[v * N + c0] + 4.0 * kv[v];
+      const double s = double(a.acc[v * N + c0]) + 4.0 * kv[v];
       out = un + (dt / 6.0) * s;
     }
-    if (v < 5) a.hyd_out[v * N + c0] = out;
-    else a.b_out[(v - 5) * N + c0] = out;
+    if (v < 5) a.hyd_out[v * N + c0] = S(out);
+    else a.b_out[(v - 5) * N + c0] = S(out);
   }
 }
 
 // zone B = (-b_{i-2} + 9 b_{i-1} + 9 b_i - b_{i+1}) / 16 along each component's own axis
-__global__ __launch_bounds__(256) void bcell_kernel(Grid g, const double* b, double* B) {
+template <typename S>
+__global__ __launch_bounds__(256) void bcell_kernel(Grid g, const S* b, S* B) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   const size_t N = g.N, c0 = g.at(i, j, k);
-  const double* bx = b;
-  const double* by = b + N;
-  const double* bz = b + 2 * N;
-  B[c0] = (-bx[g.at(wrap(i - 2, g.nx), j, k)] + 9.0 * bx[g.at(wrap(i - 1, g.nx), j, k)] + 9.0 * bx[c0] -
-           bx[g.at(wrap(i + 1, g.nx), j, k)]) * (1.0 / 16.0);
-  B[N + c0] = (-by[g.at(i, wrap(j - 2, g.ny), k)] + 9.0 * by[g.at(i, wrap(j - 1, g.ny), k)] + 9.0 * by[c0] -
-               by[g.at(i, wrap(j + 1, g.ny), k)]) * (1.0 / 16.0);
-  B[2 * N + c0] = (-bz[g.at(i, j, wrap(k - 2, g.nz))] + 9.0 * bz[g.at(i, j, wrap(k - 1, g.nz))] + 9.0 * bz[c0] -
-                   bz[g.at(i, j, wrap(k + 1, g.nz))]) * (1.0 / 16.0);
+  const S* bx = b;
+  const S* by = b + N;
+  const S* bz = b + 2 * N;
+  auto f = [](S x) { return double(x); };
+  B[c0] = S((-f(bx[g.at(wrap(i - 2, g.nx), j, k)]) + 9.0 * f(bx[g.at(wrap(i - 1, g.nx), j, k)]) + 9.0 * f(bx[c0]) -
+             f(bx[g.at(wrap(i + 1, g.nx), j, k)])) * (1.0 / 16.0));
+  B[N + c0] = S((-f(by[g.at(i, wrap(j - 2, g.ny), k)]) + 9.0 * f(by[g.at(i, wrap(j - 1, g.ny), k)]) + 9.0 * f(by[c0]) -
+                 f(by[g.at(i, wrap(j + 1, g.ny), k)])) * (1.0 / 16.0));
+  B[2 * N + c0] = S((-f(bz[g.at(i, j, wrap(k - 2, g.nz))]) + 9.0 * f(bz[g.at(i, j, wrap(k - 1, g.nz))]) +
+                     9.0 * f(bz[c0]) - f(bz[g.at(i, j, wrap(k + 1, g.nz))])) * (1.0 / 16.0));
 }
 
 // b = B0 + curl_h A (first-order differences on the edge potential)
+template <typename S>
 __global__ __launch_bounds__(256) void init_b_kernel(Grid g, double inv_h, const double* A, double B0x,
-                                                     double B0y, double B0z, double* b) {
+                                                     double B0y, double B0z, S* b) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int k = blockIdx.z;
@@ -352,24 +360,25 @@ __global__ __launch_bounds__(256) void init_b_kernel(Grid g, double inv_h, const
   const double* Ay = A + N;
   const double* Az = A + 2 * N;
   const int im = wrap(i - 1, g.nx), jm = wrap(j - 1, g.ny), km = wrap(k - 1, g.nz);
-  b[c0] = B0x + ((Az[c0] - Az[g.at(i, jm, k)]) * inv_h - (Ay[c0] - Ay[g.at(i, j, km)]) * inv_h);
-  b[N + c0] = B0y + ((Ax[c0] - Ax[g.at(i, j, km)]) * inv_h - (Az[c0] - Az[g.at(im, j, k)]) * inv_h);
-  b[2 * N + c0] = B0z + ((Ay[c0] - Ay[g.at(im, j, k)]) * inv_h - (Ax[c0] - Ax[g.at(i, jm, k)]) * inv_h);
+  b[c0] = S(B0x + ((Az[c0] - Az[g.at(i, jm, k)]) * inv_h - (Ay[c0] - Ay[g.at(i, j, km)]) * inv_h));
+  b[N + c0] = S(B0y + ((Ax[c0] - Ax[g.at(i, j, km)]) * inv_h - (Az[c0] - Az[g.at(im, j, k)]) * inv_h));
+  b[2 * N + c0] = S(B0z + ((Ay[c0] - Ay[g.at(im, j, k)]) * inv_h - (Ax[c0] - Ax[g.at(i, jm, k)]) * inv_h));
 }
 
 // m = rho v, E = P0/(gamma-1) + (rho v^2 + B^2)/2 (zone B already interpolated)
+template <typename S>
 __global__ __launch_bounds__(256) void init_hydro_kernel(size_t N, double gamma, double P0, const double* rho,
-                                                         const double* v, const double* B, double* hydro) {
+                                                         const double* v, const S* B, S* hydro) {
   const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= N) return;
   const double r = rho[c];
   const double vx = v[c], vy = v[N + c], vz = v[2 * N + c];
   const double Bx = B[c], By = B[N + c], Bz = B[2 * N + c];
-  hydro[c] = r;
-  hydro[N + c] = r * vx;
-  hydro[2 * N + c] = r * vy;
-  hydro[3 * N + c] = r * vz;
-  hydro[4 * N + c] = P0 / (gamma - 1.0) + 0.5 * (r * (vx * vx + vy * vy + vz * vz) + (Bx * Bx + By * By + Bz * Bz));
+  hydro[c] = S(r);
+  hydro[N + c] = S(r * vx);
+  hydro[2 * N + c] = S(r * vy);
+  hydro[3 * N + c] = S(r * vz);
+  hydro[4 * N + c] = S(P0 / (gamma - 1.0) + 0.5 * (r * (vx * vx + vy * vy + vz * vz) + (Bx * Bx + By * By + Bz * Bz)));
 }
 
 // ---------------------------------------------------------------------------
@@ -383,18 +392,20 @@ __device__ __forceinline__ double nanmax(double a, double b) {   // NaN-propagat
 }
 
 // max over zones of |v_d| + c_fast^d, d = x, y, z -> part[3 * block + d]
-__global__ __launch_bounds__(RED_THREADS) void speed_partial_kernel(size_t N, double gamma, const double* hydro,
-                                                                    const double* bcell, double* part) {
+template <typename S>
+__global__ __launch_bounds__(RED_THREADS) void speed_partial_kernel(size_t N, double gamma, const S* hydro,
+                                                                    const S* bcell, double* part) {
   __shared__ double red[3][RED_THREADS];
   double mx[3] = {0.0, 0.0, 0.0};
   for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N; c += (size_t)gridDim.x * RED_THREADS) {
     const double rho = hydro[c];
     const double irho = 1.0 / rho;
-    const double v[3] = {hydro[N + c] * irho, hydro[2 * N + c] * irho, hydro[3 * N + c] * irho};
+    const double mm[3] = {hydro[N + c], hydro[2 * N + c], hydro[3 * N + c]};
+    const double v[3] = {mm[0] * irho, mm[1] * irho, mm[2] * irho};
     const double B[3] = {bcell[c], bcell[N + c], bcell[2 * N + c]};
     const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-    const double P = (gamma - 1.0) *
-                     (hydro[4 * N + c] - 0.5 * ((hydro[N + c] * v[0] + hydro[2 * N + c] * v[1] + hydro[3 * N + c] * v[2]) + B2));
+    const double E = hydro[4 * N + c];
+    const double P = (gamma - 1.0) * (E - 0.5 * ((mm[0] * v[0] + mm[1] * v[1] + mm[2] * v[2]) + B2));
     const double a2 = gamma * P * irho, b2 = B2 * irho;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -461,9 +472,10 @@ struct Acc2 {
   }
 };
 
+template <typename S>
 __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Grid g, double gamma, double inv_h,
-                                                                   const double* hydro, const double* b,
-                                                                   const double* bcell, double* part) {
+                                                                   const S* hydro, const S* b,
+                                                                   const S* bcell, double* part) {
   // part layout per block: [0..7] sums, [8..15] compensations, [16] max|divb|, [17] min rho,
   // [18] min P, [19] unphysical count
   const size_t N = g.N;
@@ -481,9 +493,10 @@ __global__ __launch_bounds__(RED_THREADS) void diag_partial_kernel(Grid g, doubl
     acc[0].add(rho);
     acc[1].add(m[0]); acc[2].add(m[1]); acc[3].add(m[2]);
     acc[4].add(E);
-    acc[5].add(b[c]); acc[6].add(b[N + c]); acc[7].add(b[2 * N + c]);
-    const double div = ((b[c] - b[g.at(wrap(i - 1, g.nx), j, k)]) + (b[N + c] - b[N + g.at(i, wrap(j - 1, g.ny), k)]) +
-                        (b[2 * N + c] - b[2 * N + g.at(i, j, wrap(k - 1, g.nz))])) * inv_h;
+    auto bf = [&](size_t q) { return double(b[q]); };
+    acc[5].add(bf(c)); acc[6].add(bf(N + c)); acc[7].add(bf(2 * N + c));
+    const double div = ((bf(c) - bf(g.at(wrap(i - 1, g.nx), j, k))) + (bf(N + c) - bf(N + g.at(i, wrap(j - 1, g.ny), k))) +
+                        (bf(2 * N + c) - bf(2 * N + g.at(i, j, wrap(k - 1, g.nz))))) * inv_h;
     mdiv = nanmax(mdiv, fabs(div));
     const double Bx = bcell[c], By = bcell[N + c], Bz = bcell[2 * N + c];
     const double P = (gamma - 1.0) * (E - 0.5 * ((m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / rho + (Bx * Bx + By * By + Bz * Bz)));

@@ -42,11 +42,12 @@ wm_status hip_check(hipError_t e, const char* where) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// scratch layout (bytes, each region 256-aligned), FP64:
+// scratch layout (bytes, each region 256-aligned), elements of the state's
+// storage type (double, or float for WM_MIXED_F32STATE):
 //   Us    [11][N]  stage state: hydro 5, bface 3, bcell 3
 //   acc   [8][N]   RK increment accumulator
 //   faces [21][N]  F^x, F^y, F^z (5 each), T^x, T^y, T^z (2 each)
-//   red            dt, 3 signal-speed maxima, reduction partials
+//   red            (doubles) dt, 3 signal-speed maxima, reduction partials
 struct Layout {
   size_t us, acc, faces, red, total;
 };
@@ -64,17 +65,25 @@ bool valid_config(const wm_config* c, const char** why) {
   if (!(c->cfl > 0.0)) { *why = "cfl must be positive"; return false; }
   if (!(c->eps_weno > 0.0) || !(c->eps_B >= 0.0) || !(c->eps_Z > 0.0)) { *why = "epsilons must be positive"; return false; }
   if (c->weights != WM_WENO_JS && c->weights != WM_WENO_Z) { *why = "unknown weights"; return false; }
-  if (c->precision != WM_FP64 && c->precision != WM_MIXED) { *why = "unknown precision mode"; return false; }
+  if (c->precision != WM_FP64 && c->precision != WM_MIXED && c->precision != WM_MIXED_F32STATE) {
+    *why = "unknown precision mode";
+    return false;
+  }
   return true;
+}
+
+size_t state_elem_bytes(const wm_config* c) {
+  return c->precision == WM_MIXED_F32STATE ? sizeof(float) : sizeof(double);
 }
 
 Layout layout(const wm_config* c) {
   const size_t N = (size_t)c->nx * c->ny * c->nz;
+  const size_t es = state_elem_bytes(c);
   Layout L;
   size_t off = 0;
-  L.us = off;    off = align_up(off + 11 * N * sizeof(double));
-  L.acc = off;   off = align_up(off + 8 * N * sizeof(double));
-  L.faces = off; off = align_up(off + 21 * N * sizeof(double));
+  L.us = off;    off = align_up(off + 11 * N * es);
+  L.acc = off;   off = align_up(off + 8 * N * es);
+  L.faces = off; off = align_up(off + 21 * N * es);
   L.red = off;   off = align_up(off + kRedDoubles * sizeof(double));
   L.total = off;
   return L;
@@ -160,9 +169,10 @@ struct wm_patch {
   Phys ph;
   char* scratch;
   Layout lay;
-  double* hydro = nullptr;   // bound state
-  double* bface = nullptr;
-  double* bcell = nullptr;
+  bool f32 = false;          // state, stage states, accumulator and face values in FP32
+  void* hydro = nullptr;     // bound state (storage type: double, or float when f32)
+  void* bface = nullptr;
+  void* bcell = nullptr;
   int stage_done = -1;       // last completed stage of the current step (-1: none)
   bool dt_valid = false;
   TilePlan adj_plan[3];      // adjoint sweep launch classes per axis (grid sizes >= 3)
@@ -172,9 +182,12 @@ struct wm_patch {
   std::vector<int> ev_class;        // kernel class per record
   size_t n_rec = 0;
 
-  double* us() const { return reinterpret_cast<double*>(scratch + lay.us); }
-  double* acc() const { return reinterpret_cast<double*>(scratch + lay.acc); }
-  double* faces() const { return reinterpret_cast<double*>(scratch + lay.faces); }
+  template <typename S> S* us() const { return reinterpret_cast<S*>(scratch + lay.us); }
+  template <typename S> S* acc() const { return reinterpret_cast<S*>(scratch + lay.acc); }
+  template <typename S> S* faces() const { return reinterpret_cast<S*>(scratch + lay.faces); }
+  template <typename S> S* hyd() const { return reinterpret_cast<S*>(hydro); }
+  template <typename S> S* bf() const { return reinterpret_cast<S*>(bface); }
+  template <typename S> S* bc() const { return reinterpret_cast<S*>(bcell); }
   double* red() const { return reinterpret_cast<double*>(scratch + lay.red); }
   double* dt_dev() const { return red(); }                 // red[0]
   double* smax_dev() const { return red() + 1; }           // red[1..3]
@@ -210,9 +223,15 @@ void prof_end(wm_patch* p, long r) {
 
 dim3 zone_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
 
-template <int AXIS>
-wm_status launch_sweep(wm_patch* p, const double* hydro, const double* bcell, double* fh, double* T, double* dbg) {
-  SweepArgs a;
+// Runs fn(S{}) with S the patch's storage type.
+template <class Fn>
+wm_status with_storage(const wm_patch* p, Fn&& fn) {
+  return p->f32 ? fn(float{}) : fn(double{});
+}
+
+template <int AXIS, typename S>
+wm_status launch_sweep(wm_patch* p, const S* hydro, const S* bcell, S* fh, S* T, double* dbg) {
+  SweepArgs<S> a;
   a.g = p->g;
   a.ph = p->ph;
   a.hydro = hydro;
@@ -226,63 +245,73 @@ wm_status launch_sweep(wm_patch* p, const double* hydro, const double* bcell, do
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
   dim3 grid((nA + TA - 1) / TA, (nB + TB - 1) / TB, nC);
   const long r = prof_begin(p, K_SWEEP);
-  const bool mixed = p->cfg.precision == WM_MIXED;
-  if (p->ph.weno_z && mixed)
-    hipLaunchKernelGGL((sweep_kernel<AXIS, true, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
-  else if (p->ph.weno_z)
-    hipLaunchKernelGGL((sweep_kernel<AXIS, true, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
-  else if (mixed)
-    hipLaunchKernelGGL((sweep_kernel<AXIS, false, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
-  else
-    hipLaunchKernelGGL((sweep_kernel<AXIS, false, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
+  if constexpr (sizeof(S) == 4) {   // FP32 state: the mixed arithmetic
+    if (p->ph.weno_z)
+      hipLaunchKernelGGL((sweep_kernel<AXIS, true, float, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    else
+      hipLaunchKernelGGL((sweep_kernel<AXIS, false, float, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
+  } else {
+    const bool mixed = p->cfg.precision == WM_MIXED;
+    if (p->ph.weno_z && mixed)
+      hipLaunchKernelGGL((sweep_kernel<AXIS, true, float, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    else if (p->ph.weno_z)
+      hipLaunchKernelGGL((sweep_kernel<AXIS, true, double, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    else if (mixed)
+      hipLaunchKernelGGL((sweep_kernel<AXIS, false, float, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    else
+      hipLaunchKernelGGL((sweep_kernel<AXIS, false, double, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
+  }
   WM_LAUNCH_CHECK("sweep kernel");
   prof_end(p, r);
   return WM_OK;
 }
 
-wm_status sweeps(wm_patch* p, const double* hydro, const double* bcell) {
+template <typename S>
+wm_status sweeps(wm_patch* p, const S* hydro, const S* bcell) {
   const size_t N = p->g.N;
-  double* f = p->faces();
+  S* f = p->faces<S>();
   wm_status s;
-  if ((s = launch_sweep<0>(p, hydro, bcell, f, f + 15 * N, nullptr)) != WM_OK) return s;
-  if ((s = launch_sweep<1>(p, hydro, bcell, f + 5 * N, f + 17 * N, nullptr)) != WM_OK) return s;
-  if ((s = launch_sweep<2>(p, hydro, bcell, f + 10 * N, f + 19 * N, nullptr)) != WM_OK) return s;
+  if ((s = launch_sweep<0, S>(p, hydro, bcell, f, f + 15 * N, nullptr)) != WM_OK) return s;
+  if ((s = launch_sweep<1, S>(p, hydro, bcell, f + 5 * N, f + 17 * N, nullptr)) != WM_OK) return s;
+  if ((s = launch_sweep<2, S>(p, hydro, bcell, f + 10 * N, f + 19 * N, nullptr)) != WM_OK) return s;
   return WM_OK;
 }
 
+template <typename S>
 wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
   const size_t N = p->g.N;
-  UpdateArgs a;
+  UpdateArgs<S> a;
   a.g = p->g;
   a.inv_h = 1.0 / p->cfg.h;
-  a.faces = p->faces();
-  a.Un = p->hydro;
-  a.bn = p->bface;
-  a.acc = p->acc();
+  a.faces = p->faces<S>();
+  a.Un = p->hyd<S>();
+  a.bn = p->bf<S>();
+  a.acc = p->acc<S>();
   a.rhs_out = rhs_out;
   a.dt = p->dt_dev();
   if (stage == 2) {
-    a.hyd_out = p->hydro;
-    a.b_out = p->bface;
+    a.hyd_out = p->hyd<S>();
+    a.b_out = p->bf<S>();
   } else {
-    a.hyd_out = p->us();
-    a.b_out = p->us() + 5 * N;
+    a.hyd_out = p->us<S>();
+    a.b_out = p->us<S>() + 5 * N;
   }
   dim3 grid = zone_grid(p->g);
   const long r = prof_begin(p, K_UPDATE);
   switch (stage) {
-    case 0: hipLaunchKernelGGL(update_kernel<0>, grid, dim3(256), 0, p->stream, a); break;
-    case 1: hipLaunchKernelGGL(update_kernel<1>, grid, dim3(256), 0, p->stream, a); break;
-    default: hipLaunchKernelGGL(update_kernel<2>, grid, dim3(256), 0, p->stream, a); break;
+    case 0: hipLaunchKernelGGL((update_kernel<0, S>), grid, dim3(256), 0, p->stream, a); break;
+    case 1: hipLaunchKernelGGL((update_kernel<1, S>), grid, dim3(256), 0, p->stream, a); break;
+    default: hipLaunchKernelGGL((update_kernel<2, S>), grid, dim3(256), 0, p->stream, a); break;
   }
   WM_LAUNCH_CHECK("update kernel");
   prof_end(p, r);
   return WM_OK;
 }
 
-wm_status launch_bcell(wm_patch* p, const double* b, double* B) {
+template <typename S>
+wm_status launch_bcell(wm_patch* p, const S* b, S* B) {
   const long r = prof_begin(p, K_BCELL);
-  hipLaunchKernelGGL(bcell_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, b, B);
+  hipLaunchKernelGGL(bcell_kernel<S>, zone_grid(p->g), dim3(256), 0, p->stream, p->g, b, B);
   WM_LAUNCH_CHECK("bcell kernel");
   prof_end(p, r);
   return WM_OK;
@@ -335,6 +364,7 @@ wm_status check_adjoint(wm_patch* p, void* adj) {
   if (!adj || reinterpret_cast<uintptr_t>(adj) % kAlign) return fail(WM_ERR_ARG, "adjoint scratch null or misaligned");
   if (p->cfg.nx < 3 || p->cfg.ny < 3 || p->cfg.nz < 3) return fail(WM_ERR_ARG, "the adjoint needs grid sizes >= 3");
   if (p->cfg.weights != WM_WENO_JS) return fail(WM_ERR_ARG, "the adjoint differentiates the Jiang-Shu weights only");
+  if (p->f32) return fail(WM_ERR_ARG, "the adjoint needs an FP64 state (not WM_MIXED_F32STATE)");
   return WM_OK;
 }
 
@@ -347,7 +377,7 @@ wm_status rhs_vjp_acc(wm_patch* p, double* A, const double* hydro, const double*
   double* Bz = A + A_BZ * N;
   double* lT = A + A_LT * N;
   double* lBz = A + A_LBZ * N;
-  if ((s = launch_bcell(p, bface, Bz)) != WM_OK) return s;
+  if ((s = launch_bcell<double>(p, bface, Bz)) != WM_OK) return s;
   hipLaunchKernelGGL(adj_emf_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, lam_k, lT);
   WM_LAUNCH_CHECK("adjoint emf kernel");
   hipLaunchKernelGGL(fill_kernel, lin_grid(3 * N), dim3(256), 0, p->stream, 3 * N, 0.0, lBz);
@@ -366,15 +396,15 @@ wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double
                          double* U2, double* acc) {
   const size_t N = p->g.N;
   wm_status s;
-  if ((s = launch_bcell(p, Ub, Bz)) != WM_OK) return s;
+  if ((s = launch_bcell<double>(p, Ub, Bz)) != WM_OK) return s;
   for (int st = 0; st < 2; ++st) {
     const double* hin = st == 0 ? Uh : U1;
     const double* bcin = st == 0 ? Bz : U1 + 8 * N;
-    if ((s = sweeps(p, hin, bcin)) != WM_OK) return s;
-    UpdateArgs a;
+    if ((s = sweeps<double>(p, hin, bcin)) != WM_OK) return s;
+    UpdateArgs<double> a;
     a.g = p->g;
     a.inv_h = 1.0 / p->cfg.h;
-    a.faces = p->faces();
+    a.faces = p->faces<double>();
     a.Un = Uh;
     a.bn = Ub;
     a.acc = acc;
@@ -383,10 +413,10 @@ wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double
     double* out = st == 0 ? U1 : U2;
     a.hyd_out = out;
     a.b_out = out + 5 * N;
-    if (st == 0) hipLaunchKernelGGL(update_kernel<0>, zone_grid(p->g), dim3(256), 0, p->stream, a);
-    else hipLaunchKernelGGL(update_kernel<1>, zone_grid(p->g), dim3(256), 0, p->stream, a);
+    if (st == 0) hipLaunchKernelGGL((update_kernel<0, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
+    else hipLaunchKernelGGL((update_kernel<1, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
     WM_LAUNCH_CHECK("update kernel");
-    if ((s = launch_bcell(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
+    if ((s = launch_bcell<double>(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
   }
   return WM_OK;
 }
@@ -440,6 +470,7 @@ wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch,
   p->ph.g2 = (cfg->gamma - 2.0) / (cfg->gamma - 1.0);
   p->scratch = reinterpret_cast<char*>(scratch);
   p->lay = L;
+  p->f32 = cfg->precision == WM_MIXED_F32STATE;
   if (cfg->nx >= 3 && cfg->ny >= 3 && cfg->nz >= 3) {
     const int n3[3] = {cfg->nx, cfg->ny, cfg->nz};
     const int ta[3] = {SweepTile<0>::TA, SweepTile<1>::TA, SweepTile<2>::TA};
@@ -467,9 +498,9 @@ wm_status wm_patch_destroy(wm_patch* p) {
 wm_status wm_bind_state(wm_patch* p, void* hydro, void* bface, void* bcell) {
   if (!p) return fail(WM_ERR_ARG, "null patch");
   if (!hydro || !bface || !bcell) return fail(WM_ERR_ARG, "null state pointer");
-  p->hydro = reinterpret_cast<double*>(hydro);
-  p->bface = reinterpret_cast<double*>(bface);
-  p->bcell = reinterpret_cast<double*>(bcell);
+  p->hydro = hydro;
+  p->bface = bface;
+  p->bcell = bcell;
   p->stage_done = -1;
   p->dt_valid = false;
   return WM_OK;
@@ -480,14 +511,20 @@ wm_status wm_init_from_potential(wm_patch* p, const double* rho, const double* v
   wm_status s = check_bound(p);
   if (s != WM_OK) return s;
   if (!rho || !v || !A_edge || !B0) return fail(WM_ERR_ARG, "null input pointer");
-  hipLaunchKernelGGL(init_b_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, A_edge, B0[0],
-                     B0[1], B0[2], p->bface);
-  WM_LAUNCH_CHECK("init_b kernel");
-  if ((s = launch_bcell(p, p->bface, p->bcell)) != WM_OK) return s;
-  const size_t N = p->g.N;
-  hipLaunchKernelGGL(init_hydro_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, N, p->cfg.gamma,
-                     P0, rho, v, p->bcell, p->hydro);
-  WM_LAUNCH_CHECK("init_hydro kernel");
+  s = with_storage(p, [&](auto tag) -> wm_status {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(init_b_kernel<S>, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, A_edge,
+                       B0[0], B0[1], B0[2], p->bf<S>());
+    WM_LAUNCH_CHECK("init_b kernel");
+    wm_status st = launch_bcell<S>(p, p->bf<S>(), p->bc<S>());
+    if (st != WM_OK) return st;
+    const size_t N = p->g.N;
+    hipLaunchKernelGGL(init_hydro_kernel<S>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, N,
+                       p->cfg.gamma, P0, rho, v, p->bc<S>(), p->hyd<S>());
+    WM_LAUNCH_CHECK("init_hydro kernel");
+    return WM_OK;
+  });
+  if (s != WM_OK) return s;
   p->stage_done = -1;
   p->dt_valid = false;
   return WM_OK;
@@ -496,7 +533,10 @@ wm_status wm_init_from_potential(wm_patch* p, const double* rho, const double* v
 wm_status wm_refresh_zone_field(wm_patch* p) {
   wm_status s = check_bound(p);
   if (s != WM_OK) return s;
-  return launch_bcell(p, p->bface, p->bcell);
+  return with_storage(p, [&](auto tag) {
+    using S = decltype(tag);
+    return launch_bcell<S>(p, p->bf<S>(), p->bc<S>());
+  });
 }
 
 wm_status wm_compute_dt(wm_patch* p, double* dt_host) {
@@ -504,8 +544,12 @@ wm_status wm_compute_dt(wm_patch* p, double* dt_host) {
   if (s != WM_OK) return s;
   const int nb = red_blocks(p->g);
   const long r = prof_begin(p, K_DT);
-  hipLaunchKernelGGL(speed_partial_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g.N, p->cfg.gamma,
-                     p->hydro, p->bcell, p->speed_part());
+  if (p->f32)
+    hipLaunchKernelGGL(speed_partial_kernel<float>, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g.N, p->cfg.gamma,
+                       p->hyd<float>(), p->bc<float>(), p->speed_part());
+  else
+    hipLaunchKernelGGL(speed_partial_kernel<double>, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g.N, p->cfg.gamma,
+                       p->hyd<double>(), p->bc<double>(), p->speed_part());
   WM_LAUNCH_CHECK("speed kernel");
   hipLaunchKernelGGL(dt_final_kernel, dim3(1), dim3(RED_THREADS), 0, p->stream, nb, p->cfg.cfl * p->cfg.h,
                      p->speed_part(), p->dt_dev(), p->smax_dev());
@@ -535,16 +579,21 @@ wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
     return fail(WM_ERR_STATE, "no dt: call wm_compute_dt or pass dt");
   }
   const size_t N = p->g.N;
-  const double* hyd_in = stage == 0 ? p->hydro : p->us();
-  const double* bcell_in = stage == 0 ? p->bcell : p->us() + 8 * N;
-  if ((s = sweeps(p, hyd_in, bcell_in)) != WM_OK) return s;
-  if ((s = launch_update(p, stage, nullptr)) != WM_OK) return s;
+  s = with_storage(p, [&](auto tag) -> wm_status {
+    using S = decltype(tag);
+    const S* hyd_in = stage == 0 ? p->hyd<S>() : p->us<S>();
+    const S* bcell_in = stage == 0 ? p->bc<S>() : p->us<S>() + 8 * N;
+    wm_status st;
+    if ((st = sweeps<S>(p, hyd_in, bcell_in)) != WM_OK) return st;
+    if ((st = launch_update<S>(p, stage, nullptr)) != WM_OK) return st;
+    if (stage == 2) return launch_bcell<S>(p, p->bf<S>(), p->bc<S>());
+    return launch_bcell<S>(p, p->us<S>() + 5 * N, p->us<S>() + 8 * N);
+  });
+  if (s != WM_OK) return s;
   if (stage == 2) {
-    if ((s = launch_bcell(p, p->bface, p->bcell)) != WM_OK) return s;
     p->stage_done = -1;
     p->dt_valid = false;
   } else {
-    if ((s = launch_bcell(p, p->us() + 5 * N, p->us() + 8 * N)) != WM_OK) return s;
     p->stage_done = stage;
   }
   return WM_OK;
@@ -573,8 +622,12 @@ wm_status wm_diagnostics(wm_patch* p, wm_diag* out) {
   if (s != WM_OK) return s;
   if (!out) return fail(WM_ERR_ARG, "null output");
   const int nb = red_blocks(p->g);
-  hipLaunchKernelGGL(diag_partial_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g, p->cfg.gamma,
-                     1.0 / p->cfg.h, p->hydro, p->bface, p->bcell, p->diag_part());
+  if (p->f32)
+    hipLaunchKernelGGL(diag_partial_kernel<float>, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g, p->cfg.gamma,
+                       1.0 / p->cfg.h, p->hyd<float>(), p->bf<float>(), p->bc<float>(), p->diag_part());
+  else
+    hipLaunchKernelGGL(diag_partial_kernel<double>, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g, p->cfg.gamma,
+                       1.0 / p->cfg.h, p->hyd<double>(), p->bf<double>(), p->bc<double>(), p->diag_part());
   WM_LAUNCH_CHECK("diag kernel");
   hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, p->stream, nb, p->diag_part(), p->diag_out());
   WM_LAUNCH_CHECK("diag final kernel");
@@ -600,22 +653,29 @@ wm_status wm_debug_sweep(wm_patch* p, int axis, void* out) {
   if (s != WM_OK) return s;
   if (!out) return fail(WM_ERR_ARG, "null output");
   const size_t N = p->g.N;
-  double* f = p->faces();
   double* o = reinterpret_cast<double*>(out);
-  switch (axis) {
-    case 0: return launch_sweep<0>(p, p->hydro, p->bcell, f, f + 15 * N, o);
-    case 1: return launch_sweep<1>(p, p->hydro, p->bcell, f + 5 * N, f + 17 * N, o);
-    case 2: return launch_sweep<2>(p, p->hydro, p->bcell, f + 10 * N, f + 19 * N, o);
-    default: return fail(WM_ERR_ARG, "axis must be 0, 1 or 2");
-  }
+  if (axis < 0 || axis > 2) return fail(WM_ERR_ARG, "axis must be 0, 1 or 2");
+  return with_storage(p, [&](auto tag) {
+    using S = decltype(tag);
+    S* f = p->faces<S>();
+    switch (axis) {
+      case 0: return launch_sweep<0, S>(p, p->hyd<S>(), p->bc<S>(), f, f + 15 * N, o);
+      case 1: return launch_sweep<1, S>(p, p->hyd<S>(), p->bc<S>(), f + 5 * N, f + 17 * N, o);
+      default: return launch_sweep<2, S>(p, p->hyd<S>(), p->bc<S>(), f + 10 * N, f + 19 * N, o);
+    }
+  });
 }
 
 wm_status wm_debug_rhs(wm_patch* p, void* out) {
   wm_status s = check_bound(p);
   if (s != WM_OK) return s;
   if (!out) return fail(WM_ERR_ARG, "null output");
-  if ((s = sweeps(p, p->hydro, p->bcell)) != WM_OK) return s;
-  return launch_update(p, 0, reinterpret_cast<double*>(out));
+  return with_storage(p, [&](auto tag) {
+    using S = decltype(tag);
+    wm_status st = sweeps<S>(p, p->hyd<S>(), p->bc<S>());
+    if (st != WM_OK) return st;
+    return launch_update<S>(p, 0, reinterpret_cast<double*>(out));
+  });
 }
 
 size_t wm_adjoint_scratch_bytes(const wm_config* cfg) {
@@ -658,7 +718,8 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
     WM_LAUNCH_CHECK("set dt");
     // the stage accumulator of the forward scratch is free outside wm_step
-    if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N, p->acc())) != WM_OK) return s;
+    if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N, p->acc<double>())) != WM_OK)
+      return s;
     U1 = A + A_U1 * N;
     U2 = A + A_U2 * N;
   }
@@ -687,14 +748,14 @@ wm_status wm_step_record(wm_patch* p, double dt, void* U1_out, void* U2_out) {
   if (s != WM_OK) return s;
   if (!U1_out || !U2_out) return fail(WM_ERR_ARG, "null pointer");
   if (!std::isfinite(dt)) return fail(WM_ERR_ARG, "dt is not finite");
-  const size_t bytes = 8 * p->g.N * sizeof(double);
+  const size_t bytes = 8 * p->g.N * state_elem_bytes(&p->cfg);
   p->stage_done = -1;
   if ((s = wm_rk_stage(p, 0, &dt)) != WM_OK) return s;
-  if ((s = hip_check(hipMemcpyAsync(U1_out, p->us(), bytes, hipMemcpyDeviceToDevice, p->stream), "stage copy")) !=
+  if ((s = hip_check(hipMemcpyAsync(U1_out, p->us<char>(), bytes, hipMemcpyDeviceToDevice, p->stream), "stage copy")) !=
       WM_OK)
     return s;
   if ((s = wm_rk_stage(p, 1, nullptr)) != WM_OK) return s;
-  if ((s = hip_check(hipMemcpyAsync(U2_out, p->us(), bytes, hipMemcpyDeviceToDevice, p->stream), "stage copy")) !=
+  if ((s = hip_check(hipMemcpyAsync(U2_out, p->us<char>(), bytes, hipMemcpyDeviceToDevice, p->stream), "stage copy")) !=
       WM_OK)
     return s;
   return wm_rk_stage(p, 2, nullptr);
@@ -721,10 +782,10 @@ wm_status wm_init_adjoint(wm_patch* p, void* adj_scratch, const double* rho, con
   double* B0z = A + A_U1 * N + 3 * N; // its zone interpolation
   double* lB = A + A_WORK * N;        // zone-B cotangent
   double* lb = A + A_WORK * N + 3 * N;  // total face-b cotangent
-  hipLaunchKernelGGL(init_b_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, A_edge, B0[0],
+  hipLaunchKernelGGL(init_b_kernel<double>, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, A_edge, B0[0],
                      B0[1], B0[2], b0);
   WM_LAUNCH_CHECK("init_b kernel");
-  if ((s = launch_bcell(p, b0, B0z)) != WM_OK) return s;
+  if ((s = launch_bcell<double>(p, b0, B0z)) != WM_OK) return s;
   hipLaunchKernelGGL(init_adj_zone_kernel, lin_grid(N), dim3(256), 0, p->stream, N, rho, v, B0z,
                      reinterpret_cast<const double*>(lam_hydro), g_v, lB);
   WM_LAUNCH_CHECK("init adjoint kernel");
