@@ -122,7 +122,8 @@ def mixed_precision(n: int, steps: int):
 
 def convergence(sizes, c: float = 0.25):
     """Grid-aligned linear fast wave (Sect. 4.1 setup), one period, dt = c h^(5/3),
-    on n x 4 x 4 zones, FP64 and mixed.  Two errors against the exact
+    on n x 4 x 4 zones, FP64 and mixed (SSP-RK3), and FP64 with the classical
+    RK4 at the paper's Courant number 0.8.  Two errors against the exact
     travelling wave: the L1 of Sect. 3 (A0 = 1e-6; it meets the O(A0^2)
     nonlinear floor near N = 64) and the error of the k = 1 Fourier amplitude of
     every conserved variable (A0 = 1e-5), which nonlinearity changes only at
@@ -138,14 +139,20 @@ def convergence(sizes, c: float = 0.25):
                          for x in comps])
 
     out = {}
-    for name, prec in (("fp64", binding.WM_FP64), ("mixed", binding.WM_MIXED)):
+    runs = (("fp64", binding.WM_FP64, binding.WM_SSPRK3), ("mixed", binding.WM_MIXED, binding.WM_SSPRK3),
+            ("fp64_rk4", binding.WM_FP64, binding.WM_RK4))
+    for name, prec, integ in runs:
         l1, fk = [], []
         for n in sizes:
             for A0 in (1e-6, 1e-5):
                 U0, U1 = inputs.fast_wave(n, A0=A0), inputs.fast_wave(n, t=0.5, A0=A0)
-                p = binding.Patch(binding.config(nx=n, ny=4, nz=4, h=1.0 / n, precision=prec), device="cuda:0")
+                p = binding.Patch(binding.config(nx=n, ny=4, nz=4, h=1.0 / n, precision=prec, integrator=integ),
+                                  device="cuda:0")
                 p.set_state(U0["rho"], U0["m"], U0["E"], U0["b"])
-                nt = int(math.ceil(0.5 / (c * (1.0 / n) ** (5.0 / 3.0))))
+                if integ == binding.WM_RK4:   # the paper's setting: Courant number c_f dt / h = 0.8, c_f = 2
+                    nt = int(math.ceil(0.5 / (0.4 / n)))
+                else:
+                    nt = int(math.ceil(0.5 / (c * (1.0 / n) ** (5.0 / 3.0))))
                 for _ in range(nt):
                     p.step_dt(0.5 / nt)
                 st = p.state()
@@ -158,6 +165,36 @@ def convergence(sizes, c: float = 0.25):
         out[name] = {"l1": l1, "l1_order": [round(math.log2(l1[i] / l1[i + 1]), 3) for i in range(len(l1) - 1)],
                      "k1": fk, "k1_order": [round(math.log2(fk[i] / fk[i + 1]), 3) for i in range(len(fk) - 1)]}
     out["sizes"] = list(sizes)
+    return out
+
+
+def rk4_leg(n: int, steps: int):
+    """The headline workload (n^3, Mach 2, FP64) with the paper's classical RK4
+    at CFL 0.8 next to SSP-RK3 at CFL 0.4: zone-updates per second per step of
+    each, and simulated time advanced per wall-clock second (dt from eq. (cfl)
+    each step, read back after the step)."""
+    import torch
+    from paper_1812_04278_amd import binding, inputs
+    f = inputs.random_fields(n, seed=1, v_rms=2.0, kmax=4)
+    out = {}
+    for name, integ, cfl in (("rk4", binding.WM_RK4, 0.8), ("ssprk3", binding.WM_SSPRK3, 0.4)):
+        p = binding.Patch(binding.config(n, cfl=cfl, integrator=integ), device="cuda:0")
+        p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+        p.step()                                    # warm-up
+        p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_sim = 0.0
+        for _ in range(steps):
+            t_sim += p.step(want_dt=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"value": round(n ** 3 * steps / wall / 1e6, 3), "unit": "Mzone-updates/s",
+                     "ms_per_step": round(wall * 1e3 / steps, 4), "cfl": cfl, "sim_time": float(f"{t_sim:.6e}"),
+                     "sim_time_per_wall_s": float(f"{t_sim / wall:.6e}")}
+        del p
+    out["sim_time_rate_rk4_vs_ssprk3"] = round(out["rk4"]["sim_time_per_wall_s"] / out["ssprk3"]["sim_time_per_wall_s"], 4)
+    out["workload"] = f"{n}^3 periodic box, Mach 2, beta~1, FP64, {steps} steps of each integrator"
     return out
 
 
@@ -287,6 +324,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64-vs-mixed comparison")
     ap.add_argument("--no-convergence", action="store_true", help="skip the fast-wave convergence table")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
+    ap.add_argument("--no-rk4", action="store_true", help="skip the RK4 (CFL 0.8) throughput leg")
     ap.add_argument("--c5", action="store_true",
                     help="also run the 512^3 Mach-5 workload (FP32 state, FP64 adjoint); several minutes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -374,6 +412,9 @@ def main():
     if not args.no_mixed:
         log("bench: mixed precision vs FP64 (Mach 0.1 workload)")
         out["mixed"] = mixed_precision(n, args.steps)
+    if not args.no_rk4:
+        log("bench: classical RK4 at CFL 0.8 vs SSP-RK3 at CFL 0.4")
+        out["rk4"] = rk4_leg(n, args.steps)
     if not args.no_convergence:
         log("bench: fast-wave convergence, both precisions")
         out["convergence"] = convergence((32, 64, 128, 256))

@@ -73,6 +73,12 @@ typedef enum {
                                bracket (tau_5/(eps_Z + IS_k))^2)              */
 } wm_weights;
 
+typedef enum {
+  WM_SSPRK3 = 0,            /* three-stage SSP-RK3 (Shu-Osher), CFL 0.4       */
+  WM_RK4 = 1                /* the classical four-stage RK4 of Sect. 2.1, for
+                               which the paper uses CFL 0.8                   */
+} wm_integrator;
+
 typedef struct {
   int nx, ny, nz;           /* zones per direction, each >= 1                */
   double h;                 /* zone size (> 0)                               */
@@ -83,6 +89,7 @@ typedef struct {
   double eps_Z;             /* WENO-Z epsilon, 1e-40 in the paper            */
   int weights;              /* wm_weights                                    */
   int precision;            /* wm_precision                                  */
+  int integrator;           /* wm_integrator                                 */
 } wm_config;
 
 typedef struct {
@@ -98,8 +105,9 @@ typedef struct {
 
 typedef struct wm_patch wm_patch;   /* opaque; owns no device memory */
 
-/* Fills cfg with the paper's constants (gamma 5/3, CFL 0.4, eps 1e-6,
- * eps_B 1e-30, eps_Z 1e-40, Jiang-Shu, FP64) for an n^3 box of length 1. */
+/* Fills cfg with the paper's constants (gamma 5/3, eps 1e-6, eps_B 1e-30,
+ * eps_Z 1e-40, Jiang-Shu, FP64) and SSP-RK3 at CFL 0.4 for an n^3 box of
+ * length 1 (for WM_RK4 the paper's Courant number is 0.8). */
 void wm_config_default(wm_config* cfg, int n);
 
 /* Bytes of device scratch a patch with this configuration needs: the stage
@@ -136,14 +144,21 @@ wm_status wm_refresh_zone_field(wm_patch* p);
  * dt_host is non-NULL the stream is synchronised and dt copied there. */
 wm_status wm_compute_dt(wm_patch* p, double* dt_host);
 
-/* One SSP-RK3 stage (increment form): stage 0 reads the bound state U^n and
- * writes k0 and U1 = U^n + dt k0 into scratch; stage 1 writes k0+k1 and
- * U2 = U^n + dt/4 (k0+k1); stage 2 writes U^{n+1} = U^n + dt/6 (k0+k1+4 k2)
- * into the bound state.  Each stage ends with zone B re-interpolated from the
- * new face field.  dt_host NULL: the device dt of the last wm_compute_dt. */
+/* One Runge-Kutta stage in increment form, k_s the right-hand side at the
+ * stage state (stage 0: the bound state U^n).  WM_SSPRK3, stages 0..2:
+ * stage 0 writes k0 and U1 = U^n + dt k0 into scratch; stage 1 writes k0+k1
+ * and U2 = U^n + dt/4 (k0+k1); stage 2 writes U^{n+1} = U^n + dt/6 (k0+k1+4 k2)
+ * into the bound state.  WM_RK4, stages 0..3 (Sect. 2.1): U1 = U^n + dt/2 k0,
+ * U2 = U^n + dt/2 k1, U3 = U^n + dt k2 into scratch with the accumulator
+ * k0 + 2 k1 + 2 k2, and stage 3 writes U^{n+1} = U^n + dt/6 (k0 + 2 k1 +
+ * 2 k2 + k3) into the bound state (the paper's q_save sum).  Each stage ends
+ * with zone B re-interpolated from the new face field.  Stages run in order
+ * (WM_ERR_STATE otherwise).  dt_host NULL: the device dt of the last
+ * wm_compute_dt. */
 wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host);
 
-/* wm_compute_dt followed by the three stages.  If dt_used is non-NULL the
+/* wm_compute_dt followed by the stages of the configured integrator (three
+ * for WM_SSPRK3, four for WM_RK4).  If dt_used is non-NULL the
  * stream is synchronised and the dt of the step is returned there. */
 wm_status wm_step(wm_patch* p, double* dt_used);
 
@@ -192,14 +207,15 @@ wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const vo
  * held fixed): lam_hydro [5][..], lam_bface [3][..] hold dJ/dU^{n+1} on entry
  * and dJ/dU^n on return.  U1_stage, U2_stage: the step's two intermediate
  * stage states as wm_step_record stores them ([8][..]: hydro then face b), or
- * both NULL to recompute them from U^n into adj_scratch. */
+ * both NULL to recompute them from U^n into adj_scratch.  A WM_RK4 patch
+ * returns WM_ERR_ARG. */
 wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface,
                           const void* U1_stage, const void* U2_stage, double dt, void* lam_hydro, void* lam_bface);
 
 /* One SSP-RK3 step of the bound state with the given dt (as wm_rk_stage
  * 0, 1, 2), also copying the two intermediate stage states to U1_out and
  * U2_out ([8][nz][ny][nx] device arrays each: rho, m_x, m_y, m_z, E, b_x, b_y,
- * b_z), for a later wm_adjoint_step. */
+ * b_z), for a later wm_adjoint_step.  A WM_RK4 patch returns WM_ERR_ARG. */
 wm_status wm_step_record(wm_patch* p, double dt, void* U1_out, void* U2_out);
 
 /* lam_bface += transpose of the zone interpolation B = interp4(b) applied to

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libwenomhd.so")
 WM_OK, WM_ERR_ARG, WM_ERR_HIP, WM_ERR_UNPHYSICAL, WM_ERR_STATE = 0, -1, -2, -3, -4
 WM_FP64, WM_MIXED, WM_MIXED_F32STATE = 0, 1, 2
 WM_WENO_JS, WM_WENO_Z = 0, 1
+WM_SSPRK3, WM_RK4 = 0, 1
 
 SYMBOLS = [
     "wm_config_default", "wm_scratch_bytes", "wm_patch_create", "wm_patch_destroy", "wm_bind_state",
@@ -31,7 +32,7 @@ class WmConfig(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("h", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("eps_B", ctypes.c_double), ("eps_Z", ctypes.c_double),
-                ("weights", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("weights", ctypes.c_int), ("precision", ctypes.c_int), ("integrator", ctypes.c_int)]
 
 
 class WmDiag(ctypes.Structure):
@@ -107,12 +108,13 @@ def _check(status):
 
 
 def config(n=None, nx=None, ny=None, nz=None, h=None, gamma=5.0 / 3.0, cfl=0.4, eps=1e-6, eps_B=1e-30,
-           eps_Z=1e-40, weights=WM_WENO_JS, precision=WM_FP64) -> WmConfig:
+           eps_Z=1e-40, weights=WM_WENO_JS, precision=WM_FP64, integrator=WM_SSPRK3) -> WmConfig:
     nx = nx or n
     ny = ny or n
     nz = nz or n
     c = WmConfig(nx=nx, ny=ny, nz=nz, h=h if h is not None else 1.0 / nx, gamma=gamma, cfl=cfl,
-                 eps_weno=eps, eps_B=eps_B, eps_Z=eps_Z, weights=weights, precision=precision)
+                 eps_weno=eps, eps_B=eps_B, eps_Z=eps_Z, weights=weights, precision=precision,
+                 integrator=integrator)
     return c
 
 
@@ -202,8 +204,12 @@ class Patch:
         _check(self.lib.wm_step(self.handle, None))
         return None
 
+    @property
+    def n_stages(self) -> int:
+        return 4 if self.cfg.integrator == WM_RK4 else 3
+
     def step_dt(self, dt: float):
-        for s in range(3):
+        for s in range(self.n_stages):
             self.rk_stage(s, dt)
 
     def diagnostics(self, raise_unphysical: bool = True):

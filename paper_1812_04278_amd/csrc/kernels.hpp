@@ -247,8 +247,15 @@ struct TView {
   const S *xy, *xz, *yz, *yx, *zx, *zy;
 };
 
-template <int STAGE, typename S>
+// RK = 3: SSP-RK3 (Shu-Osher) in increment form, acc = k0, k0 + k1;
+//   U1 = U^n + dt k0, U2 = U^n + dt/4 (k0 + k1), U^{n+1} = U^n + dt/6 (k0 + k1 + 4 k2).
+// RK = 4: the classical RK4 of Sect. 2.1 in increment form, acc = k0, k0 + 2 k1,
+//   k0 + 2 k1 + 2 k2; U1 = U^n + dt/2 k0, U2 = U^n + dt/2 k1, U3 = U^n + dt k2,
+//   U^{n+1} = U^n + dt/6 (k0 + 2 k1 + 2 k2 + k3) -- the paper's q_save sum
+//   -4/3 q0 + q1/3 + 2 q2/3 + q3/3 + q4 written out.
+template <int RK, int STAGE, typename S>
 __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
+  static_assert((RK == 3 && STAGE >= 0 && STAGE < 3) || (RK == 4 && STAGE >= 0 && STAGE < 4), "stage of the scheme");
   const Grid& g = a.g;
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -311,16 +318,29 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
   for (int v = 0; v < 8; ++v) {
     const double un = v < 5 ? double(a.Un[v * N + c0]) : double(a.bn[(v - 5) * N + c0]);
     double out;
-    if (STAGE == 0) {
-      a.acc[v * N + c0] = S(kv[v]);
-      out = un + dt * kv[v];
-    } else if (STAGE == 1) {
-      const double s = double(a.acc[v * N + c0]) + kv[v];
-      a.acc[v * N + c0] = S(s);
-      out = un + (0.25 * dt) * s;
+    if constexpr (RK == 3) {
+      if constexpr (STAGE == 0) {
+        a.acc[v * N + c0] = S(kv[v]);
+        out = un + dt * kv[v];
+      } else if constexpr (STAGE == 1) {
+        const double s = double(a.acc[v * N + c0]) + kv[v];
+        a.acc[v * N + c0] = S(s);
+        out = un + (0.25 * dt) * s;
+      } else {
+        const double s = double(a.acc[v * N + c0]) + 4.0 * kv[v];
+        out = un + (dt / 6.0) * s;
+      }
     } else {
-      const double s = double(a.acc[v * N + c0]) + 4.0 * kv[v];
-      out = un + (dt / 6.0) * s;
+      if constexpr (STAGE == 0) {
+        a.acc[v * N + c0] = S(kv[v]);
+        out = un + (0.5 * dt) * kv[v];
+      } else if constexpr (STAGE < 3) {
+        a.acc[v * N + c0] = S(double(a.acc[v * N + c0]) + 2.0 * kv[v]);
+        out = un + (STAGE == 1 ? 0.5 * dt : dt) * kv[v];
+      } else {
+        const double s = double(a.acc[v * N + c0]) + kv[v];
+        out = un + (dt / 6.0) * s;
+      }
     }
     if (v < 5) a.hyd_out[v * N + c0] = S(out);
     else a.b_out[(v - 5) * N + c0] = S(out);

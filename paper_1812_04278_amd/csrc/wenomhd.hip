@@ -69,6 +69,7 @@ bool valid_config(const wm_config* c, const char** why) {
     *why = "unknown precision mode";
     return false;
   }
+  if (c->integrator != WM_SSPRK3 && c->integrator != WM_RK4) { *why = "unknown integrator"; return false; }
   return true;
 }
 
@@ -277,6 +278,8 @@ wm_status sweeps(wm_patch* p, const S* hydro, const S* bcell) {
   return WM_OK;
 }
 
+int n_stages(const wm_patch* p) { return p->cfg.integrator == WM_RK4 ? 4 : 3; }
+
 template <typename S>
 wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
   const size_t N = p->g.N;
@@ -289,7 +292,7 @@ wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
   a.acc = p->acc<S>();
   a.rhs_out = rhs_out;
   a.dt = p->dt_dev();
-  if (stage == 2) {
+  if (stage == n_stages(p) - 1) {
     a.hyd_out = p->hyd<S>();
     a.b_out = p->bf<S>();
   } else {
@@ -298,10 +301,19 @@ wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
   }
   dim3 grid = zone_grid(p->g);
   const long r = prof_begin(p, K_UPDATE);
-  switch (stage) {
-    case 0: hipLaunchKernelGGL((update_kernel<0, S>), grid, dim3(256), 0, p->stream, a); break;
-    case 1: hipLaunchKernelGGL((update_kernel<1, S>), grid, dim3(256), 0, p->stream, a); break;
-    default: hipLaunchKernelGGL((update_kernel<2, S>), grid, dim3(256), 0, p->stream, a); break;
+  if (p->cfg.integrator == WM_RK4) {
+    switch (stage) {
+      case 0: hipLaunchKernelGGL((update_kernel<4, 0, S>), grid, dim3(256), 0, p->stream, a); break;
+      case 1: hipLaunchKernelGGL((update_kernel<4, 1, S>), grid, dim3(256), 0, p->stream, a); break;
+      case 2: hipLaunchKernelGGL((update_kernel<4, 2, S>), grid, dim3(256), 0, p->stream, a); break;
+      default: hipLaunchKernelGGL((update_kernel<4, 3, S>), grid, dim3(256), 0, p->stream, a); break;
+    }
+  } else {
+    switch (stage) {
+      case 0: hipLaunchKernelGGL((update_kernel<3, 0, S>), grid, dim3(256), 0, p->stream, a); break;
+      case 1: hipLaunchKernelGGL((update_kernel<3, 1, S>), grid, dim3(256), 0, p->stream, a); break;
+      default: hipLaunchKernelGGL((update_kernel<3, 2, S>), grid, dim3(256), 0, p->stream, a); break;
+    }
   }
   WM_LAUNCH_CHECK("update kernel");
   prof_end(p, r);
@@ -413,8 +425,8 @@ wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double
     double* out = st == 0 ? U1 : U2;
     a.hyd_out = out;
     a.b_out = out + 5 * N;
-    if (st == 0) hipLaunchKernelGGL((update_kernel<0, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
-    else hipLaunchKernelGGL((update_kernel<1, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
+    if (st == 0) hipLaunchKernelGGL((update_kernel<3, 0, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
+    else hipLaunchKernelGGL((update_kernel<3, 1, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
     WM_LAUNCH_CHECK("update kernel");
     if ((s = launch_bcell<double>(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
   }
@@ -436,6 +448,7 @@ void wm_config_default(wm_config* c, int n) {
   c->eps_Z = 1e-40;
   c->weights = WM_WENO_JS;
   c->precision = WM_FP64;
+  c->integrator = WM_SSPRK3;
 }
 
 size_t wm_scratch_bytes(const wm_config* cfg) {
@@ -568,8 +581,9 @@ wm_status wm_compute_dt(wm_patch* p, double* dt_host) {
 wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
   wm_status s = check_bound(p);
   if (s != WM_OK) return s;
-  if (stage < 0 || stage > 2) return fail(WM_ERR_ARG, "stage must be 0, 1 or 2");
-  if (stage > 0 && p->stage_done != stage - 1) return fail(WM_ERR_STATE, "stages must run in order 0, 1, 2");
+  const int ns = n_stages(p);
+  if (stage < 0 || stage >= ns) return fail(WM_ERR_ARG, "stage out of range for the integrator (SSP-RK3: 0..2, RK4: 0..3)");
+  if (stage > 0 && p->stage_done != stage - 1) return fail(WM_ERR_STATE, "stages must run in order from 0");
   if (dt_host) {
     if (!std::isfinite(*dt_host)) return fail(WM_ERR_ARG, "dt is not finite");
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, p->dt_dev(), *dt_host);
@@ -586,11 +600,11 @@ wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
     wm_status st;
     if ((st = sweeps<S>(p, hyd_in, bcell_in)) != WM_OK) return st;
     if ((st = launch_update<S>(p, stage, nullptr)) != WM_OK) return st;
-    if (stage == 2) return launch_bcell<S>(p, p->bf<S>(), p->bc<S>());
+    if (stage == ns - 1) return launch_bcell<S>(p, p->bf<S>(), p->bc<S>());
     return launch_bcell<S>(p, p->us<S>() + 5 * N, p->us<S>() + 8 * N);
   });
   if (s != WM_OK) return s;
-  if (stage == 2) {
+  if (stage == ns - 1) {
     p->stage_done = -1;
     p->dt_valid = false;
   } else {
@@ -609,7 +623,7 @@ wm_status wm_step(wm_patch* p, double* dt_used) {
       return s;
   }
   p->stage_done = -1;
-  for (int st = 0; st < 3; ++st)
+  for (int st = 0; st < n_stages(p); ++st)
     if ((s = wm_rk_stage(p, st, nullptr)) != WM_OK) return s;
   if (dt_used) {
     if ((s = hip_check(hipStreamSynchronize(p->stream), "step sync")) != WM_OK) return s;
@@ -702,6 +716,7 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
                           const void* U1_stage, const void* U2_stage, double dt, void* lam_hydro, void* lam_bface) {
   wm_status s = check_adjoint(p, adj_scratch);
   if (s != WM_OK) return s;
+  if (p->cfg.integrator != WM_SSPRK3) return fail(WM_ERR_ARG, "the step adjoint is for the SSP-RK3 step");
   if (!Un_hydro || !Un_bface || !lam_hydro || !lam_bface) return fail(WM_ERR_ARG, "null pointer");
   if ((U1_stage == nullptr) != (U2_stage == nullptr)) return fail(WM_ERR_ARG, "give both stage states or neither");
   if (!std::isfinite(dt)) return fail(WM_ERR_ARG, "dt is not finite");
@@ -746,6 +761,7 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
 wm_status wm_step_record(wm_patch* p, double dt, void* U1_out, void* U2_out) {
   wm_status s = check_bound(p);
   if (s != WM_OK) return s;
+  if (p->cfg.integrator != WM_SSPRK3) return fail(WM_ERR_ARG, "stage recording is for the SSP-RK3 step");
   if (!U1_out || !U2_out) return fail(WM_ERR_ARG, "null pointer");
   if (!std::isfinite(dt)) return fail(WM_ERR_ARG, "dt is not finite");
   const size_t bytes = 8 * p->g.N * state_elem_bytes(&p->cfg);

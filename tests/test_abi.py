@@ -34,6 +34,7 @@ def test_scratch_bytes_and_default_config():
     assert (c.nx, c.ny, c.nz) == (32, 32, 32)
     assert abs(c.h - 1 / 32) < 1e-18 and abs(c.gamma - 5 / 3) < 1e-15 and c.cfl == 0.4
     assert c.eps_weno == 1e-6 and c.eps_B == 1e-30
+    assert c.integrator == B.WM_SSPRK3
     n = lib.wm_scratch_bytes(ctypes.byref(c))
     N = 32 ** 3
     assert n >= 40 * N * 8 and n % 256 == 0
@@ -42,7 +43,8 @@ def test_scratch_bytes_and_default_config():
 
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("gamma", 1.0), ("cfl", -1.0),
-                                         ("weights", 7), ("precision", 9), ("eps_weno", 0.0)])
+                                         ("weights", 7), ("precision", 9), ("eps_weno", 0.0),
+                                         ("integrator", 2)])
 def test_invalid_config_rejected(field, value):
     lib = B.load()
     c = B.config(16)

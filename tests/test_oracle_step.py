@@ -119,6 +119,79 @@ def test_ssp_rk3_amplification():
         np.testing.assert_allclose(U1[key].numpy(), amp * U[key].numpy(), rtol=1e-14, atol=1e-15)
 
 
+def _with_rhs(f, fn):
+    orig = mhd.rhs
+    try:
+        mhd.rhs = f
+        return fn()
+    finally:
+        mhd.rhs = orig
+
+
+def test_rk4_amplification():
+    """With a linear right-hand side k = z U / dt the paper's RK4 (the q_save
+    accumulation of Sect. 2.1) multiplies U by the degree-4 Taylor polynomial
+    of exp(z), the stability polynomial of every four-stage fourth-order RK."""
+    U, cfg = state(4, kmax=1)
+    z, dt = -0.7, 0.1
+    U1, _ = _with_rhs(lambda Us, cfg: {key: (z / dt) * Us[key] for key in Us}, lambda: mhd.step_rk4(U, cfg, dt))
+    amp = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    for key in U:
+        np.testing.assert_allclose(U1[key].numpy(), amp * U[key].numpy(), rtol=2e-15, atol=1e-15)
+
+
+def _riccati(Us, cfg, c=0.8):
+    return {key: c * Us[key] * Us[key] for key in Us}
+
+
+def test_rk4_is_the_classical_tableau():
+    """On the nonlinear autonomous ODE y' = 0.8 y^2 (zone by zone) one q_save
+    step equals the textbook form of the classical RK4 -- stage slopes at
+    y, y + dt/2 k1, y + dt/2 k2, y + dt k3, weights 1/6, 1/3, 1/3, 1/6 -- which
+    distinguishes it from the other four-stage fourth-order methods (they share
+    the linear polynomial but not this nonlinear step)."""
+    U, cfg = state(4, kmax=1)
+    dt = 0.05
+    U1, _ = _with_rhs(_riccati, lambda: mhd.step_rk4(U, cfg, dt))
+    for key in U:
+        y = U[key].numpy()
+        f = lambda v: 0.8 * v * v
+        k1 = f(y)
+        k2 = f(y + 0.5 * dt * k1)
+        k3 = f(y + 0.5 * dt * k2)
+        k4 = f(y + dt * k3)
+        ref = y + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        np.testing.assert_allclose(U1[key].numpy(), ref, rtol=1e-14, atol=1e-15)
+    # a different fourth-order method (Kutta's 3/8 rule) differs at O(dt^5)
+    y = U["E"].numpy()
+    f = lambda v: 0.8 * v * v
+    k1 = f(y)
+    k2 = f(y + dt / 3 * k1)
+    k3 = f(y + dt * (-k1 / 3 + k2))
+    k4 = f(y + dt * (k1 - k2 + k3))
+    other = y + dt / 8 * (k1 + 3 * k2 + 3 * k3 + k4)
+    assert float(np.abs(other - U1["E"].numpy()).max()) > 1e3 * 1e-15 * float(np.abs(y).max())
+
+
+def test_rk4_fourth_order_on_riccati():
+    """y' = 0.8 y^2 has the closed form y(t) = y0 / (1 - 0.8 y0 t); the q_save
+    RK4 error at t = 0.25 falls 16-fold per halving of dt."""
+    U, cfg = state(4, kmax=1)
+    t_end = 0.25
+    errs = []
+    for nt in (8, 16, 32):
+        def run():
+            V = U
+            for _ in range(nt):
+                V, _ = mhd.step_rk4(V, cfg, t_end / nt)
+            return V
+        V = _with_rhs(_riccati, run)
+        exact = U["rho"] / (1 - 0.8 * U["rho"] * t_end)
+        errs.append(float((V["rho"] - exact).abs().max()))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(3.8 < o < 4.2 for o in orders), (errs, orders)
+
+
 # ---------------------------------------------------------------------------
 # grid-aligned linear fast wave (Sect. 4.1 setup, wave vector along x)
 # ---------------------------------------------------------------------------
@@ -142,13 +215,15 @@ def fast_wave_state(n, ny=1, nz=1, t=0.0, A0=1e-6):
     return dict(rho=rho.contiguous(), m=m.contiguous(), E=E.contiguous(), b=b.contiguous()), cfg
 
 
-def fast_wave_error(n, t_end, c=0.25):
+def fast_wave_error(n, t_end, c=0.25, rk4=False):
+    """L1 error of the fast wave after t_end; dt ~ h^(5/3) (SSP-RK3) or
+    h^(5/4) (RK4), so that the time error falls as fast as the space error."""
     U, cfg = fast_wave_state(n)
     exact, _ = fast_wave_state(n, t=t_end)
-    nt = int(math.ceil(t_end / (c * cfg.h ** (5.0 / 3.0))))
+    nt = int(math.ceil(t_end / (c * cfg.h ** (1.25 if rk4 else 5.0 / 3.0))))
     dt = t_end / nt
     for _ in range(nt):
-        U, _ = mhd.step(U, cfg, dt)
+        U, _ = (mhd.step_rk4 if rk4 else mhd.step)(U, cfg, dt)
     return mhd.l1_error(U, exact)[1]
 
 
@@ -157,5 +232,14 @@ def test_fast_wave_converges_fifth_order():
     cancel), so the L1 error against the closed-form travelling wave falls as
     N^-5 with dt ~ h^(5/3) (Sect. 4.1 reports N^-5 in 1D)."""
     e = [fast_wave_error(n, 0.125) for n in (16, 32)]
+    order = math.log2(e[0] / e[1])
+    assert order > 4.5, (e, order)
+
+
+def test_fast_wave_converges_fifth_order_rk4():
+    """The same wave with the paper's RK4 and dt ~ h^(5/4), with c_f dt / h = 0.8
+    at N = 32 (the paper's Courant number for RK4; 0.95 at N = 16): the error
+    still falls as N^-5."""
+    e = [fast_wave_error(n, 0.125, c=0.95, rk4=True) for n in (16, 32)]
     order = math.log2(e[0] / e[1])
     assert order > 4.5, (e, order)
