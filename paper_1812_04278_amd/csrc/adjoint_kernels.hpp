@@ -88,11 +88,14 @@ struct AdjSweepArgs {
 constexpr int ADJ_NP = 11;   // cotangents of zone primitives and speeds (P_* order)
 // One thread per face; one 256-face tile per CU (LDS), so one wave per SIMD
 // with up to 512 registers per thread.
-constexpr int ADJ_THREADS = SW_THREADS;
+constexpr int ADJ_THREADS = 256;
+// adjoint tiles: TA faces along the sweep axis times TB across it, TA * TB = ADJ_THREADS
+template <int AXIS> struct AdjTile { static constexpr int TA = 16, TB = 16; };
+template <> struct AdjTile<0> { static constexpr int TA = 64, TB = 4; };
 
 template <int AXIS>
 struct AdjLds {
-  static constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  static constexpr int TA = AdjTile<AXIS>::TA, TB = AdjTile<AXIS>::TB;
   static constexpr int NC = (TA + SW_HL + SW_HR) * TB, NIF = (TA + 4) * TB, NF = TA * TB;
   static constexpr size_t bytes = sizeof(double) * (size_t)(SW_NQ * NC + SW_NP * NC + ADJ_NP * NC + SW_NQ * NIF + 7 * NF);
 };
@@ -106,7 +109,7 @@ struct AdjLds {
 // accumulation is fixed.
 template <int AXIS>
 __global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a) {
-  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  constexpr int TA = AdjTile<AXIS>::TA, TB = AdjTile<AXIS>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;
   constexpr int NI = TA + 4;
   constexpr int NC = NA * TB;

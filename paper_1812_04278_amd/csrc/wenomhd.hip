@@ -357,7 +357,7 @@ wm_status launch_adj_sweep(wm_patch* p, const double* hydro, const double* bcell
   a.lam_Bz = lam_Bz;
   const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
   const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
-  constexpr int TB = SweepTile<AXIS>::TB;
+  constexpr int TB = AdjTile<AXIS>::TB;
   const TilePlan& pl = p->adj_plan[AXIS];
   const long r = prof_begin(p, K_OTHER);
   for (int c = 0; c < pl.n; ++c) {   // classes in order: each launch adds into disjoint zones
@@ -486,7 +486,7 @@ wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch,
   p->f32 = cfg->precision == WM_MIXED_F32STATE;
   if (cfg->nx >= 3 && cfg->ny >= 3 && cfg->nz >= 3) {
     const int n3[3] = {cfg->nx, cfg->ny, cfg->nz};
-    const int ta[3] = {SweepTile<0>::TA, SweepTile<1>::TA, SweepTile<2>::TA};
+    const int ta[3] = {AdjTile<0>::TA, AdjTile<1>::TA, AdjTile<2>::TA};
     for (int d = 0; d < 3; ++d) {
       p->adj_plan[d] = plan_tiles(n3[d], ta[d]);
       if (!plan_disjoint(n3[d], ta[d], p->adj_plan[d])) {
