@@ -27,7 +27,9 @@ Readings of passages that are garbled or silent (numbered as in the design doc):
   R8  degenerate branch (alpha_f, alpha_s) = (1/sqrt2, 1/sqrt2); alpha_f^2 and
       alpha_s^2 from (1 +- (a^2 - b^2)/D)/2 clamped to [0, 1], which equals
       eq. (alpha) and is exactly 1/0 when B_perp = 0 (the explicit degeneracy
-      setting the appendix recommends)
+      setting the appendix recommends); written as (D +- dab)/(2D) with the
+      difference D - |dab| formed as 4 a^2 b_perp^2/(D + |dab|), free of the
+      cancellation that the appendix's renormalisation near degeneracies guards
   R9  CT transport fluxes T^d_a = F_d[B_a] + <B_d v_a> (the d-face average of
       the two zones), i.e. eq. (fct1)-(fct6) in the frame of each sweep
   R10 face state for L, R: arithmetic mean of the primitive states of the two
@@ -199,12 +201,16 @@ def eigenvectors(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P, gamma: float, eps_B: float)
     beta_z = torch.where(big, Bt2 / nb, torch.full_like(Bt2, 1.0 / math.sqrt(2.0)))
     sgn = torch.where(Bn >= eps_B, torch.ones_like(Bn), -torch.ones_like(Bn))
 
-    # alpha_f, alpha_s (eq. alpha, R8)
+    # alpha_f, alpha_s (eq. alpha, R8): alpha_f^2 = (1 + r)/2 = (D + dab)/(2D),
+    # alpha_s^2 = (1 - r)/2 = (D - dab)/(2D), with D - |dab| = 4 a^2 b_perp^2 / (D + |dab|)
+    # (D^2 = dab^2 + 4 a^2 b_perp^2), so the smaller one carries no cancellation
     nondeg = torch.sqrt(D) >= eps_B
     Dsafe = torch.where(nondeg, D, torch.ones_like(D))
-    r = (a2 - b2) / Dsafe
-    af2 = torch.clamp(0.5 * (1.0 + r), 0.0, 1.0)
-    as2 = torch.clamp(0.5 * (1.0 - r), 0.0, 1.0)
+    dab = a2 - b2
+    big = (Dsafe + dab.abs()) / (2.0 * Dsafe)
+    small = 4.0 * a2 * Bperp2 / rho / (Dsafe + dab.abs()) / (2.0 * Dsafe)
+    af2 = torch.clamp(torch.where(dab >= 0, big, small), 0.0, 1.0)
+    as2 = torch.clamp(torch.where(dab >= 0, small, big), 0.0, 1.0)
     alpha_f = torch.where(nondeg, torch.sqrt(af2), torch.full_like(D, 1.0 / math.sqrt(2.0)))
     alpha_s = torch.where(nondeg, torch.sqrt(as2), torch.full_like(D, 1.0 / math.sqrt(2.0)))
 
@@ -481,6 +487,20 @@ def diagnostics(U, cfg: Config):
         min_p=float(P.min()),
         n_unphysical=int(bad.sum()),
     )
+
+
+def wave_rms(U, e, background: float) -> float:
+    """Root-mean-square fluctuation of the zone field's component along the unit
+    vector e (a wave-frame axis) about its background value, over all zones:
+    the delta B_y of eq. (decay_rate) for e = the wave frame's second axis."""
+    B = zone_B(U["b"])
+    comp = B[0] * float(e[0]) + B[1] * float(e[1]) + B[2] * float(e[2])
+    return float(((comp - background) ** 2).mean().sqrt())
+
+
+def decay_rate(rms_0: float, rms_t: float, t: float) -> float:
+    """Eq. (decay_rate): tau_D = -log(delta B_y(t) / delta B_y(0)) / t."""
+    return -math.log(rms_t / rms_0) / t
 
 
 def l1_error(Ua, Ub, n_zones: int | None = None):

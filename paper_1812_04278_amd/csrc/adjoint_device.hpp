@@ -105,7 +105,8 @@ __host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const 
   const double Bp2 = Bt1 * Bt1 + Bt2 * Bt2;
   const double b2 = (Bn * Bn + Bp2) * irho;
   const double dab = a2 - b2;
-  const double Q = dab * dab + 4.0 * a2 * Bp2 * irho;
+  const double p4 = 4.0 * a2 * (Bp2 * irho);   // as in face_eig
+  const double Q = dab * dab + p4;
   const double D = sqrt_nr(Q);
   const double cf2 = 0.5 * (a2 + b2 + D);
   const double bv = e.by * vt1 + e.bz * vt2;
@@ -134,7 +135,8 @@ __host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const 
   if (D >= ph.eps_B * ph.eps_B) {
     const double iD = rcp_w(D);
     const double r = dab * iD;
-    const double cfa = 0.5 * (1.0 + r), csa = 0.5 * (1.0 - r);
+    double cfa, csa;   // the forward's clamped alpha^2 (same arithmetic), for the interior test
+    alpha_sq(dab, D, p4, cfa, csa);
     double l_r = 0.0;
     if (cfa > 0.0 && cfa < 1.0 && e.af > 0.0) l_r += l_af * 0.25 * rcp_w(e.af);
     if (csa > 0.0 && csa < 1.0 && e.as > 0.0) l_r -= l_as * 0.25 * rcp_w(e.as);

@@ -189,6 +189,20 @@ struct FaceEig {
   double v2, Gf, Ga, Gs, qa2, tau, g1, g2, omg;
 };
 
+// alpha_f^2 = (D + dab) / (2D) and alpha_s^2 = (D - dab) / (2D) of eq. (alpha),
+// dab = a^2 - b^2, D = sqrt(dab^2 + p), p = 4 a^2 b_perp^2 >= 0, clamped to
+// [0, 1].  The difference of nearly equal terms, D - |dab|, is formed as
+// p / (D + |dab|), so the smaller of the two is exact to rounding also as
+// b_perp -> 0 (it is exactly 0 at b_perp = 0, where 1 - dab/D would leave a
+// rounding residue that the square root of alpha raises to ~1e-8).
+__host__ __device__ __forceinline__ void alpha_sq(double dab, double D, double p, double& cfa, double& csa) {
+  const double h = 0.5 * rcp_w(D);
+  const double big = (D + fabs(dab)) * h;
+  const double small = p * rcp_w(D + fabs(dab)) * h;
+  cfa = fmin(fmax(dab >= 0.0 ? big : small, 0.0), 1.0);
+  csa = fmin(fmax(dab >= 0.0 ? small : big, 0.0), 1.0);
+}
+
 __host__ __device__ __forceinline__ void face_eig(double rho, double vn, double vt1, double vt2, double Bn, double Bt1,
                                                   double Bt2, double P, const Phys& ph, FaceEig& e) {
   const double gamma = ph.gamma;
@@ -202,7 +216,8 @@ __host__ __device__ __forceinline__ void face_eig(double rho, double vn, double 
   const double Bperp2 = Bt1 * Bt1 + Bt2 * Bt2;
   const double b2 = (Bn * Bn + Bperp2) * irho;
   const double dab = e.a2 - b2;
-  const double D = sqrt_nr(dab * dab + 4.0 * e.a2 * (Bperp2 * irho));
+  const double p4 = 4.0 * e.a2 * (Bperp2 * irho);
+  const double D = sqrt_nr(dab * dab + p4);
   e.cf2 = 0.5 * (e.a2 + b2 + D);
   e.cf = sqrt_nr(e.cf2);
   e.csl2 = e.cf2 > 0.0 ? e.a2 * (Bn * Bn * irho) * rcp_w(e.cf2) : 0.0;
@@ -217,9 +232,10 @@ __host__ __device__ __forceinline__ void face_eig(double rho, double vn, double 
   }
   e.s = Bn >= ph.eps_B ? 1.0 : -1.0;
   if (D >= ph.eps_B * ph.eps_B) {
-    const double r = dab * rcp_w(D);
-    e.af = sqrt_nr(fmin(fmax(0.5 * (1.0 + r), 0.0), 1.0));
-    e.as = sqrt_nr(fmin(fmax(0.5 * (1.0 - r), 0.0), 1.0));
+    double cfa, csa;
+    alpha_sq(dab, D, p4, cfa, csa);
+    e.af = sqrt_nr(cfa);
+    e.as = sqrt_nr(csa);
   } else {
     e.af = 0.70710678118654752440;
     e.as = 0.70710678118654752440;

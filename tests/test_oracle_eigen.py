@@ -171,3 +171,28 @@ def test_speed_ordering_and_textbook_form():
     np.testing.assert_allclose(cf.numpy(), torch.sqrt(0.5 * (a2 + b2 + rad)).numpy(), rtol=1e-13)
     np.testing.assert_allclose((cs ** 2).numpy(), (0.5 * (a2 + b2 - rad)).numpy(),
                                rtol=0, atol=1e-12 * float((a2 + b2).max()))
+
+
+def test_alpha_near_degeneracy_exact():
+    """eq. (alpha) near B_perp -> 0: alpha_s^2 = (1 - (a^2 - b^2)/D)/2 is a
+    difference of nearly equal terms; the eigenvectors must carry it to full
+    relative precision (checked against a 50-digit evaluation of the same
+    formula) and give alpha_s = 0, alpha_f = 1 exactly at B_perp = 0 with
+    c_A < c_s.  R[:, 0] is the fast column (first entry alpha_f), R[:, 2] the
+    slow one (first entry alpha_s)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    rho, P, Bn = 1.0, 0.6, 0.5
+    for bp in (1e-7, 3e-5, 1e-3, 0.0):
+        L, R = mhd.eigenvectors(t(rho), t(0.1), t(0.2), t(-0.3), t(Bn), t(bp), t(0.0), t(P), G, 1e-30)
+        af, as_ = float(R[0, 0]), float(R[0, 2])
+        a2 = Decimal(G) * Decimal(P) / Decimal(rho)
+        b2 = (Decimal(Bn) ** 2 + Decimal(bp) ** 2) / Decimal(rho)
+        D = ((a2 - b2) ** 2 + 4 * a2 * Decimal(bp) ** 2 / Decimal(rho)).sqrt()
+        ref_s = ((1 - (a2 - b2) / D) / 2).sqrt()
+        ref_f = ((1 + (a2 - b2) / D) / 2).sqrt()
+        if bp == 0.0:
+            assert as_ == 0.0 and af == 1.0
+        else:
+            assert abs(as_ / float(ref_s) - 1.0) < 1e-13, (bp, as_, float(ref_s))
+            assert abs(af / float(ref_f) - 1.0) < 1e-15, (bp, af, float(ref_f))
