@@ -198,6 +198,62 @@ def rk4_leg(n: int, steps: int):
     return out
 
 
+def oblique_waves(sizes, modes=("fast", "slow", "alfven", "entropy"), t_end: float = 2.0):
+    """The 3D linear-wave suite of Sect. 4.1 with the paper's WENO-Z weights and
+    RK4 at CFL 0.8: each MHD mode travels along (1, 2, 2)/3 through a 2N x N x N
+    box (3 x 1.5 x 1.5).  Reports the L1 of Sect. 3 (rho, m, zone B, E; geometric
+    norm) against the initial state after one wave period, and the decay rate of
+    eq. (decay_rate) of the transverse field B_2 (wave frame) between t = 0 and
+    t_end, with the convergence orders between successive N.  dt: the largest
+    step within CFL 0.8 at t = 0 that divides the period."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1812_04278_amd import binding, inputs
+
+    def zone_vars(p):
+        h = p.hydro.double()
+        B = p.bcell.double()
+        return [h[0], h[1], h[2], h[3], B[0], B[1], B[2], h[4]]
+
+    def rms_B2(p, e2, bg):
+        B = p.bcell.double()
+        comp = B[0] * float(e2[0]) + B[1] * float(e2[1]) + B[2] * float(e2[2])
+        return float(((comp - bg) ** 2).mean().sqrt())
+
+    out = {"sizes": list(sizes), "t_end": t_end, "weights": "wenoz", "integrator": "rk4", "cfl": 0.8}
+    for mode in modes:
+        l1, tau = [], []
+        for N in sizes:
+            w = inputs.oblique_wave(N, mode)
+            nz, ny, nx = w["shape"]
+            p = binding.Patch(binding.config(nx=nx, ny=ny, nz=nz, h=w["h"], cfl=0.8, weights=binding.WM_WENO_Z,
+                                             integrator=binding.WM_RK4), device="cuda:0")
+            p.init_from_potential(w["rho"], np.zeros((3, nz, ny, nx)), w["A"], 1.0 / w["gamma"], w["B0"])
+            p.set_state(w["rho"], w["m"], w["E"], p.bface)
+            e2 = w["frame"][1]
+            bg = math.sqrt(2.0)
+            period = 1.0 / w["speed"]
+            nt = int(math.ceil(period / p.compute_dt()))
+            dt = period / nt
+            ref = [x.clone() for x in zone_vars(p)]
+            r0 = rms_B2(p, e2, bg)
+            n_end = int(round(t_end / dt))
+            for s in range(1, n_end + 1):
+                p.step_dt(dt)
+                if s == nt:
+                    per = [float((x - y).abs().mean()) for x, y in zip(zone_vars(p), ref)]
+                    l1.append(float(f"{math.sqrt(sum(v * v for v in per)):.4e}"))
+            tau.append(float(f"{-math.log(rms_B2(p, e2, bg) / r0) / (n_end * dt):.4e}") if r0 > 0 else None)
+            del p
+        entry = {"l1": l1, "l1_order": [round(math.log2(l1[i] / l1[i + 1]), 3) for i in range(len(l1) - 1)]}
+        if all(t is not None and t > 0 for t in tau):
+            entry["decay_rate"] = tau
+            entry["decay_rate_order"] = [round(math.log2(tau[i] / tau[i + 1]), 3) for i in range(len(tau) - 1)]
+        out[mode] = entry
+    return out
+
+
 def adjoint_cost(n: int = 128, steps: int = 20, ckpt: int = 5):
     """The adjoint workload: gradient of J = h^3 sum[(rho_T - rho*)^2 + (|B_T|^2/2
     - e*)^2] (targets: the initial density and magnetic energy density of the
@@ -325,6 +381,8 @@ def main():
     ap.add_argument("--no-convergence", action="store_true", help="skip the fast-wave convergence table")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--no-rk4", action="store_true", help="skip the RK4 (CFL 0.8) throughput leg")
+    ap.add_argument("--no-waves", action="store_true", help="skip the oblique linear-wave suite")
+    ap.add_argument("--wave-sizes", default="16,32,64", help="N of the 2N x N x N wave boxes")
     ap.add_argument("--c5", action="store_true",
                     help="also run the 512^3 Mach-5 workload (FP32 state, FP64 adjoint); several minutes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -415,6 +473,9 @@ def main():
     if not args.no_rk4:
         log("bench: classical RK4 at CFL 0.8 vs SSP-RK3 at CFL 0.4")
         out["rk4"] = rk4_leg(n, args.steps)
+    if not args.no_waves:
+        log("bench: oblique linear waves (WENO-Z, RK4 at CFL 0.8)")
+        out["oblique_waves"] = oblique_waves(tuple(int(x) for x in args.wave_sizes.split(",")))
     if not args.no_convergence:
         log("bench: fast-wave convergence, both precisions")
         out["convergence"] = convergence((32, 64, 128, 256))

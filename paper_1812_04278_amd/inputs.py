@@ -160,3 +160,86 @@ def fast_wave(nx: int, ny: int = 4, nz: int = 4, t: float = 0.0, A0: float = 1e-
                 E=np.ascontiguousarray(Eb + A0 * R[7] * s),
                 b=np.ascontiguousarray(np.stack([np.ones_like(s), Bb[1] + A0 * R[5] * s, Bb[2] + A0 * R[6] * s])))
 
+
+# ---------------------------------------------------------------------------
+# oblique linear waves (Sect. 4.1, 3D setup)
+# ---------------------------------------------------------------------------
+
+_S5 = 1.0 / (6.0 * np.sqrt(5.0))
+# right eigenvectors printed in Sect. 4.1 for the conserved variables (rho, m_1,
+# m_2, m_3, B_1, B_2, B_3, E) in the wave frame, the wave speed, the background
+# velocity along the wave vector and whether the background field is present
+WAVE_MODES = {
+    "fast": (np.array([6, 12, -4 * np.sqrt(2.0), -2, 0, 8 * np.sqrt(2.0), 4, 27]) * _S5, 2.0, 0.0, True),
+    "slow": (np.array([12, 6, 8 * np.sqrt(2.0), 4, 0, -4 * np.sqrt(2.0), -2, 9]) * _S5, 0.5, 0.0, True),
+    "alfven": (np.array([0, 0, 1, -2 * np.sqrt(2.0), 0, -1, 2 * np.sqrt(2.0), 0]) * _S5, 1.0, 0.0, True),
+    "entropy": (np.array([1, 1, 0, 0, 0, 0, 0, 0.5]), 1.0, 1.0, True),
+    "sound": (np.array([1, 1, 0, 0, 0, 0, 0, 1.5]), 1.0, 0.0, False),
+    "shear": (np.array([0, 0, 1, 0, 0, 0, 0, 0]), 1.0, 1.0, False),
+    "entropy_hydro": (np.array([1, 1, 0, 0, 0, 0, 0, 0.5]), 1.0, 1.0, False),
+}
+
+
+def wave_frame():
+    """Unit vectors (e1, e2, e3) of the wave frame in lab coordinates: the
+    columns of the rotation of Sect. 4.1 with sin(alpha) = 2/3 and the angle
+    beta chosen so that the wave is periodic on the 3 x 1.5 x 1.5 box:
+    e1 = (1/3, 2/3, 2/3) (one wavelength along every box edge)."""
+    sa, ca = 2.0 / 3.0, np.sqrt(5.0) / 3.0
+    sb, cb = 2.0 / np.sqrt(5.0), 1.0 / np.sqrt(5.0)
+    e1 = np.array([ca * cb, ca * sb, sa])
+    e2 = np.array([-sb, cb, 0.0])
+    e3 = np.array([-sa * cb, -sa * sb, ca])
+    return e1, e2, e3
+
+
+def oblique_wave(N: int, mode: str, A0: float = 1e-6, t: float = 0.0, gamma: float = 5.0 / 3.0):
+    """Linear wave of Sect. 4.1 propagating along e1 = (1/3, 2/3, 2/3) through a
+    periodic 2N x N x N box of size 3 x 1.5 x 1.5 (zone size h = 1.5/N):
+    Q = Qbar + A0 R_k sin(2 pi (x_1 - c t)) in the conserved variables, x_1 = e1 . r
+    the zone-centre coordinate along the wave.  Background: rho = 1, P = 1/gamma,
+    v = v_bg e1, B = e1 + sqrt(2) e2 + e3/2 for the MHD modes (B = 0 for the
+    hydrodynamic ones).  The face field is b = B_bg + curl_h A with the edge
+    potential A = -A0/(2 pi) R_B3 cos(2 pi x_1) e2 + A0/(2 pi) R_B2 cos(2 pi x_1) e3,
+    whose curl is A0 (R_B2 e2 + R_B3 e3) sin(2 pi x_1), in phase with the other
+    variables.  Returns the zone-centred conserved fields (rho, m [3], E), the
+    potential on the edges (A [3], A_x at (i, j+1/2, k+1/2) ...), the uniform
+    field B0, the zone size, the wave speed and the frame."""
+    if mode not in WAVE_MODES:
+        raise ValueError(f"unknown mode {mode}")
+    R, c, vbg, mhd = WAVE_MODES[mode]
+    if not mhd and mode == "sound":
+        R = R.copy()
+        R[7] = 1.0 / (gamma - 1.0)
+    e1, e2, e3 = wave_frame()
+    nx, ny, nz = 2 * N, N, N
+    h = 1.5 / N
+
+    def coord(offset):
+        x = (np.arange(nx) + offset[0]) * h
+        y = (np.arange(ny) + offset[1]) * h
+        z = (np.arange(nz) + offset[2]) * h
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        return e1[0] * X + e1[1] * Y + e1[2] * Z
+
+    x1 = coord((0.5, 0.5, 0.5))
+    s = np.sin(2 * np.pi * (x1 - c * t))
+    Bw = np.array([1.0, np.sqrt(2.0), 0.5]) if mhd else np.zeros(3)
+    B0 = Bw[0] * e1 + Bw[1] * e2 + Bw[2] * e3
+    rho = 1.0 + A0 * R[0] * s
+    mw = [vbg + A0 * R[1] * s, A0 * R[2] * s, A0 * R[3] * s]
+    m = np.stack([mw[0] * e1[d] + mw[1] * e2[d] + mw[2] * e3[d] for d in range(3)])
+    Ebar = (1.0 / gamma) / (gamma - 1.0) + 0.5 * vbg * vbg + 0.5 * float(Bw @ Bw)
+    E = Ebar + A0 * R[7] * s
+    edge_offsets = [(0.5, 1.0, 1.0), (1.0, 0.5, 1.0), (1.0, 1.0, 0.5)]
+    A = np.zeros((3, nz, ny, nx))
+    if mhd:
+        for d in range(3):
+            cs = np.cos(2 * np.pi * (coord(edge_offsets[d]) - c * t))
+            a2 = -A0 / (2 * np.pi) * R[6] * cs
+            a3 = A0 / (2 * np.pi) * R[5] * cs
+            A[d] = a2 * e2[d] + a3 * e3[d]
+    return dict(rho=np.ascontiguousarray(rho), m=np.ascontiguousarray(m), E=np.ascontiguousarray(E),
+                A=np.ascontiguousarray(A), B0=tuple(float(x) for x in B0), h=h, speed=c, shape=(nz, ny, nx),
+                frame=(e1, e2, e3), gamma=gamma)
+
