@@ -407,8 +407,10 @@ __global__ __launch_bounds__(256) void init_hydro_kernel(size_t N, double gamma,
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
 
-__device__ __forceinline__ double nanmax(double a, double b) {   // NaN-propagating max
-  return (a != a || b > a) ? (b != b ? b : (a != a ? a : b)) : a;
+__device__ __forceinline__ double nanmax(double a, double b) {   // NaN-propagating max (either argument)
+  if (a != a) return a;
+  if (b != b) return b;
+  return b > a ? b : a;
 }
 
 // max over zones of |v_d| + c_fast^d, d = x, y, z -> part[3 * block + d]

@@ -265,3 +265,28 @@ def test_full_size_sampled_256():
             for comp in range(3):
                 assert rel_err(gv[comp], ov[comp]) <= TOL, (c, key, comp)
         say(f"  sample {c} ok")
+
+
+def test_failure_injection_unphysical():
+    """Host-side failure injection: a zone with E = 0 (negative gas pressure) and a
+    zone with a NaN density are reported by the diagnostics -- WM_ERR_UNPHYSICAL
+    with n_unphysical = 2 and the negative minimum pressure -- and a step from
+    that state still runs to completion, with a non-finite dt (the maxima of
+    eq. (cfl) propagate NaN) and the damage flagged afterwards."""
+    say("failure injection 16^3")
+    f = fields(16, seed=3, v_rms=0.3, kmax=2)
+    p = gpu_patch(f)
+    st = p.state()
+    rho, E = st["rho"].clone(), st["E"].clone()
+    E[3, 4, 5] = 0.0
+    rho[7, 8, 9] = float("nan")
+    p.set_state(rho, st["m"], E, st["b"])
+    with pytest.raises(B.WmError) as e:
+        p.diagnostics()
+    assert e.value.status == B.WM_ERR_UNPHYSICAL
+    d = p.diagnostics(raise_unphysical=False)
+    assert d["n_unphysical"] == 2, d
+    assert d["min_p"] < 0.0
+    dt = p.step(want_dt=True)
+    assert not math.isfinite(dt)
+    assert p.diagnostics(raise_unphysical=False)["n_unphysical"] >= 2
