@@ -189,7 +189,8 @@ wm_status wm_debug_rhs(wm_patch* p, void* out);
  * lam_bface [3][nz][ny][nx].  The adjoint needs every grid size >= 3. */
 
 /* Bytes of device scratch the adjoint calls need (caller-owned, 256-aligned,
- * reserved for one patch at a time).  0 for an invalid configuration.
+ * reserved for one patch at a time; more for WM_RK4, whose step adjoint holds
+ * a third stage state).  0 for an invalid configuration.
  * The adjoint calls linearise the FP64 method with Jiang-Shu weights (other
  * weights: WM_ERR_ARG; grid sizes below 3: WM_ERR_ARG).  On a mixed-precision
  * patch they give the FP64 linearisation at the states passed in (stage states
@@ -203,12 +204,13 @@ size_t wm_adjoint_scratch_bytes(const wm_config* cfg);
 wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const void* bface, const void* lam_k,
                      void* lam_out);
 
-/* Adjoint of one SSP-RK3 step U^{n+1} = Phi(U^n; dt) (increment form, dt
- * held fixed): lam_hydro [5][..], lam_bface [3][..] hold dJ/dU^{n+1} on entry
- * and dJ/dU^n on return.  U1_stage, U2_stage: the step's two intermediate
- * stage states as wm_step_record stores them ([8][..]: hydro then face b), or
- * both NULL to recompute them from U^n into adj_scratch.  A WM_RK4 patch
- * returns WM_ERR_ARG. */
+/* Adjoint of one step U^{n+1} = Phi(U^n; dt) of the patch's integrator
+ * (increment form, dt held fixed): lam_hydro [5][..], lam_bface [3][..] hold
+ * dJ/dU^{n+1} on entry and dJ/dU^n on return.  SSP-RK3: U1_stage, U2_stage are
+ * the step's two intermediate stage states as wm_step_record stores them
+ * ([8][..]: hydro then face b), or both NULL to recompute them from U^n into
+ * adj_scratch.  WM_RK4 (Sect. 2.1): both must be NULL (the three stage states
+ * are recomputed; WM_ERR_ARG otherwise). */
 wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface,
                           const void* U1_stage, const void* U2_stage, double dt, void* lam_hydro, void* lam_bface);
 

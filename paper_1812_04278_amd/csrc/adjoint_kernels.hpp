@@ -453,6 +453,19 @@ __global__ __launch_bounds__(256) void adj_glue_c_kernel(size_t N, double a, con
   else lb[i - 5 * N] = s;
 }
 
+// lk = a w + b x and lam^n = w + x + y + z (the four-stage sum of the RK4 step)
+__global__ __launch_bounds__(256) void adj_glue_d_kernel(size_t N, double a, const double* w, double b,
+                                                         const double* x, const double* y, const double* z,
+                                                         double* lk, double* lh, double* lb) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= 8 * N) return;
+  const double wi = w[i], xi = x[i];
+  lk[i] = a * wi + b * xi;
+  const double s = wi + xi + y[i] + z[i];
+  if (i < 5 * N) lh[i] = s;
+  else lb[i - 5 * N] = s;
+}
+
 // Initial-state map transposed, per zone: m = rho v, E = P0/(gamma-1) + (rho v^2 + B^2)/2
 // with B the zone interpolation of b:  lam_v = rho lam_m + rho v lam_E,  lam_B = B lam_E.
 __global__ __launch_bounds__(256) void init_adj_zone_kernel(size_t N, const double* rho, const double* v,

@@ -95,7 +95,9 @@ Layout layout(const wm_config* c) {
 // transport-flux cotangents (6), zone-B cotangent (3), rhs cotangent (8), stage
 // cotangents lamU2, lamU1 (8 each), lam3 (8), then the dt slot.
 enum AdjOff { A_U1 = 0, A_U2 = 11, A_BZ = 22, A_LT = 25, A_LBZ = 31, A_LK = 34, A_LU2 = 42, A_LU1 = 50,
-              A_WORK = 58, A_NARR = 66 };
+              A_WORK = 58, A_NARR = 66,
+              // RK4 only: the third stage state and its cotangent
+              A_U3 = 66, A_LU3 = 77, A_NARR4 = 85 };
 
 // Launch classes of the adjoint sweep along one axis: n zones in tiles of TA
 // faces; tile t adds into the zones t*TA - 2 .. t*TA + tav + 2 (periodic).
@@ -156,9 +158,12 @@ TilePlan plan_tiles(int n, int TA) {
   return pl;
 }
 
+// arrays of N doubles in the adjoint scratch (the dt scalar follows them)
+int adjoint_arrays(const wm_config* c) { return c->integrator == WM_RK4 ? A_NARR4 : A_NARR; }
+
 size_t adjoint_bytes(const wm_config* c) {
   const size_t N = (size_t)c->nx * c->ny * c->nz;
-  return align_up(A_NARR * N * sizeof(double) + 256);
+  return align_up(adjoint_arrays(c) * N * sizeof(double) + 256);
 }
 
 }  // namespace
@@ -404,14 +409,18 @@ wm_status rhs_vjp_acc(wm_patch* p, double* A, const double* hydro, const double*
 }
 
 // forward stages U1, U2 from U^n with the dt in *dtp (device); U1, U2 = [hydro 5, b 3, bcell 3]
+// The intermediate stage states of one step from U^n (SSP-RK3: U1, U2; RK4:
+// U1, U2, U3), each [11][N] (hydro, face b, zone B), with the given device dt.
 wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double* Bz, const double* dtp, double* U1,
-                         double* U2, double* acc) {
+                         double* U2, double* U3, double* acc) {
   const size_t N = p->g.N;
+  const bool rk4 = p->cfg.integrator == WM_RK4;
+  double* outs[3] = {U1, U2, U3};
   wm_status s;
   if ((s = launch_bcell<double>(p, Ub, Bz)) != WM_OK) return s;
-  for (int st = 0; st < 2; ++st) {
-    const double* hin = st == 0 ? Uh : U1;
-    const double* bcin = st == 0 ? Bz : U1 + 8 * N;
+  for (int st = 0; st < (rk4 ? 3 : 2); ++st) {
+    const double* hin = st == 0 ? Uh : outs[st - 1];
+    const double* bcin = st == 0 ? Bz : outs[st - 1] + 8 * N;
     if ((s = sweeps<double>(p, hin, bcin)) != WM_OK) return s;
     UpdateArgs<double> a;
     a.g = p->g;
@@ -422,11 +431,18 @@ wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double
     a.acc = acc;
     a.rhs_out = nullptr;
     a.dt = dtp;
-    double* out = st == 0 ? U1 : U2;
+    double* out = outs[st];
     a.hyd_out = out;
     a.b_out = out + 5 * N;
-    if (st == 0) hipLaunchKernelGGL((update_kernel<3, 0, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
-    else hipLaunchKernelGGL((update_kernel<3, 1, double>), zone_grid(p->g), dim3(256), 0, p->stream, a);
+    const dim3 grid = zone_grid(p->g);
+    if (rk4) {
+      if (st == 0) hipLaunchKernelGGL((update_kernel<4, 0, double>), grid, dim3(256), 0, p->stream, a);
+      else if (st == 1) hipLaunchKernelGGL((update_kernel<4, 1, double>), grid, dim3(256), 0, p->stream, a);
+      else hipLaunchKernelGGL((update_kernel<4, 2, double>), grid, dim3(256), 0, p->stream, a);
+    } else {
+      if (st == 0) hipLaunchKernelGGL((update_kernel<3, 0, double>), grid, dim3(256), 0, p->stream, a);
+      else hipLaunchKernelGGL((update_kernel<3, 1, double>), grid, dim3(256), 0, p->stream, a);
+    }
     WM_LAUNCH_CHECK("update kernel");
     if ((s = launch_bcell<double>(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
   }
@@ -716,9 +732,10 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
                           const void* U1_stage, const void* U2_stage, double dt, void* lam_hydro, void* lam_bface) {
   wm_status s = check_adjoint(p, adj_scratch);
   if (s != WM_OK) return s;
-  if (p->cfg.integrator != WM_SSPRK3) return fail(WM_ERR_ARG, "the step adjoint is for the SSP-RK3 step");
+  const bool rk4 = p->cfg.integrator == WM_RK4;
   if (!Un_hydro || !Un_bface || !lam_hydro || !lam_bface) return fail(WM_ERR_ARG, "null pointer");
   if ((U1_stage == nullptr) != (U2_stage == nullptr)) return fail(WM_ERR_ARG, "give both stage states or neither");
+  if (rk4 && U1_stage) return fail(WM_ERR_ARG, "the RK4 step adjoint recomputes its stage states (pass NULL)");
   if (!std::isfinite(dt)) return fail(WM_ERR_ARG, "dt is not finite");
   const size_t N = p->g.N;
   double* A = reinterpret_cast<double*>(adj_scratch);
@@ -728,22 +745,47 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
   double* lb = reinterpret_cast<double*>(lam_bface);
   const double* U1 = reinterpret_cast<const double*>(U1_stage);
   const double* U2 = reinterpret_cast<const double*>(U2_stage);
+  const double* U3 = nullptr;
   if (!U1) {   // recompute the stage states from U^n
-    double* dtp = A + A_NARR * N;
+    double* dtp = A + adjoint_arrays(&p->cfg) * N;
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
     WM_LAUNCH_CHECK("set dt");
     // the stage accumulator of the forward scratch is free outside wm_step
-    if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N, p->acc<double>())) != WM_OK)
+    if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N, rk4 ? A + A_U3 * N : nullptr,
+                            p->acc<double>())) != WM_OK)
       return s;
     U1 = A + A_U1 * N;
     U2 = A + A_U2 * N;
+    U3 = A + A_U3 * N;
   }
   double* lk = A + A_LK * N;
   double* lU2 = A + A_LU2 * N;
   double* lU1 = A + A_LU1 * N;
   double* w = A + A_WORK * N;
   const dim3 g8 = lin_grid(8 * N);
-  // k2 = L(U2), weight 4 dt/6
+  if (rk4) {
+    // U^{n+1} = U^n + dt/6 (k0 + 2 k1 + 2 k2 + k3), k_s = L(U_s), U1 = U^n + dt/2 k0,
+    // U2 = U^n + dt/2 k1, U3 = U^n + dt k2; lam3 = the incoming cotangent (w)
+    double* lU3 = A + A_LU3 * N;
+    // k3 = L(U3): dt/6 lam3
+    hipLaunchKernelGGL(adj_glue_a_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, lh, lb, w, lk, lU3);
+    WM_LAUNCH_CHECK("adjoint glue kernel");
+    if ((s = rhs_vjp_acc(p, A, U3, U3 + 5 * N, lk, lU3, lU3 + 5 * N)) != WM_OK) return s;
+    // k2 = L(U2): dt/3 lam3 + dt lamU3
+    hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 3.0, w, dt, lU3, lk, lU2);
+    WM_LAUNCH_CHECK("adjoint glue kernel");
+    if ((s = rhs_vjp_acc(p, A, U2, U2 + 5 * N, lk, lU2, lU2 + 5 * N)) != WM_OK) return s;
+    // k1 = L(U1): dt/3 lam3 + dt/2 lamU2
+    hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 3.0, w, 0.5 * dt, lU2, lk, lU1);
+    WM_LAUNCH_CHECK("adjoint glue kernel");
+    if ((s = rhs_vjp_acc(p, A, U1, U1 + 5 * N, lk, lU1, lU1 + 5 * N)) != WM_OK) return s;
+    // k0 = L(U^n): dt/6 lam3 + dt/2 lamU1; lam^n = lam3 + lamU1 + lamU2 + lamU3 + (dL/dU^n)^T lam_k0
+    hipLaunchKernelGGL(adj_glue_d_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, w, 0.5 * dt, lU1, lU2, lU3, lk,
+                       lh, lb);
+    WM_LAUNCH_CHECK("adjoint glue kernel");
+    return rhs_vjp_acc(p, A, Uh, Ub, lk, lh, lb);
+  }
+  // SSP-RK3: k2 = L(U2), weight 4 dt/6
   hipLaunchKernelGGL(adj_glue_a_kernel, g8, dim3(256), 0, p->stream, N, 4.0 * dt / 6.0, lh, lb, w, lk, lU2);
   WM_LAUNCH_CHECK("adjoint glue kernel");
   if ((s = rhs_vjp_acc(p, A, U2, U2 + 5 * N, lk, lU2, lU2 + 5 * N)) != WM_OK) return s;

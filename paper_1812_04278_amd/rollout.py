@@ -1,12 +1,14 @@
-"""Differentiable rollout: n SSP-RK3 steps from an initial vector potential and
-velocity, as a ``torch.autograd.Function`` whose backward runs the hand-written
-adjoint of the HIP library (``wm_adjoint_step``, ``wm_init_adjoint``).
+"""Differentiable rollout: n steps of the patch's integrator (SSP-RK3 or the
+classical RK4) from an initial vector potential and velocity, as a
+``torch.autograd.Function`` whose backward runs the hand-written adjoint of the
+HIP library (``wm_adjoint_step``, ``wm_init_adjoint``).
 
 Memory: the forward keeps a checkpoint of the state every ``ckpt_every`` steps;
 the backward re-runs each segment forward from its checkpoint, keeping that
 segment's states (and, with ``store_stages``, the two intermediate RK stages of
 every step, so the adjoint step does not recompute them: 3 states of 8 fields
-per step of the segment), and walks it in reverse.  The time steps of the
+per step of the segment; SSP-RK3 only -- the RK4 adjoint recomputes its three
+stage states), and walks it in reverse.  The time steps of the
 forward pass are recorded and held fixed in the backward (dt is not
 differentiated).
 """
@@ -33,7 +35,7 @@ class Rollout(torch.autograd.Function):
             out = (patch.hydro.clone(), patch.bface.clone(), patch.bcell.clone())
         ctx.patch, ctx.nsteps, ctx.ckpt_every = patch, nsteps, ckpt_every
         ctx.ckpts, ctx.dts, ctx.P0, ctx.B0 = ckpts, dts, P0, B0
-        ctx.store_stages = store_stages
+        ctx.store_stages = store_stages and patch.cfg.integrator == B.WM_SSPRK3
         ctx.save_for_backward(A, v, rho)
         return out
 

@@ -17,6 +17,7 @@ least eight zones per wavelength (|k| <= 2 on 16^3); the kinks that a step still
 crosses make central differences converge only linearly in the step, which is
 what the tolerance above allows for.  The oracle comparisons keep the plain
 generator (B0 = (1, 0.5, 0), |k| <= 4): autograd takes the same branches."""
+import dataclasses
 import math
 import sys
 
@@ -101,6 +102,30 @@ def test_adjoint_step_vs_oracle():
     lh, lb = lam[:5].cuda().contiguous(), lam[5:].cuda().contiguous()
     p.adjoint_step(h, b, dt, lh, lb)
     check8(torch.cat([lh.cpu(), lb.cpu()]), ref, "adjoint step")
+
+
+def test_adjoint_step_rk4_vs_oracle():
+    """The step adjoint of the classical RK4 (Sect. 2.1) at CFL 0.8 against
+    autograd through the oracle's q_save form, with dt held fixed."""
+    say("RK4 adjoint step 20x18x16")
+    f = fields(24, seed=13, v_rms=1.0, crop=(20, 18, 16))
+    U, cfg = oracle_state(f)
+    cfg = dataclasses.replace(cfg, cfl=0.8)
+    dt = 0.8 * mhd.compute_dt(U, cfg)
+    g = torch.Generator().manual_seed(4)
+    lam = torch.randn((8,) + U["rho"].shape, generator=g, dtype=torch.float64)
+    ref = oracle_vjp(lambda X: mhd.step_rk4(X, cfg, dt)[0], U, lam)
+    nz, ny, nx = U["rho"].shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h, cfl=0.8, integrator=B.WM_RK4))
+    h, b = to_gpu_state(U)
+    lh, lb = lam[:5].cuda().contiguous(), lam[5:].cuda().contiguous()
+    p.adjoint_step(h, b, dt, lh, lb)
+    check8(torch.cat([lh.cpu(), lb.cpu()]), ref, "RK4 adjoint step")
+    # the RK4 step adjoint recomputes its stage states: passing some is an error
+    S = torch.zeros((8, nz, ny, nx), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.WmError) as e:
+        p.adjoint_step(h, b, dt, lh, lb, S, S.clone())
+    assert e.value.status == B.WM_ERR_ARG
 
 
 def test_adjoint_step_recorded_stages():
@@ -269,6 +294,44 @@ def test_rollout_gradient_vs_oracle(store_stages):
     gAo2, gvo2 = torch.autograd.grad(Jo, [Ao, vo])
     for c in range(3):
         ea, ev = rel_err(gA[c].cpu(), gAo2[c]), rel_err(gv[c].cpu(), gvo2[c])
+        say(f"  component {c}: dJ/dA {ea:.1e}  dJ/dv {ev:.1e}")
+        assert ea <= TOL and ev <= TOL
+
+
+def test_rollout_gradient_rk4_vs_oracle():
+    """The rollout with the classical RK4 at CFL 0.8: gradient w.r.t. (A, v)
+    against autograd through the oracle's RK4 steps, 12^3, 5 steps,
+    checkpoints every 3 (stage states recomputed by the adjoint).  Fields with
+    |k| <= 2 at Mach 0.5: RK4 is not strong-stability preserving, and at CFL 0.8
+    the |k| <= 4, Mach-1 fields on 12 zones are under-resolved enough to blow up
+    (the oracle does too)."""
+    n, nsteps = 12, 5
+    f = fields(n, seed=1, v_rms=0.5, kmax=2)
+    rho_t, e_t = targets(n, kmax=2)
+    h = 1.0 / n
+    p = B.Patch(B.config(n, cfl=0.8, integrator=B.WM_RK4))
+    A = torch.as_tensor(f.A).cuda().requires_grad_(True)
+    v = torch.as_tensor(f.v).cuda().requires_grad_(True)
+    hyd, bf, bc = R.rollout(A, v, torch.as_tensor(f.rho).cuda(), p, nsteps, ckpt_every=3, P0=f.P0, B0=f.B0)
+    J = loss_from(hyd, bc, rho_t.cuda(), e_t.cuda(), h)
+    gA, gv = torch.autograd.grad(J, [A, v])
+    cfg = dataclasses.replace(mhd.cubic(n), cfl=0.8)
+    U_plain = mhd.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0, cfg)
+    dts = []
+    for _ in range(nsteps):
+        U_plain, dt = mhd.step_rk4(U_plain, cfg)
+        dts.append(dt)
+    Ao = torch.as_tensor(f.A).clone().requires_grad_(True)
+    vo = torch.as_tensor(f.v).clone().requires_grad_(True)
+    Uo = mhd.init_from_potential(torch.as_tensor(f.rho), vo, Ao, f.P0, f.B0, cfg)
+    for dt in dts:
+        Uo, _ = mhd.step_rk4(Uo, cfg, dt)
+    Jo = loss_from(flat8(Uo)[:5], mhd.zone_B(Uo["b"]), rho_t, e_t, h)
+    say(f"RK4 rollout loss: gpu {float(J.detach()):.15e} oracle {float(Jo.detach()):.15e}")
+    assert abs(float(J.detach()) - float(Jo.detach())) <= 1e-12 * abs(float(Jo.detach()))
+    gAo, gvo = torch.autograd.grad(Jo, [Ao, vo])
+    for c in range(3):
+        ea, ev = rel_err(gA[c].cpu(), gAo[c]), rel_err(gv[c].cpu(), gvo[c])
         say(f"  component {c}: dJ/dA {ea:.1e}  dJ/dv {ev:.1e}")
         assert ea <= TOL and ev <= TOL
 

@@ -113,7 +113,8 @@ def test_rk4_uniform_state_bitwise():
 
 def test_rk4_stage_order_and_refusals():
     """Stage numbers outside the integrator's range are argument errors, stages out
-    of order are state errors, and the SSP-RK3-only calls refuse an RK4 patch."""
+    of order are state errors, stage recording refuses an RK4 patch and its step
+    adjoint refuses stage states (it recomputes them)."""
     f = fields(8, seed=3, v_rms=0.3, kmax=2)
     p3 = B.Patch(B.config(8))
     p3.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
@@ -132,8 +133,9 @@ def test_rk4_stage_order_and_refusals():
     assert e.value.status == B.WM_ERR_ARG
     lh = torch.zeros((5, 8, 8, 8), dtype=torch.float64, device="cuda")
     lb = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
-    with pytest.raises(B.WmError) as e:
-        p.adjoint_step(p.hydro, p.bface, 1e-3, lh, lb)
+    S = torch.zeros((8, 8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.WmError) as e:   # the RK4 step adjoint recomputes its stages
+        p.adjoint_step(p.hydro.clone(), p.bface.clone(), 1e-3, lh, lb, S, S.clone())
     assert e.value.status == B.WM_ERR_ARG
     # a full step still runs after the refused calls
     p.step()
