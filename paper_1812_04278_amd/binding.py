@@ -122,11 +122,26 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _on_stream(fn):
+    """Runs a Patch method with the patch's stream current, so the torch copies
+    and allocations it makes are ordered with the library's launches."""
+    def wrapped(self, *a, **kw):
+        with torch.cuda.stream(self.stream):
+            return fn(self, *a, **kw)
+    wrapped.__name__, wrapped.__doc__ = fn.__name__, fn.__doc__
+    return wrapped
+
+
 class Patch:
     """A periodic box on one GPU: state tensors, scratch and the C patch handle.
 
     State (on ``device``; float64, or float32 for WM_MIXED_F32STATE): ``hydro``
-    [5, nz, ny, nx] (rho, m, E), ``bface`` [3, nz, ny, nx], ``bcell`` [3, nz, ny, nx]."""
+    [5, nz, ny, nx] (rho, m, E), ``bface`` [3, nz, ny, nx], ``bcell`` [3, nz, ny, nx].
+
+    Every launch of the patch goes to ``stream`` (default: the current stream
+    when the patch is created), and the methods below make their own torch
+    copies on it too.  Device tensors passed in must be ready on that stream;
+    tensors returned, and the state, are ready on it."""
 
     def __init__(self, cfg: WmConfig, device="cuda", stream: torch.cuda.Stream | None = None):
         self.lib = load()
@@ -161,6 +176,7 @@ class Patch:
             pass
 
     # ---- state
+    @_on_stream
     def init_from_potential(self, rho, v, A, P0: float, B0):
         dev = lambda x: torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()
         r, vv, AA = dev(rho), dev(v), dev(A)
@@ -169,6 +185,7 @@ class Patch:
         _check(self.lib.wm_init_from_potential(self.handle, _ptr(r), _ptr(vv), _ptr(AA), float(P0), b0))
         self.stream.synchronize()   # the inputs r, vv, AA are freed on return
 
+    @_on_stream
     def set_state(self, rho, m, E, b):
         """Loads a conserved state (rho, m, E, face b) and re-derives zone B."""
         with torch.no_grad():
@@ -178,6 +195,7 @@ class Patch:
             self.bface.copy_(torch.as_tensor(b))
         _check(self.lib.wm_refresh_zone_field(self.handle))
 
+    @_on_stream
     def state(self):
         """Host copy (float64) as the oracle's dict (rho, m, E, b)."""
         h = self.hydro.cpu().double()
@@ -219,11 +237,13 @@ class Patch:
             _check(st)
         return d.as_dict()
 
+    @_on_stream
     def debug_sweep(self, axis: int) -> torch.Tensor:
         out = torch.empty((9,) + self.shape, dtype=torch.float64, device=self.device)
         _check(self.lib.wm_debug_sweep(self.handle, axis, _ptr(out)))
         return out
 
+    @_on_stream
     def debug_rhs(self) -> torch.Tensor:
         out = torch.empty((8,) + self.shape, dtype=torch.float64, device=self.device)
         _check(self.lib.wm_debug_rhs(self.handle, _ptr(out)))
@@ -245,6 +265,7 @@ class Patch:
             self.adj_scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self.adj_scratch
 
+    @_on_stream
     def rhs_vjp(self, hydro, bface, lam_k):
         """(dL/dU)^T lam_k at U = (hydro, bface); lam_k [8, nz, ny, nx]."""
         out = torch.empty((8,) + self.shape, dtype=torch.float64, device=self.device)
@@ -252,6 +273,7 @@ class Patch:
         _check(self.lib.wm_rhs_vjp(self.handle, _ptr(self._adj()), _ptr(h), _ptr(b), _ptr(l), _ptr(out)))
         return out
 
+    @_on_stream
     def adjoint_step(self, Un_hydro, Un_bface, dt: float, lam_hydro, lam_bface, U1=None, U2=None):
         """In place: (lam_hydro, lam_bface) <- adjoint of one step from U^n with dt.
         U1, U2: the step's stage states from step_record ([8, nz, ny, nx]), or
@@ -263,6 +285,7 @@ class Patch:
                                         _ptr(U2) if U2 is not None else None,
                                         float(dt), _ptr(lam_hydro), _ptr(lam_bface)))
 
+    @_on_stream
     def step_record(self, dt: float, U1=None, U2=None):
         """One step of the bound state with dt; returns its two stage states
         ([8, nz, ny, nx] each, written into U1/U2 when given)."""
@@ -275,9 +298,11 @@ class Patch:
         _check(self.lib.wm_step_record(self.handle, float(dt), _ptr(U1), _ptr(U2)))
         return U1, U2
 
+    @_on_stream
     def zone_field_vjp(self, lam_bcell, lam_bface):
         _check(self.lib.wm_zone_field_vjp(self.handle, _ptr(lam_bcell.contiguous()), _ptr(lam_bface)))
 
+    @_on_stream
     def init_adjoint(self, rho, v, A, B0, lam_hydro, lam_bface):
         """Gradients (g_A, g_v) of the initial-state map for cotangents of the state."""
         dev = lambda x: torch.as_tensor(x, dtype=torch.float64).to(self.device).contiguous()

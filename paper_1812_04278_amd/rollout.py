@@ -25,7 +25,9 @@ class Rollout(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, A, v, rho, patch: B.Patch, nsteps: int, ckpt_every: int, P0: float, B0, store_stages=True):
-        with torch.no_grad():
+        caller = torch.cuda.current_stream(patch.device)
+        patch.stream.wait_stream(caller)        # the inputs are ready on the caller's stream
+        with torch.no_grad(), torch.cuda.stream(patch.stream):
             patch.init_from_potential(rho, v, A, P0, B0)
             ckpts, dts = [], []
             for n in range(nsteps):
@@ -37,6 +39,7 @@ class Rollout(torch.autograd.Function):
         ctx.ckpts, ctx.dts, ctx.P0, ctx.B0 = ckpts, dts, P0, B0
         ctx.store_stages = store_stages and patch.cfg.integrator == B.WM_SSPRK3
         ctx.save_for_backward(A, v, rho)
+        caller.wait_stream(patch.stream)        # the outputs are ready on the patch's stream
         return out
 
     @staticmethod
@@ -45,7 +48,9 @@ class Rollout(torch.autograd.Function):
         p = ctx.patch
         shape = p.shape
         dev = p.device
-        with torch.no_grad():
+        caller = torch.cuda.current_stream(dev)
+        p.stream.wait_stream(caller)
+        with torch.no_grad(), torch.cuda.stream(p.stream):
             lam_h = (g_hydro if g_hydro is not None else torch.zeros((5,) + shape, dtype=torch.float64, device=dev))
             lam_b = (g_bface if g_bface is not None else torch.zeros((3,) + shape, dtype=torch.float64, device=dev))
             lam_h = lam_h.to(dev, torch.float64).contiguous().clone()
@@ -74,6 +79,7 @@ class Rollout(torch.autograd.Function):
                     p.adjoint_step(Uh, Ub, ctx.dts[n], lam_h, lam_b, U1, U2)
                 del states
             gA, gv = p.init_adjoint(rho, v, A, ctx.B0, lam_h, lam_b)
+        caller.wait_stream(p.stream)
         return gA, gv, None, None, None, None, None, None, None
 
 

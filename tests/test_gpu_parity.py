@@ -290,3 +290,30 @@ def test_failure_injection_unphysical():
     dt = p.step(want_dt=True)
     assert not math.isfinite(dt)
     assert p.diagnostics(raise_unphysical=False)["n_unphysical"] >= 2
+
+
+def test_side_stream_matches_default():
+    """A patch created on its own stream (default priority) gives bitwise the
+    state of a patch on the current stream: initial state, three steps, the
+    host copy, and set_state round trips, with the caller's stream left busy."""
+    say("side stream 24x20x16")
+    f = fields(24, seed=5, v_rms=1.0, crop=(24, 20, 16))
+    ref = gpu_patch(f)
+    for _ in range(3):
+        ref.step()
+    r = ref.state()
+    side = torch.cuda.Stream()
+    nz, ny, nx = f.rho.shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=1.0 / nx), stream=side)
+    busy = torch.randn(4096, 4096, device="cuda", dtype=torch.float64)
+    for _ in range(4):
+        busy = busy @ busy * 1e-3           # keep the caller's stream occupied
+    p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+    st0 = p.state()
+    p.set_state(st0["rho"], st0["m"], st0["E"], st0["b"])
+    for _ in range(3):
+        p.step()
+    g = p.state()
+    for k in ("rho", "m", "E", "b"):
+        assert torch.equal(g[k], r[k]), k
+    torch.cuda.synchronize()
