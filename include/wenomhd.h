@@ -191,10 +191,11 @@ wm_status wm_debug_rhs(wm_patch* p, void* out);
 /* Bytes of device scratch the adjoint calls need (caller-owned, 256-aligned,
  * reserved for one patch at a time; more for WM_RK4, whose step adjoint holds
  * a third stage state).  0 for an invalid configuration.
- * The adjoint calls linearise the FP64 method with Jiang-Shu weights (other
- * weights: WM_ERR_ARG; grid sizes below 3: WM_ERR_ARG).  On a mixed-precision
- * patch they give the FP64 linearisation at the states passed in (stage states
- * recomputed by the adjoint itself come from the patch's own precision). */
+ * The adjoint calls linearise the FP64 method with the patch's weights
+ * (Jiang-Shu or WENO-Z) and integrator (grid sizes below 3: WM_ERR_ARG).  On a
+ * mixed-precision patch they give the FP64 linearisation at the states passed
+ * in (stage states recomputed by the adjoint itself come from the patch's own
+ * precision). */
 size_t wm_adjoint_scratch_bytes(const wm_config* cfg);
 
 /* lam_out = (dL/dU)^T lam_k for the semi-discrete right-hand side L of the

@@ -14,39 +14,14 @@
 namespace wm {
 
 // ---------------------------------------------------------------------------
-// phi_N: gradient with respect to its four arguments (Sect. 2.2), Jiang-Shu
-// weights.  With s_k = eps + IS_k, alpha_k = d_k/s_k^2, omega = alpha/sum,
-// g = X/3, h = Y/6 (X = a-2b+c, Y = b-2c+d) and W = g omega_0 + h omega_2:
+// phi_N: value and gradient with respect to its four arguments (Sect. 2.2).
+// With omega = alpha/sum, g = X/3, h = Y/6 (X = a-2b+c, Y = b-2c+d) and
+// W = g omega_0 + h omega_2, dphi/dalpha_k = (G_k - W)/sum, G = (g, 0, h).
+// Jiang-Shu: s_k = eps + IS_k, alpha_k = d_k/s_k^2, so
 //   dphi/ds_0 = (2 omega_0/s_0)(W - g), dphi/ds_1 = (2 omega_1/s_1) W,
 //   dphi/ds_2 = (2 omega_2/s_2)(W - h).
+// WENO-Z: alpha_k = d_k (1 + r_k^2), r_k = tau_5/(eps_Z + IS_k), tau_5 = |IS_0 - IS_2|.
 // ---------------------------------------------------------------------------
-__host__ __device__ __forceinline__ void phiN_grad(double a, double b, double c, double d, double eps,
-                                                   double gr[4]) {
-  const double t0 = a - b, t1 = a - 3.0 * b;
-  const double t2 = b - c, t3 = b + c;
-  const double t4 = c - d, t5 = 3.0 * c - d;
-  const double s0 = eps + 13.0 * t0 * t0 + 3.0 * t1 * t1;
-  const double s1 = eps + 13.0 * t2 * t2 + 3.0 * t3 * t3;
-  const double s2 = eps + 13.0 * t4 * t4 + 3.0 * t5 * t5;
-  const double i0 = 1.0 / s0, i1 = 1.0 / s1, i2 = 1.0 / s2;
-  const double al0 = i0 * i0, al1 = 6.0 * i1 * i1, al2 = 3.0 * i2 * i2;
-  const double isum = 1.0 / (al0 + al1 + al2);
-  const double w0 = al0 * isum, w1 = al1 * isum, w2 = al2 * isum;
-  const double X = a - 2.0 * b + c, Y = b - 2.0 * c + d;
-  const double g = X * (1.0 / 3.0), h = Y * (1.0 / 6.0);
-  const double W = g * w0 + h * w2;
-  const double l0 = 2.0 * w0 * i0 * (W - g);   // dphi/dIS_0
-  const double l1 = 2.0 * w1 * i1 * W;         // dphi/dIS_1
-  const double l2 = 2.0 * w2 * i2 * (W - h);   // dphi/dIS_2
-  const double cX = w0 * (1.0 / 3.0), cY = (w2 - 0.5) * (1.0 / 6.0);
-  // dIS_0/da = 26 t0 + 6 t1, dIS_0/db = -26 t0 - 18 t1
-  // dIS_1/db = 26 t2 + 6 t3, dIS_1/dc = -26 t2 + 6 t3
-  // dIS_2/dc = 26 t4 + 18 t5, dIS_2/dd = -26 t4 - 6 t5
-  gr[0] = cX + l0 * (26.0 * t0 + 6.0 * t1);
-  gr[1] = -2.0 * cX + cY + l0 * (-26.0 * t0 - 18.0 * t1) + l1 * (26.0 * t2 + 6.0 * t3);
-  gr[2] = cX - 2.0 * cY + l1 * (-26.0 * t2 + 6.0 * t3) + l2 * (26.0 * t4 + 18.0 * t5);
-  gr[3] = cY + l2 * (-26.0 * t4 - 6.0 * t5);
-}
 
 // ---------------------------------------------------------------------------
 // face eigen-system scalars: cotangents of the FaceEig members -> face state
@@ -193,31 +168,63 @@ __host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const 
 }
 
 // ---------------------------------------------------------------------------
-// phi_N with its gradient (same quantities as phiN_grad, plus the value
-// phi = omega_0 X/3 + (omega_2 - 1/2) Y/6)
+// phi = omega_0 X/3 + (omega_2 - 1/2) Y/6 and its gradient
 // ---------------------------------------------------------------------------
+template <bool WZ>
 __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, double c, double d, double eps,
-                                                       double& val, double gr[4]) {
+                                                       double epsZ, double& val, double gr[4]) {
   const double t0 = a - b, t1 = a - 3.0 * b;
   const double t2 = b - c, t3 = b + c;
   const double t4 = c - d, t5 = 3.0 * c - d;
-  const double s0 = eps + 13.0 * t0 * t0 + 3.0 * t1 * t1;
-  const double s1 = eps + 13.0 * t2 * t2 + 3.0 * t3 * t3;
-  const double s2 = eps + 13.0 * t4 * t4 + 3.0 * t5 * t5;
-  // 1/s_k from one reciprocal of s0 s1 s2 (s_k >= eps, so the product stays normal)
-  const double s12 = s1 * s2, r = rcp_w(s0 * s12);
-  const double i0 = s12 * r, i1 = s0 * s2 * r, i2 = s0 * s1 * r;
-  const double al0 = i0 * i0, al1 = 6.0 * i1 * i1, al2 = 3.0 * i2 * i2;
-  const double isum = rcp_w(al0 + al1 + al2);
-  const double w0 = al0 * isum, w1 = al1 * isum, w2 = al2 * isum;
   const double X = a - 2.0 * b + c, Y = b - 2.0 * c + d;
   const double g = X * (1.0 / 3.0), h = Y * (1.0 / 6.0);
-  const double W = g * w0 + h * w2;
-  const double l0 = 2.0 * w0 * i0 * (W - g);
-  const double l1 = 2.0 * w1 * i1 * W;
-  const double l2 = 2.0 * w2 * i2 * (W - h);
+  double w0, w2, l0, l1, l2;   // normalised weights 0, 2 and dphi/dIS_k
+  if constexpr (!WZ) {
+    (void)epsZ;
+    const double s0 = eps + 13.0 * t0 * t0 + 3.0 * t1 * t1;
+    const double s1 = eps + 13.0 * t2 * t2 + 3.0 * t3 * t3;
+    const double s2 = eps + 13.0 * t4 * t4 + 3.0 * t5 * t5;
+    // 1/s_k from one reciprocal of s0 s1 s2 (s_k >= eps, so the product stays normal)
+    const double s12 = s1 * s2, r = rcp_w(s0 * s12);
+    const double i0 = s12 * r, i1 = s0 * s2 * r, i2 = s0 * s1 * r;
+    const double al0 = i0 * i0, al1 = 6.0 * i1 * i1, al2 = 3.0 * i2 * i2;
+    const double isum = rcp_w(al0 + al1 + al2);
+    w0 = al0 * isum;
+    const double w1 = al1 * isum;
+    w2 = al2 * isum;
+    const double W = g * w0 + h * w2;
+    l0 = 2.0 * w0 * i0 * (W - g);
+    l1 = 2.0 * w1 * i1 * W;
+    l2 = 2.0 * w2 * i2 * (W - h);
+  } else {
+    // WENO-Z: alpha_k = d_k (1 + r_k^2), r_k = tau5 / (eps_Z + IS_k), tau5 = |IS_0 - IS_2|
+    (void)eps;
+    const double IS0 = 13.0 * t0 * t0 + 3.0 * t1 * t1;
+    const double IS1 = 13.0 * t2 * t2 + 3.0 * t3 * t3;
+    const double IS2 = 13.0 * t4 * t4 + 3.0 * t5 * t5;
+    const double dIS = IS0 - IS2, tau = fabs(dIS);
+    const double q0 = rcp_w(epsZ + IS0), q1 = rcp_w(epsZ + IS1), q2 = rcp_w(epsZ + IS2);
+    const double r0 = tau * q0, r1 = tau * q1, r2 = tau * q2;
+    const double al0 = 1.0 + r0 * r0, al1 = 6.0 * (1.0 + r1 * r1), al2 = 3.0 * (1.0 + r2 * r2);
+    const double isum = rcp_w(al0 + al1 + al2);
+    w0 = al0 * isum;
+    w2 = al2 * isum;
+    const double W = g * w0 + h * w2;
+    // dphi/dr_k = (G_k - W)/sum(alpha) * dalpha_k/dr_k, G = (g, 0, h)
+    const double L0 = (g - W) * isum * (2.0 * r0);
+    const double L1 = -W * isum * (12.0 * r1);
+    const double L2 = (h - W) * isum * (6.0 * r2);
+    const double ltau = L0 * q0 + L1 * q1 + L2 * q2;   // dphi/dtau5
+    const double sg = dIS > 0.0 ? 1.0 : (dIS < 0.0 ? -1.0 : 0.0);
+    l0 = -L0 * r0 * q0 + sg * ltau;
+    l1 = -L1 * r1 * q1;
+    l2 = -L2 * r2 * q2 - sg * ltau;
+  }
   const double cX = w0 * (1.0 / 3.0), cY = (w2 - 0.5) * (1.0 / 6.0);
   val = cX * X + cY * Y;
+  // dIS_0/da = 26 t0 + 6 t1, dIS_0/db = -26 t0 - 18 t1
+  // dIS_1/db = 26 t2 + 6 t3, dIS_1/dc = -26 t2 + 6 t3
+  // dIS_2/dc = 26 t4 + 18 t5, dIS_2/dd = -26 t4 - 6 t5
   gr[0] = cX + l0 * (26.0 * t0 + 6.0 * t1);
   gr[1] = -2.0 * cX + cY + l0 * (-26.0 * t0 - 18.0 * t1) + l1 * (26.0 * t2 + 6.0 * t3);
   gr[2] = cX - 2.0 * cY + l1 * (-26.0 * t2 + 6.0 * t3) + l2 * (26.0 * t4 + 18.0 * t5);
@@ -281,18 +288,19 @@ struct PairShape {
 
 // Split values, phi and its gradient for one row: from the projections uF, uq
 // (interfaces 0..4) to f and the cotangents lP (of uF), lQ (of uq) and of alpha.
+template <bool WZ>
 __host__ __device__ __forceinline__ void row_split_grad(const double uF[5], const double uq[5], double al, double lf,
-                                                        double eps, double& f, double lP[5], double lQ[5],
-                                                        double& lal) {
+                                                        double eps, double epsZ, double& f, double lP[5],
+                                                        double lQ[5], double& lal) {
   double v[8];
 #pragma unroll
   for (int k = 0; k < 4; ++k) v[k] = uF[k] + al * uq[k];
 #pragma unroll
   for (int k = 1; k < 5; ++k) v[3 + k] = uF[k] - al * uq[k];
   double g[8], g4[4], pa, pb;
-  phiN_val_grad(v[7], v[6], v[5], v[4], eps, pa, g4);
+  phiN_val_grad<WZ>(v[7], v[6], v[5], v[4], eps, epsZ, pa, g4);
   g[7] = g4[0] * lf; g[6] = g4[1] * lf; g[5] = g4[2] * lf; g[4] = g4[3] * lf;
-  phiN_val_grad(v[0], v[1], v[2], v[3], eps, pb, g4);
+  phiN_val_grad<WZ>(v[0], v[1], v[2], v[3], eps, epsZ, pb, g4);
   g[0] = -g4[0] * lf; g[1] = -g4[1] * lf; g[2] = -g4[2] * lf; g[3] = -g4[3] * lf;
   f = pa - pb;
 #pragma unroll
@@ -307,9 +315,9 @@ __host__ __device__ __forceinline__ void row_split_grad(const double uF[5], cons
 // Forward and reverse of two pairs at once: one read of the differences per
 // interface serves both, and one barrier round per interface carries both
 // pairs' cotangents (emit(k, lD[14])).
-template <class PA, bool TWOA, class PB, bool TWOB, class DL, class EMIT>
+template <class PA, bool TWOA, class PB, bool TWOB, bool WZ, class DL, class EMIT>
 __host__ __device__ __forceinline__ void pair2_rev(const PairRows& ra, const PairRows& rb, DL dl, double eps,
-                                                   PairCot& ca, PairCot& cb, EMIT emit) {
+                                                   double epsZ, PairCot& ca, PairCot& cb, EMIT emit) {
   double uFa[5], uqa[5], lFa[5], lqa[5], uFb[5], uqb[5], lFb[5], lqb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -321,10 +329,10 @@ __host__ __device__ __forceinline__ void pair2_rev(const PairRows& ra, const Pai
     sched_fence();
   }
   double lPua[5], lQua[5], lPla[5], lQla[5], lPub[5], lQub[5], lPlb[5], lQlb[5];
-  row_split_grad(uFa, uqa, ra.alu, ra.lfu, eps, ca.fu, lPua, lQua, ca.lalu);
-  if (TWOA) row_split_grad(lFa, lqa, ra.all, ra.lfl, eps, ca.fl, lPla, lQla, ca.lall);
-  row_split_grad(uFb, uqb, rb.alu, rb.lfu, eps, cb.fu, lPub, lQub, cb.lalu);
-  if (TWOB) row_split_grad(lFb, lqb, rb.all, rb.lfl, eps, cb.fl, lPlb, lQlb, cb.lall);
+  row_split_grad<WZ>(uFa, uqa, ra.alu, ra.lfu, eps, epsZ, ca.fu, lPua, lQua, ca.lalu);
+  if (TWOA) row_split_grad<WZ>(lFa, lqa, ra.all, ra.lfl, eps, epsZ, ca.fl, lPla, lQla, ca.lall);
+  row_split_grad<WZ>(uFb, uqb, rb.alu, rb.lfu, eps, epsZ, cb.fu, lPub, lQub, cb.lalu);
+  if (TWOB) row_split_grad<WZ>(lFb, lqb, rb.all, rb.lfl, eps, epsZ, cb.fl, lPlb, lQlb, cb.lall);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     if (!TWOA) { lPla[k] = 0.0; lQla[k] = 0.0; }
@@ -557,7 +565,7 @@ using EntropyShape = PairShape<0, 0, false, 127>;
 // speeds (lal[7]) and, via emit (five rounds per group), of the interface
 // differences.  The face-state cotangents follow from face_eig_vjp(eb).  The
 // pairs run in two groups, fast with slow and Alfven with entropy.
-template <class ALF, class LAM, class DL, class EMIT>
+template <bool WZ, class ALF, class LAM, class DL, class EMIT>
 __host__ __device__ __forceinline__ void face_corr_vjp(const FaceEig& e, ALF alf, LAM lamf, DL dl, const Phys& ph,
                                                        FaceEigBar& eb, double lal[7], EMIT emit) {
   {
@@ -565,7 +573,7 @@ __host__ __device__ __forceinline__ void face_corr_vjp(const FaceEig& e, ALF alf
     fast_rows(e, alf, lamf, rf);
     slow_rows(e, alf, lamf, rs);
     PairCot cf, cs;
-    pair2_rev<FastShape, true, SlowShape, true>(rf, rs, dl, ph.eps, cf, cs, emit);
+    pair2_rev<FastShape, true, SlowShape, true, WZ>(rf, rs, dl, ph.eps, ph.eps_Z, cf, cs, emit);
     fast_post(e, lamf, cf, eb);
     slow_post(e, lamf, cs, eb);
     lal[0] += cf.lalu; lal[6] += cf.lall; lal[2] += cs.lalu; lal[4] += cs.lall;
@@ -579,7 +587,7 @@ __host__ __device__ __forceinline__ void face_corr_vjp(const FaceEig& e, ALF alf
     alfven_rows(e, alf, lamf, ra);
     entropy_rows(e, alf, lamf, rn);
     PairCot ca, cn;
-    pair2_rev<AlfvenShape, true, EntropyShape, false>(ra, rn, dl, ph.eps, ca, cn, emit);
+    pair2_rev<AlfvenShape, true, EntropyShape, false, WZ>(ra, rn, dl, ph.eps, ph.eps_Z, ca, cn, emit);
     alfven_post(e, lamf, ca, eb);
     entropy_post(e, lamf, cn, eb);
     lal[1] += ca.lalu; lal[5] += ca.lall; lal[3] += cn.lalu;

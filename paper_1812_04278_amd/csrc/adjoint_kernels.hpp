@@ -107,7 +107,7 @@ struct AdjLds {
 // one launch touch disjoint zones (the host launches the tiles of an axis in
 // conflict-free classes), so the additions need no atomics and the order of
 // accumulation is fixed.
-template <int AXIS>
+template <int AXIS, bool WZ>
 __global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs a) {
   constexpr int TA = AdjTile<AXIS>::TA, TB = AdjTile<AXIS>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void adj_sweep_kernel(AdjSweepArgs 
     const FaceEig e = eig();
     FaceEigBar eb;
     eb.zero();
-    face_corr_vjp(e, alf, lamf, dl, a.ph, eb, lal, emit);
+    face_corr_vjp<WZ>(e, alf, lamf, dl, a.ph, eb, lal, emit);
     double fp[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (Pz[v * NC + cL] + Pz[v * NC + cR]);

@@ -368,8 +368,9 @@ wm_status launch_adj_sweep(wm_patch* p, const double* hydro, const double* bcell
   for (int c = 0; c < pl.n; ++c) {   // classes in order: each launch adds into disjoint zones
     a.tile0 = pl.run[c].first;
     a.tstride = pl.run[c].stride;
-    hipLaunchKernelGGL((adj_sweep_kernel<AXIS>), dim3(pl.run[c].count, (nB + TB - 1) / TB, nC), dim3(ADJ_THREADS), 0,
-                       p->stream, a);
+    const dim3 grid(pl.run[c].count, (nB + TB - 1) / TB, nC);
+    if (p->ph.weno_z) hipLaunchKernelGGL((adj_sweep_kernel<AXIS, true>), grid, dim3(ADJ_THREADS), 0, p->stream, a);
+    else hipLaunchKernelGGL((adj_sweep_kernel<AXIS, false>), grid, dim3(ADJ_THREADS), 0, p->stream, a);
     WM_LAUNCH_CHECK("adjoint sweep kernel");
   }
   prof_end(p, r);
@@ -380,7 +381,6 @@ wm_status check_adjoint(wm_patch* p, void* adj) {
   if (!p) return fail(WM_ERR_ARG, "null patch");
   if (!adj || reinterpret_cast<uintptr_t>(adj) % kAlign) return fail(WM_ERR_ARG, "adjoint scratch null or misaligned");
   if (p->cfg.nx < 3 || p->cfg.ny < 3 || p->cfg.nz < 3) return fail(WM_ERR_ARG, "the adjoint needs grid sizes >= 3");
-  if (p->cfg.weights != WM_WENO_JS) return fail(WM_ERR_ARG, "the adjoint differentiates the Jiang-Shu weights only");
   if (p->f32) return fail(WM_ERR_ARG, "the adjoint needs an FP64 state (not WM_MIXED_F32STATE)");
   return WM_OK;
 }

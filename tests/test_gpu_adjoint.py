@@ -217,15 +217,39 @@ def test_full_size_sampled_rhs_vjp_128():
     assert float(out[:, ~near].abs().max()) == 0.0
 
 
-def test_adjoint_rejects_wenoz():
-    """The adjoint linearises the Jiang-Shu weights only: other weights are an error."""
-    f = fields(12, seed=15, v_rms=1.0)
+def test_rhs_vjp_wenoz_vs_oracle():
+    """WENO-Z weights (reading R13): the right-hand-side VJP against autograd
+    through the oracle on a ragged box (|x| of tau_5 differentiated as its sign)."""
+    say("WENO-Z rhs vjp 37x21x19")
+    f = fields(40, seed=12, v_rms=1.5, crop=(37, 21, 19))
     U, cfg = oracle_state(f)
+    cfg = dataclasses.replace(cfg, weights="z")
+    g = torch.Generator().manual_seed(3)
+    lam = torch.randn((8,) + U["rho"].shape, generator=g, dtype=torch.float64)
+    ref = oracle_vjp(lambda X: mhd.rhs(X, cfg), U, lam)
+    nz, ny, nx = U["rho"].shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h, weights=B.WM_WENO_Z))
     h, b = to_gpu_state(U)
-    p = B.Patch(B.config(12, weights=B.WM_WENO_Z))
-    lam = torch.zeros((8, 12, 12, 12), dtype=torch.float64).cuda()
-    with pytest.raises(B.WmError):
-        p.rhs_vjp(h, b, lam)
+    out = p.rhs_vjp(h, b, lam.cuda()).cpu()
+    check8(out, ref, "WENO-Z rhs vjp")
+
+
+def test_adjoint_step_wenoz_rk4_vs_oracle():
+    """The paper's own configuration, WENO-Z weights with RK4 at CFL 0.8: the step
+    adjoint against autograd through the oracle."""
+    say("WENO-Z RK4 adjoint step 20x18x16")
+    f = fields(24, seed=13, v_rms=1.0, crop=(20, 18, 16))
+    U, cfg = oracle_state(f)
+    cfg = dataclasses.replace(cfg, weights="z", cfl=0.8)
+    dt = 0.8 * mhd.compute_dt(U, cfg)
+    lam = torch.randn((8,) + U["rho"].shape, generator=torch.Generator().manual_seed(5), dtype=torch.float64)
+    ref = oracle_vjp(lambda X: mhd.step_rk4(X, cfg, dt)[0], U, lam)
+    nz, ny, nx = U["rho"].shape
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h, cfl=0.8, weights=B.WM_WENO_Z, integrator=B.WM_RK4))
+    h, b = to_gpu_state(U)
+    lh, lb = lam[:5].cuda().contiguous(), lam[5:].cuda().contiguous()
+    p.adjoint_step(h, b, dt, lh, lb)
+    check8(torch.cat([lh.cpu(), lb.cpu()]), ref, "WENO-Z RK4 adjoint step")
 
 
 def test_adjoint_deterministic():
