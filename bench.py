@@ -24,7 +24,9 @@ METRIC = "Mzone-updates/s per RK3 step, FP64 vs mixed at stated L1 err; adjoint/
 
 # Algorithmic work of one sweep per face (FP64 flops: add/sub/mul 1, fma 2,
 # div 1, sqrt 1), the difference form of eq. (FWENO) as the sweep kernel
-# computes it, itemised in DESIGN.md ("Work per face").
+# computes it: differences 70, central term 42, face state 16, eigen scalars
+# ~75, fast and slow pairs ~550 each, Alfven ~390, entropy ~280, and the zone
+# prologue ~70 per zone.
 FLOPS_PER_FACE = 2060
 # Algorithmic HBM bytes of the update kernel per zone (FP64): reads 15 face
 # fluxes, 6 transport fluxes, U^n (8) and the accumulator (8, stages 1-2);

@@ -8,7 +8,8 @@ with the HIP library and imports nothing from the product package.
 
 Everything is float64 ``torch`` CPU tensors, vectorised over zones/faces; the
 algorithm follows the paper's order and notation (Sect. 2, Appendix A), with
-the readings of its garbled or silent passages listed in the design doc.  Because it
+the readings of its garbled or silent passages listed in the header of
+:mod:`oracle.mhd`.  Because it
 is plain torch, ``torch.autograd`` through :func:`mhd.step` gives the reference
 gradient used to check the hand-written adjoint.
 """

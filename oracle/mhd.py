@@ -11,7 +11,7 @@ shares the forward corner: E_z at (i+1/2, j+1/2, k), E_x at (i, j+1/2, k+1/2),
 E_y at (i+1/2, j, k+1/2) -- the corner fluxes Omega_x, Omega_y, Omega_z of
 eq. (ox1)-(ox3) in that order.
 
-Readings of passages that are garbled or silent (numbered as in the design doc):
+Readings of passages that are garbled or silent:
   R1  total pressure P* = P + |B|^2/2 (eq. for P* drops the parentheses)
   R2  fast/slow speeds c^2 = (a^2 + b^2 +- D)/2 with
       D = sqrt((a^2 - b^2)^2 + 4 a^2 b_perp^2), the expanded radicand of
@@ -38,6 +38,10 @@ Readings of passages that are garbled or silent (numbered as in the design doc):
       Sect. 2.1; classical RK4 is kept as :func:`step_rk4`
   R12 zone-centred B is never advanced by the WENO flux; it is re-interpolated
       from the face field after every stage (Sect. 2.3, 3D step list)
+  R13 WENO-Z weights alpha_k = d_k (1 + (tau_5 / (eps_Z + IS_k))^2): the
+      printed tau_5 / (eps_Z + IS_k)^2 is dimensionally inconsistent
+  R16 the RK4 of Sect. 2.1 as its q_save accumulation (factors 1/2, 1/2, 1,
+      1/6 on q0; weights -4/3, 1/3, 2/3, 1/3, 1), dt held over the step
 """
 from __future__ import annotations
 
@@ -279,7 +283,7 @@ def eigenvectors(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P, gamma: float, eps_B: float)
 
 def phi_N(a, b, c, d, cfg: Config):
     """The WENO interpolant phi_N(a, b, c, d) of eq. (FWENO) with the Jiang-Shu
-    weights (or the WENO-Z weights, R13 in the design doc, when cfg.weights == 'z')."""
+    weights (or the WENO-Z weights of reading R13 when cfg.weights == 'z')."""
     IS_0 = 13.0 * (a - b) ** 2 + 3.0 * (a - 3.0 * b) ** 2
     IS_1 = 13.0 * (b - c) ** 2 + 3.0 * (b + c) ** 2
     IS_2 = 13.0 * (c - d) ** 2 + 3.0 * (3.0 * c - d) ** 2

@@ -12,7 +12,7 @@ the HIP path and the CPU oracle turn into a conserved state on their own:
             A_z at (i+1/2, j+1/2, k), the placement of Sect. 4.1 (linear waves)
 * ``B0``, ``P0`` uniform background field and pressure.
 
-Recipe (documented in DESIGN.md, "Synthetic inputs"):
+Recipe:
 
 * mode set K(kmax) = {k in Z^3 : 0 < |k| <= kmax}, one representative of each
   +-k pair (k_z > 0, or k_z = 0 and k_y > 0, or k_z = k_y = 0 and k_x > 0),
