@@ -48,3 +48,13 @@ def assert_state_parity(gpu, ora, tol=1e-12, label=""):
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, f"{label} parity above {tol}: {bad}"
     return errs
+
+
+def _subbox(t, centre, r):
+    """Periodic sub-box of half-width r around centre (k, j, i) of [..., nz, ny, nx]."""
+    k, j, i = centre
+    for dim, c in ((-3, k), (-2, j), (-1, i)):
+        n = t.shape[dim]
+        idx = torch.tensor([(c + o) % n for o in range(-r, r)], dtype=torch.long)
+        t = t.index_select(dim, idx)
+    return t

@@ -10,7 +10,7 @@ import torch
 
 from oracle import mhd
 from paper_1812_04278_amd import binding as B
-from helpers import T64, assert_state_parity, fields, oracle_state, rel_err
+from helpers import T64, _subbox, assert_state_parity, fields, oracle_state, rel_err
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -211,16 +211,6 @@ def test_invariants_128_mach2():
         assert float((a - b).abs().max()) <= 1e-13 * sc
     h = 1.0 / 128
     assert d1["max_divb"] <= 1e-12 / h
-
-
-def _subbox(t, centre, r):
-    """Periodic sub-box of half-width r around centre (k, j, i) of [..., nz, ny, nx]."""
-    k, j, i = centre
-    for dim, c in ((-3, k), (-2, j), (-1, i)):
-        n = t.shape[dim]
-        idx = torch.tensor([(c + o) % n for o in range(-r, r)], dtype=torch.long)
-        t = t.index_select(dim, idx)
-    return t
 
 
 def test_full_size_sampled_256():
