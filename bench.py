@@ -392,8 +392,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the multi-GPU brick decomposition is a design, "
-              "not part of this build (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU brick decomposition "
+              "(halo exchange and dt all-reduce are not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
