@@ -84,15 +84,16 @@ def timed_steps(p, steps: int, dts=None):
 
 
 def mixed_precision(n: int, steps: int):
-    """The Mach-0.1 workload in FP64 and in mixed precision: throughput of each
-    (own dt from eq. (cfl), HIP-event kernel times), and the L1 of the mixed
-    state against the FP64 state after `steps` steps taken with the FP64 run's
-    dt sequence."""
+    """The Mach-0.1 workload in FP64, in mixed precision (FP64 state) and in the
+    mixed form with an FP32 state: throughput of each (own dt from eq. (cfl),
+    HIP-event kernel times), and the L1 of the two mixed states against the
+    FP64 state after `steps` steps taken with the FP64 run's dt sequence."""
     import torch
     from paper_1812_04278_amd import binding, inputs
     f = inputs.random_fields(n, seed=1, v_rms=0.1, kmax=4)
     res, states, dts = {}, {}, []
-    for name, prec in (("fp64", binding.WM_FP64), ("mixed", binding.WM_MIXED)):
+    for name, prec in (("fp64", binding.WM_FP64), ("mixed", binding.WM_MIXED),
+                       ("f32state", binding.WM_MIXED_F32STATE)):
         p = binding.Patch(binding.config(n, precision=prec), device="cuda:0")
         p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
         p.step()                                    # warm-up
@@ -118,6 +119,11 @@ def mixed_precision(n: int, steps: int):
     res["l1_mixed_vs_fp64"] = {"per_variable": [float(f"{x:.3e}") for x in per],
                                "variables": ["rho", "m_x", "m_y", "m_z", "E", "b_x", "b_y", "b_z"],
                                "geometric": float(f"{geo:.3e}")}
+    # the mixed arithmetic with the state, stage states, accumulator and face
+    # fluxes stored in FP32 (the form of the 512^3 workload)
+    per, geo = l1_per_variable(states["fp64"], states["f32state"])
+    res["speedup_f32state"] = round(res["f32state"]["value"] / res["fp64"]["value"], 4)
+    res["l1_f32state_vs_fp64"] = {"per_variable": [float(f"{x:.3e}") for x in per], "geometric": float(f"{geo:.3e}")}
     res["workload"] = f"{n}^3 periodic box, Mach 0.1, beta~1, {steps} SSP-RK3 steps"
     return res
 
