@@ -3,11 +3,13 @@
  * MHD step of Donnert et al., "WENO-Wombat" (arXiv:1812.04278).
  *
  * Method: per direction, the finite-difference WENO5 flux of Sect. 2.2
- * (eq. FWENO, Jiang-Shu weights) computed in characteristic fields with the
- * eigenvectors of Appendix A at the face, Lax-Friedrichs split; its
+ * (eq. FWENO, Jiang-Shu or WENO-Z weights) computed in characteristic fields
+ * with the eigenvectors of Appendix A at the face, Lax-Friedrichs split; its
  * conservative divergence (eq. num); the CT transport fluxes (eq. fct1-fct6),
- * corner fluxes (eq. ox1-ox3) and the face-field update of Sect. 2.3; an
- * SSP-RK3 stage in increment form at CFL 0.4.
+ * corner fluxes (eq. ox1-ox3) and the face-field update of Sect. 2.3; a
+ * Runge-Kutta stage in increment form (SSP-RK3 at CFL 0.4, or the classical
+ * RK4 of Sect. 2.1 at CFL 0.8); the adjoint (vector-Jacobian products) of the
+ * right-hand side and of a step.
  *
  * Grid: nx * ny * nz zones, periodic in all three directions, one zone size h
  * for every direction (Sect. 2.3 divides every difference by the same Delta x).
@@ -124,7 +126,8 @@ wm_status wm_patch_destroy(wm_patch* p);
 
 /* Binds the caller's state arrays (layouts above; element type double, or
  * float for WM_MIXED_F32STATE).  hydro and bface are read and advanced in
- * place by wm_rk_stage(2) / wm_step; bcell is written. */
+ * place by the last stage of wm_rk_stage (2 for SSP-RK3, 3 for RK4) and by
+ * wm_step; bcell is written. */
 wm_status wm_bind_state(wm_patch* p, void* hydro, void* bface, void* bcell);
 
 /* Initial state from primitive fields and an edge vector potential
