@@ -132,6 +132,18 @@ def _on_stream(fn):
     return wrapped
 
 
+class _StepGraph:
+    """Captured steps of a patch; ``replay()`` launches them on the patch's
+    stream (torch replays a graph on the current stream)."""
+
+    def __init__(self, graph, stream):
+        self.graph, self.stream = graph, stream
+
+    def replay(self):
+        with torch.cuda.stream(self.stream):
+            self.graph.replay()
+
+
 class Patch:
     """A periodic box on one GPU: state tensors, scratch and the C patch handle.
 
@@ -221,6 +233,25 @@ class Patch:
             return d.value
         _check(self.lib.wm_step(self.handle, None))
         return None
+
+    def capture(self, nsteps: int = 1, dt: float | None = None):
+        """Records ``nsteps`` steps into a HIP graph (a ``torch.cuda.CUDAGraph``)
+        and returns a handle whose ``replay()`` runs them with one launch on the
+        patch's stream, ordered like every other call of the patch.  dt: None
+        for eq. (cfl) on the device at every step, or a fixed value.  The patch
+        must own a stream other than the default one.  A step launches only
+        kernels (no copies, memsets or host synchronisation), so the graph
+        replays exactly what the eager calls would run."""
+        if self.stream == torch.cuda.default_stream(self.device):
+            raise ValueError("graph capture needs a patch created with its own stream")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=self.stream):
+            for _ in range(nsteps):
+                if dt is None:
+                    _check(self.lib.wm_step(self.handle, None))
+                else:
+                    self.step_dt(dt)
+        return _StepGraph(g, self.stream)
 
     @property
     def n_stages(self) -> int:
