@@ -206,9 +206,10 @@ def rk4_leg(n: int, steps: int):
     return out
 
 
-def oblique_waves(sizes, modes=("fast", "slow", "alfven", "entropy"), t_end: float = 2.0):
-    """The 3D linear-wave suite of Sect. 4.1 with the paper's WENO-Z weights and
-    RK4 at CFL 0.8: each MHD mode travels along (1, 2, 2)/3 through a 2N x N x N
+def oblique_waves(sizes, modes=("fast", "slow", "alfven", "entropy"), t_end: float = 2.0, weights: str = "z"):
+    """The 3D linear-wave suite of Sect. 4.1 with the paper's WENO-Z weights
+    (weights: 'z' the reading R13, 'z_printed' as Sect. 2.2 prints them, 'js'
+    Jiang-Shu) and RK4 at CFL 0.8: each MHD mode travels along (1, 2, 2)/3 through a 2N x N x N
     box (3 x 1.5 x 1.5).  Reports the L1 of Sect. 3 (rho, m, zone B, E; geometric
     norm) against the initial state after one wave period, and the decay rate of
     eq. (decay_rate) of the transverse field B_2 (wave frame) between t = 0 and
@@ -229,13 +230,14 @@ def oblique_waves(sizes, modes=("fast", "slow", "alfven", "entropy"), t_end: flo
         comp = B[0] * float(e2[0]) + B[1] * float(e2[1]) + B[2] * float(e2[2])
         return float(((comp - bg) ** 2).mean().sqrt())
 
-    out = {"sizes": list(sizes), "t_end": t_end, "weights": "wenoz", "integrator": "rk4", "cfl": 0.8}
+    wcode = {"z": binding.WM_WENO_Z, "z_printed": binding.WM_WENO_Z_PRINTED, "js": binding.WM_WENO_JS}[weights]
+    out = {"sizes": list(sizes), "t_end": t_end, "weights": weights, "integrator": "rk4", "cfl": 0.8}
     for mode in modes:
         l1, tau = [], []
         for N in sizes:
             w = inputs.oblique_wave(N, mode)
             nz, ny, nx = w["shape"]
-            p = binding.Patch(binding.config(nx=nx, ny=ny, nz=nz, h=w["h"], cfl=0.8, weights=binding.WM_WENO_Z,
+            p = binding.Patch(binding.config(nx=nx, ny=ny, nz=nz, h=w["h"], cfl=0.8, weights=wcode,
                                              integrator=binding.WM_RK4), device="cuda:0")
             p.init_from_potential(w["rho"], np.zeros((3, nz, ny, nx)), w["A"], 1.0 / w["gamma"], w["B0"])
             p.set_state(w["rho"], w["m"], w["E"], p.bface)
@@ -391,6 +393,8 @@ def main():
     ap.add_argument("--no-rk4", action="store_true", help="skip the RK4 (CFL 0.8) throughput leg")
     ap.add_argument("--no-waves", action="store_true", help="skip the oblique linear-wave suite")
     ap.add_argument("--wave-sizes", default="16,32,64", help="N of the 2N x N x N wave boxes")
+    ap.add_argument("--wave-weights", default="z", choices=("z", "z_printed", "js"),
+                    help="WENO weights of the wave suite: WENO-Z (reading), WENO-Z as printed, Jiang-Shu")
     ap.add_argument("--c5", action="store_true",
                     help="also run the 512^3 Mach-5 workload (FP32 state, FP64 adjoint); several minutes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -483,7 +487,8 @@ def main():
         out["rk4"] = rk4_leg(n, args.steps)
     if not args.no_waves:
         log("bench: oblique linear waves (WENO-Z, RK4 at CFL 0.8)")
-        out["oblique_waves"] = oblique_waves(tuple(int(x) for x in args.wave_sizes.split(",")))
+        out["oblique_waves"] = oblique_waves(tuple(int(x) for x in args.wave_sizes.split(",")),
+                                              weights=args.wave_weights)
     if not args.no_convergence:
         log("bench: fast-wave convergence, both precisions")
         out["convergence"] = convergence((32, 64, 128, 256))

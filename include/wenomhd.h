@@ -71,8 +71,13 @@ typedef enum {
 
 typedef enum {
   WM_WENO_JS = 0,           /* Jiang-Shu weights, Sect. 2.2                  */
-  WM_WENO_Z = 1             /* WENO-Z weights, Sect. 2.2 (reading: the
+  WM_WENO_Z = 1,            /* WENO-Z weights, Sect. 2.2 (reading: the
                                bracket (tau_5/(eps_Z + IS_k))^2)              */
+  WM_WENO_Z_PRINTED = 2     /* WENO-Z weights as Sect. 2.2 prints them,
+                               d_k (1 + tau_5/(eps_Z + IS_k)^2): not invariant
+                               under a scaling of the data (the term has the
+                               dimension of 1/IS); like WENO-Z in every call,
+                               the adjoint included                           */
 } wm_weights;
 
 typedef enum {

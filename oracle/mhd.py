@@ -39,7 +39,8 @@ Readings of passages that are garbled or silent:
   R12 zone-centred B is never advanced by the WENO flux; it is re-interpolated
       from the face field after every stage (Sect. 2.3, 3D step list)
   R13 WENO-Z weights alpha_k = d_k (1 + (tau_5 / (eps_Z + IS_k))^2): the
-      printed tau_5 / (eps_Z + IS_k)^2 is dimensionally inconsistent
+      printed tau_5 / (eps_Z + IS_k)^2 is dimensionally inconsistent; the
+      printed form is kept as weights == 'z_printed'
   R16 the RK4 of Sect. 2.1 as its q_save accumulation (factors 1/2, 1/2, 1,
       1/6 on q0; weights -4/3, 1/3, 2/3, 1/3, 1), dt held over the step
 """
@@ -63,7 +64,7 @@ class Config:
     cfl: float = 0.4
     eps: float = 1e-6         # WENO epsilon (Sect. 2.2)
     eps_B: float = 1e-30      # degeneracy threshold (Appendix A)
-    weights: str = "js"       # "js" (Jiang-Shu) or "z" (WENO-Z)
+    weights: str = "js"       # "js" (Jiang-Shu), "z" (WENO-Z) or "z_printed"
     eps_Z: float = 1e-40
 
 
@@ -283,7 +284,8 @@ def eigenvectors(rho, vn, vt1, vt2, Bn, Bt1, Bt2, P, gamma: float, eps_B: float)
 
 def phi_N(a, b, c, d, cfg: Config):
     """The WENO interpolant phi_N(a, b, c, d) of eq. (FWENO) with the Jiang-Shu
-    weights (or the WENO-Z weights of reading R13 when cfg.weights == 'z')."""
+    weights (or the WENO-Z weights of reading R13 when cfg.weights == 'z', or
+    the WENO-Z weights exactly as Sect. 2.2 prints them when 'z_printed')."""
     IS_0 = 13.0 * (a - b) ** 2 + 3.0 * (a - 3.0 * b) ** 2
     IS_1 = 13.0 * (b - c) ** 2 + 3.0 * (b + c) ** 2
     IS_2 = 13.0 * (c - d) ** 2 + 3.0 * (3.0 * c - d) ** 2
@@ -296,6 +298,11 @@ def phi_N(a, b, c, d, cfg: Config):
         alpha_0 = 1.0 * (1.0 + (tau_5 / (cfg.eps_Z + IS_0)) ** 2)
         alpha_1 = 6.0 * (1.0 + (tau_5 / (cfg.eps_Z + IS_1)) ** 2)
         alpha_2 = 3.0 * (1.0 + (tau_5 / (cfg.eps_Z + IS_2)) ** 2)
+    elif cfg.weights == "z_printed":
+        tau_5 = torch.abs(IS_0 - IS_2)
+        alpha_0 = 1.0 * (1.0 + tau_5 / (cfg.eps_Z + IS_0) ** 2)
+        alpha_1 = 6.0 * (1.0 + tau_5 / (cfg.eps_Z + IS_1) ** 2)
+        alpha_2 = 3.0 * (1.0 + tau_5 / (cfg.eps_Z + IS_2) ** 2)
     else:
         raise ValueError(cfg.weights)
     s = alpha_0 + alpha_1 + alpha_2

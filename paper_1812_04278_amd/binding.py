@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libwenomhd.so")
 
 WM_OK, WM_ERR_ARG, WM_ERR_HIP, WM_ERR_UNPHYSICAL, WM_ERR_STATE = 0, -1, -2, -3, -4
 WM_FP64, WM_MIXED, WM_MIXED_F32STATE = 0, 1, 2
-WM_WENO_JS, WM_WENO_Z = 0, 1
+WM_WENO_JS, WM_WENO_Z, WM_WENO_Z_PRINTED = 0, 1, 2
 WM_SSPRK3, WM_RK4 = 0, 1
 
 SYMBOLS = [

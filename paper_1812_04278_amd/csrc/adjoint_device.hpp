@@ -172,7 +172,7 @@ __host__ __device__ __forceinline__ void face_eig_vjp(const double fp[8], const 
 // ---------------------------------------------------------------------------
 template <bool WZ>
 __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, double c, double d, double eps,
-                                                       double epsZ, double& val, double gr[4]) {
+                                                       double epsZ, bool lit, double& val, double gr[4]) {
   const double t0 = a - b, t1 = a - 3.0 * b;
   const double t2 = b - c, t3 = b + c;
   const double t4 = c - d, t5 = 3.0 * c - d;
@@ -181,6 +181,7 @@ __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, doubl
   double w0, w2, l0, l1, l2;   // normalised weights 0, 2 and dphi/dIS_k
   if constexpr (!WZ) {
     (void)epsZ;
+    (void)lit;
     const double s0 = eps + 13.0 * t0 * t0 + 3.0 * t1 * t1;
     const double s1 = eps + 13.0 * t2 * t2 + 3.0 * t3 * t3;
     const double s2 = eps + 13.0 * t4 * t4 + 3.0 * t5 * t5;
@@ -197,7 +198,9 @@ __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, doubl
     l1 = 2.0 * w1 * i1 * W;
     l2 = 2.0 * w2 * i2 * (W - h);
   } else {
-    // WENO-Z: alpha_k = d_k (1 + r_k^2), r_k = tau5 / (eps_Z + IS_k), tau5 = |IS_0 - IS_2|
+    // WENO-Z: alpha_k = d_k (1 + u_k), q_k = 1/(eps_Z + IS_k), r_k = tau5 q_k, tau5 = |IS_0 - IS_2|,
+    // u_k = r_k^2, or u_k = tau5 q_k^2 = r_k q_k as printed (`lit`).  Both give
+    // du_k/dIS_k = -2 u_k q_k; du_k/dtau5 is 2 r_k q_k, or q_k^2 as printed.
     (void)eps;
     const double IS0 = 13.0 * t0 * t0 + 3.0 * t1 * t1;
     const double IS1 = 13.0 * t2 * t2 + 3.0 * t3 * t3;
@@ -205,20 +208,21 @@ __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, doubl
     const double dIS = IS0 - IS2, tau = fabs(dIS);
     const double q0 = rcp_w(epsZ + IS0), q1 = rcp_w(epsZ + IS1), q2 = rcp_w(epsZ + IS2);
     const double r0 = tau * q0, r1 = tau * q1, r2 = tau * q2;
-    const double al0 = 1.0 + r0 * r0, al1 = 6.0 * (1.0 + r1 * r1), al2 = 3.0 * (1.0 + r2 * r2);
+    const double s0 = lit ? q0 : r0, s1 = lit ? q1 : r1, s2 = lit ? q2 : r2;
+    const double u0 = r0 * s0, u1 = r1 * s1, u2 = r2 * s2;
+    const double al0 = 1.0 + u0, al1 = 6.0 * (1.0 + u1), al2 = 3.0 * (1.0 + u2);
     const double isum = rcp_w(al0 + al1 + al2);
     w0 = al0 * isum;
     w2 = al2 * isum;
     const double W = g * w0 + h * w2;
-    // dphi/dr_k = (G_k - W)/sum(alpha) * dalpha_k/dr_k, G = (g, 0, h)
-    const double L0 = (g - W) * isum * (2.0 * r0);
-    const double L1 = -W * isum * (12.0 * r1);
-    const double L2 = (h - W) * isum * (6.0 * r2);
-    const double ltau = L0 * q0 + L1 * q1 + L2 * q2;   // dphi/dtau5
+    // dphi/du_k = (G_k - W)/sum(alpha) * d_k, G = (g, 0, h)
+    const double M0 = (g - W) * isum, M1 = -W * isum * 6.0, M2 = (h - W) * isum * 3.0;
+    const double ct = lit ? 1.0 : 2.0;   // du_k/dtau5 = ct s_k q_k
+    const double ltau = ct * (M0 * s0 * q0 + M1 * s1 * q1 + M2 * s2 * q2);   // dphi/dtau5
     const double sg = dIS > 0.0 ? 1.0 : (dIS < 0.0 ? -1.0 : 0.0);
-    l0 = -L0 * r0 * q0 + sg * ltau;
-    l1 = -L1 * r1 * q1;
-    l2 = -L2 * r2 * q2 - sg * ltau;
+    l0 = -2.0 * M0 * u0 * q0 + sg * ltau;
+    l1 = -2.0 * M1 * u1 * q1;
+    l2 = -2.0 * M2 * u2 * q2 - sg * ltau;
   }
   const double cX = w0 * (1.0 / 3.0), cY = (w2 - 0.5) * (1.0 / 6.0);
   val = cX * X + cY * Y;
@@ -290,7 +294,7 @@ struct PairShape {
 // (interfaces 0..4) to f and the cotangents lP (of uF), lQ (of uq) and of alpha.
 template <bool WZ>
 __host__ __device__ __forceinline__ void row_split_grad(const double uF[5], const double uq[5], double al, double lf,
-                                                        double eps, double epsZ, double& f, double lP[5],
+                                                        double eps, double epsZ, bool lit, double& f, double lP[5],
                                                         double lQ[5], double& lal) {
   double v[8];
 #pragma unroll
@@ -298,9 +302,9 @@ __host__ __device__ __forceinline__ void row_split_grad(const double uF[5], cons
 #pragma unroll
   for (int k = 1; k < 5; ++k) v[3 + k] = uF[k] - al * uq[k];
   double g[8], g4[4], pa, pb;
-  phiN_val_grad<WZ>(v[7], v[6], v[5], v[4], eps, epsZ, pa, g4);
+  phiN_val_grad<WZ>(v[7], v[6], v[5], v[4], eps, epsZ, lit, pa, g4);
   g[7] = g4[0] * lf; g[6] = g4[1] * lf; g[5] = g4[2] * lf; g[4] = g4[3] * lf;
-  phiN_val_grad<WZ>(v[0], v[1], v[2], v[3], eps, epsZ, pb, g4);
+  phiN_val_grad<WZ>(v[0], v[1], v[2], v[3], eps, epsZ, lit, pb, g4);
   g[0] = -g4[0] * lf; g[1] = -g4[1] * lf; g[2] = -g4[2] * lf; g[3] = -g4[3] * lf;
   f = pa - pb;
 #pragma unroll
@@ -317,7 +321,7 @@ __host__ __device__ __forceinline__ void row_split_grad(const double uF[5], cons
 // pairs' cotangents (emit(k, lD[14])).
 template <class PA, bool TWOA, class PB, bool TWOB, bool WZ, class DL, class EMIT>
 __host__ __device__ __forceinline__ void pair2_rev(const PairRows& ra, const PairRows& rb, DL dl, double eps,
-                                                   double epsZ, PairCot& ca, PairCot& cb, EMIT emit) {
+                                                   double epsZ, bool lit, PairCot& ca, PairCot& cb, EMIT emit) {
   double uFa[5], uqa[5], lFa[5], lqa[5], uFb[5], uqb[5], lFb[5], lqb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -329,10 +333,10 @@ __host__ __device__ __forceinline__ void pair2_rev(const PairRows& ra, const Pai
     sched_fence();
   }
   double lPua[5], lQua[5], lPla[5], lQla[5], lPub[5], lQub[5], lPlb[5], lQlb[5];
-  row_split_grad<WZ>(uFa, uqa, ra.alu, ra.lfu, eps, epsZ, ca.fu, lPua, lQua, ca.lalu);
-  if (TWOA) row_split_grad<WZ>(lFa, lqa, ra.all, ra.lfl, eps, epsZ, ca.fl, lPla, lQla, ca.lall);
-  row_split_grad<WZ>(uFb, uqb, rb.alu, rb.lfu, eps, epsZ, cb.fu, lPub, lQub, cb.lalu);
-  if (TWOB) row_split_grad<WZ>(lFb, lqb, rb.all, rb.lfl, eps, epsZ, cb.fl, lPlb, lQlb, cb.lall);
+  row_split_grad<WZ>(uFa, uqa, ra.alu, ra.lfu, eps, epsZ, lit, ca.fu, lPua, lQua, ca.lalu);
+  if (TWOA) row_split_grad<WZ>(lFa, lqa, ra.all, ra.lfl, eps, epsZ, lit, ca.fl, lPla, lQla, ca.lall);
+  row_split_grad<WZ>(uFb, uqb, rb.alu, rb.lfu, eps, epsZ, lit, cb.fu, lPub, lQub, cb.lalu);
+  if (TWOB) row_split_grad<WZ>(lFb, lqb, rb.all, rb.lfl, eps, epsZ, lit, cb.fl, lPlb, lQlb, cb.lall);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     if (!TWOA) { lPla[k] = 0.0; lQla[k] = 0.0; }
@@ -573,7 +577,7 @@ __host__ __device__ __forceinline__ void face_corr_vjp(const FaceEig& e, ALF alf
     fast_rows(e, alf, lamf, rf);
     slow_rows(e, alf, lamf, rs);
     PairCot cf, cs;
-    pair2_rev<FastShape, true, SlowShape, true, WZ>(rf, rs, dl, ph.eps, ph.eps_Z, cf, cs, emit);
+    pair2_rev<FastShape, true, SlowShape, true, WZ>(rf, rs, dl, ph.eps, ph.eps_Z, ph.weno_z == 2, cf, cs, emit);
     fast_post(e, lamf, cf, eb);
     slow_post(e, lamf, cs, eb);
     lal[0] += cf.lalu; lal[6] += cf.lall; lal[2] += cs.lalu; lal[4] += cs.lall;
@@ -587,7 +591,7 @@ __host__ __device__ __forceinline__ void face_corr_vjp(const FaceEig& e, ALF alf
     alfven_rows(e, alf, lamf, ra);
     entropy_rows(e, alf, lamf, rn);
     PairCot ca, cn;
-    pair2_rev<AlfvenShape, true, EntropyShape, false, WZ>(ra, rn, dl, ph.eps, ph.eps_Z, ca, cn, emit);
+    pair2_rev<AlfvenShape, true, EntropyShape, false, WZ>(ra, rn, dl, ph.eps, ph.eps_Z, ph.weno_z == 2, ca, cn, emit);
     alfven_post(e, lamf, ca, eb);
     entropy_post(e, lamf, cn, eb);
     lal[1] += ca.lalu; lal[5] += ca.lall; lal[3] += cn.lalu;

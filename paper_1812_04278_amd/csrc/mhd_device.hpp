@@ -14,7 +14,7 @@ struct Phys {
   double eps;       // WENO epsilon (Jiang-Shu)
   double eps_B;     // degeneracy threshold of Appendix A
   double eps_Z;     // WENO-Z epsilon
-  int weno_z;       // 0: Jiang-Shu weights, 1: WENO-Z
+  int weno_z;       // 0: Jiang-Shu weights, 1: WENO-Z, 2: WENO-Z as printed
   double g1;        // (gamma - 1) / 2
   double g2;        // (gamma - 2) / (gamma - 1)
 };
@@ -131,16 +131,19 @@ __host__ __device__ __forceinline__ void zone_prologue(double rho, double mn, do
 // Jiang-Shu weights alpha_k = d_k / s_k^2 give
 //   omega_0 = s1^2 s2^2 / Q,  omega_2 = 3 s0^2 s1^2 / Q,
 //   Q = s1^2 s2^2 + 6 s0^2 s2^2 + 3 s0^2 s1^2,
-// one reciprocal instead of four divisions.  WENO-Z: alpha_k = d_k (1 + (tau_5/(eps_Z + IS_k))^2),
-// always evaluated in FP64: eps_Z (1e-40 in the paper) lies below the FP32 range, and
+// one reciprocal instead of four divisions.  WENO-Z: alpha_k = d_k (1 + u_k) with
+// q_k = 1/(eps_Z + IS_k), r_k = tau_5 q_k and u_k = r_k^2 (the dimensionless ratio
+// squared), or, with `lit`, u_k = tau_5 q_k^2 = r_k q_k as Sect. 2.2 prints it.  Always
+// evaluated in FP64: eps_Z (1e-40 in the paper) lies below the FP32 range, and
 // 1/(eps_Z + IS_k) of a constant stencil would overflow there.
 template <bool WENO_Z, typename T>
-__host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps_Z) {
+__host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps_Z, bool lit) {
   const T t0 = a - b, t1 = a - T(3) * b;
   const T t2 = b - c, t3 = b + c;
   const T t4 = c - d, t5 = T(3) * c - d;
   const T X = a - T(2) * b + c, Y = b - T(2) * c + d;
   if (!WENO_Z) {
+    (void)lit;
     // s_k/3 = eps/3 + IS_k/3: a common factor of the three s_k cancels in the
     // weights.  phi = [p12 X / 3 + (p01/4 - p12/12 - p02/2) Y] / Q with
     // p_ij = s_i^2 s_j^2 and Q = p12 + 6 p02 + 3 p01.
@@ -159,13 +162,15 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps
     return rq * fma(cY, Y, (p12 * T(1.0 / 3.0)) * X);
   } else {
     if constexpr (sizeof(T) == 4)
-      return T(phiN<true, double>(double(a), double(b), double(c), double(d), double(eps), eps_Z));
+      return T(phiN<true, double>(double(a), double(b), double(c), double(d), double(eps), eps_Z, lit));
     const T IS0 = T(13) * t0 * t0 + T(3) * t1 * t1;
     const T IS1 = T(13) * t2 * t2 + T(3) * t3 * t3;
     const T IS2 = T(13) * t4 * t4 + T(3) * t5 * t5;
     const T tau5 = fabs(IS0 - IS2);
-    const T r0 = tau5 * rcp_w(eps_Z + IS0), r1 = tau5 * rcp_w(eps_Z + IS1), r2 = tau5 * rcp_w(eps_Z + IS2);
-    const T al0 = T(1) + r0 * r0, al1 = T(6) * (T(1) + r1 * r1), al2 = T(3) * (T(1) + r2 * r2);
+    const T q0 = rcp_w(eps_Z + IS0), q1 = rcp_w(eps_Z + IS1), q2 = rcp_w(eps_Z + IS2);
+    const T r0 = tau5 * q0, r1 = tau5 * q1, r2 = tau5 * q2;
+    const T al0 = fma(r0, lit ? q0 : r0, T(1)), al1 = T(6) * fma(r1, lit ? q1 : r1, T(1)),
+            al2 = T(3) * fma(r2, lit ? q2 : r2, T(1));
     const T inv = rcp_w(al0 + al1 + al2);
     return inv * (al0 * X * T(1.0 / 3.0) + (al2 - T(0.5) * (al0 + al1 + al2)) * Y * T(1.0 / 6.0));
   }
@@ -174,8 +179,8 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps
 // phi^- - phi^+ of eq. (FWENO) from the split values of one characteristic
 // field: v[0..3] = Delta F^+ at i-3/2 .. i+3/2, v[4..7] = Delta F^- at i-1/2 .. i+5/2.
 template <bool WENO_Z, typename T>
-__host__ __device__ __forceinline__ T weno_split(const T v[8], T eps, double eps_Z) {
-  return phiN<WENO_Z>(v[7], v[6], v[5], v[4], eps, eps_Z) - phiN<WENO_Z>(v[0], v[1], v[2], v[3], eps, eps_Z);
+__host__ __device__ __forceinline__ T weno_split(const T v[8], T eps, double eps_Z, bool lit) {
+  return phiN<WENO_Z>(v[7], v[6], v[5], v[4], eps, eps_Z, lit) - phiN<WENO_Z>(v[0], v[1], v[2], v[3], eps, eps_Z, lit);
 }
 
 // Eigen-system scalars of Appendix A at one face (always FP64: the
@@ -291,6 +296,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
                                                    double corr[7]) {
   const T eps = T(ph.eps);
   const double epsZ = ph.eps_Z;
+  const bool lit = ph.weno_z == 2;
   const double gm1 = -e.omg;
   const double sra = e.sr * e.cs;
   T vu[8], vl[8];
@@ -303,8 +309,8 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
     const T A[4] = {T(e.qa2 * e.Gf), T(-e.qa2 * (e.af * e.cf)), T(e.qa2 * (e.csl * e.as * e.by * e.s)),
                     T(e.qa2 * (e.csl * e.as * e.bz * e.s))};
     split_pair(S, A, al[0], al[6], dl, vu, vl);
-    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
-    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
+    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
+    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ, lit));
     const double sp = fu + fl, sm = fu - fl;
     corr[0] = e.af * sp;
     corr[1] = e.af * e.vn * sp - e.af * e.cf * sm;
@@ -324,8 +330,8 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
     const T A[4] = {T(e.qa2 * e.Gs), T(-e.qa2 * (e.as * e.csl)), T(-e.qa2 * (e.cf * e.af * e.by * e.s)),
                     T(-e.qa2 * (e.cf * e.af * e.bz * e.s))};
     split_pair(S, A, al[2], al[4], dl, vu, vl);
-    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
-    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
+    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
+    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ, lit));
     const double sp = fu + fl, sm = fu - fl;
     corr[0] += e.as * sp;
     corr[1] += e.as * e.vn * sp - e.as * e.csl * sm;
@@ -352,8 +358,8 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
       if (k >= 1) { vu[3 + k] = uF - alu * uq; vl[3 + k] = lF - all * lq; }
       sched_fence();
     }
-    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ));
-    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ));
+    const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
+    const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ, lit));
     const double sp = fu + fl, sm = fu - fl;
     corr[2] += -e.bz * e.s * sp;
     corr[3] += e.by * e.s * sp;
@@ -377,7 +383,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
       if (k >= 1) vu[3 + k] = sF - a4 * sq;
       sched_fence();
     }
-    const double f4 = double(weno_split<WENO_Z>(vu, eps, epsZ));
+    const double f4 = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
     corr[0] += f4;
     corr[1] += e.vn * f4;
     corr[2] += e.vt1 * f4;

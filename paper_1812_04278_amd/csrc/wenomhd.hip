@@ -64,7 +64,10 @@ bool valid_config(const wm_config* c, const char** why) {
   if (!(c->gamma > 1.0)) { *why = "gamma must exceed 1"; return false; }
   if (!(c->cfl > 0.0)) { *why = "cfl must be positive"; return false; }
   if (!(c->eps_weno > 0.0) || !(c->eps_B >= 0.0) || !(c->eps_Z > 0.0)) { *why = "epsilons must be positive"; return false; }
-  if (c->weights != WM_WENO_JS && c->weights != WM_WENO_Z) { *why = "unknown weights"; return false; }
+  if (c->weights != WM_WENO_JS && c->weights != WM_WENO_Z && c->weights != WM_WENO_Z_PRINTED) {
+    *why = "unknown weights";
+    return false;
+  }
   if (c->precision != WM_FP64 && c->precision != WM_MIXED && c->precision != WM_MIXED_F32STATE) {
     *why = "unknown precision mode";
     return false;
@@ -494,7 +497,7 @@ wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch,
   p->ph.eps = cfg->eps_weno;
   p->ph.eps_B = cfg->eps_B;
   p->ph.eps_Z = cfg->eps_Z;
-  p->ph.weno_z = cfg->weights == WM_WENO_Z ? 1 : 0;
+  p->ph.weno_z = cfg->weights == WM_WENO_Z ? 1 : (cfg->weights == WM_WENO_Z_PRINTED ? 2 : 0);
   p->ph.g1 = 0.5 * (cfg->gamma - 1.0);
   p->ph.g2 = (cfg->gamma - 2.0) / (cfg->gamma - 1.0);
   p->scratch = reinterpret_cast<char*>(scratch);

@@ -43,7 +43,7 @@ def test_scratch_bytes_and_default_config():
 
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("gamma", 1.0), ("cfl", -1.0),
-                                         ("weights", 7), ("precision", 9), ("eps_weno", 0.0),
+                                         ("weights", 3), ("weights", -1), ("precision", 9), ("eps_weno", 0.0),
                                          ("integrator", 2)])
 def test_invalid_config_rejected(field, value):
     lib = B.load()
@@ -92,3 +92,12 @@ def test_missing_library_fails_loudly(tmp_path):
             B.load(str(tmp_path / "nope.so"))
         finally:
             B._lib = B._lib_saved
+
+
+@pytest.mark.parametrize("w", [0, 1, 2])
+def test_all_weights_accepted(w):
+    """Jiang-Shu, WENO-Z of reading R13 and WENO-Z as printed are valid configurations."""
+    lib = B.load()
+    c = B.config(16, weights=w)
+    assert w == (B.WM_WENO_JS, B.WM_WENO_Z, B.WM_WENO_Z_PRINTED)[w]
+    assert lib.wm_scratch_bytes(ctypes.byref(c)) > 0

@@ -67,10 +67,21 @@ def oracle_vjp(fn, U, lam):
     return torch.cat([g[0][None], g[1], g[2][None], g[3]])
 
 
-def check8(gpu, ref, label):
+def check8(gpu, ref, label, tol=TOL):
     errs = [rel_err(gpu[c], ref[c]) for c in range(8)]
     say(f"  {label}: " + " ".join(f"{e:.1e}" for e in errs))
-    assert max(errs) <= TOL, (label, errs)
+    assert max(errs) <= tol, (label, errs)
+
+
+def conditioning_tol(fn, U, lam, ref):
+    """max(TOL, 3 x the change of the oracle's own VJP when every input value moves
+    by about two ulps): the bar for a VJP that rounding alone moves above TOL."""
+    g = torch.Generator().manual_seed(99)
+    Up = {k: v * (1 + 4e-16 * torch.randn(v.shape, generator=g, dtype=torch.float64)) for k, v in U.items()}
+    alt = oracle_vjp(fn, Up, lam)
+    spread = max(rel_err(alt[c], ref[c]) for c in range(8))
+    say(f"  oracle VJP change under a two-ulp input perturbation: {spread:.1e}")
+    return max(TOL, 3.0 * spread)
 
 
 @pytest.mark.parametrize("crop", [(37, 21, 19), (12, 10, 9)])
@@ -217,39 +228,51 @@ def test_full_size_sampled_rhs_vjp_128():
     assert float(out[:, ~near].abs().max()) == 0.0
 
 
-def test_rhs_vjp_wenoz_vs_oracle():
-    """WENO-Z weights (reading R13): the right-hand-side VJP against autograd
-    through the oracle on a ragged box (|x| of tau_5 differentiated as its sign)."""
-    say("WENO-Z rhs vjp 37x21x19")
+WZ_FORMS = [("z", B.WM_WENO_Z), ("z_printed", B.WM_WENO_Z_PRINTED)]
+
+
+@pytest.mark.parametrize("form,wcode", WZ_FORMS)
+def test_rhs_vjp_wenoz_vs_oracle(form, wcode):
+    """WENO-Z weights (reading R13, and the form Sect. 2.2 prints): the
+    right-hand-side VJP against autograd through the oracle on a ragged box
+    (|x| of tau_5 differentiated as its sign).  The printed form's excess
+    tau_5/IS_k^2 has the dimension 1/IS, so its weight derivatives grow as 1/IS^2
+    where the reading's grow as 1/IS; rounding alone moves its VJP by ~1e-9, and
+    the bar is set from the oracle's own change under a two-ulp perturbation."""
+    say(f"WENO-Z ({form}) rhs vjp 37x21x19")
     f = fields(40, seed=12, v_rms=1.5, crop=(37, 21, 19))
     U, cfg = oracle_state(f)
-    cfg = dataclasses.replace(cfg, weights="z")
+    cfg = dataclasses.replace(cfg, weights=form)
     g = torch.Generator().manual_seed(3)
     lam = torch.randn((8,) + U["rho"].shape, generator=g, dtype=torch.float64)
     ref = oracle_vjp(lambda X: mhd.rhs(X, cfg), U, lam)
     nz, ny, nx = U["rho"].shape
-    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h, weights=B.WM_WENO_Z))
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h, weights=wcode))
     h, b = to_gpu_state(U)
     out = p.rhs_vjp(h, b, lam.cuda()).cpu()
-    check8(out, ref, "WENO-Z rhs vjp")
+    tol = conditioning_tol(lambda X: mhd.rhs(X, cfg), U, lam, ref) if form == "z_printed" else TOL
+    check8(out, ref, f"WENO-Z ({form}) rhs vjp", tol)
 
 
-def test_adjoint_step_wenoz_rk4_vs_oracle():
+@pytest.mark.parametrize("form,wcode", WZ_FORMS)
+def test_adjoint_step_wenoz_rk4_vs_oracle(form, wcode):
     """The paper's own configuration, WENO-Z weights with RK4 at CFL 0.8: the step
-    adjoint against autograd through the oracle."""
-    say("WENO-Z RK4 adjoint step 20x18x16")
+    adjoint against autograd through the oracle (the printed form's bar as in the
+    right-hand-side VJP test)."""
+    say(f"WENO-Z ({form}) RK4 adjoint step 20x18x16")
     f = fields(24, seed=13, v_rms=1.0, crop=(20, 18, 16))
     U, cfg = oracle_state(f)
-    cfg = dataclasses.replace(cfg, weights="z", cfl=0.8)
+    cfg = dataclasses.replace(cfg, weights=form, cfl=0.8)
     dt = 0.8 * mhd.compute_dt(U, cfg)
     lam = torch.randn((8,) + U["rho"].shape, generator=torch.Generator().manual_seed(5), dtype=torch.float64)
     ref = oracle_vjp(lambda X: mhd.step_rk4(X, cfg, dt)[0], U, lam)
     nz, ny, nx = U["rho"].shape
-    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h, cfl=0.8, weights=B.WM_WENO_Z, integrator=B.WM_RK4))
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=cfg.h, cfl=0.8, weights=wcode, integrator=B.WM_RK4))
     h, b = to_gpu_state(U)
     lh, lb = lam[:5].cuda().contiguous(), lam[5:].cuda().contiguous()
     p.adjoint_step(h, b, dt, lh, lb)
-    check8(torch.cat([lh.cpu(), lb.cpu()]), ref, "WENO-Z RK4 adjoint step")
+    tol = conditioning_tol(lambda X: mhd.step_rk4(X, cfg, dt)[0], U, lam, ref) if form == "z_printed" else TOL
+    check8(torch.cat([lh.cpu(), lb.cpu()]), ref, f"WENO-Z ({form}) RK4 adjoint step", tol)
 
 
 def test_adjoint_deterministic():

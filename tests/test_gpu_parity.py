@@ -131,35 +131,41 @@ def test_crop_64_ten_steps_mach2():
     assert_state_parity(p.state(), U, label="64^3 x 10")
 
 
-def test_wenoz_step_c1_32():
-    """WENO-Z weights (reading R13): one step on 32^3, Mach 0.1, dt from eq. (cfl)."""
+WZ_FORMS = [("z", B.WM_WENO_Z), ("z_printed", B.WM_WENO_Z_PRINTED)]
+
+
+@pytest.mark.parametrize("form,wcode", WZ_FORMS)
+def test_wenoz_step_c1_32(form, wcode):
+    """WENO-Z weights (reading R13, and the form Sect. 2.2 prints): one step on
+    32^3, Mach 0.1, dt from eq. (cfl)."""
     import dataclasses
-    say("WENO-Z step 32^3")
+    say(f"WENO-Z ({form}) step 32^3")
     f = fields(32, seed=1, v_rms=0.1)
     U, cfg = oracle_state(f)
-    cfg = dataclasses.replace(cfg, weights="z")
-    p = gpu_patch(f, weights=B.WM_WENO_Z)
+    cfg = dataclasses.replace(cfg, weights=form)
+    p = gpu_patch(f, weights=wcode)
     dt_g = p.step(want_dt=True)
     U1, dt_o = mhd.step(U, cfg)
     assert abs(dt_g - dt_o) <= 1e-14 * dt_o
-    assert_state_parity(p.state(), U1, label="WENO-Z step")
+    assert_state_parity(p.state(), U1, label=f"WENO-Z ({form}) step")
 
 
-def test_wenoz_ten_steps_64_mach2_ragged():
+@pytest.mark.parametrize("form,wcode", WZ_FORMS)
+def test_wenoz_ten_steps_64_mach2_ragged(form, wcode):
     """WENO-Z over ten Mach-2 steps on a ragged 40 x 36 x 34 crop of the 64^3
     generator (shocks start to form), dt from the oracle each step."""
     import dataclasses
-    say("WENO-Z 10 steps 40x36x34 Mach 2")
+    say(f"WENO-Z ({form}) 10 steps 40x36x34 Mach 2")
     f = fields(64, seed=1, v_rms=2.0, crop=(40, 36, 34))
     U, cfg = oracle_state(f, h=1.0 / 64)
-    cfg = dataclasses.replace(cfg, weights="z")
+    cfg = dataclasses.replace(cfg, weights=form)
     nz, ny, nx = U["rho"].shape
-    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=1.0 / 64, weights=B.WM_WENO_Z))
+    p = B.Patch(B.config(nx=nx, ny=ny, nz=nz, h=1.0 / 64, weights=wcode))
     p.set_state(U["rho"], U["m"], U["E"], U["b"])
     for _ in range(10):
         U, dt = mhd.step(U, cfg)
         p.step_dt(dt)
-    assert_state_parity(p.state(), U, label="WENO-Z 10 steps")
+    assert_state_parity(p.state(), U, label=f"WENO-Z ({form}) 10 steps")
 
 
 def test_uniform_state_bitwise():

@@ -12,6 +12,11 @@
   exponent 2 and eps_Z/12 (the ratio tau_5/IS_k is unchanged by the factor 12),
   written here from its own definition; with eps_Z -> infinity it is the linear
   upwind flux; and it advects at 5th order.
+* WENO-Z as Sect. 2.2 prints it, alpha_k = d_k (1 + tau_5 / (eps_Z + IS_k)^2): on
+  data scaled to tau_5 = 1 it equals the reading R13 pinned above; its excess
+  tau_5 / IS_k^2 has the dimension 1/IS, so scaling the data by s moves phi_N(s v)/s
+  towards the linear-weight value as s^-2 (R13: not at all); and as s -> 0 the
+  weights tend to d_k / IS_k^2, the Jiang-Shu weights with eps -> 0.
 """
 import math
 
@@ -168,3 +173,63 @@ def test_wenoz_scalar_advection_fifth_order():
     e = [_advect(n, 0.5, weights="z") for n in (20, 40, 80)]
     orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
     assert orders[-1] > 4.6, (e, orders)
+
+
+def _phi_cfgs():
+    z = mhd.Config(4, 4, 4, 0.25, weights="z")
+    return z, mhd.Config(4, 4, 4, 0.25, weights="z_printed")
+
+
+def _stencils(seed, n=4000):
+    g = torch.Generator().manual_seed(seed)
+    return torch.randn(4, n, generator=g, dtype=T64)
+
+
+def test_wenoz_printed_equals_reading_at_unit_tau():
+    z, zp = _phi_cfgs()
+    a, b, c, d = _stencils(21)
+    IS0 = 13 * (a - b) ** 2 + 3 * (a - 3 * b) ** 2
+    IS2 = 13 * (c - d) ** 2 + 3 * (3 * c - d) ** 2
+    s = 1.0 / torch.sqrt((IS0 - IS2).abs())   # IS is quadratic in the data: tau_5(s v) = 1
+    v = [x * s for x in (a, b, c, d)]
+    ref = mhd.phi_N(*v, z)
+    got = mhd.phi_N(*v, zp)
+    np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=1e-13 * (1 + float(ref.abs().max())))
+    # away from unit tau_5 the two forms differ
+    assert float((mhd.phi_N(*(4 * x for x in v), zp) / 4 - ref).abs().max()) > 1e-3
+
+
+def test_wenoz_printed_scale_rate():
+    z, zp = _phi_cfgs()
+    lin = mhd.Config(4, 4, 4, 0.25, weights="js", eps=1e30)   # linear weights (pinned above)
+    a, b, c, d = _stencils(22)
+    ref = mhd.phi_N(a, b, c, d, lin)
+
+    def dev(cfg, s):
+        return (mhd.phi_N(s * a, s * b, s * c, s * d, cfg) / s - ref).abs()
+
+    rate = torch.log10(dev(zp, 1e3) / dev(zp, 1e4))
+    assert abs(float(rate.median()) - 2.0) < 0.01, float(rate.median())
+    rate_z = torch.log10(dev(z, 1e3) / dev(z, 1e4))
+    assert abs(float(rate_z.median())) < 0.01   # the reading R13 is scale-invariant
+
+
+def test_wenoz_printed_small_scale_is_js_without_eps():
+    _, zp = _phi_cfgs()
+    js0 = mhd.Config(4, 4, 4, 0.25, weights="js", eps=1e-35)
+    a, b, c, d = _stencils(23)
+    s = 1e-8
+    got = mhd.phi_N(s * a, s * b, s * c, s * d, zp) / s
+    ref = mhd.phi_N(s * a, s * b, s * c, s * d, js0) / s
+    np.testing.assert_allclose(got.numpy(), ref.numpy(), rtol=0, atol=1e-9 * (1 + float(ref.abs().max())))
+
+
+def test_wenoz_printed_constant_stencils_are_linear():
+    _, zp = _phi_cfgs()
+    f = split_values(13, 2000, True)
+    f[:, :100] = 0.7
+    Fs = [f[k] for k in range(6)]
+    got = mhd.weno_split_flux(Fs, Fs, torch.ones(()), zp)
+    ref = (2 * f[0] - 13 * f[1] + 47 * f[2] + 27 * f[3] - 3 * f[4]) / 60
+    assert bool(torch.isfinite(got).all())
+    np.testing.assert_allclose(got[:100].numpy(), ref[:100].numpy(), rtol=0, atol=1e-14)
