@@ -29,8 +29,8 @@ METRIC = "Mzone-updates/s per RK3 step, FP64 vs mixed at stated L1 err; adjoint/
 # prologue ~70 per zone.
 FLOPS_PER_FACE = 2060
 # Algorithmic HBM bytes of the update kernel per zone (FP64): reads 15 face
-# fluxes, 6 transport fluxes, U^n (8) and the accumulator (8, stages 1-2);
-# writes the stage state (8) and the accumulator (8, stages 0-1).
+# fluxes, 6 transport fluxes, U^n (8) and the previous stage state (8, stages
+# 1-2); writes the stage state (8).
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep dispatch on the 256^3 FP64 workload, averaged over the
@@ -450,8 +450,8 @@ def main():
     nup, msup = rep["update"]
     upd_ms = msup / max(nup, 1)
     # update kernel, algorithmic bytes per zone averaged over the three stages:
-    # reads 21 face values + 8 U^n + 8 acc (stages 1, 2); writes 8 state + 8 acc (stages 0, 1)
-    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * 8 * float(n) ** 3
+    # reads 21 face values + 8 U^n + 8 previous stage state (stages 1, 2); writes 8 state
+    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8) * 8 * float(n) ** 3
     out = {
         "metric": METRIC,
         "value": round(value, 3),
