@@ -119,8 +119,8 @@ def mixed_precision(n: int, steps: int):
     res["l1_mixed_vs_fp64"] = {"per_variable": [float(f"{x:.3e}") for x in per],
                                "variables": ["rho", "m_x", "m_y", "m_z", "E", "b_x", "b_y", "b_z"],
                                "geometric": float(f"{geo:.3e}")}
-    # the mixed arithmetic with the state, stage states, accumulator and face
-    # fluxes stored in FP32 (the form of the 512^3 workload)
+    # the mixed arithmetic with the state, stage states and face fluxes stored
+    # in FP32 (the form of the 512^3 workload)
     per, geo = l1_per_variable(states["fp64"], states["f32state"])
     res["speedup_f32state"] = round(res["f32state"]["value"] / res["fp64"]["value"], 4)
     res["l1_f32state_vs_fp64"] = {"per_variable": [float(f"{x:.3e}") for x in per], "geometric": float(f"{geo:.3e}")}

@@ -63,7 +63,7 @@ typedef enum {
                                characteristic projections, WENO weights and
                                split fluxes                                   */
   WM_MIXED_F32STATE = 2     /* the WM_MIXED arithmetic with the state (hydro,
-                               bface, bcell), the stage states, the RK
+                               bface, bcell), the stage states, the RK4
                                accumulator and the face fluxes stored in FP32
                                (float arrays); increments and divergences are
                                formed in FP64 before rounding to the state    */

@@ -178,7 +178,7 @@ struct wm_patch {
   Phys ph;
   char* scratch;
   Layout lay;
-  bool f32 = false;          // state, stage states, accumulator and face values in FP32
+  bool f32 = false;          // state, stage states, RK4 accumulator and face values in FP32
   void* hydro = nullptr;     // bound state (storage type: double, or float when f32)
   void* bface = nullptr;
   void* bcell = nullptr;
