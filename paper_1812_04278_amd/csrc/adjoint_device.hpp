@@ -176,7 +176,7 @@ __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, doubl
   const double t0 = a - b, t1 = a - 3.0 * b;
   const double t2 = b - c, t3 = b + c;
   const double t4 = c - d, t5 = 3.0 * c - d;
-  const double X = a - 2.0 * b + c, Y = b - 2.0 * c + d;
+  const double X = t0 - t2, Y = t2 - t4;   // a - 2b + c, b - 2c + d
   const double g = X * (1.0 / 3.0), h = Y * (1.0 / 6.0);
   double w0, w2, l0, l1, l2;   // normalised weights 0, 2 and dphi/dIS_k
   if constexpr (!WZ) {

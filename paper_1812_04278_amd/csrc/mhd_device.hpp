@@ -141,7 +141,7 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps
   const T t0 = a - b, t1 = a - T(3) * b;
   const T t2 = b - c, t3 = b + c;
   const T t4 = c - d, t5 = T(3) * c - d;
-  const T X = a - T(2) * b + c, Y = b - T(2) * c + d;
+  const T X = t0 - t2, Y = t2 - t4;   // a - 2b + c, b - 2c + d
   if (!WENO_Z) {
     (void)lit;
     // s_k/3 = eps/3 + IS_k/3: a common factor of the three s_k cancels in the
