@@ -93,7 +93,10 @@ typedef struct {
   double cfl;               /* Courant number for wm_compute_dt (> 0)        */
   double eps_weno;          /* WENO epsilon, 1e-6 in the paper               */
   double eps_B;             /* degeneracy threshold, 1e-30 in the paper      */
-  double eps_Z;             /* WENO-Z epsilon, 1e-40 in the paper            */
+  double eps_Z;             /* WENO-Z epsilon, 1e-40 in the paper; at least
+                               1e-50 (the weights are formed with (eps_Z +
+                               IS_k)^6 in FP64, which also bounds the
+                               smoothness indicators there to ~1e50)          */
   int weights;              /* wm_weights                                    */
   int precision;            /* wm_precision                                  */
   int integrator;           /* wm_integrator                                 */

@@ -132,10 +132,9 @@ __host__ __device__ __forceinline__ void zone_prologue(double rho, double mn, do
 //   omega_0 = s1^2 s2^2 / Q,  omega_2 = 3 s0^2 s1^2 / Q,
 //   Q = s1^2 s2^2 + 6 s0^2 s2^2 + 3 s0^2 s1^2,
 // one reciprocal instead of four divisions.  WENO-Z: alpha_k = d_k (1 + u_k) with
-// q_k = 1/(eps_Z + IS_k), r_k = tau_5 q_k and u_k = r_k^2 (the dimensionless ratio
-// squared), or, with `lit`, u_k = tau_5 q_k^2 = r_k q_k as Sect. 2.2 prints it.  Always
-// evaluated in FP64: eps_Z (1e-40 in the paper) lies below the FP32 range, and
-// 1/(eps_Z + IS_k) of a constant stencil would overflow there.
+// u_k = (tau_5/(eps_Z + IS_k))^2 (the dimensionless ratio squared), or, with `lit`,
+// u_k = tau_5/(eps_Z + IS_k)^2 as Sect. 2.2 prints it.  Always evaluated in FP64:
+// eps_Z (1e-40 in the paper) lies below the FP32 range.
 template <bool WENO_Z, typename T>
 __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps_Z, bool lit) {
   const T t0 = a - b, t1 = a - T(3) * b;
@@ -167,10 +166,14 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps
     const T IS1 = T(13) * t2 * t2 + T(3) * t3 * t3;
     const T IS2 = T(13) * t4 * t4 + T(3) * t5 * t5;
     const T tau5 = fabs(IS0 - IS2);
-    const T q0 = rcp_w(eps_Z + IS0), q1 = rcp_w(eps_Z + IS1), q2 = rcp_w(eps_Z + IS2);
-    const T r0 = tau5 * q0, r1 = tau5 * q1, r2 = tau5 * q2;
-    const T al0 = fma(r0, lit ? q0 : r0, T(1)), al1 = T(6) * fma(r1, lit ? q1 : r1, T(1)),
-            al2 = T(3) * fma(r2, lit ? q2 : r2, T(1));
+    // alpha_k P^2 with P = s0 s1 s2, s_k = eps_Z + IS_k: d_k (P^2 + t m_k^2), m_k = P / s_k,
+    // t = tau_5^2 (or tau_5 as printed); the common factor P^2 cancels in the
+    // weights, so one reciprocal serves.  eps_Z >= 1e-50 keeps P^2 >= eps_Z^6 normal.
+    const T s0 = eps_Z + IS0, s1 = eps_Z + IS1, s2 = eps_Z + IS2;
+    const T m0 = s1 * s2, m1 = s0 * s2, m2 = s0 * s1;
+    const T P = s0 * m0, P2 = P * P;
+    const T t = lit ? tau5 : tau5 * tau5;
+    const T al0 = fma(t * m0, m0, P2), al1 = T(6) * fma(t * m1, m1, P2), al2 = T(3) * fma(t * m2, m2, P2);
     const T inv = rcp_w(al0 + al1 + al2);
     return inv * (al0 * X * T(1.0 / 3.0) + (al2 - T(0.5) * (al0 + al1 + al2)) * Y * T(1.0 / 6.0));
   }

@@ -64,6 +64,7 @@ bool valid_config(const wm_config* c, const char** why) {
   if (!(c->gamma > 1.0)) { *why = "gamma must exceed 1"; return false; }
   if (!(c->cfl > 0.0)) { *why = "cfl must be positive"; return false; }
   if (!(c->eps_weno > 0.0) || !(c->eps_B >= 0.0) || !(c->eps_Z > 0.0)) { *why = "epsilons must be positive"; return false; }
+  if (!(c->eps_Z >= 1e-50)) { *why = "eps_Z below 1e-50 (the WENO-Z weights need eps_Z^6 in the FP64 range)"; return false; }
   if (c->weights != WM_WENO_JS && c->weights != WM_WENO_Z && c->weights != WM_WENO_Z_PRINTED) {
     *why = "unknown weights";
     return false;

@@ -46,7 +46,7 @@ def test_scratch_bytes_and_default_config():
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("gamma", 1.0), ("cfl", -1.0),
                                          ("weights", 3), ("weights", -1), ("precision", 9), ("eps_weno", 0.0),
-                                         ("integrator", 2)])
+                                         ("integrator", 2), ("eps_Z", 1e-60)])
 def test_invalid_config_rejected(field, value):
     lib = B.load()
     c = B.config(16)
