@@ -103,8 +103,19 @@ def mixed_precision(n: int, steps: int):
         rep = p.profile_report()
         p.profile(False)
         nsw, msw = rep["sweep"]
+        nup, msup = rep["update"]
+        sw_ms, up_ms = msw / max(nsw, 1), msup / max(nup, 1)
+        es = 4 if prec == binding.WM_MIXED_F32STATE else 8
+        upd_bytes = (21 + 8 + 8 * 2 / 3 + 8) * es * float(n) ** 3
+        tf = FLOPS_PER_FACE * float(n) ** 3 / (sw_ms * 1e-3) / 1e12
+        # sweep fraction against the FP64 vector peak in all three forms: with packed
+        # FP32 instructions off, an FP32 vector instruction issues at the FP64 rate
         res[name] = {"value": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms / steps, 4),
-                     "sweep_avg_ms": round(msw / max(nsw, 1), 4)}
+                     "sweep_avg_ms": round(sw_ms, 4), "sweep_tflops": round(tf, 3),
+                     "sweep_frac_fp64_vector_peak": round(tf / PEAK_FP64_TFLOPS, 4),
+                     "update_avg_ms": round(up_ms, 4),
+                     "update_hbm_gbs": round(upd_bytes / (up_ms * 1e-3) / 1e9, 1),
+                     "update_hbm_frac": round(upd_bytes / (up_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
         # accuracy run: the FP64 dt sequence for both
         p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
         for s in range(steps):
