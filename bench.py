@@ -29,8 +29,8 @@ METRIC = "Mzone-updates/s per RK3 step, FP64 vs mixed at stated L1 err; adjoint/
 # prologue ~70 per zone.
 FLOPS_PER_FACE = 2060
 # Algorithmic HBM bytes of the update kernel per zone (FP64): reads 15 face
-# fluxes, 6 transport fluxes, U^n (8) and the previous stage state (8, stages
-# 1-2); writes the stage state (8).
+# fluxes, 6 transport fluxes, U^n (8) and the accumulator (8, stages 1-2);
+# writes the stage state (8) and the accumulator (8, stages 0-1).
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep dispatch on the 256^3 FP64 workload, averaged over the
@@ -106,7 +106,7 @@ def mixed_precision(n: int, steps: int):
         nup, msup = rep["update"]
         sw_ms, up_ms = msw / max(nsw, 1), msup / max(nup, 1)
         es = 4 if prec == binding.WM_MIXED_F32STATE else 8
-        upd_bytes = (21 + 8 + 8 * 2 / 3 + 8) * es * float(n) ** 3
+        upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * es * float(n) ** 3
         tf = FLOPS_PER_FACE * float(n) ** 3 / (sw_ms * 1e-3) / 1e12
         # sweep fraction against the FP64 vector peak in all three forms: with packed
         # FP32 instructions off, an FP32 vector instruction issues at the FP64 rate
@@ -130,8 +130,8 @@ def mixed_precision(n: int, steps: int):
     res["l1_mixed_vs_fp64"] = {"per_variable": [float(f"{x:.3e}") for x in per],
                                "variables": ["rho", "m_x", "m_y", "m_z", "E", "b_x", "b_y", "b_z"],
                                "geometric": float(f"{geo:.3e}")}
-    # the mixed arithmetic with the state, stage states and face fluxes stored
-    # in FP32 (the form of the 512^3 workload)
+    # the mixed arithmetic with the state, stage states, accumulator and face
+    # fluxes stored in FP32 (the form of the 512^3 workload)
     per, geo = l1_per_variable(states["fp64"], states["f32state"])
     res["speedup_f32state"] = round(res["f32state"]["value"] / res["fp64"]["value"], 4)
     res["l1_f32state_vs_fp64"] = {"per_variable": [float(f"{x:.3e}") for x in per], "geometric": float(f"{geo:.3e}")}
@@ -358,7 +358,7 @@ def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
     d = p.diagnostics(raise_unphysical=False)
     nup, msup = rep["update"]
     upd_ms = msup / max(nup, 1)
-    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8) * 4 * float(n) ** 3   # as for FP64, 4-byte values
+    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * 4 * float(n) ** 3   # as for FP64, 4-byte values
     out["f32state"] = {"value": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 3), "unit": "Mzone-updates/s",
                        "ms_per_step": round(ms / steps, 3),
                        "sweep_avg_ms": round(rep["sweep"][1] / max(rep["sweep"][0], 1), 4),
@@ -467,8 +467,8 @@ def main():
     nup, msup = rep["update"]
     upd_ms = msup / max(nup, 1)
     # update kernel, algorithmic bytes per zone averaged over the three stages:
-    # reads 21 face values + 8 U^n + 8 previous stage state (stages 1, 2); writes 8 state
-    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8) * 8 * float(n) ** 3
+    # reads 21 face values + 8 U^n + 8 acc (stages 1, 2); writes 8 state + 8 acc (stages 0, 1)
+    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * 8 * float(n) ** 3
     out = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -7,8 +7,8 @@
  * with the eigenvectors of Appendix A at the face, Lax-Friedrichs split; its
  * conservative divergence (eq. num); the CT transport fluxes (eq. fct1-fct6),
  * corner fluxes (eq. ox1-ox3) and the face-field update of Sect. 2.3; a
- * Runge-Kutta stage (SSP-RK3 at CFL 0.4, or the classical RK4 of Sect. 2.1
- * at CFL 0.8); the adjoint (vector-Jacobian products) of the
+ * Runge-Kutta stage in increment form (SSP-RK3 at CFL 0.4, or the classical
+ * RK4 of Sect. 2.1 at CFL 0.8); the adjoint (vector-Jacobian products) of the
  * right-hand side and of a step.
  *
  * Grid: nx * ny * nz zones, periodic in all three directions, one zone size h
@@ -63,7 +63,7 @@ typedef enum {
                                characteristic projections, WENO weights and
                                split fluxes                                   */
   WM_MIXED_F32STATE = 2     /* the WM_MIXED arithmetic with the state (hydro,
-                               bface, bcell), the stage states, the RK4
+                               bface, bcell), the stage states, the RK
                                accumulator and the face fluxes stored in FP32
                                (float arrays); increments and divergences are
                                formed in FP64 before rounding to the state    */
@@ -121,8 +121,8 @@ typedef struct wm_patch wm_patch;   /* opaque; owns no device memory */
 void wm_config_default(wm_config* cfg, int n);
 
 /* Bytes of device scratch a patch with this configuration needs: the stage
- * state, the RK4 accumulator (WM_RK4 only), the face fluxes of the three
- * sweeps and the reduction buffers.  Returns 0 for an invalid configuration. */
+ * state, the RK accumulator, the face fluxes of the three sweeps and the
+ * reduction buffers.  Returns 0 for an invalid configuration. */
 size_t wm_scratch_bytes(const wm_config* cfg);
 
 /* Creates a patch.  `hip_stream` is a hipStream_t (NULL = default stream);
@@ -155,13 +155,11 @@ wm_status wm_refresh_zone_field(wm_patch* p);
  * dt_host is non-NULL the stream is synchronised and dt copied there. */
 wm_status wm_compute_dt(wm_patch* p, double* dt_host);
 
-/* One Runge-Kutta stage, k_s the right-hand side at the stage state (stage 0:
- * the bound state U^n).  WM_SSPRK3, stages 0..2: stage 0 writes
- * U1 = U^n + dt k0 into scratch; stage 1 overwrites it with U2 = U^n + dt/4
- * (k0+k1), formed as U^n + ((U1 - U^n) + dt k1)/4; stage 2 writes U^{n+1} =
- * U^n + dt/6 (k0+k1+4 k2), formed as U^n + 2/3 ((U2 - U^n) + dt k2), into the
- * bound state (no accumulator: equal up to rounding in the state's last bit).
- * WM_RK4, stages 0..3 (Sect. 2.1), in increment form: U1 = U^n + dt/2 k0,
+/* One Runge-Kutta stage in increment form, k_s the right-hand side at the
+ * stage state (stage 0: the bound state U^n).  WM_SSPRK3, stages 0..2:
+ * stage 0 writes k0 and U1 = U^n + dt k0 into scratch; stage 1 writes k0+k1
+ * and U2 = U^n + dt/4 (k0+k1); stage 2 writes U^{n+1} = U^n + dt/6 (k0+k1+4 k2)
+ * into the bound state.  WM_RK4, stages 0..3 (Sect. 2.1): U1 = U^n + dt/2 k0,
  * U2 = U^n + dt/2 k1, U3 = U^n + dt k2 into scratch with the accumulator
  * k0 + 2 k1 + 2 k2, and stage 3 writes U^{n+1} = U^n + dt/6 (k0 + 2 k1 +
  * 2 k2 + k3) into the bound state (the paper's q_save sum).  Each stage ends

@@ -231,8 +231,7 @@ struct UpdateArgs {
   const S* faces;        // [21][N]: F^x[5], F^y[5], F^z[5], T^x[2], T^y[2], T^z[2]
   const S* Un;           // hydro [5][N] of U^n
   const S* bn;           // bface [3][N] of U^n
-  const S* prev;         // [8][N] previous stage state (hydro 5, bface 3): SSP-RK3 stages 1, 2
-  S* acc;                // [8][N] accumulated increments (RK4)
+  S* acc;                // [8][N] accumulated increments
   S* hyd_out;            // hydro [5][N] of the stage result
   S* b_out;              // bface [3][N] of the stage result
   double* rhs_out;       // optional [8][N]: the right-hand side itself (no state update)
@@ -248,13 +247,8 @@ struct TView {
   const S *xy, *xz, *yz, *yx, *zx, *zy;
 };
 
-// RK = 3: SSP-RK3 (Shu-Osher), U1 = U^n + dt k0, U2 = U^n + dt/4 (k0 + k1),
-//   U^{n+1} = U^n + dt/6 (k0 + k1 + 4 k2), with the sums of earlier increments
-//   read off the previous stage state instead of an accumulator: dt k0 = U1 - U^n
-//   and dt (k0 + k1) = 4 (U2 - U^n), so U2 = U^n + ((U1 - U^n) + dt k1)/4 and
-//   U^{n+1} = U^n + 2/3 ((U2 - U^n) + dt k2).  Equal to the increment form up to
-//   rounding (U_s - U^n carries the rounding of U_s, of the order of the state's
-//   own last bit); a uniform state stays bitwise fixed, since U_s - U^n = 0.
+// RK = 3: SSP-RK3 (Shu-Osher) in increment form, acc = k0, k0 + k1;
+//   U1 = U^n + dt k0, U2 = U^n + dt/4 (k0 + k1), U^{n+1} = U^n + dt/6 (k0 + k1 + 4 k2).
 // RK = 4: the classical RK4 of Sect. 2.1 in increment form, acc = k0, k0 + 2 k1,
 //   k0 + 2 k1 + 2 k2; U1 = U^n + dt/2 k0, U2 = U^n + dt/2 k1, U3 = U^n + dt k2,
 //   U^{n+1} = U^n + dt/6 (k0 + 2 k1 + 2 k2 + k3) -- the paper's q_save sum
@@ -326,10 +320,15 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
     double out;
     if constexpr (RK == 3) {
       if constexpr (STAGE == 0) {
+        a.acc[v * N + c0] = S(kv[v]);
         out = un + dt * kv[v];
+      } else if constexpr (STAGE == 1) {
+        const double s = double(a.acc[v * N + c0]) + kv[v];
+        a.acc[v * N + c0] = S(s);
+        out = un + (0.25 * dt) * s;
       } else {
-        const double d = fma(dt, kv[v], double(a.prev[v * N + c0]) - un);
-        out = fma(STAGE == 1 ? 0.25 : 2.0 / 3.0, d, un);
+        const double s = double(a.acc[v * N + c0]) + 4.0 * kv[v];
+        out = un + (dt / 6.0) * s;
       }
     } else {
       if constexpr (STAGE == 0) {

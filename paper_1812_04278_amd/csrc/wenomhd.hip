@@ -45,7 +45,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // scratch layout (bytes, each region 256-aligned), elements of the state's
 // storage type (double, or float for WM_MIXED_F32STATE):
 //   Us    [11][N]  stage state: hydro 5, bface 3, bcell 3
-//   acc   [8][N]   RK4 increment accumulator (absent for SSP-RK3)
+//   acc   [8][N]   RK increment accumulator
 //   faces [21][N]  F^x, F^y, F^z (5 each), T^x, T^y, T^z (2 each)
 //   red            (doubles) dt, 3 signal-speed maxima, reduction partials
 struct Layout {
@@ -87,7 +87,7 @@ Layout layout(const wm_config* c) {
   Layout L;
   size_t off = 0;
   L.us = off;    off = align_up(off + 11 * N * es);
-  L.acc = off;   off = align_up(off + (c->integrator == WM_RK4 ? 8 * N * es : 0));
+  L.acc = off;   off = align_up(off + 8 * N * es);
   L.faces = off; off = align_up(off + 21 * N * es);
   L.red = off;   off = align_up(off + kRedDoubles * sizeof(double));
   L.total = off;
@@ -179,7 +179,7 @@ struct wm_patch {
   Phys ph;
   char* scratch;
   Layout lay;
-  bool f32 = false;          // state, stage states, RK4 accumulator and face values in FP32
+  bool f32 = false;          // state, stage states, accumulator and face values in FP32
   void* hydro = nullptr;     // bound state (storage type: double, or float when f32)
   void* bface = nullptr;
   void* bcell = nullptr;
@@ -298,8 +298,7 @@ wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
   a.faces = p->faces<S>();
   a.Un = p->hyd<S>();
   a.bn = p->bf<S>();
-  a.prev = p->us<S>();   // stages write the stage state in place, zone by zone
-  a.acc = p->cfg.integrator == WM_RK4 ? p->acc<S>() : nullptr;
+  a.acc = p->acc<S>();
   a.rhs_out = rhs_out;
   a.dt = p->dt_dev();
   if (stage == n_stages(p) - 1) {
@@ -433,7 +432,6 @@ wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double
     a.faces = p->faces<double>();
     a.Un = Uh;
     a.bn = Ub;
-    a.prev = st == 0 ? nullptr : outs[st - 1];
     a.acc = acc;
     a.rhs_out = nullptr;
     a.dt = dtp;
@@ -756,9 +754,9 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
     double* dtp = A + adjoint_arrays(&p->cfg) * N;
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
     WM_LAUNCH_CHECK("set dt");
-    // the RK4 accumulator of the forward scratch is free outside wm_step
+    // the stage accumulator of the forward scratch is free outside wm_step
     if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N, rk4 ? A + A_U3 * N : nullptr,
-                            rk4 ? p->acc<double>() : nullptr)) != WM_OK)
+                            p->acc<double>())) != WM_OK)
       return s;
     U1 = A + A_U1 * N;
     U2 = A + A_U2 * N;
