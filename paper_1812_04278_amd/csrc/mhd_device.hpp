@@ -54,6 +54,16 @@ __host__ __device__ __forceinline__ double rcp_w(double x) {
   return 1.0 / x;
 #endif
 }
+// hardware reciprocal without refinement (about 1 ulp), for scale factors
+__host__ __device__ __forceinline__ float rcp_raw(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ double rcp_raw(double x) { return rcp_w(x); }
+
 __host__ __device__ __forceinline__ float rcp_w(float x) {
 #ifdef __HIP_DEVICE_COMPILE__
   float r = __builtin_amdgcn_rcpf(x);
@@ -151,8 +161,9 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps
     T s1 = fma(T(13.0 / 3.0) * t2, t2, fma(t3, t3, e3));
     T s2 = fma(T(13.0 / 3.0) * t4, t4, fma(t5, t5, e3));
     s0 *= s0; s1 *= s1; s2 *= s2;
-    if (sizeof(T) == 4) {   // FP32: normalise so the products cannot overflow
-      const T r = rcp_w(fmax(s0, fmax(s1, s2)));
+    if (sizeof(T) == 4) {   // FP32: normalise so the products cannot overflow; phi is
+      // homogeneous of degree 0 in the s_k, so the scale need not be exact
+      const T r = rcp_raw(fmax(s0, fmax(s1, s2)));
       s0 *= r; s1 *= r; s2 *= r;
     }
     const T p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
