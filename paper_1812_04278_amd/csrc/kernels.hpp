@@ -442,7 +442,7 @@ __global__ __launch_bounds__(RED_THREADS) void speed_partial_kernel(size_t N, do
   for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = mx[d];
   __syncthreads();
   for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = nanmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
     }
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(RED_THREADS) void dt_final_kernel(int nblocks, doub
   for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = mx[d];
   __syncthreads();
   for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = nanmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
     }
