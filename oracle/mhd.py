@@ -484,18 +484,25 @@ def step_rk4(U, cfg: Config, dt: float | None = None):
 # ----------------------------------------------------------------------------
 
 def diagnostics(U, cfg: Config):
-    """max|div_h b|, totals of rho, m, E, face-b sums, min rho, min P and the
-    number of zones with rho <= 0, P <= 0 or a non-finite value."""
+    """max|div_h b| (eq. divb; NaN if any divergence is NaN), totals of rho, m,
+    E, face-b sums, min rho and min P over the zones where they are not NaN
+    (NaN zones are reported by the count instead), and the number of zones with
+    rho <= 0, P <= 0 or a non-finite rho, P or E."""
     rho, v, B, P = primitives(U, cfg.gamma)
     bad = (rho <= 0) | (P <= 0) | ~torch.isfinite(rho) | ~torch.isfinite(P) | ~torch.isfinite(U["E"])
+
+    def nanmin(x):
+        x = x[~torch.isnan(x)]
+        return float(x.min()) if x.numel() else math.inf
+
     return dict(
         max_divb=float(div_faces(U["b"], cfg.h).abs().max()),
         mass=float(U["rho"].sum()),
         mom=[float(U["m"][c].sum()) for c in range(3)],
         energy=float(U["E"].sum()),
         bflux=[float(U["b"][c].sum()) for c in range(3)],
-        min_rho=float(rho.min()),
-        min_p=float(P.min()),
+        min_rho=nanmin(rho),
+        min_p=nanmin(P),
         n_unphysical=int(bad.sum()),
     )
 
