@@ -173,6 +173,25 @@ wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host);
  * stream is synchronised and the dt of the step is returned there. */
 wm_status wm_step(wm_patch* p, double* dt_used);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): wm_step on
+ * the caller's state arrays (hydro, bface, bcell: the layouts above, element
+ * type double, or float for WM_MIXED_F32STATE) without a patch and without
+ * caller scratch.  The step's scratch is a 64 MiB device array inside the
+ * library, one per GPU, created when the library's code is loaded onto that
+ * GPU and held until the process ends; its device address is looked up once
+ * per device, on the first call with that device current.  Configurations
+ * whose wm_scratch_bytes exceeds 64 MiB are rejected with WM_ERR_ARG before
+ * any device work (FP64 up to about 200,000 zones, e.g. 58^3; the FP32 state
+ * up to about 400,000, e.g. 73^3).  No device or host memory is allocated:
+ * only kernels are launched on hip_stream (plus, when dt_used is non-NULL, one
+ * copy of dt to the host and a stream synchronisation).  The step keeps no
+ * state between calls (every scratch value is written before it is read), but
+ * all calls on one GPU share the array: calls that overlap in time on the same
+ * GPU (other streams or host threads) race and give wrong results. */
+wm_status wm_step_static(const wm_config* cfg, void* hip_stream, void* hydro, void* bface, void* bcell,
+                         double* dt_used);
+
 /* Diagnostics of the bound state (synchronises the stream).  Returns
  * WM_ERR_UNPHYSICAL (with *out filled) when n_unphysical > 0. */
 wm_status wm_diagnostics(wm_patch* p, wm_diag* out);

@@ -24,6 +24,7 @@ SYMBOLS = [
     "wm_init_from_potential", "wm_refresh_zone_field", "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics",
     "wm_debug_sweep", "wm_debug_rhs", "wm_adjoint_scratch_bytes", "wm_rhs_vjp", "wm_adjoint_step",
     "wm_step_record", "wm_zone_field_vjp", "wm_init_adjoint", "wm_profile", "wm_profile_report", "wm_last_error",
+    "wm_step_static",
 ]
 KERNEL_CLASSES = ["sweep", "update", "bcell", "dt", "other"]
 
@@ -84,13 +85,14 @@ def load(path: str = LIB_PATH):
     lib.wm_init_adjoint.argtypes = [P, P, P, P, P, D, P, P, P, P]
     lib.wm_profile.argtypes = [P, ctypes.c_int]
     lib.wm_profile_report.argtypes = [P, D, ctypes.c_int]
+    lib.wm_step_static.argtypes = [C, P, P, P, P, D]
     lib.wm_last_error.argtypes = []
     lib.wm_last_error.restype = ctypes.c_char_p
     for name in ("wm_patch_create", "wm_patch_destroy", "wm_bind_state", "wm_init_from_potential",
                  "wm_refresh_zone_field",
                  "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics", "wm_debug_sweep", "wm_debug_rhs",
                  "wm_rhs_vjp", "wm_adjoint_step", "wm_step_record", "wm_zone_field_vjp", "wm_init_adjoint",
-                 "wm_profile", "wm_profile_report"):
+                 "wm_profile", "wm_profile_report", "wm_step_static"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -120,6 +122,22 @@ def config(n=None, nx=None, ny=None, nz=None, h=None, gamma=5.0 / 3.0, cfl=0.4, 
 
 def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def step_static(cfg: WmConfig, hydro: torch.Tensor, bface: torch.Tensor, bcell: torch.Tensor,
+                stream: torch.cuda.Stream | None = None, want_dt: bool = False):
+    """wm_step_static: one step of the given state tensors in place, with the
+    library's static device scratch (no allocation by the library or here).
+    Returns the step's dt when ``want_dt`` (synchronises the stream)."""
+    lib = load()
+    for t in (hydro, bface, bcell):
+        if not t.is_contiguous():
+            raise ValueError("state tensors must be contiguous")
+    s = stream or torch.cuda.current_stream(hydro.device)
+    d = ctypes.c_double() if want_dt else None
+    _check(lib.wm_step_static(ctypes.byref(cfg), ctypes.c_void_p(s.cuda_stream), _ptr(hydro), _ptr(bface),
+                              _ptr(bcell), ctypes.byref(d) if want_dt else None))
+    return d.value if want_dt else None
 
 
 def _on_stream(fn):

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,6 +16,14 @@
 #include "adjoint_kernels.hpp"
 
 using namespace wm;
+
+// Device scratch of wm_step_static, for callers that cannot allocate: one copy
+// of this array per GPU the library runs on, held until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -453,6 +462,48 @@ wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double
   return WM_OK;
 }
 
+// Fields of a patch for a valid configuration, its stream and its scratch.
+void setup_patch(wm_patch* p, const wm_config* cfg, void* hip_stream, void* scratch_buf, const Layout& L) {
+  p->cfg = *cfg;
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  p->g.nx = cfg->nx; p->g.ny = cfg->ny; p->g.nz = cfg->nz;
+  p->g.N = (size_t)cfg->nx * cfg->ny * cfg->nz;
+  p->ph.gamma = cfg->gamma;
+  p->ph.inv_h = 1.0 / cfg->h;
+  p->ph.eps = cfg->eps_weno;
+  p->ph.eps_B = cfg->eps_B;
+  p->ph.eps_Z = cfg->eps_Z;
+  p->ph.weno_z = cfg->weights == WM_WENO_Z ? 1 : (cfg->weights == WM_WENO_Z_PRINTED ? 2 : 0);
+  p->ph.g1 = 0.5 * (cfg->gamma - 1.0);
+  p->ph.g2 = (cfg->gamma - 2.0) / (cfg->gamma - 1.0);
+  p->scratch = reinterpret_cast<char*>(scratch_buf);
+  p->lay = L;
+  p->f32 = cfg->precision == WM_MIXED_F32STATE;
+}
+
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+wm_status static_scratch_address(void** out) {
+  int dev = -1;
+  wm_status s = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (s != WM_OK) return s;
+  if (dev < 0 || dev >= kMaxDevices) return fail(WM_ERR_ARG, "device index beyond the static scratch table%s");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    if ((s = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) != WM_OK)
+      return s;
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign) return fail(WM_ERR_HIP, "static scratch address invalid%s");
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
+  return WM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -477,33 +528,19 @@ size_t wm_scratch_bytes(const wm_config* cfg) {
   return layout(cfg).total;
 }
 
-wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch, size_t scratch_bytes,
+wm_status wm_patch_create(const wm_config* cfg, void* hip_stream, void* scratch_buf, size_t scratch_bytes,
                           wm_patch** out) {
   const char* why = "";
   if (!out) return fail(WM_ERR_ARG, "null output pointer");
   *out = nullptr;
   if (!valid_config(cfg, &why)) return fail(WM_ERR_ARG, "invalid config: %s", why);
   const Layout L = layout(cfg);
-  if (!scratch) return fail(WM_ERR_ARG, "null scratch");
-  if (reinterpret_cast<uintptr_t>(scratch) % kAlign) return fail(WM_ERR_ARG, "scratch not 256-byte aligned");
+  if (!scratch_buf) return fail(WM_ERR_ARG, "null scratch");
+  if (reinterpret_cast<uintptr_t>(scratch_buf) % kAlign) return fail(WM_ERR_ARG, "scratch not 256-byte aligned");
   if (scratch_bytes < L.total) return fail(WM_ERR_ARG, "scratch smaller than wm_scratch_bytes");
   wm_patch* p = new (std::nothrow) wm_patch;
   if (!p) return fail(WM_ERR_ARG, "host allocation failed");
-  p->cfg = *cfg;
-  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  p->g.nx = cfg->nx; p->g.ny = cfg->ny; p->g.nz = cfg->nz;
-  p->g.N = (size_t)cfg->nx * cfg->ny * cfg->nz;
-  p->ph.gamma = cfg->gamma;
-  p->ph.inv_h = 1.0 / cfg->h;
-  p->ph.eps = cfg->eps_weno;
-  p->ph.eps_B = cfg->eps_B;
-  p->ph.eps_Z = cfg->eps_Z;
-  p->ph.weno_z = cfg->weights == WM_WENO_Z ? 1 : (cfg->weights == WM_WENO_Z_PRINTED ? 2 : 0);
-  p->ph.g1 = 0.5 * (cfg->gamma - 1.0);
-  p->ph.g2 = (cfg->gamma - 2.0) / (cfg->gamma - 1.0);
-  p->scratch = reinterpret_cast<char*>(scratch);
-  p->lay = L;
-  p->f32 = cfg->precision == WM_MIXED_F32STATE;
+  setup_patch(p, cfg, hip_stream, scratch_buf, L);
   if (cfg->nx >= 3 && cfg->ny >= 3 && cfg->nz >= 3) {
     const int n3[3] = {cfg->nx, cfg->ny, cfg->nz};
     const int ta[3] = {AdjTile<0>::TA, AdjTile<1>::TA, AdjTile<2>::TA};
@@ -648,6 +685,32 @@ wm_status wm_step(wm_patch* p, double* dt_used) {
   if (dt_used) {
     if ((s = hip_check(hipStreamSynchronize(p->stream), "step sync")) != WM_OK) return s;
   }
+  return WM_OK;
+}
+
+wm_status wm_step_static(const wm_config* cfg, void* hip_stream, void* hydro, void* bface, void* bcell,
+                         double* dt_used) {
+  const char* why = "";
+  if (!valid_config(cfg, &why)) return fail(WM_ERR_ARG, "invalid config: %s", why);
+  if (!hydro || !bface || !bcell) return fail(WM_ERR_ARG, "null state pointer");
+  const Layout L = layout(cfg);
+  if (L.total > kStaticScratchBytes) {
+    std::snprintf(g_err, sizeof(g_err),
+                  "wm_step_static: this configuration needs %zu bytes of scratch, above the static maximum of %zu "
+                  "bytes (64 MiB); use wm_patch_create with caller-owned scratch",
+                  L.total, kStaticScratchBytes);
+    return WM_ERR_ARG;
+  }
+  void* ptr = nullptr;
+  wm_status s = static_scratch_address(&ptr);
+  if (s != WM_OK) return s;
+  wm_patch p;   // on the stack: profiling stays off, so its event lists stay empty
+  setup_patch(&p, cfg, hip_stream, ptr, L);
+  p.hydro = hydro;
+  p.bface = bface;
+  p.bcell = bcell;
+  if ((s = wm_step(&p, dt_used)) != WM_OK) return s;
+  g_err[0] = 0;
   return WM_OK;
 }
 
