@@ -22,12 +22,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mzone-updates/s per RK3 step, FP64 vs mixed at stated L1 err; adjoint/fwd cost"
 
-# Algorithmic work of one sweep per face (FP64 flops: add/sub/mul 1, fma 2,
-# div 1, sqrt 1), the difference form of eq. (FWENO) as the sweep kernel
-# computes it: differences 70, central term 42, face state 16, eigen scalars
-# ~75, fast and slow pairs ~550 each, Alfven ~390, entropy ~280, and the zone
-# prologue ~70 per zone.
-FLOPS_PER_FACE = 2060
+# Algorithmic work of one sweep per face (FP64 flops): the survey's count for
+# the characteristic WENO5 flux of a face, ~2,100 (eigen-system 240, ten 7x7
+# projections 980, split 140, 14 phi_N 560, central term and back-projection
+# 130, transport flux 8), plus ~70 for the zone prologue (primitives, flux,
+# eigenvalues) of the face's zone.
+FLOPS_PER_FACE = 2170
 # Algorithmic HBM bytes of the update kernel per zone (FP64): reads 15 face
 # fluxes, 6 transport fluxes, U^n (8) and the accumulator (8, stages 1-2);
 # writes the stage state (8) and the accumulator (8, stages 0-1).
@@ -43,22 +43,60 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n: int, steps: int):
-    """The oracle as it stands, on the host cores: `steps` SSP-RK3 steps of the
-    same generator sampled at n^3 (the 256^3 workload's per-zone work)."""
+def host_cpu():
+    """CPU model and logical CPU count of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(threads: int | None = None):
+    """The oracle as it stands, timed on the host cores on the survey's samples
+    of the workloads: C1 (32^3 Mach 0.1, one SSP-RK3 step) and the C2 crop (the
+    Mach-2 generator sampled at 64^3, ten steps), with all the threads torch
+    uses; then C1 and one 64^3 Mach-2 step on a single thread.  `value` is the
+    C2-crop rate (the Mach-2 workload's per-zone work)."""
     import torch
     from oracle import mhd
     from paper_1812_04278_amd import inputs
-    f = inputs.random_fields(n, seed=1, v_rms=2.0, kmax=4)
-    cfg = mhd.cubic(n)
-    U = mhd.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0, cfg)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        U, _ = mhd.step(U, cfg)
-    el = time.perf_counter() - t0
-    return dict(value=round(n ** 3 * steps / el / 1e6, 6), unit="Mzone-updates/s", cores=torch.get_num_threads(),
-                kind="oracle", sample=f"{steps} step(s) of the Mach-2 generator at {n}^3 (seed 1), "
-                                      f"{el:.1f} s on the host", seconds=round(el, 3))
+
+    def run(n, steps, v_rms):
+        f = inputs.random_fields(n, seed=1, v_rms=v_rms, kmax=4)
+        cfg = mhd.cubic(n)
+        U = mhd.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0, cfg)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            U, _ = mhd.step(U, cfg)
+        el = time.perf_counter() - t0
+        return {"sample": f"{n}^3 x {steps} step(s), Mach {v_rms:g}", "seconds": round(el, 3),
+                "value": round(n ** 3 * steps / el / 1e6, 6)}
+
+    model, nproc = host_cpu()
+    saved = torch.get_num_threads()
+    if threads:
+        torch.set_num_threads(threads)
+    nthr = torch.get_num_threads()
+    c1 = run(32, 1, 0.1)
+    c2 = run(64, 10, 2.0)
+    torch.set_num_threads(1)
+    try:
+        c1_1 = run(32, 1, 0.1)
+        c2_1 = run(64, 1, 2.0)
+    finally:
+        torch.set_num_threads(saved)
+    return dict(value=c2["value"], unit="Mzone-updates/s", cores=nthr, kind="oracle",
+                sample=f"C2 crop: the Mach-2 generator sampled at 64^3 (seed 1), 10 SSP-RK3 steps, "
+                       f"{c2['seconds']:.1f} s on {nthr} threads",
+                host={"cpu_model": model, "nproc": nproc, "threads_used": nthr},
+                samples={"c1_32x1": c1, "c2crop_64x10": c2},
+                single_thread={"c1_32x1": c1_1, "c2crop_64x1": c2_1})
 
 
 def l1_per_variable(a: dict, b: dict):
@@ -329,24 +367,23 @@ def adjoint_cost(n: int = 128, steps: int = 20, ckpt: int = 5):
 
 
 def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
-    """The 512^3 workload: Mach 5 (v_rms 5, |k| <= 8), beta 0.5.  Throughput of
-    the FP32-state mixed form (WM_MIXED_F32STATE) over `steps` steps with the
-    update kernel's HBM rate, then the checkpointed FP64 adjoint of the same
-    steps (stage states recomputed: memory) and its cost ratio to the FP64
-    forward.  A checkpoint every 2 steps holds the same number of states as one
-    every 5 (5 checkpoints + 2 segment states against 2 + 5, 8.6 GB each) and
-    re-runs 5 steps in the backward instead of 8."""
+    """The 512^3 workload: Mach 5 (v_rms 5, |k| <= 8), beta 0.5, the mixed form
+    with an FP32 state (WM_MIXED_F32STATE), forward and adjoint in one run:
+    throughput of `steps` steps with the update kernel's HBM rate, then the same
+    steps as a checkpointed rollout (a checkpoint every `ckpt` steps, FP32) and
+    its backward (the FP64 adjoint at the widened FP32 states, stage states
+    recomputed by the FP32-state forward), timed against the plain forward.
+    Inputs are generated on the GPU (same recipe and draws as the host
+    generator)."""
     import math
     import torch
     from paper_1812_04278_amd import binding, inputs, rollout
     B0 = tuple(math.sqrt(2.4 / 1.25) * x for x in (1.0, 0.5, 0.0))
-    log(f"bench c5: generating {n}^3 inputs")
-    f = inputs.random_fields(n, seed=1, v_rms=5.0, kmax=8, B0=B0)
-    out = {"workload": f"{n}^3 periodic box, Mach 5, |k| <= 8, beta 0.5, {steps} SSP-RK3 steps"}
-    rho = torch.as_tensor(f.rho).to("cuda:0")
-    v0 = torch.as_tensor(f.v).to("cuda:0")
-    A0 = torch.as_tensor(f.A).to("cuda:0")
-    del f.rho, f.v, f.A
+    log(f"bench c5: generating {n}^3 inputs on the GPU")
+    f = inputs.random_fields(n, seed=1, v_rms=5.0, kmax=8, B0=B0, device="cuda:0")
+    rho, v0, A0 = f.rho, f.v, f.A
+    out = {"workload": f"{n}^3 periodic box, Mach 5, |k| <= 8, beta 0.5, {steps} SSP-RK3 steps, FP32 state "
+                       f"(mixed arithmetic), adjoint in FP64 at the widened states"}
     p = binding.Patch(binding.config(n, precision=binding.WM_MIXED_F32STATE), device="cuda:0")
     p.init_from_potential(rho, v0, A0, 0.6, B0)
     p.step()
@@ -366,32 +403,27 @@ def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
                        "update_hbm_gbs": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1),
                        "update_hbm_frac": round(upd_bytes / (upd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                        "max_divb": d["max_divb"], "n_unphysical": d["n_unphysical"], "min_p": d["min_p"]}
-    del p
-    torch.cuda.empty_cache()
-    log("bench c5: FP64 forward and checkpointed adjoint")
-    p = binding.Patch(binding.config(n), device="cuda:0")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p.init_from_potential(rho, v0, A0, 0.6, B0)
-    for _ in range(steps):
-        p.step()
-    torch.cuda.synchronize()
-    fwd = (time.perf_counter() - t0) * 1e3
+    log("bench c5: checkpointed FP32-state rollout and its adjoint")
     A = A0.clone().requires_grad_(True)
     v = v0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     hyd, bf, bc = rollout.rollout(A, v, rho, p, steps, ckpt_every=ckpt, P0=0.6, B0=B0, store_stages=False)
-    J = (1.0 / n) ** 3 * ((hyd[0] - 1.0) ** 2).sum()
+    J = (1.0 / n) ** 3 * ((hyd[0].double() - 1.0) ** 2).sum()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     gA, gv = torch.autograd.grad(J, [A, v])
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    out["adjoint_fp64"] = {"forward_ms": round(fwd, 1), "checkpointed_forward_ms": round((t2 - t1) * 1e3, 1),
-                           "backward_ms": round((t3 - t2) * 1e3, 1),
-                           "ratio_backward_to_forward": round((t3 - t2) * 1e3 / fwd, 3),
-                           "loss": "h^3 sum (rho_T - 1)^2", "stage_states": "recomputed", "ckpt_every": ckpt,
-                           "grad_finite": bool(torch.isfinite(gA).all() and torch.isfinite(gv).all())}
+    ck_ms, bwd_ms = (t2 - t1) * 1e3, (t3 - t2) * 1e3
+    out["adjoint"] = {"forward_ms": round(ms, 1), "checkpointed_forward_ms": round(ck_ms, 1),
+                      "backward_ms": round(bwd_ms, 1), "ratio_backward_to_forward": round(bwd_ms / ms, 3),
+                      "ratio_total_to_forward": round((ck_ms + bwd_ms) / ms, 3),
+                      "loss": "h^3 sum (rho_T - 1)^2", "stage_states": "recomputed", "ckpt_every": ckpt,
+                      "grad_finite": bool(torch.isfinite(gA).all() and torch.isfinite(gv).all()),
+                      "peak_gib": round(torch.cuda.max_memory_allocated() / 2 ** 30, 1)}
+    del p, gA, gv, A, v, hyd, bf, bc, J
+    torch.cuda.empty_cache()
     return out
 
 
@@ -401,8 +433,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--cpu-n", type=int, default=80)
-    ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: torch's default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP64-vs-mixed comparison")
     ap.add_argument("--no-convergence", action="store_true", help="skip the fast-wave convergence table")
@@ -412,8 +443,8 @@ def main():
     ap.add_argument("--wave-sizes", default="16,32,64", help="N of the 2N x N x N wave boxes")
     ap.add_argument("--wave-weights", default="z", choices=("z", "z_printed", "js"),
                     help="WENO weights of the wave suite: WENO-Z (reading), WENO-Z as printed, Jiang-Shu")
-    ap.add_argument("--c5", action="store_true",
-                    help="also run the 512^3 Mach-5 workload (FP32 state, FP64 adjoint); several minutes")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 512^3 Mach-5 workload (FP32-state forward and its adjoint)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -512,7 +543,8 @@ def main():
     if not args.no_adjoint:
         log("bench: adjoint cost (128^3, 20 steps, checkpoints every 5)")
         out["adjoint"] = adjoint_cost()
-    if args.c5:
+    if not args.no_c5:
+        log("bench: 512^3 Mach-5 workload, FP32 state, forward and adjoint")
         out["c5"] = c5()
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written, for scaling
@@ -524,8 +556,8 @@ def main():
         out["copy_calibration_bytes"] = src.numel() * 8
         del src, dst
     if not args.no_cpu_baseline:
-        log(f"bench: cpu baseline (oracle, {args.cpu_steps} step(s) at {args.cpu_n}^3)")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
+        log("bench: cpu baseline (oracle: 32^3 x 1 and 64^3 x 10 on all threads, then one thread)")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_threads or None)
     print(json.dumps(out), flush=True)
 
 

@@ -225,7 +225,10 @@ wm_status wm_debug_rhs(wm_patch* p, void* out);
  * (Jiang-Shu or WENO-Z) and integrator (grid sizes below 3: WM_ERR_ARG).  On a
  * mixed-precision patch they give the FP64 linearisation at the states passed
  * in (stage states recomputed by the adjoint itself come from the patch's own
- * precision). */
+ * precision).  On a WM_MIXED_F32STATE patch the state arguments (U^n, the
+ * stage states, the state of wm_rhs_vjp) are float arrays like the patch's
+ * state: they are widened to FP64 on load, and the FP64 method is linearised
+ * at the widened states; cotangents are double arrays in every mode. */
 size_t wm_adjoint_scratch_bytes(const wm_config* cfg);
 
 /* lam_out = (dL/dU)^T lam_k for the semi-discrete right-hand side L of the
@@ -241,7 +244,9 @@ wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const vo
  * the step's two intermediate stage states as wm_step_record stores them
  * ([8][..]: hydro then face b), or both NULL to recompute them from U^n into
  * adj_scratch.  WM_RK4 (Sect. 2.1): both must be NULL (the three stage states
- * are recomputed; WM_ERR_ARG otherwise). */
+ * are recomputed; WM_ERR_ARG otherwise).  Recomputing them uses the forward
+ * scratch of the patch: with NULL stage states the call returns WM_ERR_STATE
+ * while a step of wm_rk_stage is in progress. */
 wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface,
                           const void* U1_stage, const void* U2_stage, double dt, void* lam_hydro, void* lam_bface);
 

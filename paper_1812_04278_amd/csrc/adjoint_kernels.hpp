@@ -419,6 +419,11 @@ __global__ __launch_bounds__(256) void fill_kernel(size_t n, double v, double* y
   const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (c < n) y[c] = v;
 }
+// y = x widened from float (n values): FP32 states enter the FP64 adjoint
+__global__ __launch_bounds__(256) void widen_kernel(size_t n, const float* x, double* y) {
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < n) y[c] = double(x[c]);
+}
 
 // The RK3 stage combinations of the adjoint step over the 8N cotangent
 // entries (hydro [5][N] then face b [3][N]; lam3 split over lh, lb):

@@ -171,8 +171,16 @@ TilePlan plan_tiles(int n, int TA) {
   return pl;
 }
 
-// arrays of N doubles in the adjoint scratch (the dt scalar follows them)
-int adjoint_arrays(const wm_config* c) { return c->integrator == WM_RK4 ? A_NARR4 : A_NARR; }
+// arrays of N doubles in the adjoint scratch (the dt scalar follows them).  A
+// patch with an FP32 state adds, after the arrays above, U^n widened to FP64
+// (8) and room for the FP32 stage states the adjoint recomputes ([11][N]
+// floats each: 11 arrays for SSP-RK3's two, 17 for RK4's three).
+int adjoint_base_arrays(const wm_config* c) { return c->integrator == WM_RK4 ? A_NARR4 : A_NARR; }
+int adjoint_arrays(const wm_config* c) {
+  int n = adjoint_base_arrays(c);
+  if (c->precision == WM_MIXED_F32STATE) n += 8 + (c->integrator == WM_RK4 ? 17 : 11);
+  return n;
+}
 
 size_t adjoint_bytes(const wm_config* c) {
   const size_t N = (size_t)c->nx * c->ny * c->nz;
@@ -394,7 +402,6 @@ wm_status check_adjoint(wm_patch* p, void* adj) {
   if (!p) return fail(WM_ERR_ARG, "null patch");
   if (!adj || reinterpret_cast<uintptr_t>(adj) % kAlign) return fail(WM_ERR_ARG, "adjoint scratch null or misaligned");
   if (p->cfg.nx < 3 || p->cfg.ny < 3 || p->cfg.nz < 3) return fail(WM_ERR_ARG, "the adjoint needs grid sizes >= 3");
-  if (p->f32) return fail(WM_ERR_ARG, "the adjoint needs an FP64 state (not WM_MIXED_F32STATE)");
   return WM_OK;
 }
 
@@ -421,44 +428,64 @@ wm_status rhs_vjp_acc(wm_patch* p, double* A, const double* hydro, const double*
   return WM_OK;
 }
 
-// forward stages U1, U2 from U^n with the dt in *dtp (device); U1, U2 = [hydro 5, b 3, bcell 3]
 // The intermediate stage states of one step from U^n (SSP-RK3: U1, U2; RK4:
-// U1, U2, U3), each [11][N] (hydro, face b, zone B), with the given device dt.
-wm_status forward_stages(wm_patch* p, const double* Uh, const double* Ub, double* Bz, const double* dtp, double* U1,
-                         double* U2, double* U3, double* acc) {
+// U1, U2, U3), each [11][N] (hydro, face b, zone B) in the storage type S of
+// the patch's forward, with the given device dt.
+template <typename S>
+wm_status forward_stages(wm_patch* p, const S* Uh, const S* Ub, S* Bz, const double* dtp, S* U1, S* U2, S* U3,
+                         S* acc) {
   const size_t N = p->g.N;
   const bool rk4 = p->cfg.integrator == WM_RK4;
-  double* outs[3] = {U1, U2, U3};
+  S* outs[3] = {U1, U2, U3};
   wm_status s;
-  if ((s = launch_bcell<double>(p, Ub, Bz)) != WM_OK) return s;
+  if ((s = launch_bcell<S>(p, Ub, Bz)) != WM_OK) return s;
   for (int st = 0; st < (rk4 ? 3 : 2); ++st) {
-    const double* hin = st == 0 ? Uh : outs[st - 1];
-    const double* bcin = st == 0 ? Bz : outs[st - 1] + 8 * N;
-    if ((s = sweeps<double>(p, hin, bcin)) != WM_OK) return s;
-    UpdateArgs<double> a;
+    const S* hin = st == 0 ? Uh : outs[st - 1];
+    const S* bcin = st == 0 ? Bz : outs[st - 1] + 8 * N;
+    if ((s = sweeps<S>(p, hin, bcin)) != WM_OK) return s;
+    UpdateArgs<S> a;
     a.g = p->g;
     a.inv_h = 1.0 / p->cfg.h;
-    a.faces = p->faces<double>();
+    a.faces = p->faces<S>();
     a.Un = Uh;
     a.bn = Ub;
     a.acc = acc;
     a.rhs_out = nullptr;
     a.dt = dtp;
-    double* out = outs[st];
+    S* out = outs[st];
     a.hyd_out = out;
     a.b_out = out + 5 * N;
     const dim3 grid = zone_grid(p->g);
     if (rk4) {
-      if (st == 0) hipLaunchKernelGGL((update_kernel<4, 0, double>), grid, dim3(256), 0, p->stream, a);
-      else if (st == 1) hipLaunchKernelGGL((update_kernel<4, 1, double>), grid, dim3(256), 0, p->stream, a);
-      else hipLaunchKernelGGL((update_kernel<4, 2, double>), grid, dim3(256), 0, p->stream, a);
+      if (st == 0) hipLaunchKernelGGL((update_kernel<4, 0, S>), grid, dim3(256), 0, p->stream, a);
+      else if (st == 1) hipLaunchKernelGGL((update_kernel<4, 1, S>), grid, dim3(256), 0, p->stream, a);
+      else hipLaunchKernelGGL((update_kernel<4, 2, S>), grid, dim3(256), 0, p->stream, a);
     } else {
-      if (st == 0) hipLaunchKernelGGL((update_kernel<3, 0, double>), grid, dim3(256), 0, p->stream, a);
-      else hipLaunchKernelGGL((update_kernel<3, 1, double>), grid, dim3(256), 0, p->stream, a);
+      if (st == 0) hipLaunchKernelGGL((update_kernel<3, 0, S>), grid, dim3(256), 0, p->stream, a);
+      else hipLaunchKernelGGL((update_kernel<3, 1, S>), grid, dim3(256), 0, p->stream, a);
     }
     WM_LAUNCH_CHECK("update kernel");
-    if ((s = launch_bcell<double>(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
+    if ((s = launch_bcell<S>(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
   }
+  return WM_OK;
+}
+
+wm_status widen(wm_patch* p, const void* x, size_t n, double* y) {
+  hipLaunchKernelGGL(widen_kernel, lin_grid(n), dim3(256), 0, p->stream, n, reinterpret_cast<const float*>(x), y);
+  WM_LAUNCH_CHECK("widen kernel");
+  return WM_OK;
+}
+
+// U^n of an FP32-state patch widened into the adjoint scratch: (hydro, face b)
+wm_status widen_state(wm_patch* p, double* A, const void* hydro, const void* bface, const double** Uh,
+                      const double** Ub) {
+  const size_t N = p->g.N;
+  double* W = A + adjoint_base_arrays(&p->cfg) * N;
+  wm_status s;
+  if ((s = widen(p, hydro, 5 * N, W)) != WM_OK) return s;
+  if ((s = widen(p, bface, 3 * N, W + 5 * N)) != WM_OK) return s;
+  *Uh = W;
+  *Ub = W + 5 * N;
   return WM_OK;
 }
 
@@ -787,12 +814,14 @@ wm_status wm_rhs_vjp(wm_patch* p, void* adj_scratch, const void* hydro, const vo
   if (s != WM_OK) return s;
   if (!hydro || !bface || !lam_k || !lam_out) return fail(WM_ERR_ARG, "null pointer");
   const size_t N = p->g.N;
+  double* A = reinterpret_cast<double*>(adj_scratch);
+  const double* Uh = reinterpret_cast<const double*>(hydro);
+  const double* Ub = reinterpret_cast<const double*>(bface);
+  if (p->f32 && (s = widen_state(p, A, hydro, bface, &Uh, &Ub)) != WM_OK) return s;
   double* out = reinterpret_cast<double*>(lam_out);
   hipLaunchKernelGGL(fill_kernel, lin_grid(8 * N), dim3(256), 0, p->stream, 8 * N, 0.0, out);
   WM_LAUNCH_CHECK("fill kernel");
-  return rhs_vjp_acc(p, reinterpret_cast<double*>(adj_scratch), reinterpret_cast<const double*>(hydro),
-                     reinterpret_cast<const double*>(bface), reinterpret_cast<const double*>(lam_k), out,
-                     out + 5 * N);
+  return rhs_vjp_acc(p, A, Uh, Ub, reinterpret_cast<const double*>(lam_k), out, out + 5 * N);
 }
 
 wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, const void* Un_bface,
@@ -813,13 +842,42 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
   const double* U1 = reinterpret_cast<const double*>(U1_stage);
   const double* U2 = reinterpret_cast<const double*>(U2_stage);
   const double* U3 = nullptr;
-  if (!U1) {   // recompute the stage states from U^n
+  if (!U1 && p->stage_done >= 0)
+    return fail(WM_ERR_STATE, "a step is in progress (wm_rk_stage): recomputing the stage states would overwrite "
+                              "its scratch%s");
+  if (p->f32) {
+    // FP32 state: U^n and the stage states are widened to FP64 and the FP64
+    // method is linearised there; missing stage states come from the FP32-state
+    // forward (the forward scratch's stage state and accumulator are free
+    // outside a step)
+    if ((s = widen_state(p, A, Un_hydro, Un_bface, &Uh, &Ub)) != WM_OK) return s;
+    double* base = A + adjoint_base_arrays(&p->cfg) * N;
+    if (U1) {
+      if ((s = widen(p, U1_stage, 8 * N, A + A_U1 * N)) != WM_OK) return s;
+      if ((s = widen(p, U2_stage, 8 * N, A + A_U2 * N)) != WM_OK) return s;
+    } else {
+      double* dtp = A + adjoint_arrays(&p->cfg) * N;
+      hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
+      WM_LAUNCH_CHECK("set dt");
+      float* F = reinterpret_cast<float*>(base + 8 * N);
+      if ((s = forward_stages<float>(p, reinterpret_cast<const float*>(Un_hydro),
+                                     reinterpret_cast<const float*>(Un_bface), p->us<float>() + 8 * N, dtp, F,
+                                     F + 11 * N, rk4 ? F + 22 * N : nullptr, p->acc<float>())) != WM_OK)
+        return s;
+      if ((s = widen(p, F, 8 * N, A + A_U1 * N)) != WM_OK) return s;
+      if ((s = widen(p, F + 11 * N, 8 * N, A + A_U2 * N)) != WM_OK) return s;
+      if (rk4 && (s = widen(p, F + 22 * N, 8 * N, A + A_U3 * N)) != WM_OK) return s;
+    }
+    U1 = A + A_U1 * N;
+    U2 = A + A_U2 * N;
+    U3 = A + A_U3 * N;
+  } else if (!U1) {   // recompute the stage states from U^n
     double* dtp = A + adjoint_arrays(&p->cfg) * N;
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, dtp, dt);
     WM_LAUNCH_CHECK("set dt");
     // the stage accumulator of the forward scratch is free outside wm_step
-    if ((s = forward_stages(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N, rk4 ? A + A_U3 * N : nullptr,
-                            p->acc<double>())) != WM_OK)
+    if ((s = forward_stages<double>(p, Uh, Ub, A + A_BZ * N, dtp, A + A_U1 * N, A + A_U2 * N,
+                                    rk4 ? A + A_U3 * N : nullptr, p->acc<double>())) != WM_OK)
       return s;
     U1 = A + A_U1 * N;
     U2 = A + A_U2 * N;

@@ -82,9 +82,37 @@ def _evaluate(n: int, ks: np.ndarray, a: np.ndarray, c: np.ndarray, offset) -> n
     return np.real(np.fft.ifftn(grid) * (n ** 3))
 
 
-def random_fields(n: int, seed: int, v_rms: float, kmax: int = 4, b_rms: float = 0.1,
-                  B0=(1.0, 0.5, 0.0), P0: float = 0.6, gamma: float = 5.0 / 3.0) -> Fields:
-    """Seeded random initial fields on an n^3 unit box (recipe in the module doc)."""
+def _evaluate_device(n: int, ks: np.ndarray, a: np.ndarray, c: np.ndarray, offset, device):
+    """:func:`_evaluate` with the inverse FFT on a torch device (same sums, another
+    FFT: the values agree to rounding).  Returns a float64 tensor [nz, ny, nx]."""
+    import torch
+    if 2 * int(np.abs(ks).max()) >= n:
+        raise ValueError(f"grid n={n} too small for modes up to |k_i|={np.abs(ks).max()}")
+    ox, oy, oz = offset
+    phase = np.exp(2j * np.pi * (ks[:, 0] * ox + ks[:, 1] * oy + ks[:, 2] * oz) / n)
+    coef = torch.as_tensor((a - 1j * c) * phase, dtype=torch.complex128, device=device)
+    idx = torch.as_tensor(((ks[:, 2] % n) * n + (ks[:, 1] % n)) * n + (ks[:, 0] % n), device=device)
+    grid = torch.zeros(n * n * n, dtype=torch.complex128, device=device)
+    grid.index_add_(0, idx, coef)
+    out = torch.fft.ifftn(grid.view(n, n, n)).real * float(n ** 3)
+    del grid
+    return out.contiguous()
+
+
+# positions of the velocity (zone centres) and of the potential components
+# (edges) in units of the zone size
+V_OFFSET = (0.5, 0.5, 0.5)
+EDGE_OFFSETS = [(0.5, 1.0, 1.0), (1.0, 0.5, 1.0), (1.0, 1.0, 0.5)]
+
+
+def fourier_modes(seed: int, v_rms: float, kmax: int = 4, b_rms: float = 0.1) -> dict:
+    """The draws of :func:`random_fields` and the Fourier amplitudes it evaluates:
+    ``kset`` (the mode set K(kmax), [M, 3] as (kx, ky, kz)), and the amplitudes
+    of v and A, ``a_v``, ``c_v``, ``a_A``, ``c_A`` ([M, 3]: component d of the
+    field is sum_k a[k, d] cos(2 pi k.x) + c[k, d] sin(2 pi k.x)), already scaled
+    to the rms values; plus the density's ``kset_rho``, mode indices ``idx`` and
+    phases ``phi``.  These amplitudes are the velocity and potential Fourier
+    fields of the adjoint workload's control."""
     rng = np.random.Generator(np.random.PCG64(seed))
     kset_rho = mode_set(min(kmax, 4))
     kset = mode_set(kmax)
@@ -94,25 +122,47 @@ def random_fields(n: int, seed: int, v_rms: float, kmax: int = 4, b_rms: float =
     cv = rng.standard_normal((len(kset), 3))
     aA = rng.standard_normal((len(kset), 3))
     cA = rng.standard_normal((len(kset), 3))
-
-    # density: 0.1 sin(theta + phi) = 0.1 (sin phi) cos theta + 0.1 (cos phi) sin theta
-    ks_r = kset_rho[idx]
-    rho = 1.0 + _evaluate(n, ks_r, 0.1 * np.sin(phi), 0.1 * np.cos(phi), (0.5, 0.5, 0.5))
-
     # velocity: grid mean of |v|^2 is 1/2 sum_k (|a_k|^2 + |c_k|^2) (no aliasing for n > 2 kmax)
     msq = 0.5 * float(np.sum(av ** 2) + np.sum(cv ** 2))
     sv = v_rms / np.sqrt(msq) if v_rms > 0 else 0.0
-    v = np.stack([_evaluate(n, kset, sv * av[:, d], sv * cv[:, d], (0.5, 0.5, 0.5))
-                  for d in range(3)])
-
     # potential: continuous curl of a cos(2 pi k.x) is -2 pi (k x a) sin(...), so
     # mean |curl A|^2 = 1/2 (2 pi)^2 sum_k (|k x a_k|^2 + |k x c_k|^2)
     kf = kset.astype(np.float64)
     cm = 0.5 * (2 * np.pi) ** 2 * float(np.sum(np.cross(kf, aA) ** 2) + np.sum(np.cross(kf, cA) ** 2))
     sA = b_rms / np.sqrt(cm) if b_rms > 0 else 0.0
-    edge_offsets = [(0.5, 1.0, 1.0), (1.0, 0.5, 1.0), (1.0, 1.0, 0.5)]
-    A = np.stack([_evaluate(n, kset, sA * aA[:, d], sA * cA[:, d], edge_offsets[d])
-                  for d in range(3)])
+    return dict(kset_rho=kset_rho, idx=idx, phi=phi, kset=kset, a_v=sv * av, c_v=sv * cv, a_A=sA * aA, c_A=sA * cA)
+
+
+def evaluate_modes(n: int, ks: np.ndarray, a: np.ndarray, c: np.ndarray, offset) -> np.ndarray:
+    """sum_k a_k cos(2 pi k.x) + c_k sin(2 pi k.x) on an n^3 grid at x = (idx +
+    offset)/n (scalar amplitudes a, c of shape [M])."""
+    return _evaluate(n, ks, a, c, offset)
+
+
+def random_fields(n: int, seed: int, v_rms: float, kmax: int = 4, b_rms: float = 0.1,
+                  B0=(1.0, 0.5, 0.0), P0: float = 0.6, gamma: float = 5.0 / 3.0, device=None) -> Fields:
+    """Seeded random initial fields on an n^3 unit box (recipe in the module doc).
+    With ``device`` (a torch device) the Fourier sums are evaluated there and the
+    fields are float64 torch tensors on it (for large boxes)."""
+    m = fourier_modes(seed, v_rms, kmax, b_rms)
+    kset_rho, idx, phi, kset = m["kset_rho"], m["idx"], m["phi"], m["kset"]
+
+    if device is not None:
+        import torch
+        ev = lambda *args: _evaluate_device(n, *args, device=device)
+        stack = torch.stack
+    else:
+        ev = lambda *args: _evaluate(n, *args)
+        stack = np.stack
+
+    # density: 0.1 sin(theta + phi) = 0.1 (sin phi) cos theta + 0.1 (cos phi) sin theta
+    ks_r = kset_rho[idx]
+    rho = 1.0 + ev(ks_r, 0.1 * np.sin(phi), 0.1 * np.cos(phi), (0.5, 0.5, 0.5))
+
+    v = stack([ev(kset, m["a_v"][:, d], m["c_v"][:, d], V_OFFSET) for d in range(3)])
+    A = stack([ev(kset, m["a_A"][:, d], m["c_A"][:, d], EDGE_OFFSETS[d]) for d in range(3)])
+    if device is not None:
+        return Fields(rho=rho, v=v, A=A, B0=tuple(float(x) for x in B0), P0=float(P0), gamma=float(gamma))
     return Fields(rho=np.ascontiguousarray(rho), v=np.ascontiguousarray(v),
                   A=np.ascontiguousarray(A), B0=tuple(float(x) for x in B0), P0=float(P0),
                   gamma=float(gamma))

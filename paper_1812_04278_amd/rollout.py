@@ -3,6 +3,10 @@ classical RK4) from an initial vector potential and velocity, as a
 ``torch.autograd.Function`` whose backward runs the hand-written adjoint of the
 HIP library (``wm_adjoint_step``, ``wm_init_adjoint``).
 
+A patch with an FP32 state (WM_MIXED_F32STATE) runs the mixed forward and keeps
+FP32 checkpoints; its backward linearises the FP64 method at those states
+widened to FP64 (the cotangents are FP64 throughout).
+
 Memory: the forward keeps a checkpoint of the state every ``ckpt_every`` steps;
 the backward re-runs each segment forward from its checkpoint, keeping that
 segment's states (and, with ``store_stages``, the two intermediate RK stages of
@@ -50,6 +54,8 @@ class Rollout(torch.autograd.Function):
                     U1 = U2 = None
                 last.append((Uh, Ub, U1, U2))
             out = (patch.hydro.clone(), patch.bface.clone(), patch.bcell.clone())
+        for t in out:                           # made on the patch's stream, used on the caller's
+            t.record_stream(caller)
         ctx.patch, ctx.nsteps, ctx.ckpt_every = patch, nsteps, ckpt_every
         ctx.ckpts, ctx.dts, ctx.P0, ctx.B0 = ckpts, dts, P0, B0
         ctx.store_stages = store_stages
@@ -100,6 +106,8 @@ class Rollout(torch.autograd.Function):
                     p.adjoint_step(Uh, Ub, ctx.dts[n], lam_h, lam_b, U1, U2)
                 del states
             gA, gv = p.init_adjoint(rho, v, A, ctx.B0, lam_h, lam_b)
+        for t in (gA, gv):
+            t.record_stream(caller)
         caller.wait_stream(p.stream)
         return gA, gv, None, None, None, None, None, None, None, None
 

@@ -422,3 +422,60 @@ def test_rollout_fd_16_fifty_directions():
     rels.sort()
     say(f"rollout FD, 50 directions: median {rels[25]:.2e} worst {rels[-1]:.2e}")
     assert rels[25] <= 3e-7 and rels[-1] <= 1e-5
+
+
+def test_fourier_control_fd_16():
+    """The adjoint workload's control is the velocity and potential Fourier
+    amplitudes of the generator: their gradient (the transpose of the Fourier
+    evaluation applied to the rollout's real-space gradient) against central
+    differences in 12 random directions of amplitude space, 16^3, 20 steps,
+    checkpoints every 5, dt sequence held fixed."""
+    from paper_1812_04278_amd import control, inputs
+    n, nsteps = 16, 20
+    B0 = (1.0, 0.6, 0.8)
+    f = fields(n, seed=1, v_rms=1.0, kmax=2, B0=B0)
+    m = inputs.fourier_modes(seed=1, v_rms=1.0, kmax=2)
+    ks = m["kset"]
+
+    def fields_of(th):
+        v = np.stack([inputs.evaluate_modes(n, ks, th["a_v"][:, d], th["c_v"][:, d], inputs.V_OFFSET)
+                      for d in range(3)])
+        A = np.stack([inputs.evaluate_modes(n, ks, th["a_A"][:, d], th["c_A"][:, d], inputs.EDGE_OFFSETS[d])
+                      for d in range(3)])
+        return torch.as_tensor(A).cuda(), torch.as_tensor(v).cuda()
+
+    th0 = {k: m[k] for k in ("a_v", "c_v", "a_A", "c_A")}
+    A0, v0 = fields_of(th0)
+    assert float((v0.cpu() - torch.as_tensor(f.v)).abs().max()) < 1e-13
+    rho_t, e_t = [x.cuda() for x in targets(n, kmax=2, B0=B0)]
+    h = 1.0 / n
+    p = B.Patch(B.config(n))
+    A = A0.clone().requires_grad_(True)
+    v = v0.clone().requires_grad_(True)
+    hyd, bf, bc = R.rollout(A, v, torch.as_tensor(f.rho).cuda(), p, nsteps, ckpt_every=5, P0=f.P0, B0=f.B0)
+    J = loss_from(hyd, bc, rho_t, e_t, h)
+    gA, gv = torch.autograd.grad(J, [A, v])
+    grad = control.amplitude_gradients(gA, gv, ks)
+    p.init_from_potential(f.rho, f.v, f.A, f.P0, f.B0)
+    dts = [p.step(want_dt=True) for _ in range(nsteps)]
+    norm = math.sqrt(sum(float((th0[k] ** 2).sum()) for k in th0))
+    rng = np.random.default_rng(17)
+    rels = []
+    for d in range(12):
+        dth = {k: rng.standard_normal(th0[k].shape) for k in th0}
+        s = math.sqrt(sum(float((dth[k] ** 2).sum()) for k in dth))
+        dth = {k: x / s for k, x in dth.items()}
+        eps = 1e-8 * norm
+        Jpm = []
+        for sgn in (1.0, -1.0):
+            Ap, vp = fields_of({k: th0[k] + sgn * eps * dth[k] for k in th0})
+            Jpm.append(loss_from(*gpu_forward_fixed(p, f, Ap, vp, dts), rho_t, e_t, h))
+        fd = float(Jpm[0] - Jpm[1]) / (2 * eps)
+        ad = sum(float((grad[k].cpu() * torch.as_tensor(dth[k])).sum()) for k in th0)
+        err = abs(fd - ad) / max(abs(ad), 1e-30)
+        rels.append(err)
+        if d < 3:
+            say(f"  direction {d}: fd {fd:.10e} adjoint {ad:.10e} rel {err:.1e}")
+    rels.sort()
+    say(f"Fourier-amplitude FD, 12 directions: median {rels[6]:.2e} worst {rels[-1]:.2e}")
+    assert rels[6] <= 3e-7 and rels[-1] <= 1e-5

@@ -10,7 +10,7 @@ import torch
 
 from oracle import mhd
 from paper_1812_04278_amd import binding as B
-from helpers import T64, _subbox, assert_state_parity, fields, oracle_state, rel_err
+from helpers import T64, _subbox, assert_diag_parity, assert_state_parity, diag_state, fields, oracle_state, rel_err
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -129,6 +129,9 @@ def test_crop_64_ten_steps_mach2():
         assert abs(dt_g - dt_o) <= 1e-13 * dt_o, (s, dt_g, dt_o)
         say(f"  step {s} dt {dt_g:.6e}")
     assert_state_parity(p.state(), U, label="64^3 x 10")
+    # diagnostics of the oracle's state, loaded into the patch (same state on both sides)
+    p.set_state(U["rho"], U["m"], U["E"], U["b"])
+    assert_diag_parity(p.diagnostics(), mhd.diagnostics(U, cfg), U, cfg.h)
 
 
 WZ_FORMS = [("z", B.WM_WENO_Z), ("z_printed", B.WM_WENO_Z_PRINTED)]
@@ -283,6 +286,8 @@ def test_failure_injection_unphysical():
     d = p.diagnostics(raise_unphysical=False)
     assert d["n_unphysical"] == 2, d
     assert d["min_p"] < 0.0
+    Ub = dict(rho=rho, m=st["m"], E=E, b=st["b"])
+    assert_diag_parity(d, mhd.diagnostics(Ub, mhd.cubic(16)), Ub, 1.0 / 16)
     dt = p.step(want_dt=True)
     assert not math.isfinite(dt)
     assert p.diagnostics(raise_unphysical=False)["n_unphysical"] >= 2
@@ -367,3 +372,24 @@ def test_graph_capture_replays_match_eager(fixed_dt):
             assert torch.equal(got[k], ref[k]), (r, k)
     with pytest.raises(ValueError):
         B.Patch(B.config(8)).capture(1)
+
+
+@pytest.mark.parametrize("variant", ["planted", "nan_energy", "nan_density"])
+def test_diagnostics_parity_hand_state(variant):
+    """wm_diagnostics against the oracle on the hand-built 8^3 state of the
+    oracle pins (gamma = 1.5): planted minimum density, a negative-pressure
+    zone, a planted divergence of 2^-7, known totals; then with a NaN energy
+    or a NaN density in one more zone."""
+    say(f"diagnostics parity, hand state ({variant})")
+    U, cfg = diag_state()
+    if variant == "nan_energy":
+        U["E"][1, 1, 1] = float("nan")
+    elif variant == "nan_density":
+        U["rho"][2, 3, 4] = float("nan")
+    p = B.Patch(B.config(8, gamma=cfg.gamma))
+    p.set_state(U["rho"], U["m"], U["E"], U["b"])
+    g = p.diagnostics(raise_unphysical=False)
+    o = mhd.diagnostics(U, cfg)
+    assert_diag_parity(g, o, U, cfg.h)
+    assert g["n_unphysical"] == {"planted": 1, "nan_energy": 2, "nan_density": 2}[variant]
+    assert g["max_divb"] == 2.0 ** -7

@@ -68,7 +68,7 @@ def vector_errors(g, o, floor=0.0):
             for key in ("rho", "m", "E", "b")}
 
 
-@pytest.mark.parametrize("mode", ["fast", "alfven", "entropy", "sound"])
+@pytest.mark.parametrize("mode", ["fast", "slow", "alfven", "entropy", "sound"])
 def test_oblique_wave_parity(mode):
     """A0 = 1e-2: perturbations large enough for the relative bar."""
     say(f"oblique {mode} wave 16x8x8, A0 1e-2, 3 RK4 steps")

@@ -13,6 +13,7 @@ import torch
 
 from oracle import mhd
 from paper_1812_04278_amd import inputs
+from helpers import diag_state
 
 T64 = torch.float64
 
@@ -129,35 +130,6 @@ def test_init_pressure_recovered_mach2():
 # ---------------------------------------------------------------------------
 # diagnostics
 # ---------------------------------------------------------------------------
-
-def diag_state():
-    """8^3 box, gamma = 1.5 (gamma - 1 = 1/2 exactly), h = 1/8.
-
-    Background: rho = 1, v = 0, P = 1, face b = (1, 1/2, 0), so zone B = (1, 1/2, 0)
-    and E = 2 + 0.625 = 2.625.  Planted:
-      zone (i=3, j=5, k=6): rho = 1/2                     (min rho = 0.5)
-      zone (i=0, j=0, k=0): m_x = 1/2 with E = 2.75       (P = 1 still)
-      zone (i=6, j=6, k=2): m_z = -1/4, E = 2.625 + 1/32  (P = 1 still)
-      zone (i=4, j=7, k=5): E = 0.475                     (P = (0.475 - 0.625)/2 = -0.075)
-      face b_y at (i=1, j=2, k=1) += 2^-10                (div = +-2^-10 / h = +-2^-7)
-    Totals: mass 511.5, m = (1/2, 0, -1/4), E = 512 * 2.625 + 0.125 + 1/32 - 2.15,
-    b = (512, 256 + 2^-10, 0)."""
-    n, g = 8, 1.5
-    rho = torch.ones(n, n, n, dtype=T64)
-    m = torch.zeros(3, n, n, n, dtype=T64)
-    E = torch.full((n, n, n), 2.625, dtype=T64)
-    b = torch.zeros(3, n, n, n, dtype=T64)
-    b[0], b[1] = 1.0, 0.5
-    rho[6, 5, 3] = 0.5
-    m[0, 0, 0, 0] = 0.5
-    E[0, 0, 0] = 2.75
-    m[2, 2, 6, 6] = -0.25
-    E[2, 6, 6] = 2.625 + 1.0 / 32
-    E[5, 7, 4] = 0.475
-    b[1, 1, 2, 1] += 2.0 ** -10
-    cfg = mhd.Config(n, n, n, 1.0 / n, gamma=g)
-    return dict(rho=rho, m=m, E=E, b=b), cfg
-
 
 def test_diagnostics_by_hand():
     U, cfg = diag_state()
