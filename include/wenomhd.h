@@ -11,8 +11,15 @@
  * RK4 of Sect. 2.1 at CFL 0.8); the adjoint (vector-Jacobian products) of the
  * right-hand side and of a step.
  *
- * Grid: nx * ny * nz zones, periodic in all three directions, one zone size h
- * for every direction (Sect. 2.3 divides every difference by the same Delta x).
+ * Grid: nx * ny * nz zones, one zone size h for every direction (Sect. 2.3
+ * divides every difference by the same Delta x), periodic in each direction
+ * unless wm_config.walls marks it: then the box has reflecting, perfectly
+ * conducting walls at both ends of that axis (the reflecting boundaries of the
+ * paper's test problems, Sect. 4): ghost zones mirror the interior (normal
+ * momentum and normal field odd, the rest even), the corner fluxes on wall
+ * edges vanish and the normal face field on the wall faces is zero -- the last
+ * face of bface along a walled axis (index n-1) is the upper wall face and
+ * must hold 0; the lower wall face is implicit.
  * Every array is structure-of-arrays, [component][z][y][x] with x contiguous,
  * in device memory of the GPU that is current when the patch is created, and
  * double precision -- except the bound state (hydro, bface, bcell) and the
@@ -100,6 +107,16 @@ typedef struct {
   int weights;              /* wm_weights                                    */
   int precision;            /* wm_precision                                  */
   int integrator;           /* wm_integrator                                 */
+  int walls[3];             /* per axis x, y, z: 0 periodic, 1 reflecting
+                               conducting walls (that axis needs >= 3 zones;
+                               no adjoint)                                    */
+  double rho_floor;         /* opt-in density floor, 0 = off: after every
+                               stage a density below it is raised to it (the
+                               momentum kept)                                 */
+  double p_floor;           /* opt-in gas-pressure floor, 0 = off: then a
+                               pressure below it is raised to it by adding
+                               internal energy; floors need WM_SSPRK3 and
+                               have no adjoint                                */
 } wm_config;
 
 typedef struct {
@@ -111,13 +128,16 @@ typedef struct {
   double min_rho;           /* minimum density                               */
   double min_p;             /* minimum gas pressure (eq. P, zone B)          */
   long long n_unphysical;   /* zones with rho<=0, P<=0 or non-finite values  */
+  long long n_floored;      /* floor activations (a density and a pressure
+                               activation count separately) since the state
+                               was bound, initialised or refreshed            */
 } wm_diag;
 
 typedef struct wm_patch wm_patch;   /* opaque; owns no device memory */
 
 /* Fills cfg with the paper's constants (gamma 5/3, eps 1e-6, eps_B 1e-30,
- * eps_Z 1e-40, Jiang-Shu, FP64) and SSP-RK3 at CFL 0.4 for an n^3 box of
- * length 1 (for WM_RK4 the paper's Courant number is 0.8). */
+ * eps_Z 1e-40, Jiang-Shu, FP64) and SSP-RK3 at CFL 0.4 for a periodic n^3 box
+ * of length 1 without floors (for WM_RK4 the paper's Courant number is 0.8). */
 void wm_config_default(wm_config* cfg, int n);
 
 /* Bytes of device scratch a patch with this configuration needs: the stage
@@ -141,7 +161,9 @@ wm_status wm_bind_state(wm_patch* p, void* hydro, void* bface, void* bcell);
 /* Initial state from primitive fields and an edge vector potential
  * (Sect. 4.1): b = B0 + curl_h A by first-order differences (div_h b = 0),
  * zone B by the fourth-order interpolation of Sect. 2.3, m = rho v and
- * E = P0/(gamma-1) + (rho v^2 + B^2)/2 (eq. P).  rho [nz][ny][nx],
+ * E = P0/(gamma-1) + (rho v^2 + B^2)/2 (eq. P).  With walls, the normal face
+ * field on the wall faces is set to zero (give A with no tangential component
+ * on the wall edges to keep div_h b = 0 there).  rho [nz][ny][nx],
  * v [3][nz][ny][nx], A_edge [3][nz][ny][nx]: device arrays; B0 a host array. */
 wm_status wm_init_from_potential(wm_patch* p, const double* rho, const double* v,
                                  const double* A_edge, double P0, const double B0[3]);

@@ -43,6 +43,14 @@ Readings of passages that are garbled or silent:
       printed form is kept as weights == 'z_printed'
   R16 the RK4 of Sect. 2.1 as its q_save accumulation (factors 1/2, 1/2, 1,
       1/6 on q0; weights -4/3, 1/3, 2/3, 1/3, 1), dt held over the step
+  R20 reflecting walls (the paper's reflecting boundaries, Sect. 4): perfectly
+      conducting, ghost zones that mirror the interior (normal momentum and
+      normal field odd, everything else even); the corner fluxes on wall edges
+      vanish and the normal face field on a wall face is zero
+  R21 floors (the protection floors of Sect. 4, unspecified there): after each
+      stage, rho below rho_floor is raised to it with the momentum kept, then a
+      gas pressure below p_floor is raised to it by adding internal energy;
+      activations are counted
 """
 from __future__ import annotations
 
@@ -66,6 +74,9 @@ class Config:
     eps_B: float = 1e-30      # degeneracy threshold (Appendix A)
     weights: str = "js"       # "js" (Jiang-Shu), "z" (WENO-Z) or "z_printed"
     eps_Z: float = 1e-40
+    walls: tuple = (False, False, False)   # reflecting conducting walls per axis (R20)
+    rho_floor: float = 0.0    # opt-in density floor (R21; 0 = off)
+    p_floor: float = 0.0      # opt-in gas-pressure floor (R21; 0 = off)
 
 
 def cubic(n: int, L: float = 1.0, **kw) -> Config:
@@ -98,6 +109,22 @@ def zone_B(b: torch.Tensor) -> torch.Tensor:
     return torch.stack([interp4(b[a], a) for a in range(3)])
 
 
+def zone_B_cfg(b: torch.Tensor, cfg) -> torch.Tensor:
+    """Zone field of a face field with the configuration's walls: along a walled
+    axis the fourth-order interpolation reads the mirror ghost faces (R20)."""
+    if not any(cfg.walls):
+        return zone_B(b)
+    D, n = b, [cfg.nx, cfg.ny, cfg.nz]
+    for axis in range(3):
+        if cfg.walls[axis]:
+            D = mirror_double_faces(D, axis)
+    B = zone_B(D)
+    for axis in range(3):
+        if cfg.walls[axis]:
+            B = B.narrow(B.dim() - 1 - axis, 0, n[axis])
+    return B
+
+
 def curl_edges(A: torch.Tensor, h: float) -> torch.Tensor:
     """Face field from an edge vector potential by first-order differences
     (Sect. 4.1): b = curl_h A, with A_x at (i, j+1/2, k+1/2) etc."""
@@ -120,22 +147,27 @@ def div_faces(b: torch.Tensor, h: float) -> torch.Tensor:
 def init_from_potential(rho, v, A, P0: float, B0, cfg: Config):
     """Conserved state from primitive fields and an edge vector potential:
     b = B0 + curl_h A, zone B by fourth-order interpolation, m = rho v and
-    E = P/(gamma-1) + (rho v^2 + B^2)/2 (eq. P)."""
+    E = P/(gamma-1) + (rho v^2 + B^2)/2 (eq. P).  With walls (R20) the normal
+    field on the wall faces is set to zero."""
     rho = torch.as_tensor(rho, dtype=DT)
     v = torch.as_tensor(v, dtype=DT)
     A = torch.as_tensor(A, dtype=DT)
     b = curl_edges(A, cfg.h)
     b = torch.stack([b[a] + float(B0[a]) for a in range(3)])
-    B = zone_B(b)
+    for axis in range(3):                       # a wall face carries no normal field (R20)
+        if cfg.walls[axis]:
+            b[axis].narrow(b[axis].dim() - 1 - axis, b[axis].shape[-1 - axis] - 1, 1).zero_()
+    B = zone_B_cfg(b, cfg)
     m = rho * v
     E = P0 / (cfg.gamma - 1.0) + 0.5 * (rho * (v * v).sum(0) + (B * B).sum(0))
     return dict(rho=rho, m=m, E=E, b=b)
 
 
-def primitives(U, gamma: float):
-    """rho, v, zone B and gas pressure from the conserved state (eq. P)."""
+def primitives(U, gamma: float, cfg=None):
+    """rho, v, zone B and gas pressure from the conserved state (eq. P); with a
+    configuration, zone B follows its walls."""
     rho, m, E = U["rho"], U["m"], U["E"]
-    B = zone_B(U["b"])
+    B = zone_B(U["b"]) if cfg is None else zone_B_cfg(U["b"], cfg)
     v = m / rho
     P = (gamma - 1.0) * (E - 0.5 * ((m * v).sum(0) + (B * B).sum(0)))
     return rho, v, B, P
@@ -378,6 +410,16 @@ def sweep(U, axis: int, cfg: Config, prims=None):
 # ----------------------------------------------------------------------------
 
 def rhs(U, cfg: Config, return_parts: bool = False):
+    """dU/dt of the semi-discrete scheme (periodic, or with the walls of
+    cfg.walls: :func:`rhs_walled`)."""
+    if any(cfg.walls):
+        if return_parts:
+            raise ValueError("parts are for the periodic scheme")
+        return rhs_walled(U, cfg)
+    return rhs_periodic(U, cfg, return_parts)
+
+
+def rhs_periodic(U, cfg: Config, return_parts: bool = False):
     """dU/dt of the semi-discrete scheme: conservative WENO flux divergence
     (eq. num) for rho, m, E summed over the three sweeps, and the CT update of
     the face field from the corner fluxes (eq. ox1-ox3 and the b equations)."""
@@ -405,18 +447,121 @@ def rhs(U, cfg: Config, return_parts: bool = False):
     Omega_x = 0.5 * (g_x + at(g_x, 1, X)) - 0.5 * (f_y + at(f_y, 1, Y))   # eq. (ox1), edge (i+1/2, j+1/2, k)
     Omega_y = 0.5 * (h_y + at(h_y, 1, Y)) - 0.5 * (g_z + at(g_z, 1, Z))   # eq. (ox2), edge (i, j+1/2, k+1/2)
     Omega_z = 0.5 * (f_z + at(f_z, 1, Z)) - 0.5 * (h_x + at(h_x, 1, X))   # eq. (ox3), edge (i+1/2, j, k+1/2)
-    k_bx = -(Omega_x - at(Omega_x, -1, Y)) / h + (Omega_z - at(Omega_z, -1, Z)) / h
-    k_by = -(Omega_y - at(Omega_y, -1, Z)) / h + (Omega_x - at(Omega_x, -1, X)) / h
-    k_bz = -(Omega_z - at(Omega_z, -1, X)) / h + (Omega_y - at(Omega_y, -1, Y)) / h
-    k = dict(rho=k_rho, m=k_m, E=k_E, b=torch.stack([k_bx, k_by, k_bz]))
+    k = dict(rho=k_rho, m=k_m, E=k_E, b=face_field_rhs(Omega_x, Omega_y, Omega_z, h))
     if return_parts:
         return k, dict(sweeps=parts, Omega=(Omega_x, Omega_y, Omega_z))
     return k
 
 
+def face_field_rhs(Omega_x, Omega_y, Omega_z, h: float):
+    """db/dt = -curl_h of the corner fluxes (the b equations of Sect. 2.3):
+    Omega_x = E_z at (i+1/2, j+1/2, k), Omega_y = E_x at (i, j+1/2, k+1/2),
+    Omega_z = E_y at (i+1/2, j, k+1/2)."""
+    X, Y, Z = 0, 1, 2
+    k_bx = -(Omega_x - at(Omega_x, -1, Y)) / h + (Omega_z - at(Omega_z, -1, Z)) / h
+    k_by = -(Omega_y - at(Omega_y, -1, Z)) / h + (Omega_x - at(Omega_x, -1, X)) / h
+    k_bz = -(Omega_z - at(Omega_z, -1, X)) / h + (Omega_y - at(Omega_y, -1, Y)) / h
+    return torch.stack([k_bx, k_by, k_bz])
+
+
+# ----------------------------------------------------------------------------
+# reflecting walls (R20) and floors (R21)
+# ----------------------------------------------------------------------------
+
+def _zone_dim(t: torch.Tensor, axis: int) -> int:
+    return t.dim() - 1 - axis
+
+
+def mirror_double(U, axis: int):
+    """The state extended to 2N zones along ``axis`` by its mirror image about
+    the upper wall face (N-1/2): zone N+m is zone N-1-m with the normal momentum
+    negated; the normal face field is odd about both wall faces (N-1/2 and
+    -1/2 = 2N-1/2, where it is zero), the tangential face fields even.  These are
+    the ghost zones of a reflecting, perfectly conducting wall."""
+    def ext(f, sign=1.0):
+        d = _zone_dim(f, axis)
+        return torch.cat([f, sign * torch.flip(f, dims=[d])], dim=d)
+    m = torch.stack([ext(U["m"][c], -1.0 if c == axis else 1.0) for c in range(3)])
+    return dict(rho=ext(U["rho"]), m=m, E=ext(U["E"]), b=mirror_double_faces(U["b"], axis))
+
+
+def mirror_double_faces(b: torch.Tensor, axis: int) -> torch.Tensor:
+    """The face field part of :func:`mirror_double`."""
+    bs = []
+    for c in range(3):
+        f = b[c]
+        d = _zone_dim(f, axis)
+        if c != axis:
+            bs.append(torch.cat([f, torch.flip(f, dims=[d])], dim=d))
+            continue
+        n = f.shape[d]
+        # doubled faces N..2N-2 are -b(N-2..0); face 2N-1 is the lower wall
+        tail = -torch.flip(f.narrow(d, 0, n - 1), dims=[d])
+        bs.append(torch.cat([f, tail, torch.zeros_like(f.narrow(d, 0, 1))], dim=d))
+    return torch.stack(bs)
+
+
+def rhs_walled(U, cfg: Config):
+    """Right-hand side with reflecting conducting walls on the axes cfg.walls
+    marks (R20): the periodic scheme on the box mirror-doubled along each
+    walled axis (ghost zones that mirror the interior), restricted to the
+    original zones, with the corner fluxes on the wall edges set to zero (the
+    tangential electric field of a conducting wall) and the normal face field
+    on the wall faces held at zero."""
+    D = U
+    sizes = [cfg.nx, cfg.ny, cfg.nz]
+    for axis in range(3):
+        if cfg.walls[axis]:
+            D = mirror_double(D, axis)
+            sizes[axis] *= 2
+    cfgD = dataclasses.replace(cfg, nx=sizes[0], ny=sizes[1], nz=sizes[2], walls=(False, False, False))
+    k, parts = rhs_periodic(D, cfgD, return_parts=True)
+    Ox, Oy, Oz = [o.clone() for o in parts["Omega"]]
+    n = [cfg.nx, cfg.ny, cfg.nz]
+    # wall planes of the doubled box along a walled axis: faces N-1 and 2N-1
+    for axis in range(3):
+        if not cfg.walls[axis]:
+            continue
+        for o, on_axis in ((Ox, (0, 1)), (Oy, (1, 2)), (Oz, (0, 2))):
+            if axis in on_axis:            # the edge lies in planes of constant axis
+                d = _zone_dim(o, axis)
+                o.index_fill_(d, torch.tensor([n[axis] - 1, 2 * n[axis] - 1]), 0.0)
+    kb = face_field_rhs(Ox, Oy, Oz, cfg.h)
+
+    def crop(f):
+        for axis in range(3):
+            if cfg.walls[axis]:
+                f = f.narrow(_zone_dim(f, axis), 0, n[axis])
+        return f
+    out = dict(rho=crop(k["rho"]), m=crop(k["m"]), E=crop(k["E"]), b=crop(kb))
+    for axis in range(3):
+        if cfg.walls[axis]:
+            out["b"][axis].narrow(_zone_dim(out["b"][axis], axis), n[axis] - 1, 1).zero_()
+    return out
+
+
+def apply_floors(U, cfg: Config):
+    """Opt-in floors (R21) on a stage result: rho < rho_floor is raised to the
+    floor (momentum kept), then a gas pressure below p_floor (eq. P with the
+    zone field of the state's face field) is raised to the floor by adding
+    internal energy.  Returns (state, number of activations)."""
+    n = 0
+    rho, m, E = U["rho"], U["m"], U["E"]
+    if cfg.rho_floor > 0:
+        low = rho < cfg.rho_floor
+        n += int(low.sum())
+        rho = torch.where(low, torch.full_like(rho, cfg.rho_floor), rho)
+    if cfg.p_floor > 0:
+        _, _, _, P = primitives(dict(rho=rho, m=m, E=E, b=U["b"]), cfg.gamma, cfg)
+        low = P < cfg.p_floor
+        n += int(low.sum())
+        E = torch.where(low, E + (cfg.p_floor - P) / (cfg.gamma - 1.0), E)
+    return dict(rho=rho, m=m, E=E, b=U["b"]), n
+
+
 def max_signal_speeds(U, cfg: Config):
     """max over zones of |v_d| + c_fast^d for d = x, y, z (denominator of eq. cfl)."""
-    rho, v, B, P = primitives(U, cfg.gamma)
+    rho, v, B, P = primitives(U, cfg.gamma, cfg)
     out = []
     for axis in range(3):
         n, t1, t2 = frame(axis)
@@ -455,14 +600,27 @@ def rk_stage(stage: int, Un, acc, Us, dt: float, cfg: Config):
     raise ValueError(stage)
 
 
-def step(U, cfg: Config, dt: float | None = None):
-    """One SSP-RK3 step; dt from eq. (cfl) on U unless given.  Returns (U, dt)."""
+def step(U, cfg: Config, dt: float | None = None, stats: dict | None = None):
+    """One SSP-RK3 step; dt from eq. (cfl) on U unless given.  Returns (U, dt).
+    With floors (R21) each stage result is floored; the activations are added
+    to stats["n_floored"] when a dict is given."""
     if dt is None:
         dt = compute_dt(U, cfg)
+    floors = cfg.rho_floor > 0 or cfg.p_floor > 0
+
+    def fl(V):
+        if not floors:
+            return V
+        V, n = apply_floors(V, cfg)
+        if stats is not None:
+            stats["n_floored"] = stats.get("n_floored", 0) + n
+        return V
     acc, U1 = rk_stage(0, U, None, U, dt, cfg)
+    U1 = fl(U1)
     acc, U2 = rk_stage(1, U, acc, U1, dt, cfg)
+    U2 = fl(U2)
     _, U3 = rk_stage(2, U, acc, U2, dt, cfg)
-    return U3, dt
+    return fl(U3), dt
 
 
 def step_rk4(U, cfg: Config, dt: float | None = None):
@@ -488,7 +646,7 @@ def diagnostics(U, cfg: Config):
     E, face-b sums, min rho and min P over the zones where they are not NaN
     (NaN zones are reported by the count instead), and the number of zones with
     rho <= 0, P <= 0 or a non-finite rho, P or E."""
-    rho, v, B, P = primitives(U, cfg.gamma)
+    rho, v, B, P = primitives(U, cfg.gamma, cfg)
     bad = (rho <= 0) | (P <= 0) | ~torch.isfinite(rho) | ~torch.isfinite(P) | ~torch.isfinite(U["E"])
 
     def nanmin(x):

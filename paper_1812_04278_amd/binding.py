@@ -33,18 +33,19 @@ class WmConfig(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("h", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("eps_B", ctypes.c_double), ("eps_Z", ctypes.c_double),
-                ("weights", ctypes.c_int), ("precision", ctypes.c_int), ("integrator", ctypes.c_int)]
+                ("weights", ctypes.c_int), ("precision", ctypes.c_int), ("integrator", ctypes.c_int),
+                ("walls", ctypes.c_int * 3), ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double)]
 
 
 class WmDiag(ctypes.Structure):
     _fields_ = [("max_divb", ctypes.c_double), ("mass", ctypes.c_double), ("mom", ctypes.c_double * 3),
                 ("energy", ctypes.c_double), ("bflux", ctypes.c_double * 3), ("min_rho", ctypes.c_double),
-                ("min_p", ctypes.c_double), ("n_unphysical", ctypes.c_longlong)]
+                ("min_p", ctypes.c_double), ("n_unphysical", ctypes.c_longlong), ("n_floored", ctypes.c_longlong)]
 
     def as_dict(self):
         return dict(max_divb=self.max_divb, mass=self.mass, mom=list(self.mom), energy=self.energy,
                     bflux=list(self.bflux), min_rho=self.min_rho, min_p=self.min_p,
-                    n_unphysical=int(self.n_unphysical))
+                    n_unphysical=int(self.n_unphysical), n_floored=int(self.n_floored))
 
 
 _lib = None
@@ -110,13 +111,15 @@ def _check(status):
 
 
 def config(n=None, nx=None, ny=None, nz=None, h=None, gamma=5.0 / 3.0, cfl=0.4, eps=1e-6, eps_B=1e-30,
-           eps_Z=1e-40, weights=WM_WENO_JS, precision=WM_FP64, integrator=WM_SSPRK3) -> WmConfig:
+           eps_Z=1e-40, weights=WM_WENO_JS, precision=WM_FP64, integrator=WM_SSPRK3, walls=(0, 0, 0),
+           rho_floor=0.0, p_floor=0.0) -> WmConfig:
     nx = nx or n
     ny = ny or n
     nz = nz or n
     c = WmConfig(nx=nx, ny=ny, nz=nz, h=h if h is not None else 1.0 / nx, gamma=gamma, cfl=cfl,
                  eps_weno=eps, eps_B=eps_B, eps_Z=eps_Z, weights=weights, precision=precision,
-                 integrator=integrator)
+                 integrator=integrator, walls=(ctypes.c_int * 3)(*[int(w) for w in walls]),
+                 rho_floor=rho_floor, p_floor=p_floor)
     return c
 
 

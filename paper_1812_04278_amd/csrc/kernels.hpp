@@ -18,10 +18,25 @@ namespace wm {
 struct Grid {
   int nx, ny, nz;
   size_t N;   // nx * ny * nz
+  int wall[3];  // 1: reflecting conducting walls at both ends of the axis
   __device__ __forceinline__ size_t at(int i, int j, int k) const {
     return ((size_t)k * ny + j) * nx + i;
   }
 };
+
+// Face value b_f of the normal field along an axis of n faces, f in [-2, n]:
+// periodic wrap, or at walls the mirror ghost faces (odd about the wall faces
+// -1/2 and n-1/2; the lower wall face is zero, the upper one is stored).
+template <typename F>
+__device__ __forceinline__ double normal_face(F read, int f, int n, int wall) {
+  if (wall) {
+    if (f == -1) return 0.0;
+    if (f < -1) return -read(-2 - f);
+    if (f > n - 1) return -read(2 * n - 2 - f);
+    return read(f);
+  }
+  return read(wrap(f, n));
+}
 
 // ---------------------------------------------------------------------------
 // directional sweep
@@ -49,14 +64,32 @@ struct SweepArgs {
   S* fhydro;             // [5][N] interface flux, global frame (rho, mx, my, mz, E)
   S* T;                  // [2][N] transport fluxes T^n_t1, T^n_t2
   double* dbg;           // optional [9][N]: 7 sweep-frame flux components + 2 T
+  S* wallF;              // walled sweep axis: [5][nB * nC] fluxes through the lower wall face
 };
 
-// LDS per block: zone q and F in FP64 (the differences are formed in FP64),
-// zone primitives and speeds in the work type TW.
-template <int AXIS, typename TW>
-constexpr size_t sweep_lds_doubles() {
-  return (size_t)SW_NQ * (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB +
-         ((size_t)SW_NP * (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB * sizeof(TW) + 7) / 8;
+// Zone index along a sweep axis of n zones for a stencil position z: periodic
+// wrap, or at walls the mirror zone, with flip = -1 where the normal momentum
+// and field change sign (ghost zones, R20).  The mirror is the periodic
+// extension of the mirror-doubled axis (period 2n), so any z -- also the
+// positions of a tile longer than the axis, whose faces are discarded --
+// maps into [0, n); for z in [-n, 2n) it is the plain reflection.
+__device__ __forceinline__ int sweep_zone(int z, int n, int wall, double& flip) {
+  flip = 1.0;
+  if (!wall) return wrap(z, n);
+  const int zz = wrap(z, 2 * n);
+  if (zz >= n) { flip = -1.0; return 2 * n - 1 - zz; }
+  return zz;
+}
+
+// LDS per block, two arrays: zone q and F in FP64 (the differences are formed
+// in FP64, then stored over them), and the zone primitives and speeds in the
+// work type TW.
+template <int AXIS> constexpr int sweep_zones() {
+  return (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB;
+}
+template <int AXIS> constexpr size_t sweep_q_doubles() { return (size_t)SW_NQ * sweep_zones<AXIS>(); }
+template <int AXIS, typename TW> constexpr size_t sweep_p_doubles() {
+  return ((size_t)SW_NP * sweep_zones<AXIS>() * sizeof(TW) + 7) / 8;
 }
 
 // Phases: (1) zone prologue of the tile and its halo into LDS; (2) per face:
@@ -68,6 +101,7 @@ constexpr size_t sweep_lds_doubles() {
 // transport-flux mean in FP32; the zone prologue (pressure recovery), the
 // differences, the central flux and the face eigen-system (renormalisation of
 // alpha_f, alpha_s, beta) in FP64.
+
 template <int AXIS, bool WENO_Z, typename TW, typename S>
 __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_kernel(SweepArgs<S> a) {
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
@@ -77,35 +111,42 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
   constexpr int NIF = NI * TB;
   static_assert(TA * TB == SW_THREADS, "one face per lane");
   static_assert(TA >= 4, "extra interfaces are built by lanes fa < 4");
-  __shared__ double smem[sweep_lds_doubles<AXIS, TW>()];
-  double* Q = smem;                          // [14][NC] zone q and F, later the differences
-  TW* Pz = reinterpret_cast<TW*>(smem + SW_NQ * NC);   // [11][NC] zone primitives and speeds
-  TW* Dl = reinterpret_cast<TW*>(smem);      // [14][NIF] interface differences (aliases Q)
+  __shared__ double sQ[sweep_q_doubles<AXIS>()];
+  __shared__ double sP[sweep_p_doubles<AXIS, TW>()];
+  double* Q = sQ;                            // [14][NC] zone q and F, later the differences
+  TW* Pz = reinterpret_cast<TW*>(sP);        // [11][NC] zone primitives and speeds
+  TW* Dl = reinterpret_cast<TW*>(sQ);        // [14][NIF] interface differences (aliases Q)
 
   const Grid& g = a.g;
   const int nA = AXIS == 0 ? g.nx : (AXIS == 1 ? g.ny : g.nz);
   const int nB = AXIS == 0 ? g.ny : g.nx;
-  const int a0 = blockIdx.x * TA;
-  const int b0 = blockIdx.y * TB;
-  const int c = blockIdx.z;
   constexpr int CN = AXIS, CT1 = (AXIS + 1) % 3, CT2 = (AXIS + 2) % 3;
   auto cidx = [](int aa, int bb) { return AXIS == 0 ? bb * NA + aa : aa * TB + bb; };
   auto iidx = [](int ia, int bb) { return AXIS == 0 ? bb * NI + ia : ia * TB + bb; };
+  // faces 0 .. nA-1 (i+1/2), and with walls also the lower wall face -1/2
+  const int wl = g.wall[AXIS];
+  const int a0 = blockIdx.x * TA - wl;
+  const int b0 = blockIdx.y * TB;
+  const int c = blockIdx.z;
+  const int tid = threadIdx.x;
 
   // ---- (1) zone prologue, zones i-2 .. i+TA+2 along the axis with periodic wrap
-  for (int cell = threadIdx.x; cell < NC; cell += SW_THREADS) {
+  for (int cell = tid; cell < NC; cell += SW_THREADS) {
     int aa, bb;
     if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
     else           { bb = cell % TB; aa = cell / TB; }
-    const int ia = wrap(a0 - SW_HL + aa, nA);
+    double flip;
+    const int ia = sweep_zone(a0 - SW_HL + aa, nA, wl, flip);
     const int ib = min(b0 + bb, nB - 1);
     int i, j, k;
     if (AXIS == 0)      { i = ia; j = ib; k = c; }
     else if (AXIS == 1) { i = ib; j = ia; k = c; }
     else                { i = ib; j = c;  k = ia; }
     const size_t gi = g.at(i, j, k);
-    const double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
-    const double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
+    double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
+    double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
+    m[CN] *= flip;
+    B[CN] *= flip;
     double z[Z_NVAR];
     zone_prologue(a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
 #pragma unroll
@@ -126,8 +167,8 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
 
   // ---- (2) per face: central flux, face state, LF speeds, own interface differences
   int fa, fb;
-  if (AXIS == 0) { fa = threadIdx.x % TA; fb = threadIdx.x / TA; }
-  else           { fb = threadIdx.x % TB; fa = threadIdx.x / TB; }
+  if (AXIS == 0) { fa = tid % TA; fb = tid / TA; }
+  else           { fb = tid % TB; fa = tid / TB; }
   const int cL = cidx(fa + 2, fb), cR = cidx(fa + 3, fb);
   double Fc[7];
 #pragma unroll
@@ -198,7 +239,17 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
   // guarded block defeats register allocation (hundreds of spills)
 #pragma unroll
   for (int j = 0; j < 7; ++j) asm volatile("" : "+v"(Ff[j]));
-  if (a0 + fa >= nA || b0 + fb >= nB) return;
+  if (a0 + fa < 0 && b0 + fb < nB) {          // the lower wall face (-1/2): hydro fluxes only
+    double fm[3];
+    fm[CN] = Ff[1]; fm[CT1] = Ff[2]; fm[CT2] = Ff[3];
+    const size_t wi = (size_t)(b0 + fb) + (size_t)nB * c;
+    const size_t P = (size_t)nB * (AXIS == 2 ? g.ny : g.nz);
+    a.wallF[wi] = S(Ff[0]);
+    a.wallF[P + wi] = S(fm[0]);
+    a.wallF[2 * P + wi] = S(fm[1]);
+    a.wallF[3 * P + wi] = S(fm[2]);
+    a.wallF[4 * P + wi] = S(Ff[6]);
+  } else if (a0 + fa < nA && b0 + fb < nB) {
   int i, j, k;
   if (AXIS == 0)      { i = a0 + fa; j = b0 + fb; k = c; }
   else if (AXIS == 1) { i = b0 + fb; j = a0 + fa; k = c; }
@@ -219,6 +270,7 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
     a.dbg[7 * g.N + gi] = T1;
     a.dbg[8 * g.N + gi] = T2;
   }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -236,6 +288,7 @@ struct UpdateArgs {
   S* b_out;              // bface [3][N] of the stage result
   double* rhs_out;       // optional [8][N]: the right-hand side itself (no state update)
   const double* dt;      // device scalar
+  const S* wallF[3];     // per walled axis: [5][nB * nC] fluxes through the lower wall face
 };
 
 // corner fluxes (eq. ox1-ox3), each from four transport fluxes:
@@ -272,29 +325,40 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
   const S* Fy = a.faces + 5 * N;
   const S* Fz = a.faces + 10 * N;
   double kv[8];
+  // the face behind the zone: at a lower wall, the flux through the wall face
+  // (per-axis plane buffers indexed like the sweep's (across, plane) tiles)
+  const bool lwx = g.wall[0] && i == 0, lwy = g.wall[1] && j == 0, lwz = g.wall[2] && k == 0;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const size_t o = v * N;
-    const double dx = -(double(Fx[o + c0]) - double(Fx[o + cxm])) * ih;
-    const double dy = -(double(Fy[o + c0]) - double(Fy[o + cym])) * ih;
-    const double dz = -(double(Fz[o + c0]) - double(Fz[o + czm])) * ih;
+    const double fxm = lwx ? double(a.wallF[0][(size_t)v * g.ny * g.nz + j + (size_t)g.ny * k]) : double(Fx[o + cxm]);
+    const double fym = lwy ? double(a.wallF[1][(size_t)v * g.nx * g.nz + i + (size_t)g.nx * k]) : double(Fy[o + cym]);
+    const double fzm = lwz ? double(a.wallF[2][(size_t)v * g.nx * g.ny + i + (size_t)g.nx * j]) : double(Fz[o + czm]);
+    const double dx = -(double(Fx[o + c0]) - fxm) * ih;
+    const double dy = -(double(Fy[o + c0]) - fym) * ih;
+    const double dz = -(double(Fz[o + c0]) - fzm) * ih;
     kv[v] = (dx + dy) + dz;
   }
   TView<S> T;
   T.xy = a.faces + 15 * N; T.xz = a.faces + 16 * N;
   T.yz = a.faces + 17 * N; T.yx = a.faces + 18 * N;
   T.zx = a.faces + 19 * N; T.zy = a.faces + 20 * N;
-  auto Ez = [&](int ii, int jj, int kk) {
+  // corner fluxes on edges that lie in a wall plane vanish (conducting wall);
+  // with walls the lower wall's edges wrap to index n-1, the upper wall's
+  auto Ez = [&](int ii, int jj, int kk) -> double {
+    if ((g.wall[0] && ii == g.nx - 1) || (g.wall[1] && jj == g.ny - 1)) return 0.0;
     const int iip = ii + 1 == g.nx ? 0 : ii + 1, jjp = jj + 1 == g.ny ? 0 : jj + 1;
     return 0.5 * (double(T.yx[g.at(ii, jj, kk)]) + double(T.yx[g.at(iip, jj, kk)])) -
            0.5 * (double(T.xy[g.at(ii, jj, kk)]) + double(T.xy[g.at(ii, jjp, kk)]));
   };
-  auto Ex = [&](int ii, int jj, int kk) {
+  auto Ex = [&](int ii, int jj, int kk) -> double {
+    if ((g.wall[1] && jj == g.ny - 1) || (g.wall[2] && kk == g.nz - 1)) return 0.0;
     const int jjp = jj + 1 == g.ny ? 0 : jj + 1, kkp = kk + 1 == g.nz ? 0 : kk + 1;
     return 0.5 * (double(T.zy[g.at(ii, jj, kk)]) + double(T.zy[g.at(ii, jjp, kk)])) -
            0.5 * (double(T.yz[g.at(ii, jj, kk)]) + double(T.yz[g.at(ii, jj, kkp)]));
   };
-  auto Ey = [&](int ii, int jj, int kk) {
+  auto Ey = [&](int ii, int jj, int kk) -> double {
+    if ((g.wall[0] && ii == g.nx - 1) || (g.wall[2] && kk == g.nz - 1)) return 0.0;
     const int iip = ii + 1 == g.nx ? 0 : ii + 1, kkp = kk + 1 == g.nz ? 0 : kk + 1;
     return 0.5 * (double(T.xz[g.at(ii, jj, kk)]) + double(T.xz[g.at(ii, jj, kkp)])) -
            0.5 * (double(T.zx[g.at(ii, jj, kk)]) + double(T.zx[g.at(iip, jj, kk)]));
@@ -307,6 +371,10 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
   kv[5] = -(ez - ez_jm) * ih + (ey - ey_km) * ih;
   kv[6] = -(ex - ex_km) * ih + (ez - ez_im) * ih;
   kv[7] = -(ey - ey_im) * ih + (ex - ex_jm) * ih;
+  // the normal field on a wall face stays zero
+  if (g.wall[0] && i == g.nx - 1) kv[5] = 0.0;
+  if (g.wall[1] && j == g.ny - 1) kv[6] = 0.0;
+  if (g.wall[2] && k == g.nz - 1) kv[7] = 0.0;
 
   if (a.rhs_out) {
 #pragma unroll
@@ -358,13 +426,18 @@ __global__ __launch_bounds__(256) void bcell_kernel(Grid g, const S* b, S* B) {
   const S* bx = b;
   const S* by = b + N;
   const S* bz = b + 2 * N;
-  auto f = [](S x) { return double(x); };
-  B[c0] = S((-f(bx[g.at(wrap(i - 2, g.nx), j, k)]) + 9.0 * f(bx[g.at(wrap(i - 1, g.nx), j, k)]) + 9.0 * f(bx[c0]) -
-             f(bx[g.at(wrap(i + 1, g.nx), j, k)])) * (1.0 / 16.0));
-  B[N + c0] = S((-f(by[g.at(i, wrap(j - 2, g.ny), k)]) + 9.0 * f(by[g.at(i, wrap(j - 1, g.ny), k)]) + 9.0 * f(by[c0]) -
-                 f(by[g.at(i, wrap(j + 1, g.ny), k)])) * (1.0 / 16.0));
-  B[2 * N + c0] = S((-f(bz[g.at(i, j, wrap(k - 2, g.nz))]) + 9.0 * f(bz[g.at(i, j, wrap(k - 1, g.nz))]) +
-                     9.0 * f(bz[c0]) - f(bz[g.at(i, j, wrap(k + 1, g.nz))])) * (1.0 / 16.0));
+  auto rx = [&](int f) { return double(bx[g.at(f, j, k)]); };
+  auto ry = [&](int f) { return double(by[g.at(i, f, k)]); };
+  auto rz = [&](int f) { return double(bz[g.at(i, j, f)]); };
+  auto interp = [](double m2, double m1, double p0, double p1) {
+    return (-m2 + 9.0 * m1 + 9.0 * p0 - p1) * (1.0 / 16.0);
+  };
+  B[c0] = S(interp(normal_face(rx, i - 2, g.nx, g.wall[0]), normal_face(rx, i - 1, g.nx, g.wall[0]),
+                   normal_face(rx, i, g.nx, g.wall[0]), normal_face(rx, i + 1, g.nx, g.wall[0])));
+  B[N + c0] = S(interp(normal_face(ry, j - 2, g.ny, g.wall[1]), normal_face(ry, j - 1, g.ny, g.wall[1]),
+                       normal_face(ry, j, g.ny, g.wall[1]), normal_face(ry, j + 1, g.ny, g.wall[1])));
+  B[2 * N + c0] = S(interp(normal_face(rz, k - 2, g.nz, g.wall[2]), normal_face(rz, k - 1, g.nz, g.wall[2]),
+                           normal_face(rz, k, g.nz, g.wall[2]), normal_face(rz, k + 1, g.nz, g.wall[2])));
 }
 
 // b = B0 + curl_h A (first-order differences on the edge potential)
@@ -383,6 +456,10 @@ __global__ __launch_bounds__(256) void init_b_kernel(Grid g, double inv_h, const
   b[c0] = S(B0x + ((Az[c0] - Az[g.at(i, jm, k)]) * inv_h - (Ay[c0] - Ay[g.at(i, j, km)]) * inv_h));
   b[N + c0] = S(B0y + ((Ax[c0] - Ax[g.at(i, j, km)]) * inv_h - (Az[c0] - Az[g.at(im, j, k)]) * inv_h));
   b[2 * N + c0] = S(B0z + ((Ay[c0] - Ay[g.at(im, j, k)]) * inv_h - (Ax[c0] - Ax[g.at(i, jm, k)]) * inv_h));
+  // a wall face carries no normal field
+  if (g.wall[0] && i == g.nx - 1) b[c0] = S(0.0);
+  if (g.wall[1] && j == g.ny - 1) b[N + c0] = S(0.0);
+  if (g.wall[2] && k == g.nz - 1) b[2 * N + c0] = S(0.0);
 }
 
 // m = rho v, E = P0/(gamma-1) + (rho v^2 + B^2)/2 (zone B already interpolated)
@@ -481,6 +558,52 @@ __global__ __launch_bounds__(RED_THREADS) void dt_final_kernel(int nblocks, doub
 }
 
 __global__ void set_scalar_kernel(double* p, double v) { *p = v; }
+
+// Opt-in floors on a stage result (hydro [5][N] with its zone field): rho below
+// rho_f is raised to it (momentum kept), then P below p_f (eq. P) is raised to
+// it by adding internal energy.  part[block] = activations of the block (a
+// density and a pressure activation count separately).
+template <typename S>
+__global__ __launch_bounds__(RED_THREADS) void floor_kernel(size_t N, double gamma, double rho_f, double p_f,
+                                                            S* hydro, const S* bcell, double* part) {
+  __shared__ double red[RED_THREADS];
+  double cnt = 0.0;
+  for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N; c += (size_t)gridDim.x * RED_THREADS) {
+    double rho = hydro[c];
+    if (rho_f > 0.0 && rho < rho_f) {
+      rho = rho_f;
+      hydro[c] = S(rho);
+      cnt += 1.0;
+    }
+    if (p_f > 0.0) {
+      const double m[3] = {hydro[N + c], hydro[2 * N + c], hydro[3 * N + c]};
+      const double B[3] = {bcell[c], bcell[N + c], bcell[2 * N + c]};
+      const double E = hydro[4 * N + c];
+      const double r = double(S(rho));
+      const double P = (gamma - 1.0) * (E - 0.5 * ((m[0] * (m[0] / r) + m[1] * (m[1] / r) + m[2] * (m[2] / r)) +
+                                                   (B[0] * B[0] + B[1] * B[1] + B[2] * B[2])));
+      if (P < p_f) {
+        hydro[4 * N + c] = S(E + (p_f - P) / (gamma - 1.0));
+        cnt += 1.0;
+      }
+    }
+  }
+  red[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// total += sum of the block counts (one thread, fixed order)
+__global__ void floor_final_kernel(int nblocks, const double* part, double* total, int reset) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = reset ? 0.0 : *total;
+  for (int b = 0; b < nblocks; ++b) s += part[b];
+  *total = s;
+}
 
 // diagnostics partials: per block, Neumaier sums of rho, m(3), E, b(3) and
 // max|div b|, min rho, min P, unphysical count

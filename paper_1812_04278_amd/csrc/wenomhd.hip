@@ -57,11 +57,14 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 //   acc   [8][N]   RK increment accumulator
 //   faces [21][N]  F^x, F^y, F^z (5 each), T^x, T^y, T^z (2 each)
 //   red            (doubles) dt, 3 signal-speed maxima, reduction partials
+//   wall  [5][ny nz] + [5][nx nz] + [5][nx ny]  lower-wall-face fluxes (walls)
 struct Layout {
-  size_t us, acc, faces, red, total;
+  size_t us, acc, faces, wall, red, total;
 };
 
-constexpr size_t kRedDoubles = 8 + 3 * RED_BLOCKS + 20 * RED_BLOCKS + 16;
+// red: dt, 3 signal-speed maxima, speed partials (3/block), diagnostics partials
+// (20/block), 12 diagnostics results and the floor count, floor partials (1/block)
+constexpr size_t kRedDoubles = 4 + 3 * RED_BLOCKS + 20 * RED_BLOCKS + 13 + RED_BLOCKS + 8;
 
 bool valid_config(const wm_config* c, const char** why) {
   if (!c) { *why = "null config"; return false; }
@@ -83,6 +86,19 @@ bool valid_config(const wm_config* c, const char** why) {
     return false;
   }
   if (c->integrator != WM_SSPRK3 && c->integrator != WM_RK4) { *why = "unknown integrator"; return false; }
+  const int n3[3] = {c->nx, c->ny, c->nz};
+  for (int d = 0; d < 3; ++d) {
+    if (c->walls[d] != 0 && c->walls[d] != 1) { *why = "walls must be 0 or 1"; return false; }
+    if (c->walls[d] && n3[d] < 3) { *why = "a walled axis needs at least 3 zones"; return false; }
+  }
+  if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0) || !std::isfinite(c->rho_floor) || !std::isfinite(c->p_floor)) {
+    *why = "floors must be finite and >= 0";
+    return false;
+  }
+  if ((c->rho_floor > 0.0 || c->p_floor > 0.0) && c->integrator != WM_SSPRK3) {
+    *why = "floors are applied to the SSP-RK3 stages";
+    return false;
+  }
   return true;
 }
 
@@ -98,6 +114,8 @@ Layout layout(const wm_config* c) {
   L.us = off;    off = align_up(off + 11 * N * es);
   L.acc = off;   off = align_up(off + 8 * N * es);
   L.faces = off; off = align_up(off + 21 * N * es);
+  L.wall = off;
+  off = align_up(off + 5 * ((size_t)c->ny * c->nz + (size_t)c->nx * c->nz + (size_t)c->nx * c->ny) * es);
   L.red = off;   off = align_up(off + kRedDoubles * sizeof(double));
   L.total = off;
   return L;
@@ -200,6 +218,8 @@ struct wm_patch {
   void* hydro = nullptr;     // bound state (storage type: double, or float when f32)
   void* bface = nullptr;
   void* bcell = nullptr;
+  bool floors = false;       // opt-in floors configured
+  bool floor_reset = true;   // the floor count restarts at the next floor pass
   int stage_done = -1;       // last completed stage of the current step (-1: none)
   bool dt_valid = false;
   TilePlan adj_plan[3];      // adjoint sweep launch classes per axis (grid sizes >= 3)
@@ -218,7 +238,15 @@ struct wm_patch {
   double* red() const { return reinterpret_cast<double*>(scratch + lay.red); }
   double* dt_dev() const { return red(); }                 // red[0]
   double* smax_dev() const { return red() + 1; }           // red[1..3]
-  double* diag_out() const { return red() + 4 + 3 * RED_BLOCKS + 20 * RED_BLOCKS; }  // 12 values
+  double* diag_out() const { return red() + 4 + 3 * RED_BLOCKS + 20 * RED_BLOCKS; }  // 12 values + floor count
+  double* floor_total() const { return diag_out() + 12; }
+  double* floor_part() const { return diag_out() + 13; }
+  // lower-wall-face fluxes of a walled axis: [5][nB * nC], the sweep's (across, plane) order
+  template <typename S> S* wallF(int axis) const {
+    S* w = reinterpret_cast<S*>(scratch + lay.wall);
+    const size_t yz = (size_t)g.ny * g.nz, xz = (size_t)g.nx * g.nz;
+    return axis == 0 ? w : (axis == 1 ? w + 5 * yz : w + 5 * (yz + xz));
+  }
   double* speed_part() const { return red() + 4; }
   double* diag_part() const { return red() + 4 + 3 * RED_BLOCKS; }
 };
@@ -266,11 +294,13 @@ wm_status launch_sweep(wm_patch* p, const S* hydro, const S* bcell, S* fh, S* T,
   a.fhydro = fh;
   a.T = T;
   a.dbg = dbg;
+  a.wallF = p->g.wall[AXIS] ? p->wallF<S>(AXIS) : nullptr;
   const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
   const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
   const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
-  dim3 grid((nA + TA - 1) / TA, (nB + TB - 1) / TB, nC);
+  // with walls the sweep also computes the lower wall face (-1/2)
+  dim3 grid((nA + p->g.wall[AXIS] + TA - 1) / TA, (nB + TB - 1) / TB, nC);
   const long r = prof_begin(p, K_SWEEP);
   if constexpr (sizeof(S) == 4) {   // FP32 state: the mixed arithmetic
     if (p->ph.weno_z)
@@ -318,6 +348,7 @@ wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
   a.acc = p->acc<S>();
   a.rhs_out = rhs_out;
   a.dt = p->dt_dev();
+  for (int d = 0; d < 3; ++d) a.wallF[d] = p->g.wall[d] ? p->wallF<S>(d) : nullptr;
   if (stage == n_stages(p) - 1) {
     a.hyd_out = p->hyd<S>();
     a.b_out = p->bf<S>();
@@ -402,6 +433,8 @@ wm_status check_adjoint(wm_patch* p, void* adj) {
   if (!p) return fail(WM_ERR_ARG, "null patch");
   if (!adj || reinterpret_cast<uintptr_t>(adj) % kAlign) return fail(WM_ERR_ARG, "adjoint scratch null or misaligned");
   if (p->cfg.nx < 3 || p->cfg.ny < 3 || p->cfg.nz < 3) return fail(WM_ERR_ARG, "the adjoint needs grid sizes >= 3");
+  if (p->g.wall[0] || p->g.wall[1] || p->g.wall[2] || p->floors)
+    return fail(WM_ERR_ARG, "the adjoint is for periodic boxes without floors");
   return WM_OK;
 }
 
@@ -452,6 +485,7 @@ wm_status forward_stages(wm_patch* p, const S* Uh, const S* Ub, S* Bz, const dou
     a.acc = acc;
     a.rhs_out = nullptr;
     a.dt = dtp;
+    for (int d = 0; d < 3; ++d) a.wallF[d] = nullptr;   // the adjoint is for periodic boxes
     S* out = outs[st];
     a.hyd_out = out;
     a.b_out = out + 5 * N;
@@ -495,6 +529,9 @@ void setup_patch(wm_patch* p, const wm_config* cfg, void* hip_stream, void* scra
   p->stream = reinterpret_cast<hipStream_t>(hip_stream);
   p->g.nx = cfg->nx; p->g.ny = cfg->ny; p->g.nz = cfg->nz;
   p->g.N = (size_t)cfg->nx * cfg->ny * cfg->nz;
+  for (int d = 0; d < 3; ++d) p->g.wall[d] = cfg->walls[d];
+  p->floors = cfg->rho_floor > 0.0 || cfg->p_floor > 0.0;
+  p->floor_reset = true;
   p->ph.gamma = cfg->gamma;
   p->ph.inv_h = 1.0 / cfg->h;
   p->ph.eps = cfg->eps_weno;
@@ -506,6 +543,20 @@ void setup_patch(wm_patch* p, const wm_config* cfg, void* hip_stream, void* scra
   p->scratch = reinterpret_cast<char*>(scratch_buf);
   p->lay = L;
   p->f32 = cfg->precision == WM_MIXED_F32STATE;
+}
+
+// Opt-in floors on a stage result (hydro with its zone field) and the count.
+template <typename S>
+wm_status launch_floors(wm_patch* p, S* hydro, const S* bcell) {
+  const int nb = red_blocks(p->g);
+  hipLaunchKernelGGL(floor_kernel<S>, dim3(nb), dim3(RED_THREADS), 0, p->stream, p->g.N, p->cfg.gamma,
+                     p->cfg.rho_floor, p->cfg.p_floor, hydro, bcell, p->floor_part());
+  WM_LAUNCH_CHECK("floor kernel");
+  hipLaunchKernelGGL(floor_final_kernel, dim3(1), dim3(1), 0, p->stream, nb, p->floor_part(), p->floor_total(),
+                     p->floor_reset ? 1 : 0);
+  WM_LAUNCH_CHECK("floor count kernel");
+  p->floor_reset = false;
+  return WM_OK;
 }
 
 // Device address of `scratch` on the current device, looked up once per device
@@ -547,6 +598,9 @@ void wm_config_default(wm_config* c, int n) {
   c->weights = WM_WENO_JS;
   c->precision = WM_FP64;
   c->integrator = WM_SSPRK3;
+  c->walls[0] = c->walls[1] = c->walls[2] = 0;
+  c->rho_floor = 0.0;
+  c->p_floor = 0.0;
 }
 
 size_t wm_scratch_bytes(const wm_config* cfg) {
@@ -600,6 +654,7 @@ wm_status wm_bind_state(wm_patch* p, void* hydro, void* bface, void* bcell) {
   p->bcell = bcell;
   p->stage_done = -1;
   p->dt_valid = false;
+  p->floor_reset = true;
   return WM_OK;
 }
 
@@ -624,12 +679,14 @@ wm_status wm_init_from_potential(wm_patch* p, const double* rho, const double* v
   if (s != WM_OK) return s;
   p->stage_done = -1;
   p->dt_valid = false;
+  p->floor_reset = true;
   return WM_OK;
 }
 
 wm_status wm_refresh_zone_field(wm_patch* p) {
   wm_status s = check_bound(p);
   if (s != WM_OK) return s;
+  p->floor_reset = true;
   return with_storage(p, [&](auto tag) {
     using S = decltype(tag);
     return launch_bcell<S>(p, p->bf<S>(), p->bc<S>());
@@ -684,8 +741,11 @@ wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
     wm_status st;
     if ((st = sweeps<S>(p, hyd_in, bcell_in)) != WM_OK) return st;
     if ((st = launch_update<S>(p, stage, nullptr)) != WM_OK) return st;
-    if (stage == ns - 1) return launch_bcell<S>(p, p->bf<S>(), p->bc<S>());
-    return launch_bcell<S>(p, p->us<S>() + 5 * N, p->us<S>() + 8 * N);
+    S* hyd_out = stage == ns - 1 ? p->hyd<S>() : p->us<S>();
+    S* b_out = stage == ns - 1 ? p->bf<S>() : p->us<S>() + 5 * N;
+    S* bc_out = stage == ns - 1 ? p->bc<S>() : p->us<S>() + 8 * N;
+    if ((st = launch_bcell<S>(p, b_out, bc_out)) != WM_OK) return st;
+    return p->floors ? launch_floors<S>(p, hyd_out, bc_out) : WM_OK;
   });
   if (s != WM_OK) return s;
   if (stage == ns - 1) {
@@ -755,7 +815,7 @@ wm_status wm_diagnostics(wm_patch* p, wm_diag* out) {
   WM_LAUNCH_CHECK("diag kernel");
   hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, p->stream, nb, p->diag_part(), p->diag_out());
   WM_LAUNCH_CHECK("diag final kernel");
-  double h[12];
+  double h[13];
   if ((s = hip_check(hipMemcpyAsync(h, p->diag_out(), sizeof(h), hipMemcpyDeviceToHost, p->stream), "diag copy")) !=
       WM_OK)
     return s;
@@ -768,6 +828,7 @@ wm_status wm_diagnostics(wm_patch* p, wm_diag* out) {
   out->min_rho = h[9];
   out->min_p = h[10];
   out->n_unphysical = (long long)h[11];
+  out->n_floored = (p->floors && !p->floor_reset) ? (long long)h[12] : 0;
   if (out->n_unphysical > 0) return fail(WM_ERR_UNPHYSICAL, "unphysical zones in the state%s");
   return WM_OK;
 }

@@ -212,3 +212,29 @@ def assert_diag_parity(g, o, U, h):
     if g["n_unphysical"] != o["n_unphysical"]:
         bad.append(("n_unphysical", g["n_unphysical"], o["n_unphysical"], 0))
     assert not bad, bad
+
+
+def walled_state(n=(12, 10, 8), seed=3, v_rms=0.8, walls=(True, False, False)):
+    """Generator fields on an nx x ny x nz box whose face field has no normal
+    component on the wall faces: the edge potential components tangential to
+    each wall vanish on it (edge index n-1 along the walled axis is the wall,
+    -1/2 and n-1/2 being the same index), and the uniform field has no normal
+    component there; b = B0 + curl_h A keeps div_h b = 0."""
+    nx, ny, nz = n
+    m = max(n)
+    f = inputs.random_fields(m + (m % 2), seed, v_rms, kmax=2, B0=(0.0, 0.0, 0.0))
+    rho = np.ascontiguousarray(f.rho[:nz, :ny, :nx])
+    v = np.ascontiguousarray(f.v[:, :nz, :ny, :nx])
+    A = np.array(f.A[:, :nz, :ny, :nx])
+    B0 = [0.3, 0.6, 0.8]
+    for axis in range(3):
+        if walls[axis]:
+            B0[axis] = 0.0
+            for c in range(3):
+                if c != axis:                       # tangential components on the wall edges
+                    idx = [slice(None)] * 3
+                    idx[2 - axis] = n[axis] - 1
+                    A[(c,) + tuple(idx)] = 0.0
+    cfg = mhd.Config(nx, ny, nz, 1.0 / m, walls=tuple(walls))
+    U = mhd.init_from_potential(rho, v, A, f.P0, B0, cfg)
+    return U, cfg

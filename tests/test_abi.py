@@ -56,6 +56,24 @@ def test_invalid_config_rejected(field, value):
     assert lib.wm_last_error().decode().startswith("invalid config")
 
 
+@pytest.mark.parametrize("kw", [dict(walls=(1, 0, 0), nx=2), dict(walls=(0, 2, 0)), dict(rho_floor=-1.0),
+                                dict(p_floor=float("nan")), dict(rho_floor=0.1, integrator=1)])
+def test_invalid_walls_and_floors_rejected(kw):
+    """A walled axis needs three zones (the mirror stencil), walls are 0 or 1,
+    floors are finite and non-negative and apply to the SSP-RK3 stages."""
+    lib = B.load()
+    args = dict(n=16)
+    args.update(kw)
+    c = B.config(**args)
+    assert lib.wm_scratch_bytes(ctypes.byref(c)) == 0
+
+
+def test_walls_and_floors_accepted():
+    lib = B.load()
+    c = B.config(16, walls=(1, 0, 1), rho_floor=1e-3, p_floor=1e-4)
+    assert lib.wm_scratch_bytes(ctypes.byref(c)) > lib.wm_scratch_bytes(ctypes.byref(B.config(16))) - 1
+
+
 def test_patch_create_argument_errors():
     lib = B.load()
     c = B.config(16)
