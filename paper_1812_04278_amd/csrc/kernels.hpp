@@ -65,6 +65,9 @@ struct SweepArgs {
   S* T;                  // [2][N] transport fluxes T^n_t1, T^n_t2
   double* dbg;           // optional [9][N]: 7 sweep-frame flux components + 2 T
   S* wallF;              // walled sweep axis: [5][nB * nC] fluxes through the lower wall face
+#ifdef WM_SWEEP_CLOCK
+  unsigned long long* clk;   // clock build: [block][wave][8] phase stamps, or null
+#endif
 };
 
 // Zone index along a sweep axis of n zones for a stencil position z: periodic
@@ -129,9 +132,22 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
   const int b0 = blockIdx.y * TB;
   const int c = blockIdx.z;
   const int tid = threadIdx.x;
+#ifdef WM_SWEEP_CLOCK
+  // clock build: per-wave shader-clock stamps at the phase boundaries
+  unsigned long long stamp[8];
+  stamp[0] = clock64();
+#endif
 
-  // ---- (1) zone prologue, zones i-2 .. i+TA+2 along the axis with periodic wrap
-  for (int cell = tid; cell < NC; cell += SW_THREADS) {
+  // ---- (1) zone prologue, zones i-2 .. i+TA+2 along the axis (periodic wrap
+  // or wall mirror).  The tile has more zones than lanes (NR = 2 per lane at
+  // most): every lane issues the loads of all its zones before evaluating any,
+  // so the block waits for one round trip to memory, not two.  Lanes past the
+  // last zone load it again and discard it.
+  constexpr int NR = (NC + SW_THREADS - 1) / SW_THREADS;
+  double raw[NR][8];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int cell = min(tid + r * SW_THREADS, NC - 1);
     int aa, bb;
     if (AXIS == 0) { aa = cell % NA; bb = cell / NA; }
     else           { bb = cell % TB; aa = cell / TB; }
@@ -143,12 +159,21 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
     else if (AXIS == 1) { i = ib; j = ia; k = c; }
     else                { i = ib; j = c;  k = ia; }
     const size_t gi = g.at(i, j, k);
-    double m[3] = {a.hydro[g.N + gi], a.hydro[2 * g.N + gi], a.hydro[3 * g.N + gi]};
-    double B[3] = {a.bcell[gi], a.bcell[g.N + gi], a.bcell[2 * g.N + gi]};
-    m[CN] *= flip;
-    B[CN] *= flip;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) raw[r][v] = double(a.hydro[v * g.N + gi]);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) raw[r][5 + v] = double(a.bcell[v * g.N + gi]);
+    raw[r][1 + CN] *= flip;
+    raw[r][5 + CN] *= flip;
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int cell = tid + r * SW_THREADS;
+    if (cell >= NC) continue;
+    const double* m = raw[r] + 1;
+    const double* B = raw[r] + 5;
     double z[Z_NVAR];
-    zone_prologue(a.hydro[gi], m[CN], m[CT1], m[CT2], a.hydro[4 * g.N + gi], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
+    zone_prologue(raw[r][0], m[CN], m[CT1], m[CT2], raw[r][4], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
 #pragma unroll
     for (int v = 0; v < SW_NQ; ++v) Q[v * NC + cell] = z[v];
     Pz[P_RHO * NC + cell] = TW(z[Z_RHO]);
@@ -163,7 +188,13 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
     Pz[P_CA * NC + cell] = TW(z[Z_CA]);
     Pz[P_CS * NC + cell] = TW(z[Z_CS]);
   }
+#ifdef WM_SWEEP_CLOCK
+  stamp[1] = clock64();
+#endif
   __syncthreads();
+#ifdef WM_SWEEP_CLOCK
+  stamp[2] = clock64();
+#endif
 
   // ---- (2) per face: central flux, face state, LF speeds, own interface differences
   int fa, fb;
@@ -207,6 +238,9 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
       for (int v = 0; v < SW_NQ; ++v) d1[v] = Q[v * NC + c3] - Q[v * NC + c2];
     }
   }
+#ifdef WM_SWEEP_CLOCK
+  stamp[3] = clock64();
+#endif
   __syncthreads();
   // differences stored as (Delta F, Delta q): j = 0..6 flux, 7..13 state
 #pragma unroll
@@ -222,6 +256,9 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
     }
   }
   __syncthreads();
+#ifdef WM_SWEEP_CLOCK
+  stamp[4] = clock64();
+#endif
 
   // ---- (3) characteristic WENO flux of this face
   auto dl = [&](int j, int k) -> TW { return Dl[j * NIF + iidx(fa + k, fb)]; };
@@ -234,6 +271,9 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
   for (int j = 0; j < 7; ++j) Ff[j] = Fc[j] + corr[j];
   const double T1 = Ff[4] + tc1;
   const double T2 = Ff[5] + tc2;
+#ifdef WM_SWEEP_CLOCK
+  stamp[5] = clock64();
+#endif
 
   // keep the face computation ahead of the range guard: sinking it into the
   // guarded block defeats register allocation (hundreds of spills)
@@ -271,6 +311,16 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
     a.dbg[8 * g.N + gi] = T2;
   }
   }
+#ifdef WM_SWEEP_CLOCK
+  stamp[6] = clock64();
+  stamp[7] = __smid();
+  if (a.clk && (tid & 63) == 0) {
+    const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    unsigned long long* o = a.clk + (blk * (SW_THREADS / 64) + tid / 64) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = stamp[q];
+  }
+#endif
 }
 
 // ---------------------------------------------------------------------------

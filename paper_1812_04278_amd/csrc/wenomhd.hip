@@ -17,6 +17,13 @@
 
 using namespace wm;
 
+#ifdef WM_SWEEP_CLOCK
+#include "../../include/wenomhd_clock.h"
+// clock build: process-wide per-axis stamp buffers (device) and their capacity
+static unsigned long long* g_sweep_clk[3] = {nullptr, nullptr, nullptr};
+static size_t g_sweep_clk_n[3] = {0, 0, 0};
+#endif
+
 // Device scratch of wm_step_static, for callers that cannot allocate: one copy
 // of this array per GPU the library runs on, held until the process ends.
 // Host code never passes the array's name to a kernel or a copy (on the host
@@ -295,12 +302,18 @@ wm_status launch_sweep(wm_patch* p, const S* hydro, const S* bcell, S* fh, S* T,
   a.T = T;
   a.dbg = dbg;
   a.wallF = p->g.wall[AXIS] ? p->wallF<S>(AXIS) : nullptr;
+#ifdef WM_SWEEP_CLOCK
+  a.clk = nullptr;
+#endif
   const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
   const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
   const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
   constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
   // with walls the sweep also computes the lower wall face (-1/2)
   dim3 grid((nA + p->g.wall[AXIS] + TA - 1) / TA, (nB + TB - 1) / TB, nC);
+#ifdef WM_SWEEP_CLOCK
+  if ((size_t)grid.x * grid.y * grid.z * (SW_THREADS / 64) * 8 <= g_sweep_clk_n[AXIS]) a.clk = g_sweep_clk[AXIS];
+#endif
   const long r = prof_begin(p, K_SWEEP);
   if constexpr (sizeof(S) == 4) {   // FP32 state: the mixed arithmetic
     if (p->ph.weno_z)
@@ -1068,3 +1081,13 @@ wm_status wm_profile_report(wm_patch* p, double* out, int n_out) {
 const char* wm_last_error(void) { return g_err; }
 
 }  // extern "C"
+
+#ifdef WM_SWEEP_CLOCK
+extern "C" wm_status wm_clock_sweep_buffer(int axis, void* stamps, size_t n_stamps) {
+  if (axis < 0 || axis > 2) return fail(WM_ERR_ARG, "axis must be 0, 1 or 2");
+  if (stamps == nullptr) n_stamps = 0;
+  g_sweep_clk[axis] = static_cast<unsigned long long*>(stamps);
+  g_sweep_clk_n[axis] = n_stamps;
+  return WM_OK;
+}
+#endif

@@ -27,6 +27,23 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_clock_build_exports_its_call():
+    """The phase-clock measurement build exports the call of its own header;
+    the product library does not."""
+    from paper_1812_04278_amd import build
+    text = open(os.path.join(ROOT, "include", "wenomhd_clock.h")).read()
+    names = sorted(set(re.findall(r"\b(wm_[a-z_0-9]+)\s*\(", re.sub(r"/\*.*?\*/", "", text, flags=re.S))))
+    assert names == ["wm_clock_sweep_buffer"]
+    if not os.path.exists(build.CLOCK_LIB):
+        pytest.skip("clock build not present")
+    clk = ctypes.CDLL(build.CLOCK_LIB)
+    assert hasattr(clk, "wm_clock_sweep_buffer")
+    clk.wm_clock_sweep_buffer.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
+    assert clk.wm_clock_sweep_buffer(3, None, 0) != 0          # invalid axis, no GPU touched
+    assert clk.wm_clock_sweep_buffer(0, None, 0) == 0          # unregister
+    assert not hasattr(B.load(), "wm_clock_sweep_buffer")
+
+
 def test_scratch_bytes_and_default_config():
     lib = B.load()
     c = B.WmConfig()
