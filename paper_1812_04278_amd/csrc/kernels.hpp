@@ -465,6 +465,182 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
   }
 }
 
+// The update of an FP32 state, two x-adjacent zones (i0 even, i0 + 1) per
+// thread: every load and store of the zone pair moves 8 bytes, so a wave keeps
+// as many bytes in flight as the FP64 kernel (4-byte loads halve them, and the
+// FP32 update is bound by the latency of its many streams).  Needs nx even
+// (and arrays at even float offsets); blocks of 64 x 8 zones.  Each zone's
+// arithmetic is update_kernel's, term by term in the same order (the compiler
+// may still fuse a different product into an FMA).
+template <int RK, int STAGE>
+__global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<float> a) {
+  static_assert((RK == 3 && STAGE >= 0 && STAGE < 3) || (RK == 4 && STAGE >= 0 && STAGE < 4), "stage of the scheme");
+  const Grid& g = a.g;
+  const int i0 = blockIdx.x * 64 + 2 * (threadIdx.x & 31);
+  const int j = blockIdx.y * 8 + (threadIdx.x >> 5);
+  const int k = blockIdx.z;
+  if (i0 >= g.nx || j >= g.ny) return;
+  const int nx = g.nx;
+  const int jm = j == 0 ? g.ny - 1 : j - 1, jp = j + 1 == g.ny ? 0 : j + 1;
+  const int km = k == 0 ? g.nz - 1 : k - 1, kp = k + 1 == g.nz ? 0 : k + 1;
+  const int imm = i0 == 0 ? nx - 2 : i0 - 2;          // pair holding zone i0 - 1 (as .y)
+  const int ipp = i0 + 2 == nx ? 0 : i0 + 2;          // pair holding zone i0 + 2 (as .x)
+  const size_t N = g.N;
+  const size_t c0 = g.at(i0, j, k);
+  const double ih = a.inv_h;
+  struct D2 { double x, y; };
+  auto pr = [&](const float* q, int jj, int kk) -> D2 {      // zones i0, i0 + 1
+    const float2 t = *reinterpret_cast<const float2*>(q + g.at(i0, jj, kk));
+    return {double(t.x), double(t.y)};
+  };
+  auto lo = [&](const float* q, int jj, int kk) -> double {  // zone i0 - 1
+    return double(reinterpret_cast<const float2*>(q + g.at(imm, jj, kk))->y);
+  };
+  auto hi = [&](const float* q, int jj, int kk) -> double {  // zone i0 + 2
+    return double(reinterpret_cast<const float2*>(q + g.at(ipp, jj, kk))->x);
+  };
+  const float* Fx = a.faces;
+  const float* Fy = a.faces + 5 * N;
+  const float* Fz = a.faces + 10 * N;
+  double kv[2][8];
+  const bool lwx = g.wall[0] && i0 == 0, lwy = g.wall[1] && j == 0, lwz = g.wall[2] && k == 0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const size_t o = v * N;
+    const D2 fx = pr(Fx + o, j, k), fy = pr(Fy + o, j, k), fz = pr(Fz + o, j, k);
+    const double fxm0 = lwx ? double(a.wallF[0][(size_t)v * g.ny * g.nz + j + (size_t)g.ny * k]) : lo(Fx + o, j, k);
+    D2 fym, fzm;
+    // the wall-face planes may start at an odd float offset: two 4-byte loads
+    if (lwy) {
+      const float* w = a.wallF[1] + (size_t)v * nx * g.nz + i0 + (size_t)nx * k;
+      fym = {double(w[0]), double(w[1])};
+    } else {
+      fym = pr(Fy + o, jm, k);
+    }
+    if (lwz) {
+      const float* w = a.wallF[2] + (size_t)v * nx * g.ny + i0 + (size_t)nx * j;
+      fzm = {double(w[0]), double(w[1])};
+    } else {
+      fzm = pr(Fz + o, j, km);
+    }
+    kv[0][v] = (-(fx.x - fxm0) * ih + -(fy.x - fym.x) * ih) + -(fz.x - fzm.x) * ih;
+    kv[1][v] = (-(fx.y - fx.x) * ih + -(fy.y - fym.y) * ih) + -(fz.y - fzm.y) * ih;
+  }
+  const float* Txy = a.faces + 15 * N;
+  const float* Txz = a.faces + 16 * N;
+  const float* Tyz = a.faces + 17 * N;
+  const float* Tyx = a.faces + 18 * N;
+  const float* Tzx = a.faces + 19 * N;
+  const float* Tzy = a.faces + 20 * N;
+  // corner fluxes (eq. ox1-ox3) as in update_kernel; x positions: m = i0 - 1,
+  // 0 = i0, 1 = i0 + 1, p = i0 + 2; zero on edges in a wall plane
+  const bool w0top = g.wall[0] && i0 + 1 == nx - 1;   // zone i0 + 1's upper x edge lies in the wall
+  const bool w1 = g.wall[1], w2 = g.wall[2];
+  const bool w0m = g.wall[0] && i0 == 0;              // the edge below zone i0 (index nx - 1) is a wall edge
+  // Ez(ii, jj) = (Tyx(ii) + Tyx(ii+1))/2 - (Txy(jj) + Txy(jj+1))/2
+  const D2 yxj = pr(Tyx, j, k), yxm = pr(Tyx, jm, k);
+  const double yxj_m = lo(Tyx, j, k), yxj_p = hi(Tyx, j, k), yxm_p = hi(Tyx, jm, k);
+  const D2 xyj = pr(Txy, j, k), xyp = pr(Txy, jp, k), xym = pr(Txy, jm, k);
+  const double xyj_m = lo(Txy, j, k), xyp_m = lo(Txy, jp, k);
+  const bool zj = w1 && j == g.ny - 1, zjm = w1 && jm == g.ny - 1;
+  const double ez0 = zj ? 0.0 : 0.5 * (yxj.x + yxj.y) - 0.5 * (xyj.x + xyp.x);
+  const double ez1 = (zj || w0top) ? 0.0 : 0.5 * (yxj.y + yxj_p) - 0.5 * (xyj.y + xyp.y);
+  const double ezm = (zj || w0m) ? 0.0 : 0.5 * (yxj_m + yxj.x) - 0.5 * (xyj_m + xyp_m);
+  const double ez0_jm = zjm ? 0.0 : 0.5 * (yxm.x + yxm.y) - 0.5 * (xym.x + xyj.x);
+  const double ez1_jm = (zjm || w0top) ? 0.0 : 0.5 * (yxm.y + yxm_p) - 0.5 * (xym.y + xyj.y);
+  // Ex(jj, kk) = (Tzy(jj) + Tzy(jj+1))/2 - (Tyz(kk) + Tyz(kk+1))/2, at each zone's own x
+  const D2 zy_jk = pr(Tzy, j, k), zy_pk = pr(Tzy, jp, k), zy_jkm = pr(Tzy, j, km), zy_pkm = pr(Tzy, jp, km);
+  const D2 zy_mk = pr(Tzy, jm, k);
+  const D2 yz_jk = pr(Tyz, j, k), yz_jkp = pr(Tyz, j, kp), yz_jkm = pr(Tyz, j, km), yz_mk = pr(Tyz, jm, k),
+           yz_mkp = pr(Tyz, jm, kp);
+  const bool zk = w2 && k == g.nz - 1, zkm = w2 && km == g.nz - 1;
+  auto exf = [](double a0, double a1, double b0, double b1) { return 0.5 * (a0 + a1) - 0.5 * (b0 + b1); };
+  const double ex0 = (zj || zk) ? 0.0 : exf(zy_jk.x, zy_pk.x, yz_jk.x, yz_jkp.x);
+  const double ex1 = (zj || zk) ? 0.0 : exf(zy_jk.y, zy_pk.y, yz_jk.y, yz_jkp.y);
+  const double ex0_km = (zj || zkm) ? 0.0 : exf(zy_jkm.x, zy_pkm.x, yz_jkm.x, yz_jk.x);
+  const double ex1_km = (zj || zkm) ? 0.0 : exf(zy_jkm.y, zy_pkm.y, yz_jkm.y, yz_jk.y);
+  const double ex0_jm = (zjm || zk) ? 0.0 : exf(zy_mk.x, zy_jk.x, yz_mk.x, yz_mkp.x);
+  const double ex1_jm = (zjm || zk) ? 0.0 : exf(zy_mk.y, zy_jk.y, yz_mk.y, yz_mkp.y);
+  // Ey(ii, kk) = (Txz(kk) + Txz(kk+1))/2 - (Tzx(ii) + Tzx(ii+1))/2
+  const D2 xzk = pr(Txz, j, k), xzp = pr(Txz, j, kp), xzm = pr(Txz, j, km);
+  const double xzk_m = lo(Txz, j, k), xzp_m = lo(Txz, j, kp);
+  const D2 zxk = pr(Tzx, j, k), zxm = pr(Tzx, j, km);
+  const double zxk_m = lo(Tzx, j, k), zxk_p = hi(Tzx, j, k), zxm_p = hi(Tzx, j, km);
+  const double ey0 = zk ? 0.0 : 0.5 * (xzk.x + xzp.x) - 0.5 * (zxk.x + zxk.y);
+  const double ey1 = (zk || w0top) ? 0.0 : 0.5 * (xzk.y + xzp.y) - 0.5 * (zxk.y + zxk_p);
+  const double eym = (zk || w0m) ? 0.0 : 0.5 * (xzk_m + xzp_m) - 0.5 * (zxk_m + zxk.x);
+  const double ey0_km = zkm ? 0.0 : 0.5 * (xzm.x + xzk.x) - 0.5 * (zxm.x + zxm.y);
+  const double ey1_km = (zkm || w0top) ? 0.0 : 0.5 * (xzm.y + xzk.y) - 0.5 * (zxm.y + zxm_p);
+  // Sect. 2.3 face-field equations, per zone
+  const double ez[2] = {ez0, ez1}, ez_jm[2] = {ez0_jm, ez1_jm}, ez_im[2] = {ezm, ez0};
+  const double ex[2] = {ex0, ex1}, ex_km[2] = {ex0_km, ex1_km}, ex_jm[2] = {ex0_jm, ex1_jm};
+  const double ey[2] = {ey0, ey1}, ey_km[2] = {ey0_km, ey1_km}, ey_im[2] = {eym, ey0};
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+    kv[z][5] = -(ez[z] - ez_jm[z]) * ih + (ey[z] - ey_km[z]) * ih;
+    kv[z][6] = -(ex[z] - ex_km[z]) * ih + (ez[z] - ez_im[z]) * ih;
+    kv[z][7] = -(ey[z] - ey_im[z]) * ih + (ex[z] - ex_jm[z]) * ih;
+  }
+  if (g.wall[0] && i0 + 1 == nx - 1) kv[1][5] = 0.0;
+  if (g.wall[1] && j == g.ny - 1) { kv[0][6] = 0.0; kv[1][6] = 0.0; }
+  if (g.wall[2] && k == g.nz - 1) { kv[0][7] = 0.0; kv[1][7] = 0.0; }
+
+  if (a.rhs_out) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      a.rhs_out[v * N + c0] = kv[0][v];
+      a.rhs_out[v * N + c0 + 1] = kv[1][v];
+    }
+    return;
+  }
+  const double dt = *a.dt;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const float* unp = v < 5 ? a.Un + v * N : a.bn + (v - 5) * N;
+    const float2 u = *reinterpret_cast<const float2*>(unp + c0);
+    const double un[2] = {double(u.x), double(u.y)};
+    float2* accp = reinterpret_cast<float2*>(a.acc + v * N + c0);
+    double out[2], acc_new[2];
+    double acc_old[2] = {0.0, 0.0};
+    if constexpr (STAGE > 0) {
+      const float2 t = *accp;
+      acc_old[0] = double(t.x);
+      acc_old[1] = double(t.y);
+    }
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      if constexpr (RK == 3) {
+        if constexpr (STAGE == 0) {
+          acc_new[z] = kv[z][v];
+          out[z] = un[z] + dt * kv[z][v];
+        } else if constexpr (STAGE == 1) {
+          const double s = acc_old[z] + kv[z][v];
+          acc_new[z] = s;
+          out[z] = un[z] + (0.25 * dt) * s;
+        } else {
+          const double s = acc_old[z] + 4.0 * kv[z][v];
+          out[z] = un[z] + (dt / 6.0) * s;
+        }
+      } else {
+        if constexpr (STAGE == 0) {
+          acc_new[z] = kv[z][v];
+          out[z] = un[z] + (0.5 * dt) * kv[z][v];
+        } else if constexpr (STAGE < 3) {
+          acc_new[z] = acc_old[z] + 2.0 * kv[z][v];
+          out[z] = un[z] + (STAGE == 1 ? 0.5 * dt : dt) * kv[z][v];
+        } else {
+          const double s = acc_old[z] + kv[z][v];
+          out[z] = un[z] + (dt / 6.0) * s;
+        }
+      }
+    }
+    constexpr bool writes_acc = RK == 3 ? STAGE < 2 : STAGE < 3;
+    if constexpr (writes_acc) *accp = make_float2(float(acc_new[0]), float(acc_new[1]));
+    float* outp = v < 5 ? a.hyd_out + v * N : a.b_out + (v - 5) * N;
+    *reinterpret_cast<float2*>(outp + c0) = make_float2(float(out[0]), float(out[1]));
+  }
+}
+
 // zone B = (-b_{i-2} + 9 b_{i-1} + 9 b_i - b_{i+1}) / 16 along each component's own axis
 template <typename S>
 __global__ __launch_bounds__(256) void bcell_kernel(Grid g, const S* b, S* B) {

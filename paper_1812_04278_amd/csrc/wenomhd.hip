@@ -349,6 +349,42 @@ wm_status sweeps(wm_patch* p, const S* hydro, const S* bcell) {
 
 int n_stages(const wm_patch* p) { return p->cfg.integrator == WM_RK4 ? 4 : 3; }
 
+// Launches the update of one stage: for an FP32 state with nx even and every
+// array at an 8-byte boundary, the two-zone kernel (8-byte loads), else one
+// zone per thread.
+template <int RK, int STAGE, typename S>
+void launch_update_kernel(wm_patch* p, const UpdateArgs<S>& a) {
+  if constexpr (sizeof(S) == 4) {
+    auto al8 = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 7) == 0; };
+    bool pair = p->g.nx % 2 == 0 && al8(a.faces) && al8(a.Un) && al8(a.bn) && al8(a.acc) && al8(a.hyd_out) &&
+                al8(a.b_out);
+    if (pair) {
+      const dim3 grid((p->g.nx + 63) / 64, (p->g.ny + 7) / 8, p->g.nz);
+      hipLaunchKernelGGL((update_pair_kernel<RK, STAGE>), grid, dim3(256), 0, p->stream, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((update_kernel<RK, STAGE, S>), zone_grid(p->g), dim3(256), 0, p->stream, a);
+}
+
+template <typename S>
+void launch_update_stage(wm_patch* p, const UpdateArgs<S>& a, bool rk4, int stage) {
+  if (rk4) {
+    switch (stage) {
+      case 0: launch_update_kernel<4, 0, S>(p, a); break;
+      case 1: launch_update_kernel<4, 1, S>(p, a); break;
+      case 2: launch_update_kernel<4, 2, S>(p, a); break;
+      default: launch_update_kernel<4, 3, S>(p, a); break;
+    }
+  } else {
+    switch (stage) {
+      case 0: launch_update_kernel<3, 0, S>(p, a); break;
+      case 1: launch_update_kernel<3, 1, S>(p, a); break;
+      default: launch_update_kernel<3, 2, S>(p, a); break;
+    }
+  }
+}
+
 template <typename S>
 wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
   const size_t N = p->g.N;
@@ -369,22 +405,8 @@ wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
     a.hyd_out = p->us<S>();
     a.b_out = p->us<S>() + 5 * N;
   }
-  dim3 grid = zone_grid(p->g);
   const long r = prof_begin(p, K_UPDATE);
-  if (p->cfg.integrator == WM_RK4) {
-    switch (stage) {
-      case 0: hipLaunchKernelGGL((update_kernel<4, 0, S>), grid, dim3(256), 0, p->stream, a); break;
-      case 1: hipLaunchKernelGGL((update_kernel<4, 1, S>), grid, dim3(256), 0, p->stream, a); break;
-      case 2: hipLaunchKernelGGL((update_kernel<4, 2, S>), grid, dim3(256), 0, p->stream, a); break;
-      default: hipLaunchKernelGGL((update_kernel<4, 3, S>), grid, dim3(256), 0, p->stream, a); break;
-    }
-  } else {
-    switch (stage) {
-      case 0: hipLaunchKernelGGL((update_kernel<3, 0, S>), grid, dim3(256), 0, p->stream, a); break;
-      case 1: hipLaunchKernelGGL((update_kernel<3, 1, S>), grid, dim3(256), 0, p->stream, a); break;
-      default: hipLaunchKernelGGL((update_kernel<3, 2, S>), grid, dim3(256), 0, p->stream, a); break;
-    }
-  }
+  launch_update_stage<S>(p, a, p->cfg.integrator == WM_RK4, stage);
   WM_LAUNCH_CHECK("update kernel");
   prof_end(p, r);
   return WM_OK;
@@ -502,15 +524,7 @@ wm_status forward_stages(wm_patch* p, const S* Uh, const S* Ub, S* Bz, const dou
     S* out = outs[st];
     a.hyd_out = out;
     a.b_out = out + 5 * N;
-    const dim3 grid = zone_grid(p->g);
-    if (rk4) {
-      if (st == 0) hipLaunchKernelGGL((update_kernel<4, 0, S>), grid, dim3(256), 0, p->stream, a);
-      else if (st == 1) hipLaunchKernelGGL((update_kernel<4, 1, S>), grid, dim3(256), 0, p->stream, a);
-      else hipLaunchKernelGGL((update_kernel<4, 2, S>), grid, dim3(256), 0, p->stream, a);
-    } else {
-      if (st == 0) hipLaunchKernelGGL((update_kernel<3, 0, S>), grid, dim3(256), 0, p->stream, a);
-      else hipLaunchKernelGGL((update_kernel<3, 1, S>), grid, dim3(256), 0, p->stream, a);
-    }
+    launch_update_stage<S>(p, a, rk4, st);
     WM_LAUNCH_CHECK("update kernel");
     if ((s = launch_bcell<S>(p, out + 5 * N, out + 8 * N)) != WM_OK) return s;
   }

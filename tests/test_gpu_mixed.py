@@ -14,6 +14,8 @@ FP32 state (WM_MIXED_F32STATE: the mixed arithmetic with hydro, face b, zone B,
 stage states, accumulator and face fluxes stored in FP32; each store rounds to
 ~6e-8 relative):
   one step, 32^3 Mach 0.1 ........................ <= 1e-6  vs the oracle
+  one step, 36 and 37 x 21 x 19 Mach 1 ........... <= 1e-6  vs the oracle (two-zone
+                                                   and one-zone update)
   ten steps, 64^3 Mach 2 ......................... <= 2e-5  vs the oracle
   ten steps, 128^3 Mach 0.1 ...................... L1 per variable <= 1e-6 vs FP64
 """
@@ -162,6 +164,25 @@ def test_f32state_one_step_32():
     dt = p.step(want_dt=True)
     U1, dt_o = mhd.step(U, cfg)
     assert abs(dt - dt_o) <= 1e-6 * dt_o
+    errs = state_errors(p.state(), U1)
+    say("  ", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-6, errs
+
+
+@pytest.mark.parametrize("nx", [36, 37])
+def test_f32state_one_step_ragged(nx):
+    """FP32 state on a ragged box (nx x 21 x 19, Mach ~1): with nx even the
+    update takes two x-adjacent zones per thread (8-byte loads), with nx odd one;
+    both against the oracle stepped from the same FP32-rounded state."""
+    say(f"FP32 state, one step {nx}x21x19")
+    f = fields(40, seed=7, v_rms=1.0, crop=(nx, 21, 19))
+    U, cfg = oracle_state(f)
+    Uf = {k: v.float().double() for k, v in U.items()}
+    p = B.Patch(B.config(nx=nx, ny=21, nz=19, h=cfg.h, precision=B.WM_MIXED_F32STATE))
+    p.set_state(Uf["rho"], Uf["m"], Uf["E"], Uf["b"])
+    dt = 0.8 * mhd.compute_dt(Uf, cfg)
+    p.step_dt(dt)
+    U1, _ = mhd.step(Uf, cfg, dt)
     errs = state_errors(p.state(), U1)
     say("  ", {k: f"{v:.2e}" for k, v in errs.items()})
     assert max(errs.values()) <= 1e-6, errs

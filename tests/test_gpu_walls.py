@@ -118,14 +118,18 @@ def test_walled_init_from_potential():
     assert rel_err(p.bcell.cpu(), mhd.zone_B_cfg(Uo["b"], cfg)) <= 1e-12
 
 
+@pytest.mark.parametrize("shape,walls", [((70, 20, 18), (True, False, False)), ((22, 19, 20), (True, True, True)),
+                                         ((21, 40, 18), (False, True, False))])
 @pytest.mark.parametrize("precision,tol", [(B.WM_MIXED, 5e-8), (B.WM_MIXED_F32STATE, 1e-6)])
-def test_walled_step_mixed(precision, tol):
+def test_walled_step_mixed(precision, tol, shape, walls):
     """One mixed step of a walled box.  The walled state moves at v_rms = 0.8,
     not Mach 0.1: the mixed error grows with the flux corrections carried in
     FP32 (periodic one step at Mach 0.1: 1.8e-9; ten steps at Mach 2: 4.7e-8),
-    so the bar is the Mach-2 one, 5e-8 (measured 1.4e-8); FP32 state 1e-6."""
-    say(f"walled step, precision {precision}")
-    U, cfg = walled_state(n=(70, 20, 18), walls=(True, False, False))
+    so the bar is the Mach-2 one, 5e-8 (measured 1.4e-8); FP32 state 1e-6.
+    The FP32-state update takes two x-adjacent zones per thread when nx is
+    even (70, 22) and one otherwise (21)."""
+    say(f"walled step {shape} walls {walls}, precision {precision}")
+    U, cfg = walled_state(n=shape, walls=walls)
     p = gpu_patch(U, cfg, precision=precision)
     dt = mhd.compute_dt(U, cfg)
     p.step_dt(dt)
