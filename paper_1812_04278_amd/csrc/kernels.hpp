@@ -24,18 +24,24 @@ struct Grid {
   }
 };
 
-// Face value b_f of the normal field along an axis of n faces, f in [-2, n]:
-// periodic wrap, or at walls the mirror ghost faces (odd about the wall faces
-// -1/2 and n-1/2; the lower wall face is zero, the upper one is stored).
-template <typename F>
-__device__ __forceinline__ double normal_face(F read, int f, int n, int wall) {
-  if (wall) {
-    if (f == -1) return 0.0;
-    if (f < -1) return -read(-2 - f);
-    if (f > n - 1) return -read(2 * n - 2 - f);
-    return read(f);
+// The four normal-field faces b_f, f = c-2 .. c+1, that the zone-B
+// interpolation of zone c reads along an axis of n faces: periodic wrap, or at
+// walls the mirror ghost faces (odd about the wall faces -1/2 and n-1/2; the
+// lower wall face, index -1, is zero).  Index and sign only, with selects, so
+// that the caller issues its loads together (a walled axis has n >= 3).
+__device__ __forceinline__ void face_stencil(int c, int n, int wall, int idx[4], double sg[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int f = c - 2 + q;
+    if (wall) {
+      const bool ghost = f < -1 || f > n - 1;
+      idx[q] = f < -1 ? -2 - f : (f > n - 1 ? 2 * n - 2 - f : max(f, 0));
+      sg[q] = f == -1 ? 0.0 : (ghost ? -1.0 : 1.0);
+    } else {   // periodic: f lies in [-2, n], so one add or subtract wraps it (n = 1: zone 0)
+      idx[q] = n == 1 ? 0 : (f < 0 ? f + n : (f >= n ? f - n : f));
+      sg[q] = 1.0;
+    }
   }
-  return read(wrap(f, n));
 }
 
 // ---------------------------------------------------------------------------
@@ -652,18 +658,26 @@ __global__ __launch_bounds__(256) void bcell_kernel(Grid g, const S* b, S* B) {
   const S* bx = b;
   const S* by = b + N;
   const S* bz = b + 2 * N;
-  auto rx = [&](int f) { return double(bx[g.at(f, j, k)]); };
-  auto ry = [&](int f) { return double(by[g.at(i, f, k)]); };
-  auto rz = [&](int f) { return double(bz[g.at(i, j, f)]); };
-  auto interp = [](double m2, double m1, double p0, double p1) {
-    return (-m2 + 9.0 * m1 + 9.0 * p0 - p1) * (1.0 / 16.0);
+  int ix[4], iy[4], iz[4];
+  double sx[4], sy[4], sz[4];
+  face_stencil(i, g.nx, g.wall[0], ix, sx);
+  face_stencil(j, g.ny, g.wall[1], iy, sy);
+  face_stencil(k, g.nz, g.wall[2], iz, sz);
+  double vx[4], vy[4], vz[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    vx[q] = double(bx[g.at(ix[q], j, k)]);
+    vy[q] = double(by[g.at(i, iy[q], k)]);
+    vz[q] = double(bz[g.at(i, j, iz[q])]);
+  }
+  // the sign after the loads (a select, so the zero face ignores the value read)
+  auto sgn = [](double s, double v) { return s == 1.0 ? v : (s == 0.0 ? 0.0 : -v); };
+  auto interp = [&](const double* v, const double* sg) {
+    return (-sgn(sg[0], v[0]) + 9.0 * sgn(sg[1], v[1]) + 9.0 * sgn(sg[2], v[2]) - sgn(sg[3], v[3])) * (1.0 / 16.0);
   };
-  B[c0] = S(interp(normal_face(rx, i - 2, g.nx, g.wall[0]), normal_face(rx, i - 1, g.nx, g.wall[0]),
-                   normal_face(rx, i, g.nx, g.wall[0]), normal_face(rx, i + 1, g.nx, g.wall[0])));
-  B[N + c0] = S(interp(normal_face(ry, j - 2, g.ny, g.wall[1]), normal_face(ry, j - 1, g.ny, g.wall[1]),
-                       normal_face(ry, j, g.ny, g.wall[1]), normal_face(ry, j + 1, g.ny, g.wall[1])));
-  B[2 * N + c0] = S(interp(normal_face(rz, k - 2, g.nz, g.wall[2]), normal_face(rz, k - 1, g.nz, g.wall[2]),
-                           normal_face(rz, k, g.nz, g.wall[2]), normal_face(rz, k + 1, g.nz, g.wall[2])));
+  B[c0] = S(interp(vx, sx));
+  B[N + c0] = S(interp(vy, sy));
+  B[2 * N + c0] = S(interp(vz, sz));
 }
 
 // b = B0 + curl_h A (first-order differences on the edge potential)
