@@ -471,15 +471,22 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
   }
 }
 
-// The update of an FP32 state, two x-adjacent zones (i0 even, i0 + 1) per
-// thread: every load and store of the zone pair moves 8 bytes, so a wave keeps
-// as many bytes in flight as the FP64 kernel (4-byte loads halve them, and the
-// FP32 update is bound by the latency of its many streams).  Needs nx even
-// (and arrays at even float offsets); blocks of 64 x 8 zones.  Each zone's
-// arithmetic is update_kernel's, term by term in the same order (the compiler
-// may still fuse a different product into an FMA).
-template <int RK, int STAGE>
-__global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<float> a) {
+// Two storage values as one load or store (8 bytes for float, 16 for double).
+template <typename S> struct Pair2;
+template <> struct Pair2<float> { using T = float2; };
+template <> struct Pair2<double> { using T = double2; };
+
+// The update with two x-adjacent zones (i0 even, i0 + 1) per thread: every load
+// and store of the zone pair is one vector access, so a wave keeps more bytes
+// in flight per instruction (with 4-byte values, one zone per thread keeps
+// half the bytes of the FP64 kernel, and the update is bound by the latency
+// of its many streams).  Needs nx even and arrays at even element offsets;
+// blocks of 64 x 8 zones.  Each zone's arithmetic is update_kernel's, term by
+// term in the same order (the compiler may still fuse a different product
+// into an FMA).
+template <int RK, int STAGE, typename S>
+__global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<S> a) {
+  using V2 = typename Pair2<S>::T;
   static_assert((RK == 3 && STAGE >= 0 && STAGE < 3) || (RK == 4 && STAGE >= 0 && STAGE < 4), "stage of the scheme");
   const Grid& g = a.g;
   const int i0 = blockIdx.x * 64 + 2 * (threadIdx.x & 31);
@@ -495,19 +502,19 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<float> a) {
   const size_t c0 = g.at(i0, j, k);
   const double ih = a.inv_h;
   struct D2 { double x, y; };
-  auto pr = [&](const float* q, int jj, int kk) -> D2 {      // zones i0, i0 + 1
-    const float2 t = *reinterpret_cast<const float2*>(q + g.at(i0, jj, kk));
+  auto pr = [&](const S* q, int jj, int kk) -> D2 {      // zones i0, i0 + 1
+    const V2 t = *reinterpret_cast<const V2*>(q + g.at(i0, jj, kk));
     return {double(t.x), double(t.y)};
   };
-  auto lo = [&](const float* q, int jj, int kk) -> double {  // zone i0 - 1
-    return double(reinterpret_cast<const float2*>(q + g.at(imm, jj, kk))->y);
+  auto lo = [&](const S* q, int jj, int kk) -> double {  // zone i0 - 1
+    return double(reinterpret_cast<const V2*>(q + g.at(imm, jj, kk))->y);
   };
-  auto hi = [&](const float* q, int jj, int kk) -> double {  // zone i0 + 2
-    return double(reinterpret_cast<const float2*>(q + g.at(ipp, jj, kk))->x);
+  auto hi = [&](const S* q, int jj, int kk) -> double {  // zone i0 + 2
+    return double(reinterpret_cast<const V2*>(q + g.at(ipp, jj, kk))->x);
   };
-  const float* Fx = a.faces;
-  const float* Fy = a.faces + 5 * N;
-  const float* Fz = a.faces + 10 * N;
+  const S* Fx = a.faces;
+  const S* Fy = a.faces + 5 * N;
+  const S* Fz = a.faces + 10 * N;
   double kv[2][8];
   const bool lwx = g.wall[0] && i0 == 0, lwy = g.wall[1] && j == 0, lwz = g.wall[2] && k == 0;
 #pragma unroll
@@ -516,15 +523,15 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<float> a) {
     const D2 fx = pr(Fx + o, j, k), fy = pr(Fy + o, j, k), fz = pr(Fz + o, j, k);
     const double fxm0 = lwx ? double(a.wallF[0][(size_t)v * g.ny * g.nz + j + (size_t)g.ny * k]) : lo(Fx + o, j, k);
     D2 fym, fzm;
-    // the wall-face planes may start at an odd float offset: two 4-byte loads
+    // the wall-face planes may start at an odd element offset: two scalar loads
     if (lwy) {
-      const float* w = a.wallF[1] + (size_t)v * nx * g.nz + i0 + (size_t)nx * k;
+      const S* w = a.wallF[1] + (size_t)v * nx * g.nz + i0 + (size_t)nx * k;
       fym = {double(w[0]), double(w[1])};
     } else {
       fym = pr(Fy + o, jm, k);
     }
     if (lwz) {
-      const float* w = a.wallF[2] + (size_t)v * nx * g.ny + i0 + (size_t)nx * j;
+      const S* w = a.wallF[2] + (size_t)v * nx * g.ny + i0 + (size_t)nx * j;
       fzm = {double(w[0]), double(w[1])};
     } else {
       fzm = pr(Fz + o, j, km);
@@ -532,12 +539,12 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<float> a) {
     kv[0][v] = (-(fx.x - fxm0) * ih + -(fy.x - fym.x) * ih) + -(fz.x - fzm.x) * ih;
     kv[1][v] = (-(fx.y - fx.x) * ih + -(fy.y - fym.y) * ih) + -(fz.y - fzm.y) * ih;
   }
-  const float* Txy = a.faces + 15 * N;
-  const float* Txz = a.faces + 16 * N;
-  const float* Tyz = a.faces + 17 * N;
-  const float* Tyx = a.faces + 18 * N;
-  const float* Tzx = a.faces + 19 * N;
-  const float* Tzy = a.faces + 20 * N;
+  const S* Txy = a.faces + 15 * N;
+  const S* Txz = a.faces + 16 * N;
+  const S* Tyz = a.faces + 17 * N;
+  const S* Tyx = a.faces + 18 * N;
+  const S* Tzx = a.faces + 19 * N;
+  const S* Tzy = a.faces + 20 * N;
   // corner fluxes (eq. ox1-ox3) as in update_kernel; x positions: m = i0 - 1,
   // 0 = i0, 1 = i0 + 1, p = i0 + 2; zero on edges in a wall plane
   const bool w0top = g.wall[0] && i0 + 1 == nx - 1;   // zone i0 + 1's upper x edge lies in the wall
@@ -602,14 +609,14 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<float> a) {
   const double dt = *a.dt;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
-    const float* unp = v < 5 ? a.Un + v * N : a.bn + (v - 5) * N;
-    const float2 u = *reinterpret_cast<const float2*>(unp + c0);
+    const S* unp = v < 5 ? a.Un + v * N : a.bn + (v - 5) * N;
+    const V2 u = *reinterpret_cast<const V2*>(unp + c0);
     const double un[2] = {double(u.x), double(u.y)};
-    float2* accp = reinterpret_cast<float2*>(a.acc + v * N + c0);
+    V2* accp = reinterpret_cast<V2*>(a.acc + v * N + c0);
     double out[2], acc_new[2];
     double acc_old[2] = {0.0, 0.0};
     if constexpr (STAGE > 0) {
-      const float2 t = *accp;
+      const V2 t = *accp;
       acc_old[0] = double(t.x);
       acc_old[1] = double(t.y);
     }
@@ -641,9 +648,17 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<float> a) {
       }
     }
     constexpr bool writes_acc = RK == 3 ? STAGE < 2 : STAGE < 3;
-    if constexpr (writes_acc) *accp = make_float2(float(acc_new[0]), float(acc_new[1]));
-    float* outp = v < 5 ? a.hyd_out + v * N : a.b_out + (v - 5) * N;
-    *reinterpret_cast<float2*>(outp + c0) = make_float2(float(out[0]), float(out[1]));
+    if constexpr (writes_acc) {
+      V2 t;
+      t.x = S(acc_new[0]);
+      t.y = S(acc_new[1]);
+      *accp = t;
+    }
+    S* outp = v < 5 ? a.hyd_out + v * N : a.b_out + (v - 5) * N;
+    V2 o;
+    o.x = S(out[0]);
+    o.y = S(out[1]);
+    *reinterpret_cast<V2*>(outp + c0) = o;
   }
 }
 

@@ -349,18 +349,18 @@ wm_status sweeps(wm_patch* p, const S* hydro, const S* bcell) {
 
 int n_stages(const wm_patch* p) { return p->cfg.integrator == WM_RK4 ? 4 : 3; }
 
-// Launches the update of one stage: for an FP32 state with nx even and every
-// array at an 8-byte boundary, the two-zone kernel (8-byte loads), else one
-// zone per thread.
+// Launches the update of one stage: with nx even and every array aligned to
+// two elements, the two-zone kernel (vector loads), else one zone per thread.
+constexpr bool kUpdatePairs = true;
 template <int RK, int STAGE, typename S>
 void launch_update_kernel(wm_patch* p, const UpdateArgs<S>& a) {
-  if constexpr (sizeof(S) == 4) {
-    auto al8 = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 7) == 0; };
-    bool pair = p->g.nx % 2 == 0 && al8(a.faces) && al8(a.Un) && al8(a.bn) && al8(a.acc) && al8(a.hyd_out) &&
-                al8(a.b_out);
+  if (kUpdatePairs) {
+    auto al = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) % (2 * sizeof(S))) == 0; };
+    const bool pair = p->g.nx % 2 == 0 && al(a.faces) && al(a.Un) && al(a.bn) && al(a.acc) && al(a.hyd_out) &&
+                      al(a.b_out);
     if (pair) {
       const dim3 grid((p->g.nx + 63) / 64, (p->g.ny + 7) / 8, p->g.nz);
-      hipLaunchKernelGGL((update_pair_kernel<RK, STAGE>), grid, dim3(256), 0, p->stream, a);
+      hipLaunchKernelGGL((update_pair_kernel<RK, STAGE, S>), grid, dim3(256), 0, p->stream, a);
       return;
     }
   }
