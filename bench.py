@@ -28,15 +28,17 @@ METRIC = "Mzone-updates/s per RK3 step, FP64 vs mixed at stated L1 err; adjoint/
 # 130, transport flux 8), plus ~70 for the zone prologue (primitives, flux,
 # eigenvalues) of the face's zone.
 FLOPS_PER_FACE = 2170
-# Algorithmic HBM bytes of the update kernel per zone (FP64): reads 15 face
-# fluxes, 6 transport fluxes, U^n (8) and the accumulator (8, stages 1-2);
-# writes the stage state (8) and the accumulator (8, stages 0-1).
+# Algorithmic HBM traffic of the update kernel per zone, in stored values
+# averaged over the three SSP-RK3 stages: reads 15 face fluxes, 6 transport
+# fluxes, U^n (8) and the accumulator (8, stages 1-2); writes the stage state
+# (8) and the accumulator (8, stages 0-1).  Times 8 bytes (FP64) or 4 (FP32 state).
+UPDATE_VALUES_PER_ZONE = 21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per sweep dispatch on the 256^3 FP64 workload, averaged over the
 # three axes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain copy of
 # known size gives), profiles/fp64_step_256cube_pmc_traffic.md.
-SWEEP_TRAFFIC_BYTES_256 = 2.417e9
+SWEEP_TRAFFIC_BYTES_256 = 2.416e9
 
 
 def log(*a):
@@ -144,7 +146,7 @@ def mixed_precision(n: int, steps: int):
         nup, msup = rep["update"]
         sw_ms, up_ms = msw / max(nsw, 1), msup / max(nup, 1)
         es = 4 if prec == binding.WM_MIXED_F32STATE else 8
-        upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * es * float(n) ** 3
+        upd_bytes = UPDATE_VALUES_PER_ZONE * es * float(n) ** 3
         tf = FLOPS_PER_FACE * float(n) ** 3 / (sw_ms * 1e-3) / 1e12
         # sweep fraction against the FP64 vector peak in all three forms: with packed
         # FP32 instructions off, an FP32 vector instruction issues at the FP64 rate
@@ -395,7 +397,7 @@ def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
     d = p.diagnostics(raise_unphysical=False)
     nup, msup = rep["update"]
     upd_ms = msup / max(nup, 1)
-    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * 4 * float(n) ** 3   # as for FP64, 4-byte values
+    upd_bytes = UPDATE_VALUES_PER_ZONE * 4 * float(n) ** 3
     out["f32state"] = {"value": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 3), "unit": "Mzone-updates/s",
                        "ms_per_step": round(ms / steps, 3),
                        "sweep_avg_ms": round(rep["sweep"][1] / max(rep["sweep"][0], 1), 4),
@@ -499,7 +501,7 @@ def main():
     upd_ms = msup / max(nup, 1)
     # update kernel, algorithmic bytes per zone averaged over the three stages:
     # reads 21 face values + 8 U^n + 8 acc (stages 1, 2); writes 8 state + 8 acc (stages 0, 1)
-    upd_bytes = (21 + 8 + 8 * 2 / 3 + 8 + 8 * 2 / 3) * 8 * float(n) ** 3
+    upd_bytes = UPDATE_VALUES_PER_ZONE * 8 * float(n) ** 3
     out = {
         "metric": METRIC,
         "value": round(value, 3),
