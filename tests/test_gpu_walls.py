@@ -76,6 +76,23 @@ def test_walled_sweeps_and_rhs(shape, walls):
         assert rel_err(k[c], ref[c]) <= 1e-12, ("rhs", c, rel_err(k[c], ref[c]))
 
 
+@pytest.mark.parametrize("weights", [B.WM_WENO_JS, B.WM_WENO_Z])
+def test_walled_rk4_steps(weights):
+    """The paper's RK4 at CFL 0.8 (reading R16) on the all-walls box, with both
+    weight families: two steps against the oracle's RK4 at the same dt."""
+    say(f"walled RK4 steps 22x19x20, weights {weights}")
+    U, cfg = walled_state(n=(22, 19, 20), walls=(True, True, True))
+    wz = weights == B.WM_WENO_Z
+    if wz:
+        cfg = dataclasses.replace(cfg, weights="z")
+    p = gpu_patch(U, cfg, integrator=B.WM_RK4, cfl=0.8, weights=weights)
+    dt = mhd.compute_dt(U, dataclasses.replace(cfg, cfl=0.8))
+    for _ in range(2):
+        p.step_dt(dt)
+        U, _ = mhd.step_rk4(U, cfg, dt)
+    assert_state_parity(p.state(), U, label=f"walled RK4 weights {weights}")
+
+
 @pytest.mark.parametrize("shape,walls", CASES)
 def test_walled_steps(shape, walls):
     """Three steps (dt from each side's eq. cfl): parity, the wall faces' normal
