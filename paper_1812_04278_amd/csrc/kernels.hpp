@@ -48,11 +48,15 @@ __device__ __forceinline__ void face_stencil(int c, int n, int wall, int idx[4],
 // directional sweep
 // ---------------------------------------------------------------------------
 // Tile of TA faces along the sweep axis by TB faces across it (256 lanes, one
-// face each).  The x sweep uses 64 x 4 so that a wave reads whole 128-byte
-// lines of a row; the y and z sweeps use 16 x 16 with x across, so that every
-// row of the tile is a 128-byte segment in x.
-template <int AXIS> struct SweepTile { static constexpr int TA = 16, TB = 16; };
-template <> struct SweepTile<0> { static constexpr int TA = 64, TB = 4; };
+// face each), for work type TW.  The x sweep uses 64 x 4 so that a wave reads
+// whole 128-byte lines of a row.  The y and z sweeps have x across: in FP64
+// 32 x 8 (296 zones for 256 faces; rows of 64 bytes), measured 2% faster than
+// 16 x 16 (336 zones, 128-byte rows), which the FP32 work type keeps (it runs
+// three waves per SIMD and measured 1% slower with 32 x 8).
+template <int AXIS, typename TW> struct SweepTile {
+  static constexpr int TA = sizeof(TW) == 8 ? 32 : 16, TB = sizeof(TW) == 8 ? 8 : 16;
+};
+template <typename TW> struct SweepTile<0, TW> { static constexpr int TA = 64, TB = 4; };
 constexpr int SW_THREADS = 256;
 constexpr int SW_HL = 2, SW_HR = 3;          // stencil zones i-2 .. i+3
 constexpr int SW_NQ = 14;                    // q (7) and F (7) per zone
@@ -93,12 +97,14 @@ __device__ __forceinline__ int sweep_zone(int z, int n, int wall, double& flip) 
 // LDS per block, two arrays: zone q and F in FP64 (the differences are formed
 // in FP64, then stored over them), and the zone primitives and speeds in the
 // work type TW.
-template <int AXIS> constexpr int sweep_zones() {
-  return (SweepTile<AXIS>::TA + SW_HL + SW_HR) * SweepTile<AXIS>::TB;
+template <int AXIS, typename TW> constexpr int sweep_zones() {
+  return (SweepTile<AXIS, TW>::TA + SW_HL + SW_HR) * SweepTile<AXIS, TW>::TB;
 }
-template <int AXIS> constexpr size_t sweep_q_doubles() { return (size_t)SW_NQ * sweep_zones<AXIS>(); }
+template <int AXIS, typename TW> constexpr size_t sweep_q_doubles() {
+  return (size_t)SW_NQ * sweep_zones<AXIS, TW>();
+}
 template <int AXIS, typename TW> constexpr size_t sweep_p_doubles() {
-  return ((size_t)SW_NP * sweep_zones<AXIS>() * sizeof(TW) + 7) / 8;
+  return ((size_t)SW_NP * sweep_zones<AXIS, TW>() * sizeof(TW) + 7) / 8;
 }
 
 // Phases: (1) zone prologue of the tile and its halo into LDS; (2) per face:
@@ -113,14 +119,14 @@ template <int AXIS, typename TW> constexpr size_t sweep_p_doubles() {
 
 template <int AXIS, bool WENO_Z, typename TW, typename S>
 __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_kernel(SweepArgs<S> a) {
-  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
+  constexpr int TA = SweepTile<AXIS, TW>::TA, TB = SweepTile<AXIS, TW>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;     // zones along the axis
   constexpr int NI = TA + 4;                 // interfaces i-3/2 .. i+TA+3/2
   constexpr int NC = NA * TB;
   constexpr int NIF = NI * TB;
   static_assert(TA * TB == SW_THREADS, "one face per lane");
   static_assert(TA >= 4, "extra interfaces are built by lanes fa < 4");
-  __shared__ double sQ[sweep_q_doubles<AXIS>()];
+  __shared__ double sQ[sweep_q_doubles<AXIS, TW>()];
   __shared__ double sP[sweep_p_doubles<AXIS, TW>()];
   double* Q = sQ;                            // [14][NC] zone q and F, later the differences
   TW* Pz = reinterpret_cast<TW*>(sP);        // [11][NC] zone primitives and speeds

@@ -308,9 +308,15 @@ wm_status launch_sweep(wm_patch* p, const S* hydro, const S* bcell, S* fh, S* T,
   const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
   const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
   const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
-  constexpr int TA = SweepTile<AXIS>::TA, TB = SweepTile<AXIS>::TB;
-  // with walls the sweep also computes the lower wall face (-1/2)
-  dim3 grid((nA + p->g.wall[AXIS] + TA - 1) / TA, (nB + TB - 1) / TB, nC);
+  // the tile depends on the work type (FP32 for the FP32 state and the mixed
+  // form); with walls the sweep also computes the lower wall face (-1/2)
+  auto grid_for = [&](auto tw) {
+    using TW = decltype(tw);
+    constexpr int TA = SweepTile<AXIS, TW>::TA, TB = SweepTile<AXIS, TW>::TB;
+    return dim3((nA + p->g.wall[AXIS] + TA - 1) / TA, (nB + TB - 1) / TB, nC);
+  };
+  const bool f32_work = sizeof(S) == 4 || p->cfg.precision == WM_MIXED;
+  const dim3 grid = f32_work ? grid_for(float{}) : grid_for(double{});
 #ifdef WM_SWEEP_CLOCK
   if ((size_t)grid.x * grid.y * grid.z * (SW_THREADS / 64) * 8 <= g_sweep_clk_n[AXIS]) a.clk = g_sweep_clk[AXIS];
 #endif

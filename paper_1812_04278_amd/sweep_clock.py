@@ -23,7 +23,8 @@ from . import inputs
 
 PHASES = ["zone loads + prologue", "barrier 1", "phase 2 (central flux, face state, differences)",
           "barriers 2-3 + difference stores", "phase 3 (eigensystem + WENO)", "flux stores"]
-TILES = {0: (64, 4), 1: (16, 16), 2: (16, 16)}
+TILES = {0: (64, 4), 1: (32, 8), 2: (32, 8)}          # FP64 work type
+TILES_F32 = {0: (64, 4), 1: (16, 16), 2: (16, 16)}    # mixed and FP32 state
 WAVES_PER_BLOCK = 4
 
 
@@ -65,8 +66,9 @@ def main() -> None:
         p.step()
     torch.cuda.synchronize()
     bufs = []
+    tiles = TILES if args.precision == B.WM_FP64 else TILES_F32
     for ax in range(3):
-        TA, TB = TILES[ax]
+        TA, TB = tiles[ax]
         nblk = -(-n // TA) * -(-n // TB) * n
         b = torch.zeros(nblk * WAVES_PER_BLOCK * 8, dtype=torch.int64, device="cuda")
         if lib.wm_clock_sweep_buffer(ax, ctypes.c_void_p(b.data_ptr()), b.numel()) != 0:
