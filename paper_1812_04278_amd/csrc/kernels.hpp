@@ -486,17 +486,22 @@ template <> struct Pair2<double> { using T = double2; };
 // and store of the zone pair is one vector access, so a wave keeps more bytes
 // in flight per instruction (with 4-byte values, one zone per thread keeps
 // half the bytes of the FP64 kernel, and the update is bound by the latency
-// of its many streams).  Needs nx even and arrays at even element offsets;
-// blocks of 64 x 8 zones.  Each zone's arithmetic is update_kernel's, term by
-// term in the same order (the compiler may still fuse a different product
-// into an FMA).
+// of its many streams).  Needs nx even and arrays at even element offsets.
+// Blocks of PAIR_ROW_ZONES x PAIR_ROWS zones: long rows (a wave covers 128
+// contiguous zones of a row) keep the x-neighbour reads at the row ends few;
+// 256 x 2 measured 1.252 ms per FP64 update at 256^3 against 1.260 (128 x 4)
+// and 1.329 (64 x 8), and 0.632 ms against 0.643 and 0.700 for the FP32 state.
+// Each zone's arithmetic is update_kernel's, term by term in the same order
+// (the compiler may still fuse a different product into an FMA).
+constexpr int PAIR_ROW_ZONES = 256;
+constexpr int PAIR_ROWS = 2 * 256 / PAIR_ROW_ZONES;   // 256 threads, two zones each
 template <int RK, int STAGE, typename S>
 __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<S> a) {
   using V2 = typename Pair2<S>::T;
   static_assert((RK == 3 && STAGE >= 0 && STAGE < 3) || (RK == 4 && STAGE >= 0 && STAGE < 4), "stage of the scheme");
   const Grid& g = a.g;
-  const int i0 = blockIdx.x * 64 + 2 * (threadIdx.x & 31);
-  const int j = blockIdx.y * 8 + (threadIdx.x >> 5);
+  const int i0 = blockIdx.x * PAIR_ROW_ZONES + 2 * (threadIdx.x % (PAIR_ROW_ZONES / 2));
+  const int j = blockIdx.y * PAIR_ROWS + threadIdx.x / (PAIR_ROW_ZONES / 2);
   const int k = blockIdx.z;
   if (i0 >= g.nx || j >= g.ny) return;
   const int nx = g.nx;
@@ -669,10 +674,14 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<S> a) {
 }
 
 // zone B = (-b_{i-2} + 9 b_{i-1} + 9 b_i - b_{i+1}) / 16 along each component's own axis
+// Blocks of BCELL_ROW_ZONES x BCELL_ROWS zones (256 threads): 64 x 4 measured
+// 0.191 ms per 256^3 FP64 pass against 0.192 (128 x 2) and 0.200 (256 x 1).
+constexpr int BCELL_ROW_ZONES = 64;
+constexpr int BCELL_ROWS = 256 / BCELL_ROW_ZONES;
 template <typename S>
 __global__ __launch_bounds__(256) void bcell_kernel(Grid g, const S* b, S* B) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int i = blockIdx.x * BCELL_ROW_ZONES + threadIdx.x % BCELL_ROW_ZONES;
+  const int j = blockIdx.y * BCELL_ROWS + threadIdx.x / BCELL_ROW_ZONES;
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   const size_t N = g.N, c0 = g.at(i, j, k);

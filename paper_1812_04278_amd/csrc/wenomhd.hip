@@ -365,7 +365,7 @@ void launch_update_kernel(wm_patch* p, const UpdateArgs<S>& a) {
     const bool pair = p->g.nx % 2 == 0 && al(a.faces) && al(a.Un) && al(a.bn) && al(a.acc) && al(a.hyd_out) &&
                       al(a.b_out);
     if (pair) {
-      const dim3 grid((p->g.nx + 63) / 64, (p->g.ny + 7) / 8, p->g.nz);
+      const dim3 grid((p->g.nx + PAIR_ROW_ZONES - 1) / PAIR_ROW_ZONES, (p->g.ny + PAIR_ROWS - 1) / PAIR_ROWS, p->g.nz);
       hipLaunchKernelGGL((update_pair_kernel<RK, STAGE, S>), grid, dim3(256), 0, p->stream, a);
       return;
     }
@@ -421,7 +421,8 @@ wm_status launch_update(wm_patch* p, int stage, double* rhs_out) {
 template <typename S>
 wm_status launch_bcell(wm_patch* p, const S* b, S* B) {
   const long r = prof_begin(p, K_BCELL);
-  hipLaunchKernelGGL(bcell_kernel<S>, zone_grid(p->g), dim3(256), 0, p->stream, p->g, b, B);
+  const dim3 grid((p->g.nx + BCELL_ROW_ZONES - 1) / BCELL_ROW_ZONES, (p->g.ny + BCELL_ROWS - 1) / BCELL_ROWS, p->g.nz);
+  hipLaunchKernelGGL(bcell_kernel<S>, grid, dim3(256), 0, p->stream, p->g, b, B);
   WM_LAUNCH_CHECK("bcell kernel");
   prof_end(p, r);
   return WM_OK;
