@@ -398,9 +398,13 @@ def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
     nup, msup = rep["update"]
     upd_ms = msup / max(nup, 1)
     upd_bytes = UPDATE_VALUES_PER_ZONE * 4 * float(n) ** 3
+    sw_ms = rep["sweep"][1] / max(rep["sweep"][0], 1)
+    sw_tf = FLOPS_PER_FACE * float(n) ** 3 / (sw_ms * 1e-3) / 1e12
     out["f32state"] = {"value": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 3), "unit": "Mzone-updates/s",
                        "ms_per_step": round(ms / steps, 3),
-                       "sweep_avg_ms": round(rep["sweep"][1] / max(rep["sweep"][0], 1), 4),
+                       "sweep_avg_ms": round(sw_ms, 4), "sweep_tflops": round(sw_tf, 3),
+                       # FP32 vector instructions issue at the FP64 rate with packed FP32 off
+                       "sweep_frac_fp64_vector_peak": round(sw_tf / PEAK_FP64_TFLOPS, 4),
                        "update_avg_ms": round(upd_ms, 4),
                        "update_hbm_gbs": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1),
                        "update_hbm_frac": round(upd_bytes / (upd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
