@@ -345,6 +345,37 @@ def test_rollout_gradient_vs_oracle(store_stages):
         assert ea <= TOL and ev <= TOL
 
 
+def test_rollout_side_stream_matches_default():
+    """The rollout on a patch with its own stream gives bitwise the loss and the
+    gradients of a patch on the caller's stream, with the caller's stream kept
+    busy, and the returned tensors survive later work on the patch's stream
+    (its allocations may reuse freed blocks only after the caller's use)."""
+    say("rollout on a side stream, 16^3, 4 steps, checkpoints every 2")
+    n, nsteps = 16, 4
+    f = fields(n, seed=3, v_rms=1.0, kmax=3)
+    rho_t, e_t = targets(n)
+    h = 1.0 / n
+    out = []
+    for side in (False, True):
+        p = B.Patch(B.config(n), stream=torch.cuda.Stream() if side else None)
+        A = torch.as_tensor(f.A).cuda().requires_grad_(True)
+        v = torch.as_tensor(f.v).cuda().requires_grad_(True)
+        busy = torch.randn(3072, 3072, device="cuda", dtype=torch.float64)
+        for _ in range(3):
+            busy = busy @ busy * 1e-3                   # keep the caller's stream occupied
+        hyd, bf, bc = R.rollout(A, v, torch.as_tensor(f.rho).cuda(), p, nsteps, ckpt_every=2, P0=f.P0, B0=f.B0)
+        J = loss_from(hyd, bc, rho_t.cuda(), e_t.cuda(), h)
+        gA, gv = torch.autograd.grad(J, [A, v])
+        snap = (J.detach().clone(), gA.clone(), gv.clone())
+        for ax in range(3):
+            p.debug_sweep(ax)                           # allocations and work on the patch's stream
+        torch.cuda.synchronize()
+        assert torch.equal(gA, snap[1]) and torch.equal(gv, snap[2])
+        out.append(snap)
+    (J0, gA0, gv0), (J1, gA1, gv1) = out
+    assert torch.equal(J0, J1) and torch.equal(gA0, gA1) and torch.equal(gv0, gv1)
+
+
 def test_rollout_gradient_rk4_vs_oracle():
     """The rollout with the classical RK4 at CFL 0.8: gradient w.r.t. (A, v)
     against autograd through the oracle's RK4 steps, 12^3, 5 steps,
