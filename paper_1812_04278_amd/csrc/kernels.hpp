@@ -86,10 +86,17 @@ struct SweepArgs {
 // extension of the mirror-doubled axis (period 2n), so any z -- also the
 // positions of a tile longer than the axis, whose faces are discarded --
 // maps into [0, n); for z in [-n, 2n) it is the plain reflection.
+// Positions within one period of [0, p) wrap with one add or subtract; the
+// modulo (an integer division by the runtime length) is left for tiles longer
+// than the axis.
+__device__ __forceinline__ int wrap_near(int z, int p) {
+  if (z >= -p && z < 2 * p) return z < 0 ? z + p : (z >= p ? z - p : z);
+  return wrap(z, p);
+}
 __device__ __forceinline__ int sweep_zone(int z, int n, int wall, double& flip) {
   flip = 1.0;
-  if (!wall) return wrap(z, n);
-  const int zz = wrap(z, 2 * n);
+  if (!wall) return wrap_near(z, n);
+  const int zz = wrap_near(z, 2 * n);
   if (zz >= n) { flip = -1.0; return 2 * n - 1 - zz; }
   return zz;
 }
