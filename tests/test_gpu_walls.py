@@ -176,3 +176,22 @@ def test_floors_parity_and_counts():
     # rebinding the state restarts the count
     p.set_state(U["rho"], U["m"], U["E"], U["b"])
     assert p.diagnostics()["n_floored"] == 0
+
+
+@pytest.mark.parametrize("kw", [dict(walls=(True, False, False)), dict(rho_floor=1e-3)])
+def test_adjoint_refuses_walls_and_floors(kw):
+    """The adjoint covers periodic boxes without floors (walls and floors are
+    not differentiated): its calls refuse such a patch with WM_ERR_ARG before
+    any launch."""
+    say(f"adjoint refusal {kw}")
+    walls = kw.get("walls", (False, False, False))
+    U, cfg = walled_state(n=(12, 10, 8), walls=walls)
+    cfg = dataclasses.replace(cfg, rho_floor=kw.get("rho_floor", 0.0))
+    p = gpu_patch(U, cfg)
+    lam = torch.zeros((8, cfg.nz, cfg.ny, cfg.nx), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.WmError) as e:
+        p.rhs_vjp(p.hydro, p.bface, lam)
+    assert e.value.status == B.WM_ERR_ARG
+    with pytest.raises(B.WmError) as e:
+        p.adjoint_step(p.hydro.clone(), p.bface.clone(), 1e-3, lam[:5].clone(), lam[5:].clone())
+    assert e.value.status == B.WM_ERR_ARG
