@@ -22,8 +22,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mzone-updates/s per RK3 step, FP64 vs mixed at stated L1 err; adjoint/fwd cost"
 
-# Algorithmic work of one sweep per face (FP64 flops): the survey's count for
-# the characteristic WENO5 flux of a face, ~2,100 (eigen-system 240, ten 7x7
+# Algorithmic work of one sweep per face (FP64 flops): the count for the
+# characteristic WENO5 flux of a face, ~2,100 (eigen-system 240, ten 7x7
 # projections 980, split 140, 14 phi_N 560, central term and back-projection
 # 130, transport flux 8), plus ~70 for the zone prologue (primitives, flux,
 # eigenvalues) of the face's zone.
@@ -60,11 +60,11 @@ def host_cpu():
 
 
 def cpu_baseline(threads: int | None = None):
-    """The oracle as it stands, timed on the host cores on the survey's samples
-    of the workloads: C1 (32^3 Mach 0.1, one SSP-RK3 step) and the C2 crop (the
-    Mach-2 generator sampled at 64^3, ten steps), with all the threads torch
-    uses; then C1 and one 64^3 Mach-2 step on a single thread.  `value` is the
-    C2-crop rate (the Mach-2 workload's per-zone work)."""
+    """The oracle as it stands, timed on the host cores on samples of the
+    workloads: 32^3 Mach 0.1 with one SSP-RK3 step, and the Mach-2 generator
+    sampled at 64^3 with ten steps, with all the threads torch uses; then the
+    32^3 step and one 64^3 Mach-2 step on a single thread.  `value` is the 64^3
+    Mach-2 rate (the Mach-2 workload's per-zone work)."""
     import torch
     from oracle import mhd
     from paper_1812_04278_amd import inputs
@@ -85,20 +85,20 @@ def cpu_baseline(threads: int | None = None):
     if threads:
         torch.set_num_threads(threads)
     nthr = torch.get_num_threads()
-    c1 = run(32, 1, 0.1)
-    c2 = run(64, 10, 2.0)
+    s32 = run(32, 1, 0.1)
+    s64 = run(64, 10, 2.0)
     torch.set_num_threads(1)
     try:
-        c1_1 = run(32, 1, 0.1)
-        c2_1 = run(64, 1, 2.0)
+        s32_1 = run(32, 1, 0.1)
+        s64_1 = run(64, 1, 2.0)
     finally:
         torch.set_num_threads(saved)
-    return dict(value=c2["value"], unit="Mzone-updates/s", cores=nthr, kind="oracle",
-                sample=f"C2 crop: the Mach-2 generator sampled at 64^3 (seed 1), 10 SSP-RK3 steps, "
-                       f"{c2['seconds']:.1f} s on {nthr} threads",
+    return dict(value=s64["value"], unit="Mzone-updates/s", cores=nthr, kind="oracle",
+                sample=f"the Mach-2 generator sampled at 64^3 (seed 1), 10 SSP-RK3 steps, "
+                       f"{s64['seconds']:.1f} s on {nthr} threads",
                 host={"cpu_model": model, "nproc": nproc, "threads_used": nthr},
-                samples={"c1_32x1": c1, "c2crop_64x10": c2},
-                single_thread={"c1_32x1": c1_1, "c2crop_64x1": c2_1})
+                samples={"mach0.1_32x1": s32, "mach2_64x10": s64},
+                single_thread={"mach0.1_32x1": s32_1, "mach2_64x1": s64_1})
 
 
 def l1_per_variable(a: dict, b: dict):
@@ -368,7 +368,7 @@ def adjoint_cost(n: int = 128, steps: int = 20, ckpt: int = 5):
             "loss": J, "grad_norm_A": float(gA.norm()), "grad_norm_v": float(gv.norm())}
 
 
-def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
+def mach5_512(steps: int = 10, ckpt: int = 2, n: int = 512):
     """The 512^3 workload: Mach 5 (v_rms 5, |k| <= 8), beta 0.5, the mixed form
     with an FP32 state (WM_MIXED_F32STATE), forward and adjoint in one run:
     throughput of `steps` steps with the update kernel's HBM rate, then the same
@@ -381,7 +381,7 @@ def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
     import torch
     from paper_1812_04278_amd import binding, inputs, rollout
     B0 = tuple(math.sqrt(2.4 / 1.25) * x for x in (1.0, 0.5, 0.0))
-    log(f"bench c5: generating {n}^3 inputs on the GPU")
+    log(f"bench {n}^3: generating inputs on the GPU")
     f = inputs.random_fields(n, seed=1, v_rms=5.0, kmax=8, B0=B0, device="cuda:0")
     rho, v0, A0 = f.rho, f.v, f.A
     out = {"workload": f"{n}^3 periodic box, Mach 5, |k| <= 8, beta 0.5, {steps} SSP-RK3 steps, FP32 state "
@@ -409,7 +409,7 @@ def c5(steps: int = 10, ckpt: int = 2, n: int = 512):
                        "update_hbm_gbs": round(upd_bytes / (upd_ms * 1e-3) / 1e9, 1),
                        "update_hbm_frac": round(upd_bytes / (upd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                        "max_divb": d["max_divb"], "n_unphysical": d["n_unphysical"], "min_p": d["min_p"]}
-    log("bench c5: checkpointed FP32-state rollout and its adjoint")
+    log("bench 512^3: checkpointed FP32-state rollout and its adjoint")
     A = A0.clone().requires_grad_(True)
     v = v0.clone().requires_grad_(True)
     torch.cuda.synchronize()
@@ -449,7 +449,7 @@ def main():
     ap.add_argument("--wave-sizes", default="16,32,64", help="N of the 2N x N x N wave boxes")
     ap.add_argument("--wave-weights", default="z", choices=("z", "z_printed", "js"),
                     help="WENO weights of the wave suite: WENO-Z (reading), WENO-Z as printed, Jiang-Shu")
-    ap.add_argument("--no-c5", action="store_true",
+    ap.add_argument("--no-512", action="store_true",
                     help="skip the 512^3 Mach-5 workload (FP32-state forward and its adjoint)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -549,9 +549,9 @@ def main():
     if not args.no_adjoint:
         log("bench: adjoint cost (128^3, 20 steps, checkpoints every 5)")
         out["adjoint"] = adjoint_cost()
-    if not args.no_c5:
+    if not args.no_512:
         log("bench: 512^3 Mach-5 workload, FP32 state, forward and adjoint")
-        out["c5"] = c5()
+        out["mach5_512"] = mach5_512()
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written, for scaling
         # the FETCH_SIZE / WRITE_SIZE counters of the kernels above

@@ -169,26 +169,26 @@ def random_fields(n: int, seed: int, v_rms: float, kmax: int = 4, b_rms: float =
 
 
 # Named workloads: grid, steps and generator parameters.
-CONFIGS = {
+WORKLOADS = {
     # one FP64 step on 32^3, Mach 0.1, beta ~ 1
-    "c1_32": dict(n=32, steps=1, seed=1, v_rms=0.1, kmax=4, B0=(1.0, 0.5, 0.0)),
+    "mach0.1_32": dict(n=32, steps=1, seed=1, v_rms=0.1, kmax=4, B0=(1.0, 0.5, 0.0)),
     # 10 FP64 steps on 256^3, Mach 2, beta ~ 1 (the throughput workload)
-    "c2_256": dict(n=256, steps=10, seed=1, v_rms=2.0, kmax=4, B0=(1.0, 0.5, 0.0)),
+    "mach2_256": dict(n=256, steps=10, seed=1, v_rms=2.0, kmax=4, B0=(1.0, 0.5, 0.0)),
     # same generator sampled at 64^3: the oracle-sized version of the 256^3 run
-    "c2_64": dict(n=64, steps=10, seed=1, v_rms=2.0, kmax=4, B0=(1.0, 0.5, 0.0)),
+    "mach2_64": dict(n=64, steps=10, seed=1, v_rms=2.0, kmax=4, B0=(1.0, 0.5, 0.0)),
     # mixed precision workload, Mach 0.1 inputs on 256^3
-    "c3_256": dict(n=256, steps=10, seed=1, v_rms=0.1, kmax=4, B0=(1.0, 0.5, 0.0)),
+    "mixed_mach0.1_256": dict(n=256, steps=10, seed=1, v_rms=0.1, kmax=4, B0=(1.0, 0.5, 0.0)),
     # adjoint workload, Mach 1 on 128^3, 20 steps
-    "c4_128": dict(n=128, steps=20, seed=1, v_rms=1.0, kmax=4, B0=(1.0, 0.5, 0.0)),
+    "adjoint_mach1_128": dict(n=128, steps=20, seed=1, v_rms=1.0, kmax=4, B0=(1.0, 0.5, 0.0)),
     # Mach 5 turbulence on 512^3, k <= 8, beta = 0.5
-    "c5_512": dict(n=512, steps=10, seed=1, v_rms=5.0, kmax=8,
+    "mach5_512": dict(n=512, steps=10, seed=1, v_rms=5.0, kmax=8,
                    B0=tuple(float(np.sqrt(2.4 / 1.25)) * x for x in (1.0, 0.5, 0.0))),
 }
 
 
-def config_fields(name: str, n: int | None = None, seed: int | None = None) -> Fields:
+def workload_fields(name: str, n: int | None = None, seed: int | None = None) -> Fields:
     """Fields of a named workload, optionally resampled at another grid size/seed."""
-    c = CONFIGS[name]
+    c = WORKLOADS[name]
     return random_fields(n or c["n"], seed if seed is not None else c["seed"], c["v_rms"],
                          kmax=c["kmax"], B0=c["B0"])
 

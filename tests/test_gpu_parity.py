@@ -75,7 +75,7 @@ def test_rhs_parity():
         assert e <= TOL, (c, e)
 
 
-def test_step_c1_32():
+def test_step_32_mach01():
     """One SSP-RK3 step on 32^3, Mach 0.1 (the small FP64 workload), dt from
     eq. (cfl) on each side."""
     say("step 32^3")
@@ -138,7 +138,7 @@ WZ_FORMS = [("z", B.WM_WENO_Z), ("z_printed", B.WM_WENO_Z_PRINTED)]
 
 
 @pytest.mark.parametrize("form,wcode", WZ_FORMS)
-def test_wenoz_step_c1_32(form, wcode):
+def test_wenoz_step_32_mach01(form, wcode):
     """WENO-Z weights (reading R13, and the form Sect. 2.2 prints): one step on
     32^3, Mach 0.1, dt from eq. (cfl)."""
     import dataclasses
