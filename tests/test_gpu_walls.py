@@ -19,7 +19,10 @@ from helpers import assert_state_parity, rel_err, state_errors, walled_state
 pytestmark = pytest.mark.gpu
 
 CASES = [((70, 20, 18), (True, False, False)), ((21, 40, 18), (False, True, False)),
-         ((20, 18, 35), (False, False, True)), ((22, 19, 20), (True, True, True))]
+         ((20, 18, 35), (False, False, True)), ((22, 19, 20), (True, True, True)),
+         # the walled axes' faces (zones + the lower wall face) exactly fill one tile:
+         # x 63 + 1 = 64 (x tile), y 31 + 1 = 32 (FP64 y tile)
+         ((63, 31, 12), (True, True, False))]
 
 
 def say(*a):
