@@ -62,6 +62,10 @@ constexpr int SW_HL = 2, SW_HR = 3;          // stencil zones i-2 .. i+3
 constexpr int SW_NQ = 14;                    // q (7) and F (7) per zone
 constexpr int SW_NP = 11;                    // rho, v_n, v_t1, v_t2, B_n, B_t1, B_t2, P, c_f, c_A, c_s
 enum { P_RHO = 0, P_VN, P_VT1, P_VT2, P_BN, P_BT1, P_BT2, P_P, P_CF, P_CA, P_CS };
+// the forward sweep's zone primitives and speeds: rho, B_t1 and B_t2 are read
+// from the zone q in LDS instead
+constexpr int SW_NPF = 8;
+enum { FP_VN = 0, FP_VT1, FP_VT2, FP_BN, FP_P, FP_CF, FP_CA, FP_CS };
 
 // S: storage type of the state and of the face values (double, or float for
 // the FP32-state form); arithmetic is in double / TW as described below.
@@ -111,7 +115,7 @@ template <int AXIS, typename TW> constexpr size_t sweep_q_doubles() {
   return (size_t)SW_NQ * sweep_zones<AXIS, TW>();
 }
 template <int AXIS, typename TW> constexpr size_t sweep_p_doubles() {
-  return ((size_t)SW_NP * sweep_zones<AXIS, TW>() * sizeof(TW) + 7) / 8;
+  return ((size_t)SW_NPF * sweep_zones<AXIS, TW>() * sizeof(TW) + 7) / 8;
 }
 
 // Phases: (1) zone prologue of the tile and its halo into LDS; (2) per face:
@@ -125,7 +129,7 @@ template <int AXIS, typename TW> constexpr size_t sweep_p_doubles() {
 // alpha_f, alpha_s, beta) in FP64.
 
 template <int AXIS, bool WENO_Z, typename TW, typename S>
-__global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_kernel(SweepArgs<S> a) {
+__global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
   constexpr int TA = SweepTile<AXIS, TW>::TA, TB = SweepTile<AXIS, TW>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;     // zones along the axis
   constexpr int NI = TA + 4;                 // interfaces i-3/2 .. i+TA+3/2
@@ -195,17 +199,14 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
     zone_prologue(raw[r][0], m[CN], m[CT1], m[CT2], raw[r][4], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
 #pragma unroll
     for (int v = 0; v < SW_NQ; ++v) Q[v * NC + cell] = z[v];
-    Pz[P_RHO * NC + cell] = TW(z[Z_RHO]);
-    Pz[P_VN * NC + cell] = TW(z[Z_VN]);
-    Pz[P_VT1 * NC + cell] = TW(z[Z_VT1]);
-    Pz[P_VT2 * NC + cell] = TW(z[Z_VT2]);
-    Pz[P_BN * NC + cell] = TW(z[Z_BN]);
-    Pz[P_BT1 * NC + cell] = TW(z[Z_BT1]);
-    Pz[P_BT2 * NC + cell] = TW(z[Z_BT2]);
-    Pz[P_P * NC + cell] = TW(z[Z_P]);
-    Pz[P_CF * NC + cell] = TW(z[Z_CF]);
-    Pz[P_CA * NC + cell] = TW(z[Z_CA]);
-    Pz[P_CS * NC + cell] = TW(z[Z_CS]);
+    Pz[FP_VN * NC + cell] = TW(z[Z_VN]);
+    Pz[FP_VT1 * NC + cell] = TW(z[Z_VT1]);
+    Pz[FP_VT2 * NC + cell] = TW(z[Z_VT2]);
+    Pz[FP_BN * NC + cell] = TW(z[Z_BN]);
+    Pz[FP_P * NC + cell] = TW(z[Z_P]);
+    Pz[FP_CF * NC + cell] = TW(z[Z_CF]);
+    Pz[FP_CA * NC + cell] = TW(z[Z_CA]);
+    Pz[FP_CS * NC + cell] = TW(z[Z_CS]);
   }
 #ifdef WM_SWEEP_CLOCK
   stamp[1] = clock64();
@@ -228,24 +229,13 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
   }
   auto PL = [&](int v) { return double(Pz[v * NC + cL]); };
   auto PR = [&](int v) { return double(Pz[v * NC + cR]); };
-  double fp[8];   // face state: mean of the primitive states of zones i and i+1
-#pragma unroll
-  for (int v = 0; v < 8; ++v) fp[v] = 0.5 * (PL(P_RHO + v) + PR(P_RHO + v));
-  TW al[7];
-  {
-    const double vL = PL(P_VN), vR = PR(P_VN);
-    const double cfL = PL(P_CF), cfR = PR(P_CF), cAL = PL(P_CA), cAR = PR(P_CA), csL = PL(P_CS), csR = PR(P_CS);
-    al[0] = TW(fmax(fabs(vL - cfL), fabs(vR - cfR)));
-    al[1] = TW(fmax(fabs(vL - cAL), fabs(vR - cAR)));
-    al[2] = TW(fmax(fabs(vL - csL), fabs(vR - csR)));
-    al[3] = TW(fmax(fabs(vL), fabs(vR)));
-    al[4] = TW(fmax(fabs(vL + csL), fabs(vR + csR)));
-    al[5] = TW(fmax(fabs(vL + cAL), fabs(vR + cAR)));
-    al[6] = TW(fmax(fabs(vL + cfL), fabs(vR + cfR)));
-  }
-  // CT transport-flux correction: face mean of B_n v_t (eq. fct1-fct6)
-  const double tc1 = 0.5 * (PL(P_BN) * PL(P_VT1) + PR(P_BN) * PR(P_VT1));
-  const double tc2 = 0.5 * (PL(P_BN) * PL(P_VT2) + PR(P_BN) * PR(P_VT2));
+  auto QL = [&](int v) { return Q[v * NC + cL]; };
+  auto QR = [&](int v) { return Q[v * NC + cR]; };
+  // face state: mean of the primitive states of zones i and i+1 (rho, B_t from q)
+  const double fp[8] = {0.5 * (QL(Z_RHO) + QR(Z_RHO)), 0.5 * (PL(FP_VN) + PR(FP_VN)),
+                        0.5 * (PL(FP_VT1) + PR(FP_VT1)), 0.5 * (PL(FP_VT2) + PR(FP_VT2)),
+                        0.5 * (PL(FP_BN) + PR(FP_BN)), 0.5 * (QL(Z_BT1) + QR(Z_BT1)),
+                        0.5 * (QL(Z_BT2) + QR(Z_BT2)), 0.5 * (PL(FP_P) + PR(FP_P))};
   double d0[SW_NQ], d1[SW_NQ];
   {
     const int c0 = cidx(fa, fb), c1 = cidx(fa + 1, fb);
@@ -281,13 +271,25 @@ __global__ __launch_bounds__(SW_THREADS, sizeof(TW) == 4 ? 3 : 2) void sweep_ker
 
   // ---- (3) characteristic WENO flux of this face
   auto dl = [&](int j, int k) -> TW { return Dl[j * NIF + iidx(fa + k, fb)]; };
+  // Lax-Friedrichs speed of field m (0-based), read when its pair needs it:
+  // max(|v_L + sg c_L|, |v_R + sg c_R|), c = c_f (m = 0, 6), c_A (1, 5), c_s (2, 4), 0 (3)
+  auto alf = [&](int m) -> TW {
+    const double vL = PL(FP_VN), vR = PR(FP_VN);
+    if (m == 3) return TW(fmax(fabs(vL), fabs(vR)));
+    const int sp = (m == 0 || m == 6) ? FP_CF : ((m == 1 || m == 5) ? FP_CA : FP_CS);
+    const double sg = m < 3 ? -1.0 : 1.0;
+    return TW(fmax(fabs(vL + sg * PL(sp)), fabs(vR + sg * PR(sp))));
+  };
   FaceEig e;
   face_eig(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], fp[6], fp[7], a.ph, e);
-  double corr[7];
-  face_corr<WENO_Z, TW>(e, al, dl, a.ph, corr);
+  // F = F_c + corr: the characteristic part is added onto the central term
   double Ff[7];
 #pragma unroll
-  for (int j = 0; j < 7; ++j) Ff[j] = Fc[j] + corr[j];
+  for (int j = 0; j < 7; ++j) Ff[j] = Fc[j];
+  face_corr<WENO_Z, TW>(e, alf, dl, a.ph, Ff);
+  // CT transport-flux correction: face mean of B_n v_t (eq. fct1-fct6)
+  const double tc1 = 0.5 * (PL(FP_BN) * PL(FP_VT1) + PR(FP_BN) * PR(FP_VT1));
+  const double tc2 = 0.5 * (PL(FP_BN) * PL(FP_VT2) + PR(FP_BN) * PR(FP_VT2));
   const double T1 = Ff[4] + tc1;
   const double T2 = Ff[5] + tc2;
 #ifdef WM_SWEEP_CLOCK

@@ -302,11 +302,12 @@ __host__ __device__ __forceinline__ void split_pair(const T S[7], const T A[4], 
 // so that F_{i+1/2} = F_c + corr with the central term F_c in physical space
 // (R L = I), eq. (FWENO).  L and R follow Appendix A: m = 1, 2, 3 take the
 // upper signs and 7, 6, 5 the lower; m = 2, 6 are the Alfven waves and m = 3, 5
-// the slow waves.  `al[m]` is the Lax-Friedrichs speed of field m (0-based),
+// the slow waves.  `al(m)` gives the Lax-Friedrichs speed of field m (0-based),
 // `dl(j, k)` reads interface difference j of interface k.  Projections, split
 // and weights run in T; the eigen scalars and the back-projection in FP64.
-template <bool WENO_Z, typename T, class DL>
-__host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[7], DL dl, const Phys& ph,
+// corr is added to (the caller passes the central term F_c in it).
+template <bool WENO_Z, typename T, class AL, class DL>
+__host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL dl, const Phys& ph,
                                                    double corr[7]) {
   const T eps = T(ph.eps);
   const double epsZ = ph.eps_Z;
@@ -322,17 +323,17 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
                     T(e.qa2 * (e.omg * e.af * e.Bt2 + sra * e.as * e.bz)), T(e.qa2 * (gm1 * e.af))};
     const T A[4] = {T(e.qa2 * e.Gf), T(-e.qa2 * (e.af * e.cf)), T(e.qa2 * (e.csl * e.as * e.by * e.s)),
                     T(e.qa2 * (e.csl * e.as * e.bz * e.s))};
-    split_pair(S, A, al[0], al[6], dl, vu, vl);
+    split_pair(S, A, al(0), al(6), dl, vu, vl);
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
     const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ, lit));
     const double sp = fu + fl, sm = fu - fl;
-    corr[0] = e.af * sp;
-    corr[1] = e.af * e.vn * sp - e.af * e.cf * sm;
-    corr[2] = e.af * e.vt1 * sp + e.csl * e.as * e.by * e.s * sm;
-    corr[3] = e.af * e.vt2 * sp + e.csl * e.as * e.bz * e.s * sm;
-    corr[4] = e.cs * e.as * e.by * e.isr * sp;
-    corr[5] = e.cs * e.as * e.bz * e.isr * sp;
-    corr[6] = e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2) * sp - e.Gf * sm;
+    corr[0] += e.af * sp;
+    corr[1] += e.af * e.vn * sp - e.af * e.cf * sm;
+    corr[2] += e.af * e.vt1 * sp + e.csl * e.as * e.by * e.s * sm;
+    corr[3] += e.af * e.vt2 * sp + e.csl * e.as * e.bz * e.s * sm;
+    corr[4] += e.cs * e.as * e.by * e.isr * sp;
+    corr[5] += e.cs * e.as * e.bz * e.isr * sp;
+    corr[6] += e.af * (0.5 * e.v2 + e.cf2 - e.g2 * e.a2) * sp - e.Gf * sm;
   }
   sched_fence();
   // ---- slow pair (m = 3, 5)
@@ -343,7 +344,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
                     T(e.qa2 * (e.omg * e.as * e.Bt2 - sra * e.af * e.bz)), T(e.qa2 * (gm1 * e.as))};
     const T A[4] = {T(e.qa2 * e.Gs), T(-e.qa2 * (e.as * e.csl)), T(-e.qa2 * (e.cf * e.af * e.by * e.s)),
                     T(-e.qa2 * (e.cf * e.af * e.bz * e.s))};
-    split_pair(S, A, al[2], al[4], dl, vu, vl);
+    split_pair(S, A, al(2), al(4), dl, vu, vl);
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
     const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ, lit));
     const double sp = fu + fl, sm = fu - fl;
@@ -360,7 +361,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
   {
     const T S0 = T(0.25 * e.Ga), S2 = T(-0.25 * e.bz * e.s), S3 = T(0.25 * e.by * e.s);
     const T A4 = T(-0.25 * e.sr * e.bz), A5 = T(0.25 * e.sr * e.by);
-    const T alu = al[1], all = al[5];
+    const T alu = al(1), all = al(5);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const T sF = S0 * dl(0, k) + S2 * dl(2, k) + S3 * dl(3, k);
@@ -387,7 +388,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, const T al[
     const double ht = 0.5 * e.tau;
     const T l[7] = {T(0.5 - 0.5 * ht * e.v2), T(ht * e.vn), T(ht * e.vt1), T(ht * e.vt2),
                     T(ht * e.Bt1), T(ht * e.Bt2), T(-ht)};
-    const T a4 = al[3];
+    const T a4 = al(3);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       T sF = l[0] * dl(0, k), sq = l[0] * dl(7, k);
