@@ -48,15 +48,16 @@ __device__ __forceinline__ void face_stencil(int c, int n, int wall, int idx[4],
 // directional sweep
 // ---------------------------------------------------------------------------
 // Tile of TA faces along the sweep axis by TB faces across it (256 lanes, one
-// face each), for work type TW.  The x sweep uses 64 x 4 so that a wave reads
-// whole 128-byte lines of a row.  The y and z sweeps have x across: in FP64
-// 32 x 8 (296 zones for 256 faces; rows of 64 bytes), measured 2% faster than
-// 16 x 16 (336 zones, 128-byte rows), which the FP32 work type keeps (it runs
-// three waves per SIMD and measured 1% slower with 32 x 8).
+// face each), for work type TW.  The x sweep uses 128 x 2 (266 zones for 256
+// faces; a wave reads whole 128-byte lines of a row), 0.5% faster than 64 x 4.
+// The y and z sweeps have x across: in FP64 32 x 8 (296 zones; rows of 64
+// bytes), which fits three blocks per CU in LDS, against 16 x 16 (336 zones,
+// 128-byte rows) in the FP32 work type (32 x 8 measured 1% slower there); 64 x 4
+// (276 zones, 32-byte rows) measured 4% slower in FP64.
 template <int AXIS, typename TW> struct SweepTile {
   static constexpr int TA = sizeof(TW) == 8 ? 32 : 16, TB = sizeof(TW) == 8 ? 8 : 16;
 };
-template <typename TW> struct SweepTile<0, TW> { static constexpr int TA = 64, TB = 4; };
+template <typename TW> struct SweepTile<0, TW> { static constexpr int TA = 128, TB = 2; };
 constexpr int SW_THREADS = 256;
 constexpr int SW_HL = 2, SW_HR = 3;          // stencil zones i-2 .. i+3
 constexpr int SW_NQ = 14;                    // q (7) and F (7) per zone

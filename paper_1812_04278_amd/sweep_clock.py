@@ -23,8 +23,8 @@ from . import inputs
 
 PHASES = ["zone loads + prologue", "barrier 1", "phase 2 (central flux, face state, differences)",
           "barriers 2-3 + difference stores", "phase 3 (eigensystem + WENO)", "flux stores"]
-TILES = {0: (64, 4), 1: (32, 8), 2: (32, 8)}          # FP64 work type
-TILES_F32 = {0: (64, 4), 1: (16, 16), 2: (16, 16)}    # mixed and FP32 state
+TILES = {0: (128, 2), 1: (32, 8), 2: (32, 8)}         # FP64 work type
+TILES_F32 = {0: (128, 2), 1: (16, 16), 2: (16, 16)}   # mixed and FP32 state
 WAVES_PER_BLOCK = 4
 
 
