@@ -41,8 +41,8 @@ __host__ __device__ __forceinline__ void sched_fence() {
 #endif
 }
 
-// Reciprocal for the WENO weights: hardware estimate refined by Newton steps
-// (relative error far below the rounding of the weights themselves).
+// Reciprocal: the hardware estimate (relative error up to 4.6e-8 on MI355X,
+// measured over 2^22 arguments) refined by two Newton steps, exact to rounding.
 __host__ __device__ __forceinline__ double rcp_w(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
   double r = __builtin_amdgcn_rcp(x);
@@ -72,9 +72,23 @@ __host__ __device__ __forceinline__ float rcp_w(float x) {
   return 1.0f / x;
 #endif
 }
+// One Newton step on the hardware estimate: relative error up to 2.2e-15
+// (measured), for the common denominator of the FP64 WENO weights, where it
+// scales the interpolant phi_N by at most that factor.  The FP32 form is rcp_w.
+__host__ __device__ __forceinline__ double rcp_1(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(fma(-x, r, 1.0), r, r);
+#else
+  return 1.0 / x;
+#endif
+}
+__host__ __device__ __forceinline__ float rcp_1(float x) { return rcp_w(x); }
 
-// 1/sqrt(x) and sqrt(x) for x >= 0 from the hardware estimate and two Newton
-// steps (relative error ~1 ulp; sqrt(0) = 0).
+// 1/sqrt(x) for x > 0 from the hardware estimate (relative error up to 5.2e-8,
+// measured) and two Newton steps (~1 ulp); sqrt(x) for x >= 0 from one Newton
+// step on 1/sqrt (up to 4.3e-15) and one on the square root itself, which
+// brings it to ~1 ulp (sqrt(0) = 0).
 __host__ __device__ __forceinline__ double rsq_nr(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
   double y = __builtin_amdgcn_rsq(x);
@@ -88,7 +102,9 @@ __host__ __device__ __forceinline__ double rsq_nr(double x) {
 }
 __host__ __device__ __forceinline__ double sqrt_nr(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
-  const double y = rsq_nr(fmax(x, 1e-300));
+  const double xc = fmax(x, 1e-300);
+  const double y0 = __builtin_amdgcn_rsq(xc);
+  const double y = fma(0.5 * y0, fma(-xc * y0, y0, 1.0), y0);
   const double r = x * y;
   return fma(0.5 * y, fma(-r, r, x), r);
 #else
@@ -167,7 +183,7 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps
       s0 *= r; s1 *= r; s2 *= r;
     }
     const T p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
-    const T rq = rcp_w(fma(T(3), p01, fma(T(6), p02, p12)));
+    const T rq = rcp_1(fma(T(3), p01, fma(T(6), p02, p12)));
     const T cY = fma(T(0.25), p01, fma(T(-1.0 / 12.0), p12, T(-0.5) * p02));
     return rq * fma(cY, Y, (p12 * T(1.0 / 3.0)) * X);
   } else {
@@ -185,7 +201,7 @@ __host__ __device__ __forceinline__ T phiN(T a, T b, T c, T d, T eps, double eps
     const T P = s0 * m0, P2 = P * P;
     const T t = lit ? tau5 : tau5 * tau5;
     const T al0 = fma(t * m0, m0, P2), al1 = T(6) * fma(t * m1, m1, P2), al2 = T(3) * fma(t * m2, m2, P2);
-    const T inv = rcp_w(al0 + al1 + al2);
+    const T inv = rcp_1(al0 + al1 + al2);
     return inv * (al0 * X * T(1.0 / 3.0) + (al2 - T(0.5) * (al0 + al1 + al2)) * Y * T(1.0 / 6.0));
   }
 }
