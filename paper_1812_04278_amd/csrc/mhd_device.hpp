@@ -331,15 +331,50 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
   const double gm1 = -e.omg;
   const double sra = e.sr * e.cs;
   T vu[8], vl[8];
+  // The fast and slow left rows share W = (g1 v2, omg vn, omg vt1, omg vt2,
+  // omg Bt1, omg Bt2, gm1): fast S = qa2 (af W + sra as beta), slow S = qa2 (as W
+  // - sra af beta) with beta = (0, 0, 0, 0, by, bz, 0), and the entropy row is
+  // e0/2 - 2 qa2 W (ht = 2 qa2 (gamma - 1)).  The projections W.dF, W.dq of the
+  // five interfaces are formed once, in the fast pair, and reused.
+  // W.d = g1 v2 d0 + omg (vn d1 + vt1 d2 + vt2 d3 + Bt1 d4 + Bt2 d5) + gm1 d6, with the
+  // uniform factors applied after the per-lane sum (fewer live registers than W itself)
+  const T w0 = T(e.g1 * e.v2), wv[5] = {T(e.vn), T(e.vt1), T(e.vt2), T(e.Bt1), T(e.Bt2)};
+  const T omgT = T(e.omg), gm1T = T(gm1);
+  auto wdot = [&](const T* d) {
+    T in = wv[0] * d[1];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) in += wv[j] * d[1 + j];
+    return omgT * in + (w0 * d[0] + gm1T * d[6]);
+  };
+  const T by = T(e.by), bz = T(e.bz);
+  T WF[5], Wq[5];
+  // split values of interface k from the projections onto the rows S + A and S - A
+  auto split_k = [&](int k, T sF, T sq, T aF, T aq, T alu, T all) {
+    const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
+    if (k <= 3) { vu[k] = uF + alu * uq; vl[k] = lF + all * lq; }
+    if (k >= 1) { vu[3 + k] = uF - alu * uq; vl[3 + k] = lF - all * lq; }
+  };
   // ---- fast pair (m = 1, 7)
   {
-    const T S[7] = {T(e.qa2 * (e.af * e.g1 * e.v2)), T(e.qa2 * (e.omg * e.af * e.vn)),
-                    T(e.qa2 * (e.omg * e.af * e.vt1)), T(e.qa2 * (e.omg * e.af * e.vt2)),
-                    T(e.qa2 * (e.omg * e.af * e.Bt1 + sra * e.as * e.by)),
-                    T(e.qa2 * (e.omg * e.af * e.Bt2 + sra * e.as * e.bz)), T(e.qa2 * (gm1 * e.af))};
+    const T cW = T(e.qa2 * e.af), cB = T(e.qa2 * (sra * e.as));
     const T A[4] = {T(e.qa2 * e.Gf), T(-e.qa2 * (e.af * e.cf)), T(e.qa2 * (e.csl * e.as * e.by * e.s)),
                     T(e.qa2 * (e.csl * e.as * e.bz * e.s))};
-    split_pair(S, A, al(0), al(6), dl, vu, vl);
+    const T alu = al(0), all = al(6);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      T dF[7], dq[7];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) { dF[j] = dl(j, k); dq[j] = dl(7 + j, k); }
+      const T wF = wdot(dF), wq = wdot(dq);
+      WF[k] = wF;
+      Wq[k] = wq;
+      const T bF = by * dF[4] + bz * dF[5], bq = by * dq[4] + bz * dq[5];
+      T aF = A[0] * dF[0], aq = A[0] * dq[0];
+#pragma unroll
+      for (int j = 1; j < 4; ++j) { aF += A[j] * dF[j]; aq += A[j] * dq[j]; }
+      split_k(k, cW * wF + cB * bF, cW * wq + cB * bq, aF, aq, alu, all);
+      sched_fence();
+    }
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
     const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ, lit));
     const double sp = fu + fl, sm = fu - fl;
@@ -354,13 +389,22 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
   sched_fence();
   // ---- slow pair (m = 3, 5)
   {
-    const T S[7] = {T(e.qa2 * (e.as * e.g1 * e.v2)), T(e.qa2 * (e.omg * e.as * e.vn)),
-                    T(e.qa2 * (e.omg * e.as * e.vt1)), T(e.qa2 * (e.omg * e.as * e.vt2)),
-                    T(e.qa2 * (e.omg * e.as * e.Bt1 - sra * e.af * e.by)),
-                    T(e.qa2 * (e.omg * e.as * e.Bt2 - sra * e.af * e.bz)), T(e.qa2 * (gm1 * e.as))};
+    const T cW = T(e.qa2 * e.as), cB = T(-e.qa2 * (sra * e.af));
     const T A[4] = {T(e.qa2 * e.Gs), T(-e.qa2 * (e.as * e.csl)), T(-e.qa2 * (e.cf * e.af * e.by * e.s)),
                     T(-e.qa2 * (e.cf * e.af * e.bz * e.s))};
-    split_pair(S, A, al(2), al(4), dl, vu, vl);
+    const T alu = al(2), all = al(4);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      T dF[6], dq[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) { dF[j] = dl(j, k); dq[j] = dl(7 + j, k); }
+      const T bF = by * dF[4] + bz * dF[5], bq = by * dq[4] + bz * dq[5];
+      T aF = A[0] * dF[0], aq = A[0] * dq[0];
+#pragma unroll
+      for (int j = 1; j < 4; ++j) { aF += A[j] * dF[j]; aq += A[j] * dq[j]; }
+      split_k(k, cW * WF[k] + cB * bF, cW * Wq[k] + cB * bq, aF, aq, alu, all);
+      sched_fence();
+    }
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
     const double fl = double(weno_split<WENO_Z>(vl, eps, epsZ, lit));
     const double sp = fu + fl, sm = fu - fl;
@@ -371,6 +415,25 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
     corr[4] += -e.cs * e.af * e.by * e.isr * sp;
     corr[5] += -e.cs * e.af * e.bz * e.isr * sp;
     corr[6] += e.as * (0.5 * e.v2 + e.csl2 - e.g2 * e.a2) * sp - e.Gs * sm;
+  }
+  sched_fence();
+  // ---- entropy (m = 4): L = (1 - tau v^2/2, tau v, tau B_t, -tau), times 1/2, = e0/2 - 2 qa2 W
+  {
+    const T cE = T(-2.0 * e.qa2);
+    const T a4 = al(3);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const T sF = T(0.5) * dl(0, k) + cE * WF[k], sq = T(0.5) * dl(7, k) + cE * Wq[k];
+      if (k <= 3) vu[k] = sF + a4 * sq;
+      if (k >= 1) vu[3 + k] = sF - a4 * sq;
+      sched_fence();
+    }
+    const double f4 = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
+    corr[0] += f4;
+    corr[1] += e.vn * f4;
+    corr[2] += e.vt1 * f4;
+    corr[3] += e.vt2 * f4;
+    corr[6] += 0.5 * e.v2 * f4;
   }
   sched_fence();
   // ---- Alfven pair (m = 2, 6): L = (Ga/2, 0, -bz s/2, by s/2, -+sr bz/2, +-sr by/2, 0)
@@ -384,9 +447,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
       const T sq = S0 * dl(7, k) + S2 * dl(9, k) + S3 * dl(10, k);
       const T aF = A4 * dl(4, k) + A5 * dl(5, k);
       const T aq = A4 * dl(11, k) + A5 * dl(12, k);
-      const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
-      if (k <= 3) { vu[k] = uF + alu * uq; vl[k] = lF + all * lq; }
-      if (k >= 1) { vu[3 + k] = uF - alu * uq; vl[3 + k] = lF - all * lq; }
+      split_k(k, sF, sq, aF, aq, alu, all);
       sched_fence();
     }
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
@@ -397,29 +458,6 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
     corr[4] += -e.bz * e.isr * sm;
     corr[5] += e.by * e.isr * sm;
     corr[6] += -e.Ga * sp;
-  }
-  sched_fence();
-  // ---- entropy (m = 4): L = (1 - tau v^2/2, tau v, tau B_t, -tau), times 1/2
-  {
-    const double ht = 0.5 * e.tau;
-    const T l[7] = {T(0.5 - 0.5 * ht * e.v2), T(ht * e.vn), T(ht * e.vt1), T(ht * e.vt2),
-                    T(ht * e.Bt1), T(ht * e.Bt2), T(-ht)};
-    const T a4 = al(3);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      T sF = l[0] * dl(0, k), sq = l[0] * dl(7, k);
-#pragma unroll
-      for (int j = 1; j < 7; ++j) { sF += l[j] * dl(j, k); sq += l[j] * dl(7 + j, k); }
-      if (k <= 3) vu[k] = sF + a4 * sq;
-      if (k >= 1) vu[3 + k] = sF - a4 * sq;
-      sched_fence();
-    }
-    const double f4 = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
-    corr[0] += f4;
-    corr[1] += e.vn * f4;
-    corr[2] += e.vt1 * f4;
-    corr[3] += e.vt2 * f4;
-    corr[6] += 0.5 * e.v2 * f4;
   }
 }
 
