@@ -22,7 +22,33 @@ struct Grid {
   __device__ __forceinline__ size_t at(int i, int j, int k) const {
     return ((size_t)k * ny + j) * nx + i;
   }
+  // the same index in 32 bits (N < 2^31 always)
+  __device__ __forceinline__ unsigned at32(int i, int j, int k) const {
+    return ((unsigned)k * (unsigned)ny + (unsigned)j) * (unsigned)nx + (unsigned)i;
+  }
 };
+
+// Raw buffer access to one array of at most 4 GiB: the array's base lives in a
+// scalar descriptor and the hardware adds the lane's 32-bit byte offset, so an
+// access costs no 64-bit address arithmetic.  Word 3 of the descriptor is the
+// gfx9 value for untyped 32-bit accesses.
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(unsigned)bytes, 0x00020000);
+}
+typedef unsigned BufU2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double buf_load(BufRsrc r, unsigned off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_load(BufRsrc r, unsigned off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(BufRsrc r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(BufRsrc r, unsigned off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
 
 // The four normal-field faces b_f, f = c-2 .. c+1, that the zone-B
 // interpolation of zone c reads along an axis of n faces: periodic wrap, or at
@@ -157,6 +183,9 @@ __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
   const int c = blockIdx.z;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid) / 64;   // uniform: held in a scalar register
+  // every array of the state and the fluxes within 4 GiB: buffer accesses with 32-bit offsets
+  const size_t abytes = g.N * sizeof(S);
+  const bool off32 = abytes < (size_t(1) << 32);
 #ifdef WM_SWEEP_CLOCK
   // clock build: per-wave shader-clock stamps at the phase boundaries
   unsigned long long stamp[8];
@@ -183,11 +212,19 @@ __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
     if (AXIS == 0)      { i = ia; j = ib; k = c; }
     else if (AXIS == 1) { i = ib; j = ia; k = c; }
     else                { i = ib; j = c;  k = ia; }
-    const size_t gi = g.at(i, j, k);
+    if (off32) {
+      const unsigned off = g.at32(i, j, k) * (unsigned)sizeof(S);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) raw[r][v] = double(a.hydro[v * g.N + gi]);
+      for (int v = 0; v < 5; ++v) raw[r][v] = double(buf_load(buf_rsrc(a.hydro + v * g.N, abytes), off, S()));
 #pragma unroll
-    for (int v = 0; v < 3; ++v) raw[r][5 + v] = double(a.bcell[v * g.N + gi]);
+      for (int v = 0; v < 3; ++v) raw[r][5 + v] = double(buf_load(buf_rsrc(a.bcell + v * g.N, abytes), off, S()));
+    } else {
+      const size_t gi = g.at(i, j, k);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) raw[r][v] = double(a.hydro[v * g.N + gi]);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) raw[r][5 + v] = double(a.bcell[v * g.N + gi]);
+    }
     raw[r][1 + CN] *= flip;
     raw[r][5 + CN] *= flip;
   }
@@ -328,13 +365,24 @@ __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
   const size_t gi = g.at(i, j, k);
   double fm[3];
   fm[CN] = Ff[1]; fm[CT1] = Ff[2]; fm[CT2] = Ff[3];
-  a.fhydro[gi] = S(Ff[0]);
-  a.fhydro[g.N + gi] = S(fm[0]);
-  a.fhydro[2 * g.N + gi] = S(fm[1]);
-  a.fhydro[3 * g.N + gi] = S(fm[2]);
-  a.fhydro[4 * g.N + gi] = S(Ff[6]);
-  a.T[gi] = S(T1);
-  a.T[g.N + gi] = S(T2);
+  if (off32) {
+    const unsigned off = g.at32(i, j, k) * (unsigned)sizeof(S);
+    buf_store(buf_rsrc(a.fhydro, abytes), off, S(Ff[0]));
+    buf_store(buf_rsrc(a.fhydro + g.N, abytes), off, S(fm[0]));
+    buf_store(buf_rsrc(a.fhydro + 2 * g.N, abytes), off, S(fm[1]));
+    buf_store(buf_rsrc(a.fhydro + 3 * g.N, abytes), off, S(fm[2]));
+    buf_store(buf_rsrc(a.fhydro + 4 * g.N, abytes), off, S(Ff[6]));
+    buf_store(buf_rsrc(a.T, abytes), off, S(T1));
+    buf_store(buf_rsrc(a.T + g.N, abytes), off, S(T2));
+  } else {
+    a.fhydro[gi] = S(Ff[0]);
+    a.fhydro[g.N + gi] = S(fm[0]);
+    a.fhydro[2 * g.N + gi] = S(fm[1]);
+    a.fhydro[3 * g.N + gi] = S(fm[2]);
+    a.fhydro[4 * g.N + gi] = S(Ff[6]);
+    a.T[gi] = S(T1);
+    a.T[g.N + gi] = S(T2);
+  }
   if (a.dbg) {
 #pragma unroll
     for (int v = 0; v < 7; ++v) a.dbg[v * g.N + gi] = Ff[v];
