@@ -346,7 +346,6 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
     for (int j = 1; j < 5; ++j) in += wv[j] * d[1 + j];
     return omgT * in + (w0 * d[0] + gm1T * d[6]);
   };
-  const T by = T(e.by), bz = T(e.bz);
   T WF[5], Wq[5];
   // split values of interface k from the projections onto the rows S + A and S - A
   auto split_k = [&](int k, T sF, T sq, T aF, T aq, T alu, T all) {
@@ -356,7 +355,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
   };
   // ---- fast pair (m = 1, 7)
   {
-    const T cW = T(e.qa2 * e.af), cB = T(e.qa2 * (sra * e.as));
+    const T cW = T(e.qa2 * e.af), cBy = T(e.qa2 * (sra * e.as) * e.by), cBz = T(e.qa2 * (sra * e.as) * e.bz);
     const T A[4] = {T(e.qa2 * e.Gf), T(-e.qa2 * (e.af * e.cf)), T(e.qa2 * (e.csl * e.as * e.by * e.s)),
                     T(e.qa2 * (e.csl * e.as * e.bz * e.s))};
     const T alu = al(0), all = al(6);
@@ -368,11 +367,10 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
       const T wF = wdot(dF), wq = wdot(dq);
       WF[k] = wF;
       Wq[k] = wq;
-      const T bF = by * dF[4] + bz * dF[5], bq = by * dq[4] + bz * dq[5];
       T aF = A[0] * dF[0], aq = A[0] * dq[0];
 #pragma unroll
       for (int j = 1; j < 4; ++j) { aF += A[j] * dF[j]; aq += A[j] * dq[j]; }
-      split_k(k, cW * wF + cB * bF, cW * wq + cB * bq, aF, aq, alu, all);
+      split_k(k, cW * wF + (cBy * dF[4] + cBz * dF[5]), cW * wq + (cBy * dq[4] + cBz * dq[5]), aF, aq, alu, all);
       sched_fence();
     }
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
@@ -389,7 +387,7 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
   sched_fence();
   // ---- slow pair (m = 3, 5)
   {
-    const T cW = T(e.qa2 * e.as), cB = T(-e.qa2 * (sra * e.af));
+    const T cW = T(e.qa2 * e.as), cBy = T(-e.qa2 * (sra * e.af) * e.by), cBz = T(-e.qa2 * (sra * e.af) * e.bz);
     const T A[4] = {T(e.qa2 * e.Gs), T(-e.qa2 * (e.as * e.csl)), T(-e.qa2 * (e.cf * e.af * e.by * e.s)),
                     T(-e.qa2 * (e.cf * e.af * e.bz * e.s))};
     const T alu = al(2), all = al(4);
@@ -398,11 +396,11 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
       T dF[6], dq[6];
 #pragma unroll
       for (int j = 0; j < 6; ++j) { dF[j] = dl(j, k); dq[j] = dl(7 + j, k); }
-      const T bF = by * dF[4] + bz * dF[5], bq = by * dq[4] + bz * dq[5];
       T aF = A[0] * dF[0], aq = A[0] * dq[0];
 #pragma unroll
       for (int j = 1; j < 4; ++j) { aF += A[j] * dF[j]; aq += A[j] * dq[j]; }
-      split_k(k, cW * WF[k] + cB * bF, cW * Wq[k] + cB * bq, aF, aq, alu, all);
+      split_k(k, cW * WF[k] + (cBy * dF[4] + cBz * dF[5]), cW * Wq[k] + (cBy * dq[4] + cBz * dq[5]), aF, aq, alu,
+              all);
       sched_fence();
     }
     const double fu = double(weno_split<WENO_Z>(vu, eps, epsZ, lit));
