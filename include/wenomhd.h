@@ -226,6 +226,13 @@ wm_status wm_diagnostics(wm_patch* p, wm_diag* out);
  * fluxes T^n_t1, T^n_t2 of eq. (fct1)-(fct6). */
 wm_status wm_debug_sweep(wm_patch* p, int axis, void* out);
 
+/* Testing switch (on != 0): the sweep addresses its loads and stores with
+ * 64-bit pointers, the path it otherwise takes only for arrays of 4 GiB and
+ * more (raw buffer accesses with 32-bit offsets below that).  The arithmetic is
+ * the same, so results are bitwise equal either way.  WM_ERR_ARG for a null
+ * patch. */
+wm_status wm_debug_wide_addressing(wm_patch* p, int on);
+
 /* Right-hand side dU/dt of the bound state: out [8][nz][ny][nx] (device) =
  * d(rho, m_x, m_y, m_z, E)/dt from the flux divergence (eq. num) and
  * d(b_x, b_y, b_z)/dt from the corner fluxes (Sect. 2.3). */

@@ -22,7 +22,7 @@ WM_SSPRK3, WM_RK4 = 0, 1
 SYMBOLS = [
     "wm_config_default", "wm_scratch_bytes", "wm_patch_create", "wm_patch_destroy", "wm_bind_state",
     "wm_init_from_potential", "wm_refresh_zone_field", "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics",
-    "wm_debug_sweep", "wm_debug_rhs", "wm_adjoint_scratch_bytes", "wm_rhs_vjp", "wm_adjoint_step",
+    "wm_debug_sweep", "wm_debug_wide_addressing", "wm_debug_rhs", "wm_adjoint_scratch_bytes", "wm_rhs_vjp", "wm_adjoint_step",
     "wm_step_record", "wm_zone_field_vjp", "wm_init_adjoint", "wm_profile", "wm_profile_report", "wm_last_error",
     "wm_step_static",
 ]
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
     lib.wm_step.argtypes = [P, D]
     lib.wm_diagnostics.argtypes = [P, ctypes.POINTER(WmDiag)]
     lib.wm_debug_sweep.argtypes = [P, ctypes.c_int, P]
+    lib.wm_debug_wide_addressing.argtypes = [P, ctypes.c_int]
     lib.wm_debug_rhs.argtypes = [P, P]
     lib.wm_adjoint_scratch_bytes.argtypes = [C]
     lib.wm_adjoint_scratch_bytes.restype = ctypes.c_size_t
@@ -91,7 +92,8 @@ def load(path: str = LIB_PATH):
     lib.wm_last_error.restype = ctypes.c_char_p
     for name in ("wm_patch_create", "wm_patch_destroy", "wm_bind_state", "wm_init_from_potential",
                  "wm_refresh_zone_field",
-                 "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics", "wm_debug_sweep", "wm_debug_rhs",
+                 "wm_compute_dt", "wm_rk_stage", "wm_step", "wm_diagnostics", "wm_debug_sweep",
+                 "wm_debug_wide_addressing", "wm_debug_rhs",
                  "wm_rhs_vjp", "wm_adjoint_step", "wm_step_record", "wm_zone_field_vjp", "wm_init_adjoint",
                  "wm_profile", "wm_profile_report", "wm_step_static"):
         getattr(lib, name).restype = ctypes.c_int
@@ -288,6 +290,10 @@ class Patch:
         if st != WM_OK and (raise_unphysical or st != WM_ERR_UNPHYSICAL):
             _check(st)
         return d.as_dict()
+
+    def debug_wide_addressing(self, on: bool = True) -> None:
+        """Testing switch: the sweep uses 64-bit addresses (its path for arrays of 4 GiB or more)."""
+        _check(self.lib.wm_debug_wide_addressing(self.handle, int(bool(on))))
 
     @_on_stream
     def debug_sweep(self, axis: int) -> torch.Tensor:

@@ -19,6 +19,7 @@ struct Grid {
   int nx, ny, nz;
   size_t N;   // nx * ny * nz
   int wall[3];  // 1: reflecting conducting walls at both ends of the axis
+  int wide;     // 1: the sweep takes 64-bit addresses also for arrays under 4 GiB (testing)
   __device__ __forceinline__ size_t at(int i, int j, int k) const {
     return ((size_t)k * ny + j) * nx + i;
   }
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid) / 64;   // uniform: held in a scalar register
   // every array of the state and the fluxes within 4 GiB: buffer accesses with 32-bit offsets
   const size_t abytes = g.N * sizeof(S);
-  const bool off32 = abytes < (size_t(1) << 32);
+  const bool off32 = !g.wide && abytes < (size_t(1) << 32);
 #ifdef WM_SWEEP_CLOCK
   // clock build: per-wave shader-clock stamps at the phase boundaries
   unsigned long long stamp[8];

@@ -564,6 +564,7 @@ void setup_patch(wm_patch* p, const wm_config* cfg, void* hip_stream, void* scra
   p->g.nx = cfg->nx; p->g.ny = cfg->ny; p->g.nz = cfg->nz;
   p->g.N = (size_t)cfg->nx * cfg->ny * cfg->nz;
   for (int d = 0; d < 3; ++d) p->g.wall[d] = cfg->walls[d];
+  p->g.wide = 0;
   p->floors = cfg->rho_floor > 0.0 || cfg->p_floor > 0.0;
   p->floor_reset = true;
   p->ph.gamma = cfg->gamma;
@@ -864,6 +865,12 @@ wm_status wm_diagnostics(wm_patch* p, wm_diag* out) {
   out->n_unphysical = (long long)h[11];
   out->n_floored = (p->floors && !p->floor_reset) ? (long long)h[12] : 0;
   if (out->n_unphysical > 0) return fail(WM_ERR_UNPHYSICAL, "unphysical zones in the state%s");
+  return WM_OK;
+}
+
+wm_status wm_debug_wide_addressing(wm_patch* p, int on) {
+  if (!p) return fail(WM_ERR_ARG, "null patch");
+  p->g.wide = on != 0;
   return WM_OK;
 }
 

@@ -198,6 +198,24 @@ def test_determinism():
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("precision,walls", [(B.WM_FP64, (0, 0, 0)), (B.WM_FP64, (1, 0, 1)),
+                                             (B.WM_MIXED_F32STATE, (0, 0, 0))])
+def test_wide_addressing_bitwise(precision, walls):
+    """The sweep's 64-bit addressing path, which it takes for arrays of 4 GiB or
+    more, gives bitwise the same steps as its 32-bit buffer-offset path."""
+    say(f"wide addressing, precision {precision}, walls {walls}")
+    f = fields(40, seed=9, v_rms=2.0)
+    outs = []
+    for wide in (False, True):
+        p = gpu_patch(f, precision=precision, walls=walls)
+        p.debug_wide_addressing(wide)
+        for _ in range(2):
+            p.step()
+        torch.cuda.synchronize()
+        outs.append((p.hydro.clone(), p.bface.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
 def test_invariants_128_mach2():
     """Conservation of totals and plane sums and div_h b at round-off, 128^3 x 5 steps."""
     say("invariants 128^3")
