@@ -241,7 +241,7 @@ __host__ __device__ __forceinline__ void phiN_val_grad(double a, double b, doubl
 // A pair has the left rows S + A (upper) and S - A (lower) with the
 // Lax-Friedrichs speeds alu, all; S is nonzero on the components in SM, A on
 // A0 .. A0+NA-1 (TWO = false: the single row S).  Split values as in
-// split_pair; f = phi(v7, v6, v5, v4) - phi(v0, v1, v2, v3) per row.  The
+// face_corr; f = phi(v7, v6, v5, v4) - phi(v0, v1, v2, v3) per row.  The
 // cotangents lfu, lfl of the two f only involve the right eigenvectors, so they
 // are known before the pass, which computes f (needed for the right-vector
 // cotangents) and the cotangents of S, A, the two speeds and the interface

@@ -287,32 +287,6 @@ __host__ __device__ __forceinline__ void face_eig(double rho, double vn, double 
   e.Gs = e.as * e.csl * vn + e.af * e.cf * e.s * bv;
 }
 
-// Split values of a pair of characteristic fields whose left rows are S + A
-// (upper, lambda = v - c) and S - A (lower), A nonzero in components 0..3,
-// for the five interface differences DL(j, k): j = 0..6 Delta F, 7..13 Delta q,
-// k = 0..4 interfaces i-3/2 .. i+5/2.  Lax-Friedrichs: Delta F^+- = (Delta F^s
-// +- alpha Delta q^s)/2, with the 1/2 already carried by the rows.
-template <typename T, class DL>
-__host__ __device__ __forceinline__ void split_pair(const T S[7], const T A[4], T alu, T all, DL dl, T vu[8],
-                                                    T vl[8]) {
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    T dF[7], dq[7];
-#pragma unroll
-    for (int j = 0; j < 7; ++j) { dF[j] = dl(j, k); dq[j] = dl(7 + j, k); }
-    T sF = S[0] * dF[0], sq = S[0] * dq[0];
-#pragma unroll
-    for (int j = 1; j < 7; ++j) { sF += S[j] * dF[j]; sq += S[j] * dq[j]; }
-    T aF = A[0] * dF[0], aq = A[0] * dq[0];
-#pragma unroll
-    for (int j = 1; j < 4; ++j) { aF += A[j] * dF[j]; aq += A[j] * dq[j]; }
-    const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
-    if (k <= 3) { vu[k] = uF + alu * uq; vl[k] = lF + all * lq; }
-    if (k >= 1) { vu[3 + k] = uF - alu * uq; vl[3 + k] = lF - all * lq; }
-    sched_fence();
-  }
-}
-
 // Characteristic part of the interface flux at face i+1/2,
 //   corr = sum_m R(:,m) (phi^-_m - phi^+_m),
 // so that F_{i+1/2} = F_c + corr with the central term F_c in physical space
@@ -347,7 +321,11 @@ __host__ __device__ __forceinline__ void face_corr(const FaceEig& e, AL al, DL d
     return omgT * in + (w0 * d[0] + gm1T * d[6]);
   };
   T WF[5], Wq[5];
-  // split values of interface k from the projections onto the rows S + A and S - A
+  // Split values of a pair whose left rows are S + A (upper, lambda = v - c) and
+  // S - A (lower), at interface k = 0..4 (i-3/2 .. i+5/2) from the projections
+  // sF = S.dF, sq = S.dq, aF = A.dF, aq = A.dq (dl(j, k): j = 0..6 Delta F,
+  // 7..13 Delta q).  Lax-Friedrichs: Delta F^+- = (Delta F^s +- alpha Delta q^s)/2,
+  // the 1/2 carried by the rows; vu[0..3] / vu[4..7] feed phi^+ / phi^-.
   auto split_k = [&](int k, T sF, T sq, T aF, T aq, T alu, T all) {
     const T uF = sF + aF, uq = sq + aq, lF = sF - aF, lq = sq - aq;
     if (k <= 3) { vu[k] = uF + alu * uq; vl[k] = lF + all * lq; }
