@@ -31,12 +31,20 @@ namespace wm {
 // rhs_by = -(Ex - Ex[k-1])/h + (Ez - Ez[i-1])/h, rhs_bz = -(Ey - Ey[i-1])/h +
 // (Ex - Ex[j-1])/h with Ez = (Tyx + Tyx[i+1])/2 - (Txy + Txy[j+1])/2,
 // Ex = (Tzy + Tzy[j+1])/2 - (Tyz + Tyz[k+1])/2, Ey = (Txz + Txz[k+1])/2 - (Tzx + Tzx[i+1])/2.
-__global__ __launch_bounds__(256) void adj_emf_kernel(Grid g, double inv_h, const double* lam_k, double* lam_T) {
+// It also clears zero3 ([3][N], the zone-B cotangent that the sweeps then add into).
+__global__ __launch_bounds__(256) void adj_emf_kernel(Grid g, double inv_h, const double* lam_k, double* lam_T,
+                                                      double* zero3) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   const size_t N = g.N;
+  {
+    const size_t c = g.at(i, j, k);
+    zero3[c] = 0.0;
+    zero3[N + c] = 0.0;
+    zero3[2 * N + c] = 0.0;
+  }
   const double* lbx = lam_k + 5 * N;
   const double* lby = lam_k + 6 * N;
   const double* lbz = lam_k + 7 * N;
@@ -425,46 +433,46 @@ __global__ __launch_bounds__(256) void widen_kernel(size_t n, const float* x, do
   if (c < n) y[c] = double(x[c]);
 }
 
-// The RK3 stage combinations of the adjoint step over the 8N cotangent
-// entries (hydro [5][N] then face b [3][N]; lam3 split over lh, lb):
-//   glue_a: w = lam3, lk = c lam3, z = 0
-//   glue_b: lk = a w + b x, z = 0
-//   glue_c: lk = a w + b x + c y, (lh, lb) = w + x + y
+// The stage combinations of the adjoint step over the 8N cotangent entries
+// (hydro [5][N] then face b [3][N]).  lam3, the incoming cotangent, is read in
+// place from (lh, lb), which keep it until the last combination overwrites them:
+//   glue_a: lk = c lam3, z = 0
+//   glue_b: lk = a lam3 + b x, z = 0
+//   glue_c: lk = a lam3 + b x + c y, (lh, lb) = lam3 + x + y
+//   glue_d: lk = a lam3 + b x, (lh, lb) = lam3 + x + y + z (the four-stage sum of RK4)
+__device__ __forceinline__ double lam3_at(size_t i, size_t N, const double* lh, const double* lb) {
+  return i < 5 * N ? lh[i] : lb[i - 5 * N];
+}
 __global__ __launch_bounds__(256) void adj_glue_a_kernel(size_t N, double c, const double* lh, const double* lb,
-                                                         double* w, double* lk, double* z) {
+                                                         double* lk, double* z) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= 8 * N) return;
-  const double l3 = i < 5 * N ? lh[i] : lb[i - 5 * N];
-  w[i] = l3;
-  lk[i] = c * l3;
+  lk[i] = c * lam3_at(i, N, lh, lb);
   z[i] = 0.0;
 }
-__global__ __launch_bounds__(256) void adj_glue_b_kernel(size_t n8, double a, const double* w, double b,
-                                                         const double* x, double* lk, double* z) {
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n8) return;
-  lk[i] = a * w[i] + b * x[i];
-  z[i] = 0.0;
-}
-__global__ __launch_bounds__(256) void adj_glue_c_kernel(size_t N, double a, const double* w, double b,
-                                                         const double* x, double c, const double* y, double* lk,
-                                                         double* lh, double* lb) {
+__global__ __launch_bounds__(256) void adj_glue_b_kernel(size_t N, double a, const double* lh, const double* lb,
+                                                         double b, const double* x, double* lk, double* z) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= 8 * N) return;
-  const double wi = w[i], xi = x[i], yi = y[i];
+  lk[i] = a * lam3_at(i, N, lh, lb) + b * x[i];
+  z[i] = 0.0;
+}
+__global__ __launch_bounds__(256) void adj_glue_c_kernel(size_t N, double a, double b, const double* x, double c,
+                                                         const double* y, double* lk, double* lh, double* lb) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= 8 * N) return;
+  const double wi = lam3_at(i, N, lh, lb), xi = x[i], yi = y[i];
   lk[i] = a * wi + b * xi + c * yi;
   const double s = wi + xi + yi;
   if (i < 5 * N) lh[i] = s;
   else lb[i - 5 * N] = s;
 }
-
-// lk = a w + b x and lam^n = w + x + y + z (the four-stage sum of the RK4 step)
-__global__ __launch_bounds__(256) void adj_glue_d_kernel(size_t N, double a, const double* w, double b,
-                                                         const double* x, const double* y, const double* z,
-                                                         double* lk, double* lh, double* lb) {
+__global__ __launch_bounds__(256) void adj_glue_d_kernel(size_t N, double a, double b, const double* x,
+                                                         const double* y, const double* z, double* lk, double* lh,
+                                                         double* lb) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= 8 * N) return;
-  const double wi = w[i], xi = x[i];
+  const double wi = lam3_at(i, N, lh, lb), xi = x[i];
   lk[i] = a * wi + b * xi;
   const double s = wi + xi + y[i] + z[i];
   if (i < 5 * N) lh[i] = s;

@@ -490,10 +490,9 @@ wm_status rhs_vjp_acc(wm_patch* p, double* A, const double* hydro, const double*
   double* lT = A + A_LT * N;
   double* lBz = A + A_LBZ * N;
   if ((s = launch_bcell<double>(p, bface, Bz)) != WM_OK) return s;
-  hipLaunchKernelGGL(adj_emf_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, lam_k, lT);
+  hipLaunchKernelGGL(adj_emf_kernel, zone_grid(p->g), dim3(256), 0, p->stream, p->g, 1.0 / p->cfg.h, lam_k, lT,
+                     lBz);
   WM_LAUNCH_CHECK("adjoint emf kernel");
-  hipLaunchKernelGGL(fill_kernel, lin_grid(3 * N), dim3(256), 0, p->stream, 3 * N, 0.0, lBz);
-  WM_LAUNCH_CHECK("fill kernel");
   if ((s = launch_adj_sweep<0>(p, hydro, Bz, lam_k, lT, acc_h, lBz)) != WM_OK) return s;
   if ((s = launch_adj_sweep<1>(p, hydro, Bz, lam_k, lT + 2 * N, acc_h, lBz)) != WM_OK) return s;
   if ((s = launch_adj_sweep<2>(p, hydro, Bz, lam_k, lT + 4 * N, acc_h, lBz)) != WM_OK) return s;
@@ -988,41 +987,39 @@ wm_status wm_adjoint_step(wm_patch* p, void* adj_scratch, const void* Un_hydro, 
   double* lk = A + A_LK * N;
   double* lU2 = A + A_LU2 * N;
   double* lU1 = A + A_LU1 * N;
-  double* w = A + A_WORK * N;
   const dim3 g8 = lin_grid(8 * N);
   if (rk4) {
     // U^{n+1} = U^n + dt/6 (k0 + 2 k1 + 2 k2 + k3), k_s = L(U_s), U1 = U^n + dt/2 k0,
-    // U2 = U^n + dt/2 k1, U3 = U^n + dt k2; lam3 = the incoming cotangent (w)
+    // U2 = U^n + dt/2 k1, U3 = U^n + dt k2; lam3 = the incoming cotangent, in (lh, lb)
     double* lU3 = A + A_LU3 * N;
     // k3 = L(U3): dt/6 lam3
-    hipLaunchKernelGGL(adj_glue_a_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, lh, lb, w, lk, lU3);
+    hipLaunchKernelGGL(adj_glue_a_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, lh, lb, lk, lU3);
     WM_LAUNCH_CHECK("adjoint glue kernel");
     if ((s = rhs_vjp_acc(p, A, U3, U3 + 5 * N, lk, lU3, lU3 + 5 * N)) != WM_OK) return s;
     // k2 = L(U2): dt/3 lam3 + dt lamU3
-    hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 3.0, w, dt, lU3, lk, lU2);
+    hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, N, dt / 3.0, lh, lb, dt, lU3, lk, lU2);
     WM_LAUNCH_CHECK("adjoint glue kernel");
     if ((s = rhs_vjp_acc(p, A, U2, U2 + 5 * N, lk, lU2, lU2 + 5 * N)) != WM_OK) return s;
     // k1 = L(U1): dt/3 lam3 + dt/2 lamU2
-    hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 3.0, w, 0.5 * dt, lU2, lk, lU1);
+    hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, N, dt / 3.0, lh, lb, 0.5 * dt, lU2, lk, lU1);
     WM_LAUNCH_CHECK("adjoint glue kernel");
     if ((s = rhs_vjp_acc(p, A, U1, U1 + 5 * N, lk, lU1, lU1 + 5 * N)) != WM_OK) return s;
     // k0 = L(U^n): dt/6 lam3 + dt/2 lamU1; lam^n = lam3 + lamU1 + lamU2 + lamU3 + (dL/dU^n)^T lam_k0
-    hipLaunchKernelGGL(adj_glue_d_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, w, 0.5 * dt, lU1, lU2, lU3, lk,
-                       lh, lb);
+    hipLaunchKernelGGL(adj_glue_d_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, 0.5 * dt, lU1, lU2, lU3, lk, lh,
+                       lb);
     WM_LAUNCH_CHECK("adjoint glue kernel");
     return rhs_vjp_acc(p, A, Uh, Ub, lk, lh, lb);
   }
   // SSP-RK3: k2 = L(U2), weight 4 dt/6
-  hipLaunchKernelGGL(adj_glue_a_kernel, g8, dim3(256), 0, p->stream, N, 4.0 * dt / 6.0, lh, lb, w, lk, lU2);
+  hipLaunchKernelGGL(adj_glue_a_kernel, g8, dim3(256), 0, p->stream, N, 4.0 * dt / 6.0, lh, lb, lk, lU2);
   WM_LAUNCH_CHECK("adjoint glue kernel");
   if ((s = rhs_vjp_acc(p, A, U2, U2 + 5 * N, lk, lU2, lU2 + 5 * N)) != WM_OK) return s;
   // k1 = L(U1): dt/6 lam3 + dt/4 lamU2
-  hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, 8 * N, dt / 6.0, w, 0.25 * dt, lU2, lk, lU1);
+  hipLaunchKernelGGL(adj_glue_b_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, lh, lb, 0.25 * dt, lU2, lk, lU1);
   WM_LAUNCH_CHECK("adjoint glue kernel");
   if ((s = rhs_vjp_acc(p, A, U1, U1 + 5 * N, lk, lU1, lU1 + 5 * N)) != WM_OK) return s;
   // k0 = L(U^n): dt/6 lam3 + dt/4 lamU2 + dt lamU1; lam^n = lam3 + lamU2 + lamU1 + (dL/dU^n)^T lam_k0
-  hipLaunchKernelGGL(adj_glue_c_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, w, 0.25 * dt, lU2, dt, lU1, lk,
-                     lh, lb);
+  hipLaunchKernelGGL(adj_glue_c_kernel, g8, dim3(256), 0, p->stream, N, dt / 6.0, 0.25 * dt, lU2, dt, lU1, lk, lh, lb);
   WM_LAUNCH_CHECK("adjoint glue kernel");
   return rhs_vjp_acc(p, A, Uh, Ub, lk, lh, lb);
 }
