@@ -421,6 +421,24 @@ struct UpdateArgs {
   const S* wallF[3];     // per walled axis: [5][nB * nC] fluxes through the lower wall face
 };
 
+// The update's outputs (stage state, accumulator) as nontemporal stores: they
+// stream past the caches, which keeps the face fluxes the update re-reads at
+// tile edges cached (update -3.4% at 256^3 FP64, the sweeps unchanged).
+template <typename S>
+__device__ __forceinline__ void nt_store(S* p, S x) {
+  __builtin_nontemporal_store(x, p);
+}
+template <typename S> struct NtV2;
+template <> struct NtV2<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct NtV2<double> { typedef double T __attribute__((ext_vector_type(2))); };
+template <typename S>
+__device__ __forceinline__ void nt_store2(S* p, S x, S y) {
+  typename NtV2<S>::T v;
+  v.x = x;
+  v.y = y;
+  __builtin_nontemporal_store(v, reinterpret_cast<typename NtV2<S>::T*>(p));
+}
+
 // corner fluxes (eq. ox1-ox3), each from four transport fluxes:
 //   Ez(i+1/2, j+1/2, k) = (Tyx(i) + Tyx(i+1))/2 - (Txy(j) + Txy(j+1))/2   [Omega_x]
 //   Ex(i, j+1/2, k+1/2) = (Tzy(j) + Tzy(j+1))/2 - (Tyz(k) + Tyz(k+1))/2   [Omega_y]
@@ -518,11 +536,11 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
     double out;
     if constexpr (RK == 3) {
       if constexpr (STAGE == 0) {
-        a.acc[v * N + c0] = S(kv[v]);
+        nt_store(a.acc + v * N + c0, S(kv[v]));
         out = un + dt * kv[v];
       } else if constexpr (STAGE == 1) {
         const double s = double(a.acc[v * N + c0]) + kv[v];
-        a.acc[v * N + c0] = S(s);
+        nt_store(a.acc + v * N + c0, S(s));
         out = un + (0.25 * dt) * s;
       } else {
         const double s = double(a.acc[v * N + c0]) + 4.0 * kv[v];
@@ -530,18 +548,18 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
       }
     } else {
       if constexpr (STAGE == 0) {
-        a.acc[v * N + c0] = S(kv[v]);
+        nt_store(a.acc + v * N + c0, S(kv[v]));
         out = un + (0.5 * dt) * kv[v];
       } else if constexpr (STAGE < 3) {
-        a.acc[v * N + c0] = S(double(a.acc[v * N + c0]) + 2.0 * kv[v]);
+        nt_store(a.acc + v * N + c0, S(double(a.acc[v * N + c0]) + 2.0 * kv[v]));
         out = un + (STAGE == 1 ? 0.5 * dt : dt) * kv[v];
       } else {
         const double s = double(a.acc[v * N + c0]) + kv[v];
         out = un + (dt / 6.0) * s;
       }
     }
-    if (v < 5) a.hyd_out[v * N + c0] = S(out);
-    else a.b_out[(v - 5) * N + c0] = S(out);
+    if (v < 5) nt_store(a.hyd_out + v * N + c0, S(out));
+    else nt_store(a.b_out + (v - 5) * N + c0, S(out));
   }
 }
 
@@ -728,16 +746,10 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<S> a) {
     }
     constexpr bool writes_acc = RK == 3 ? STAGE < 2 : STAGE < 3;
     if constexpr (writes_acc) {
-      V2 t;
-      t.x = S(acc_new[0]);
-      t.y = S(acc_new[1]);
-      *accp = t;
+      nt_store2(a.acc + v * N + c0, S(acc_new[0]), S(acc_new[1]));
     }
     S* outp = v < 5 ? a.hyd_out + v * N : a.b_out + (v - 5) * N;
-    V2 o;
-    o.x = S(out[0]);
-    o.y = S(out[1]);
-    *reinterpret_cast<V2*>(outp + c0) = o;
+    nt_store2(outp + c0, S(out[0]), S(out[1]));
   }
 }
 
