@@ -421,12 +421,18 @@ struct UpdateArgs {
   const S* wallF[3];     // per walled axis: [5][nB * nC] fluxes through the lower wall face
 };
 
-// The update's outputs (stage state, accumulator) as nontemporal stores: they
-// stream past the caches, which keeps the face fluxes the update re-reads at
-// tile edges cached (update -3.4% at 256^3 FP64, the sweeps unchanged).
+// The update's streams that are used once (U^n and the accumulator read, the
+// stage state and the accumulator written) as nontemporal accesses: they pass
+// the caches by, which keeps the face fluxes the update re-reads at tile edges
+// cached (update -3.2% for the stores and -4.4% more for the loads at 256^3
+// FP64, the sweeps unchanged).
 template <typename S>
 __device__ __forceinline__ void nt_store(S* p, S x) {
   __builtin_nontemporal_store(x, p);
+}
+template <typename S>
+__device__ __forceinline__ S nt_load(const S* p) {
+  return __builtin_nontemporal_load(p);
 }
 template <typename S> struct NtV2;
 template <> struct NtV2<float> { typedef float T __attribute__((ext_vector_type(2))); };
@@ -532,18 +538,18 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
   const double dt = *a.dt;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
-    const double un = v < 5 ? double(a.Un[v * N + c0]) : double(a.bn[(v - 5) * N + c0]);
+    const double un = double(nt_load(v < 5 ? a.Un + v * N + c0 : a.bn + (v - 5) * N + c0));
     double out;
     if constexpr (RK == 3) {
       if constexpr (STAGE == 0) {
         nt_store(a.acc + v * N + c0, S(kv[v]));
         out = un + dt * kv[v];
       } else if constexpr (STAGE == 1) {
-        const double s = double(a.acc[v * N + c0]) + kv[v];
+        const double s = double(nt_load(a.acc + v * N + c0)) + kv[v];
         nt_store(a.acc + v * N + c0, S(s));
         out = un + (0.25 * dt) * s;
       } else {
-        const double s = double(a.acc[v * N + c0]) + 4.0 * kv[v];
+        const double s = double(nt_load(a.acc + v * N + c0)) + 4.0 * kv[v];
         out = un + (dt / 6.0) * s;
       }
     } else {
@@ -551,10 +557,10 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<S> a) {
         nt_store(a.acc + v * N + c0, S(kv[v]));
         out = un + (0.5 * dt) * kv[v];
       } else if constexpr (STAGE < 3) {
-        nt_store(a.acc + v * N + c0, S(double(a.acc[v * N + c0]) + 2.0 * kv[v]));
+        nt_store(a.acc + v * N + c0, S(double(nt_load(a.acc + v * N + c0)) + 2.0 * kv[v]));
         out = un + (STAGE == 1 ? 0.5 * dt : dt) * kv[v];
       } else {
-        const double s = double(a.acc[v * N + c0]) + kv[v];
+        const double s = double(nt_load(a.acc + v * N + c0)) + kv[v];
         out = un + (dt / 6.0) * s;
       }
     }
@@ -707,13 +713,14 @@ __global__ __launch_bounds__(256) void update_pair_kernel(UpdateArgs<S> a) {
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const S* unp = v < 5 ? a.Un + v * N : a.bn + (v - 5) * N;
-    const V2 u = *reinterpret_cast<const V2*>(unp + c0);
+    using NV = typename NtV2<S>::T;
+    const NV u = __builtin_nontemporal_load(reinterpret_cast<const NV*>(unp + c0));
     const double un[2] = {double(u.x), double(u.y)};
     V2* accp = reinterpret_cast<V2*>(a.acc + v * N + c0);
     double out[2], acc_new[2];
     double acc_old[2] = {0.0, 0.0};
     if constexpr (STAGE > 0) {
-      const V2 t = *accp;
+      const NV t = __builtin_nontemporal_load(reinterpret_cast<const NV*>(accp));
       acc_old[0] = double(t.x);
       acc_old[1] = double(t.y);
     }
