@@ -174,7 +174,9 @@ wm_status wm_refresh_zone_field(wm_patch* p);
 
 /* Time step of eq. (cfl) at equality: dt = cfl h / sum_d max(|v_d| + c_fast^d),
  * from the bound state.  The result stays in device memory for the stages; if
- * dt_host is non-NULL the stream is synchronised and dt copied there. */
+ * dt_host is non-NULL the stream is synchronised and dt copied there.  A NaN
+ * in the state, or a fast speed that is not real (negative pressure), gives a
+ * NaN dt. */
 wm_status wm_compute_dt(wm_patch* p, double* dt_host);
 
 /* One Runge-Kutta stage in increment form, k_s the right-hand side at the
@@ -190,8 +192,12 @@ wm_status wm_compute_dt(wm_patch* p, double* dt_host);
  * wm_compute_dt. */
 wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host);
 
-/* wm_compute_dt followed by the stages of the configured integrator (three
- * for WM_SSPRK3, four for WM_RK4).  If dt_used is non-NULL the
+/* The dt of wm_compute_dt followed by the stages of the configured integrator
+ * (three for WM_SSPRK3, four for WM_RK4).  The maxima of eq. (cfl) are taken
+ * from the zones the first stage's sweeps already evaluate, so the step reads
+ * the state once less; dt, and so the step, are bitwise those of
+ * wm_compute_dt followed by wm_rk_stage.  The first stage's accumulator
+ * scratch holds the partial maxima meanwhile.  If dt_used is non-NULL the
  * stream is synchronised and the dt of the step is returned there. */
 wm_status wm_step(wm_patch* p, double* dt_used);
 

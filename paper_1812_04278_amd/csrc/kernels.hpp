@@ -11,6 +11,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mhd_device.hpp"
 
 namespace wm {
@@ -97,6 +99,55 @@ enum { FP_VN = 0, FP_VT1, FP_VT2, FP_BN, FP_P, FP_CF, FP_CA, FP_CS };
 
 // S: storage type of the state and of the face values (double, or float for
 // the FP32-state form); arithmetic is in double / TW as described below.
+__device__ __forceinline__ double nanmax(double a, double b) {   // NaN-propagating max (either argument)
+  if (a != a) return a;
+  if (b != b) return b;
+  return b > a ? b : a;
+}
+
+// Signal speed |v_n| + c_fast of eq. (cfl) from a zone prologue along n, as
+// the bit pattern of the double: the sweep of the first stage of a step and the
+// stand-alone time-step pass both take it from zone_prologue, so their maxima
+// agree bitwise.  Non-negative doubles order like their bit patterns read as
+// unsigned integers, so the maximum is an integer max.  A fast speed that is
+// not real (a negative argument of its square roots, which sqrt_nr returns as
+// a negative value) makes the speed negative, and a NaN state makes it NaN:
+// both keys lie above every non-negative speed's, and dt_final_kernel turns
+// such a maximum into NaN.
+typedef unsigned long long SpeedKey;
+__device__ __forceinline__ SpeedKey cfl_key(const double* z) {
+  return __builtin_bit_cast(SpeedKey, fabs(z[Z_VN]) + z[Z_CF]);
+}
+__device__ __forceinline__ SpeedKey kmax(SpeedKey a, SpeedKey b) { return b > a ? b : a; }
+
+// Maximum of a 32-bit unsigned value over the 64 lanes of a wave, returned to
+// every lane: maxima over the preceding 1, 2, 4, 8 lanes of each row of 16
+// (DPP row shifts), then row 0's into row 1 and row 2's into row 3 (row
+// broadcast of lane 15), then rows 0-1 into rows 2-3 (broadcast of lane 31):
+// lane 63 ends with the maximum.  Lanes without a source keep 0, the identity.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  auto step = [](unsigned x, auto ctrl, auto rows) {
+    const unsigned y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, decltype(ctrl)::value,
+                                                             decltype(rows)::value, 0xf, false);
+    return y > x ? y : x;
+  };
+  v = step(v, std::integral_constant<int, 0x111>{}, std::integral_constant<int, 0xf>{});   // row_shr:1
+  v = step(v, std::integral_constant<int, 0x112>{}, std::integral_constant<int, 0xf>{});   // row_shr:2
+  v = step(v, std::integral_constant<int, 0x114>{}, std::integral_constant<int, 0xf>{});   // row_shr:4
+  v = step(v, std::integral_constant<int, 0x118>{}, std::integral_constant<int, 0xf>{});   // row_shr:8
+  v = step(v, std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xa>{});   // row_bcast:15
+  v = step(v, std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xc>{});   // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+// the same for a 64-bit key, exactly: the high words' maximum, then the
+// maximum of the low words of the lanes that hold it
+__device__ __forceinline__ SpeedKey wave_max_key(SpeedKey k) {
+  const unsigned hi = (unsigned)(k >> 32), lo = (unsigned)k;
+  const unsigned hm = wave_max_u32(hi);
+  const unsigned lm = wave_max_u32(hi == hm ? lo : 0u);
+  return ((SpeedKey)hm << 32) | lm;
+}
+
 template <typename S>
 struct SweepArgs {
   Grid g;
@@ -107,6 +158,7 @@ struct SweepArgs {
   S* T;                  // [2][N] transport fluxes T^n_t1, T^n_t2
   double* dbg;           // optional [9][N]: 7 sweep-frame flux components + 2 T
   S* wallF;              // walled sweep axis: [5][nB * nC] fluxes through the lower wall face
+  SpeedKey* smax_blk;    // optional: per wave (4 per block), the maximum of |v_n| + c_fast over its zones (cfl_key)
 #ifdef WM_SWEEP_CLOCK
   unsigned long long* clk;   // clock build: [block][wave][8] phase stamps, or null
 #endif
@@ -154,9 +206,11 @@ template <int AXIS, typename TW> constexpr size_t sweep_p_doubles() {
 // (mixed): projections, split, weights, zone primitives, LF speeds and the
 // transport-flux mean in FP32; the zone prologue (pressure recovery), the
 // differences, the central flux and the face eigen-system (renormalisation of
-// alpha_f, alpha_s, beta) in FP64.
+// alpha_f, alpha_s, beta) in FP64.  DTMAX: each wave also writes the maximum
+// of the eq. (cfl) signal speed over its zones to a.smax_blk (the first stage
+// of a step), a separate instantiation so that the other sweeps carry none of it.
 
-template <int AXIS, bool WENO_Z, typename TW, typename S>
+template <int AXIS, bool WENO_Z, typename TW, typename S, bool DTMAX = false>
 __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
   constexpr int TA = SweepTile<AXIS, TW>::TA, TB = SweepTile<AXIS, TW>::TB;
   constexpr int NA = TA + SW_HL + SW_HR;     // zones along the axis
@@ -229,6 +283,7 @@ __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
     raw[r][1 + CN] *= flip;
     raw[r][5 + CN] *= flip;
   }
+  SpeedKey key = 0;   // the lane's maximum over its zones (cfl_key)
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int cell = tid + r * SW_THREADS;
@@ -237,6 +292,7 @@ __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
     const double* B = raw[r] + 5;
     double z[Z_NVAR];
     zone_prologue(raw[r][0], m[CN], m[CT1], m[CT2], raw[r][4], B[CN], B[CT1], B[CT2], a.ph.gamma, z);
+    if constexpr (DTMAX) key = kmax(key, cfl_key(z));
 #pragma unroll
     for (int v = 0; v < SW_NQ; ++v) Q[v * NC + cell] = z[v];
     Pz[FP_VN * NC + cell] = TW(z[Z_VN]);
@@ -247,6 +303,12 @@ __global__ __launch_bounds__(SW_THREADS, 3) void sweep_kernel(SweepArgs<S> a) {
     Pz[FP_CF * NC + cell] = TW(z[Z_CF]);
     Pz[FP_CA * NC + cell] = TW(z[Z_CA]);
     Pz[FP_CS * NC + cell] = TW(z[Z_CS]);
+  }
+  if constexpr (DTMAX) {   // the wave's maximum, one value per wave
+    static_assert(SW_THREADS == 256, "four waves per block");
+    const SpeedKey wk = wave_max_key(key);
+    if (__lane_id() == 0)
+      a.smax_blk[((blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4 + wave] = wk;
   }
 #ifdef WM_SWEEP_CLOCK
   stamp[1] = clock64();
@@ -841,35 +903,25 @@ __global__ __launch_bounds__(256) void init_hydro_kernel(size_t N, double gamma,
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
 
-__device__ __forceinline__ double nanmax(double a, double b) {   // NaN-propagating max (either argument)
-  if (a != a) return a;
-  if (b != b) return b;
-  return b > a ? b : a;
-}
-
-// max over zones of |v_d| + c_fast^d, d = x, y, z -> part[3 * block + d]
+// max over zones of |v_d| + c_fast^d, d = x, y, z -> part[3 * block + d] (cfl_key);
+// the signal speed along d is the one the sweep along d forms (zone_prologue in
+// its frame n = d, t1 = d + 1, t2 = d + 2), so a step that takes the maxima from
+// its first stage's sweeps finds bitwise the same dt
 template <typename S>
 __global__ __launch_bounds__(RED_THREADS) void speed_partial_kernel(size_t N, double gamma, const S* hydro,
-                                                                    const S* bcell, double* part) {
-  __shared__ double red[3][RED_THREADS];
-  double mx[3] = {0.0, 0.0, 0.0};
+                                                                    const S* bcell, SpeedKey* part) {
+  __shared__ SpeedKey red[3][RED_THREADS];
+  SpeedKey mx[3] = {0, 0, 0};
   for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N; c += (size_t)gridDim.x * RED_THREADS) {
-    const double rho = hydro[c];
-    const double irho = 1.0 / rho;
-    const double mm[3] = {hydro[N + c], hydro[2 * N + c], hydro[3 * N + c]};
-    const double v[3] = {mm[0] * irho, mm[1] * irho, mm[2] * irho};
-    const double B[3] = {bcell[c], bcell[N + c], bcell[2 * N + c]};
-    const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-    const double E = hydro[4 * N + c];
-    const double P = (gamma - 1.0) * (E - 0.5 * ((mm[0] * v[0] + mm[1] * v[1] + mm[2] * v[2]) + B2));
-    const double a2 = gamma * P * irho, b2 = B2 * irho;
+    const double rho = double(hydro[c]), E = double(hydro[4 * N + c]);
+    const double m[3] = {double(hydro[N + c]), double(hydro[2 * N + c]), double(hydro[3 * N + c])};
+    const double B[3] = {double(bcell[c]), double(bcell[N + c]), double(bcell[2 * N + c])};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double bperp2 = (B2 - B[d] * B[d]) * irho;
-      const double dab = a2 - b2;
-      const double D = sqrt(dab * dab + 4.0 * a2 * bperp2);
-      const double cf = sqrt(0.5 * (a2 + b2 + D));
-      mx[d] = nanmax(mx[d], fabs(v[d]) + cf);
+      const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+      double z[Z_NVAR];
+      zone_prologue(rho, m[d], m[t1], m[t2], E, B[d], B[t1], B[t2], gamma, z);
+      mx[d] = kmax(mx[d], cfl_key(z));
     }
   }
 #pragma unroll
@@ -878,7 +930,7 @@ __global__ __launch_bounds__(RED_THREADS) void speed_partial_kernel(size_t N, do
   for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = nanmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
+      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = kmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
     }
     __syncthreads();
   }
@@ -888,14 +940,43 @@ __global__ __launch_bounds__(RED_THREADS) void speed_partial_kernel(size_t N, do
   }
 }
 
-// dt = cfl h / sum_d max_d (eq. cfl); also keeps the three maxima
-__global__ __launch_bounds__(RED_THREADS) void dt_final_kernel(int nblocks, double cfl_h, const double* part,
+// The maxima of the first stage's sweeps: part holds n[0] + n[1] + n[2] block
+// keys (the x, y, z sweeps in turn) -> out[3 * block + d], for dt_final_kernel
+__global__ __launch_bounds__(RED_THREADS) void speed_blocks_kernel(const SpeedKey* part, unsigned n0, unsigned n1,
+                                                                   unsigned n2, SpeedKey* out) {
+  __shared__ SpeedKey red[3][RED_THREADS];
+  const unsigned n[3] = {n0, n1, n2};
+  const SpeedKey* base[3] = {part, part + n0, part + (size_t)n0 + n1};
+  SpeedKey mx[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    for (unsigned b = blockIdx.x * RED_THREADS + threadIdx.x; b < n[d]; b += gridDim.x * RED_THREADS)
+      mx[d] = kmax(mx[d], base[d][b]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = mx[d];
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = kmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[3 * blockIdx.x + d] = red[d][0];
+  }
+}
+
+// dt = cfl h / sum_d max_d (eq. cfl); also keeps the three maxima.  A maximum
+// whose key has the sign bit set (a negative speed) or is NaN gives NaN.
+__global__ __launch_bounds__(RED_THREADS) void dt_final_kernel(int nblocks, double cfl_h, const SpeedKey* part,
                                                                double* dt, double* smax) {
-  __shared__ double red[3][RED_THREADS];
-  double mx[3] = {0.0, 0.0, 0.0};
+  __shared__ SpeedKey red[3][RED_THREADS];
+  SpeedKey mx[3] = {0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) mx[d] = nanmax(mx[d], part[3 * b + d]);
+    for (int d = 0; d < 3; ++d) mx[d] = kmax(mx[d], part[3 * b + d]);
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = mx[d];
@@ -903,14 +984,20 @@ __global__ __launch_bounds__(RED_THREADS) void dt_final_kernel(int nblocks, doub
   for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = nanmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
+      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = kmax(red[d][threadIdx.x], red[d][threadIdx.x + s]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double s = (red[0][0] + red[1][0]) + red[2][0];
+    double m[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const SpeedKey k = red[d][0];
+      m[d] = (k >> 63) ? __builtin_nan("") : __builtin_bit_cast(double, k);
+    }
+    const double s = (m[0] + m[1]) + m[2];
     *dt = cfl_h / s;
-    smax[0] = red[0][0]; smax[1] = red[1][0]; smax[2] = red[2][0];
+    smax[0] = m[0]; smax[1] = m[1]; smax[2] = m[2];
   }
 }
 

@@ -122,32 +122,37 @@ struct ZoneVals {
 __host__ __device__ __forceinline__ void zone_prologue(double rho, double mn, double mt1, double mt2, double E,
                                               double Bn, double Bt1, double Bt2, double gamma,
                                               double* out) {
+  // Every rounding step is written out (no implicit FMA contraction, whose
+  // choice of product can differ between the kernels this is inlined into):
+  // the sweep and the stand-alone time-step pass get bitwise the same speeds.
+#pragma clang fp contract(off)
   const double irho = rcp_w(rho);
   const double vn = mn * irho, vt1 = mt1 * irho, vt2 = mt2 * irho;
-  const double Bperp2 = Bt1 * Bt1 + Bt2 * Bt2;
-  const double B2 = Bn * Bn + Bperp2;
-  const double P = (gamma - 1.0) * (E - 0.5 * ((mn * vn + mt1 * vt1 + mt2 * vt2) + B2));
-  const double Pstar = P + 0.5 * B2;
-  const double vB = vn * Bn + vt1 * Bt1 + vt2 * Bt2;
+  const double Bperp2 = fma(Bt2, Bt2, Bt1 * Bt1);
+  const double B2 = fma(Bn, Bn, Bperp2);
+  const double mv = fma(mt2, vt2, fma(mt1, vt1, mn * vn));
+  const double P = (gamma - 1.0) * fma(-0.5, mv + B2, E);
+  const double Pstar = fma(0.5, B2, P);
+  const double vB = fma(vt2, Bt2, fma(vt1, Bt1, vn * Bn));
+  const double rvn = rho * vn;
   out[Z_RHO] = rho; out[Z_MN] = mn; out[Z_MT1] = mt1; out[Z_MT2] = mt2;
   out[Z_BT1] = Bt1; out[Z_BT2] = Bt2; out[Z_E] = E;
-  out[Z_F0] = rho * vn;
-  out[Z_F1] = rho * vn * vn + Pstar - Bn * Bn;
-  out[Z_F2] = rho * vn * vt1 - Bn * Bt1;
-  out[Z_F3] = rho * vn * vt2 - Bn * Bt2;
-  out[Z_F4] = Bt1 * vn - Bn * vt1;
-  out[Z_F5] = Bt2 * vn - Bn * vt2;
-  out[Z_F6] = (E + Pstar) * vn - Bn * vB;
+  out[Z_F0] = rvn;
+  out[Z_F1] = fma(-Bn, Bn, fma(rvn, vn, Pstar));
+  out[Z_F2] = fma(-Bn, Bt1, rvn * vt1);
+  out[Z_F3] = fma(-Bn, Bt2, rvn * vt2);
+  out[Z_F4] = fma(Bt1, vn, -(Bn * vt1));
+  out[Z_F5] = fma(Bt2, vn, -(Bn * vt2));
+  out[Z_F6] = fma(E + Pstar, vn, -(Bn * vB));
   out[Z_VN] = vn; out[Z_VT1] = vt1; out[Z_VT2] = vt2; out[Z_BN] = Bn; out[Z_P] = P;
   // c_f,s^2 = (a^2 + b^2 +- D)/2, D = sqrt((a^2 - b^2)^2 + 4 a^2 b_perp^2),
   // c_slow^2 = a^2 b_n^2 / c_fast^2 (no cancellation), c_A = |B_n|/sqrt(rho)
-  const double a2 = gamma * P * irho;
-  const double b2 = B2 * irho;
-  const double bn2 = Bn * Bn * irho;
-  const double dab = a2 - b2;
-  const double D = sqrt_nr(dab * dab + 4.0 * a2 * (Bperp2 * irho));
-  const double cf2 = 0.5 * (a2 + b2 + D);
-  const double cs2 = cf2 > 0.0 ? a2 * bn2 * rcp_w(cf2) : 0.0;
+  const double a2 = (gamma * P) * irho;
+  const double bn2 = (Bn * Bn) * irho;
+  const double dab = fma(-B2, irho, a2), apb = fma(B2, irho, a2);   // a^2 -+ b^2
+  const double D = sqrt_nr(fma(dab, dab, (4.0 * a2) * (Bperp2 * irho)));
+  const double cf2 = 0.5 * (apb + D);
+  const double cs2 = cf2 > 0.0 ? (a2 * bn2) * rcp_w(cf2) : 0.0;
   out[Z_CF] = sqrt_nr(cf2);
   out[Z_CA] = sqrt_nr(bn2);
   out[Z_CS] = sqrt_nr(cs2);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/wenomhd.h"
@@ -254,7 +255,7 @@ struct wm_patch {
     const size_t yz = (size_t)g.ny * g.nz, xz = (size_t)g.nx * g.nz;
     return axis == 0 ? w : (axis == 1 ? w + 5 * yz : w + 5 * (yz + xz));
   }
-  double* speed_part() const { return red() + 4; }
+  SpeedKey* speed_part() const { return reinterpret_cast<SpeedKey*>(red() + 4); }   // cfl_key maxima
   double* diag_part() const { return red() + 4 + 3 * RED_BLOCKS; }
 };
 
@@ -291,8 +292,28 @@ wm_status with_storage(const wm_patch* p, Fn&& fn) {
   return p->f32 ? fn(float{}) : fn(double{});
 }
 
+// Launch grid of the sweep along AXIS: the tile depends on the work type
+// (FP32 for the FP32 state and the mixed form); with walls the sweep also
+// computes the lower wall face (-1/2)
+template <int AXIS>
+dim3 sweep_grid(const wm_patch* p) {
+  const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
+  const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
+  const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
+  auto grid_for = [&](auto tw) {
+    using TW = decltype(tw);
+    constexpr int TA = SweepTile<AXIS, TW>::TA, TB = SweepTile<AXIS, TW>::TB;
+    return dim3((nA + p->g.wall[AXIS] + TA - 1) / TA, (nB + TB - 1) / TB, nC);
+  };
+  const bool f32_work = p->f32 || p->cfg.precision == WM_MIXED;
+  return f32_work ? grid_for(float{}) : grid_for(double{});
+}
+
+size_t sweep_blocks(const dim3& g) { return (size_t)g.x * g.y * g.z; }
+
 template <int AXIS, typename S>
-wm_status launch_sweep(wm_patch* p, const S* hydro, const S* bcell, S* fh, S* T, double* dbg) {
+wm_status launch_sweep(wm_patch* p, const S* hydro, const S* bcell, S* fh, S* T, double* dbg,
+                       SpeedKey* smax_blk = nullptr) {
   SweepArgs<S> a;
   a.g = p->g;
   a.ph = p->ph;
@@ -302,54 +323,52 @@ wm_status launch_sweep(wm_patch* p, const S* hydro, const S* bcell, S* fh, S* T,
   a.T = T;
   a.dbg = dbg;
   a.wallF = p->g.wall[AXIS] ? p->wallF<S>(AXIS) : nullptr;
+  a.smax_blk = smax_blk;
 #ifdef WM_SWEEP_CLOCK
   a.clk = nullptr;
 #endif
-  const int nA = AXIS == 0 ? p->g.nx : (AXIS == 1 ? p->g.ny : p->g.nz);
-  const int nB = AXIS == 0 ? p->g.ny : p->g.nx;
-  const int nC = AXIS == 2 ? p->g.ny : p->g.nz;
-  // the tile depends on the work type (FP32 for the FP32 state and the mixed
-  // form); with walls the sweep also computes the lower wall face (-1/2)
-  auto grid_for = [&](auto tw) {
-    using TW = decltype(tw);
-    constexpr int TA = SweepTile<AXIS, TW>::TA, TB = SweepTile<AXIS, TW>::TB;
-    return dim3((nA + p->g.wall[AXIS] + TA - 1) / TA, (nB + TB - 1) / TB, nC);
-  };
-  const bool f32_work = sizeof(S) == 4 || p->cfg.precision == WM_MIXED;
-  const dim3 grid = f32_work ? grid_for(float{}) : grid_for(double{});
+  const dim3 grid = sweep_grid<AXIS>(p);
 #ifdef WM_SWEEP_CLOCK
   if ((size_t)grid.x * grid.y * grid.z * (SW_THREADS / 64) * 8 <= g_sweep_clk_n[AXIS]) a.clk = g_sweep_clk[AXIS];
 #endif
   const long r = prof_begin(p, K_SWEEP);
+  // kernel choice: work type (FP32 for the FP32 state and the mixed form),
+  // weights, and whether the block writes its signal-speed maximum
+  auto go = [&](auto tw, auto wz, auto dtmax) {
+    hipLaunchKernelGGL((sweep_kernel<AXIS, decltype(wz)::value, decltype(tw), S, decltype(dtmax)::value>), grid,
+                       dim3(SW_THREADS), 0, p->stream, a);
+  };
+  auto pick_dt = [&](auto tw, auto wz) {
+    if (smax_blk) go(tw, wz, std::true_type{});
+    else go(tw, wz, std::false_type{});
+  };
+  auto pick_wz = [&](auto tw) {
+    if (p->ph.weno_z) pick_dt(tw, std::true_type{});
+    else pick_dt(tw, std::false_type{});
+  };
   if constexpr (sizeof(S) == 4) {   // FP32 state: the mixed arithmetic
-    if (p->ph.weno_z)
-      hipLaunchKernelGGL((sweep_kernel<AXIS, true, float, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
-    else
-      hipLaunchKernelGGL((sweep_kernel<AXIS, false, float, float>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    pick_wz(float{});
   } else {
-    const bool mixed = p->cfg.precision == WM_MIXED;
-    if (p->ph.weno_z && mixed)
-      hipLaunchKernelGGL((sweep_kernel<AXIS, true, float, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
-    else if (p->ph.weno_z)
-      hipLaunchKernelGGL((sweep_kernel<AXIS, true, double, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
-    else if (mixed)
-      hipLaunchKernelGGL((sweep_kernel<AXIS, false, float, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
-    else
-      hipLaunchKernelGGL((sweep_kernel<AXIS, false, double, double>), grid, dim3(SW_THREADS), 0, p->stream, a);
+    if (p->cfg.precision == WM_MIXED) pick_wz(float{});
+    else pick_wz(double{});
   }
   WM_LAUNCH_CHECK("sweep kernel");
   prof_end(p, r);
   return WM_OK;
 }
 
+// smax: optional, the per-wave signal-speed maxima of the three sweeps in turn
+// (4 per block of each axis' grid), for the fused time step
 template <typename S>
-wm_status sweeps(wm_patch* p, const S* hydro, const S* bcell) {
+wm_status sweeps(wm_patch* p, const S* hydro, const S* bcell, SpeedKey* smax = nullptr) {
   const size_t N = p->g.N;
   S* f = p->faces<S>();
+  SpeedKey* s1 = smax ? smax + 4 * sweep_blocks(sweep_grid<0>(p)) : nullptr;
+  SpeedKey* s2 = smax ? s1 + 4 * sweep_blocks(sweep_grid<1>(p)) : nullptr;
   wm_status s;
-  if ((s = launch_sweep<0, S>(p, hydro, bcell, f, f + 15 * N, nullptr)) != WM_OK) return s;
-  if ((s = launch_sweep<1, S>(p, hydro, bcell, f + 5 * N, f + 17 * N, nullptr)) != WM_OK) return s;
-  if ((s = launch_sweep<2, S>(p, hydro, bcell, f + 10 * N, f + 19 * N, nullptr)) != WM_OK) return s;
+  if ((s = launch_sweep<0, S>(p, hydro, bcell, f, f + 15 * N, nullptr, smax)) != WM_OK) return s;
+  if ((s = launch_sweep<1, S>(p, hydro, bcell, f + 5 * N, f + 17 * N, nullptr, s1)) != WM_OK) return s;
+  if ((s = launch_sweep<2, S>(p, hydro, bcell, f + 10 * N, f + 19 * N, nullptr, s2)) != WM_OK) return s;
   return WM_OK;
 }
 
@@ -753,27 +772,53 @@ wm_status wm_compute_dt(wm_patch* p, double* dt_host) {
   return WM_OK;
 }
 
-wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
-  wm_status s = check_bound(p);
-  if (s != WM_OK) return s;
+namespace {
+
+// The fused time step: the sweeps of a step's first stage write per-wave
+// maxima of the eq. (cfl) signal speed (4 per block) into the accumulator
+// region (free until that stage's update writes it), and speed_blocks_kernel +
+// dt_final_kernel turn them into dt before the update.  Returns the number of
+// wave values, or 0 when they do not fit there, in which case the step runs the
+// stand-alone time-step pass first (only grids with rows of one or two zones).
+size_t fused_dt_blocks(const wm_patch* p) {
+  const size_t nb =
+      4 * (sweep_blocks(sweep_grid<0>(p)) + sweep_blocks(sweep_grid<1>(p)) + sweep_blocks(sweep_grid<2>(p)));
+  const size_t acc_bytes = 8 * p->g.N * (p->f32 ? sizeof(float) : sizeof(double));
+  // (at most 2^31 values: the kernels index them in 32 bits)
+  return nb * sizeof(SpeedKey) <= acc_bytes && nb <= (size_t(1) << 31) ? nb : 0;
+}
+
+wm_status launch_fused_dt(wm_patch* p) {
+  const unsigned n0 = (unsigned)(4 * sweep_blocks(sweep_grid<0>(p))),
+                 n1 = (unsigned)(4 * sweep_blocks(sweep_grid<1>(p))),
+                 n2 = (unsigned)(4 * sweep_blocks(sweep_grid<2>(p)));
+  const unsigned nmax = std::max(n0, std::max(n1, n2));
+  const int nb = (int)std::min<unsigned>((nmax + RED_THREADS - 1) / RED_THREADS, (unsigned)RED_BLOCKS);
+  const long r = prof_begin(p, K_DT);
+  hipLaunchKernelGGL(speed_blocks_kernel, dim3(nb), dim3(RED_THREADS), 0, p->stream,
+                     reinterpret_cast<const SpeedKey*>(p->acc<char>()), n0, n1, n2, p->speed_part());
+  WM_LAUNCH_CHECK("speed blocks kernel");
+  hipLaunchKernelGGL(dt_final_kernel, dim3(1), dim3(RED_THREADS), 0, p->stream, nb, p->cfg.cfl * p->cfg.h,
+                     p->speed_part(), p->dt_dev(), p->smax_dev());
+  WM_LAUNCH_CHECK("dt kernel");
+  prof_end(p, r);
+  p->dt_valid = true;
+  return WM_OK;
+}
+
+// One stage (after the caller's checks); fuse_dt (stage 0 only): dt from the
+// stage's own sweeps
+wm_status run_stage(wm_patch* p, int stage, bool fuse_dt) {
   const int ns = n_stages(p);
-  if (stage < 0 || stage >= ns) return fail(WM_ERR_ARG, "stage out of range for the integrator (SSP-RK3: 0..2, RK4: 0..3)");
-  if (stage > 0 && p->stage_done != stage - 1) return fail(WM_ERR_STATE, "stages must run in order from 0");
-  if (dt_host) {
-    if (!std::isfinite(*dt_host)) return fail(WM_ERR_ARG, "dt is not finite");
-    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, p->dt_dev(), *dt_host);
-    WM_LAUNCH_CHECK("set dt");
-    p->dt_valid = true;
-  } else if (!p->dt_valid) {
-    return fail(WM_ERR_STATE, "no dt: call wm_compute_dt or pass dt");
-  }
   const size_t N = p->g.N;
-  s = with_storage(p, [&](auto tag) -> wm_status {
+  wm_status s = with_storage(p, [&](auto tag) -> wm_status {
     using S = decltype(tag);
     const S* hyd_in = stage == 0 ? p->hyd<S>() : p->us<S>();
     const S* bcell_in = stage == 0 ? p->bc<S>() : p->us<S>() + 8 * N;
     wm_status st;
-    if ((st = sweeps<S>(p, hyd_in, bcell_in)) != WM_OK) return st;
+    SpeedKey* smax = fuse_dt ? reinterpret_cast<SpeedKey*>(p->acc<char>()) : nullptr;
+    if ((st = sweeps<S>(p, hyd_in, bcell_in, smax)) != WM_OK) return st;
+    if (fuse_dt && (st = launch_fused_dt(p)) != WM_OK) return st;
     if ((st = launch_update<S>(p, stage, nullptr)) != WM_OK) return st;
     S* hyd_out = stage == ns - 1 ? p->hyd<S>() : p->us<S>();
     S* b_out = stage == ns - 1 ? p->bf<S>() : p->us<S>() + 5 * N;
@@ -791,19 +836,37 @@ wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
   return WM_OK;
 }
 
+}  // namespace
+
+wm_status wm_rk_stage(wm_patch* p, int stage, const double* dt_host) {
+  wm_status s = check_bound(p);
+  if (s != WM_OK) return s;
+  const int ns = n_stages(p);
+  if (stage < 0 || stage >= ns) return fail(WM_ERR_ARG, "stage out of range for the integrator (SSP-RK3: 0..2, RK4: 0..3)");
+  if (stage > 0 && p->stage_done != stage - 1) return fail(WM_ERR_STATE, "stages must run in order from 0");
+  if (dt_host) {
+    if (!std::isfinite(*dt_host)) return fail(WM_ERR_ARG, "dt is not finite");
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, p->stream, p->dt_dev(), *dt_host);
+    WM_LAUNCH_CHECK("set dt");
+    p->dt_valid = true;
+  } else if (!p->dt_valid) {
+    return fail(WM_ERR_STATE, "no dt: call wm_compute_dt or pass dt");
+  }
+  return run_stage(p, stage, false);
+}
+
 wm_status wm_step(wm_patch* p, double* dt_used) {
   wm_status s = check_bound(p);
   if (s != WM_OK) return s;
-  if ((s = wm_compute_dt(p, nullptr)) != WM_OK) return s;
+  p->stage_done = -1;
+  const bool fuse = fused_dt_blocks(p) > 0;
+  if (!fuse && (s = wm_compute_dt(p, nullptr)) != WM_OK) return s;
+  for (int st = 0; st < n_stages(p); ++st)
+    if ((s = run_stage(p, st, fuse && st == 0)) != WM_OK) return s;
   if (dt_used) {
     if ((s = hip_check(hipMemcpyAsync(dt_used, p->dt_dev(), sizeof(double), hipMemcpyDeviceToHost, p->stream),
                        "dt copy")) != WM_OK)
       return s;
-  }
-  p->stage_done = -1;
-  for (int st = 0; st < n_stages(p); ++st)
-    if ((s = wm_rk_stage(p, st, nullptr)) != WM_OK) return s;
-  if (dt_used) {
     if ((s = hip_check(hipStreamSynchronize(p->stream), "step sync")) != WM_OK) return s;
   }
   return WM_OK;

@@ -284,6 +284,40 @@ def test_full_size_sampled_256():
         say(f"  sample {c} ok")
 
 
+FUSED_DT_CASES = [
+    ("fp64", (37, 21, 19), dict()),
+    ("mixed", (37, 21, 19), dict(precision=B.WM_MIXED)),
+    ("f32state", (37, 21, 19), dict(precision=B.WM_MIXED_F32STATE)),
+    ("rk4-wenoz", (33, 24, 20), dict(integrator=B.WM_RK4, weights=B.WM_WENO_Z)),
+    ("walls", (22, 19, 20), dict(walls=(1, 0, 1))),
+    ("tiny", (3, 2, 5), dict(precision=B.WM_MIXED_F32STATE)),
+]
+
+
+@pytest.mark.parametrize("name,shape,kw", FUSED_DT_CASES, ids=[c[0] for c in FUSED_DT_CASES])
+def test_fused_dt_bitwise(name, shape, kw):
+    """A step takes the maxima of eq. (cfl) from its first stage's sweeps: its
+    dt, and the state after it, are bitwise those of the stand-alone time-step
+    pass (wm_compute_dt) followed by the stages with that dt, over three steps,
+    for every precision mode, RK4 with WENO-Z weights, walls, and a box smaller
+    than one tile in every direction."""
+    say(f"fused dt {name} {shape}")
+    nx, ny, nz = shape
+    f = fields(max(shape), seed=12, v_rms=1.0, crop=shape)
+    a = gpu_patch(f, **kw)
+    b = gpu_patch(f, **kw)
+    for n in range(3):
+        dt_b = b.compute_dt()
+        b.step_dt(dt_b)
+        dt_a = a.step(want_dt=True)
+        assert math.isfinite(dt_a) and dt_a > 0.0
+        assert dt_a == dt_b, (name, n, dt_a, dt_b)
+        sa, sb = a.state(), b.state()
+        for k in ("rho", "m", "E", "b"):
+            assert torch.equal(sa[k], sb[k]), (name, n, k)
+    say(f"  dt {dt_a:.17g} ok")
+
+
 def test_failure_injection_unphysical():
     """Host-side failure injection: a zone with E = 0 (negative gas pressure) and a
     zone with a NaN density are reported by the diagnostics -- WM_ERR_UNPHYSICAL
