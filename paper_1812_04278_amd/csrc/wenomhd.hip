@@ -779,7 +779,7 @@ namespace {
 // region (free until that stage's update writes it), and speed_blocks_kernel +
 // dt_final_kernel turn them into dt before the update.  Returns the number of
 // wave values, or 0 when they do not fit there, in which case the step runs the
-// stand-alone time-step pass first (only grids with rows of one or two zones).
+// stand-alone time-step pass first (very thin grids, e.g. 1 x 1 x n).
 size_t fused_dt_blocks(const wm_patch* p) {
   const size_t nb =
       4 * (sweep_blocks(sweep_grid<0>(p)) + sweep_blocks(sweep_grid<1>(p)) + sweep_blocks(sweep_grid<2>(p)));

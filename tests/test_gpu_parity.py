@@ -291,6 +291,8 @@ FUSED_DT_CASES = [
     ("rk4-wenoz", (33, 24, 20), dict(integrator=B.WM_RK4, weights=B.WM_WENO_Z)),
     ("walls", (22, 19, 20), dict(walls=(1, 0, 1))),
     ("tiny", (3, 2, 5), dict(precision=B.WM_MIXED_F32STATE)),
+    # the per-wave maxima do not fit the FP32 accumulator: the step takes the stand-alone pass
+    ("thin-f32", (1, 1, 16), dict(precision=B.WM_MIXED_F32STATE)),
 ]
 
 
@@ -299,8 +301,9 @@ def test_fused_dt_bitwise(name, shape, kw):
     """A step takes the maxima of eq. (cfl) from its first stage's sweeps: its
     dt, and the state after it, are bitwise those of the stand-alone time-step
     pass (wm_compute_dt) followed by the stages with that dt, over three steps,
-    for every precision mode, RK4 with WENO-Z weights, walls, and a box smaller
-    than one tile in every direction."""
+    for every precision mode, RK4 with WENO-Z weights, walls, a box smaller than
+    one tile in every direction, and a 1 x 1 x 16 FP32-state box, whose step falls
+    back to the stand-alone pass."""
     say(f"fused dt {name} {shape}")
     nx, ny, nz = shape
     f = fields(max(shape), seed=12, v_rms=1.0, crop=shape)
