@@ -321,6 +321,34 @@ def test_fused_dt_bitwise(name, shape, kw):
     say(f"  dt {dt_a:.17g} ok")
 
 
+@pytest.mark.parametrize("damage", ["zero_energy", "nan_density", "infinite_energy"])
+def test_fused_dt_damaged_state(damage):
+    """The failure semantics of the fused time step match the stand-alone pass:
+    a zone with E = 0 (negative gas pressure), a NaN density, or an infinite
+    energy gives a step whose dt is bitwise that of wm_compute_dt, or NaN on
+    both sides (a NaN density always gives NaN)."""
+    say(f"fused dt, damaged state: {damage}")
+    f = fields(16, seed=3, v_rms=0.3, kmax=2)
+    pa, pb = gpu_patch(f), gpu_patch(f)
+    st = pa.state()
+    rho, E = st["rho"].clone(), st["E"].clone()
+    if damage == "zero_energy":
+        E[3, 4, 5] = 0.0
+    elif damage == "nan_density":
+        rho[7, 8, 9] = float("nan")
+    else:
+        E[2, 2, 2] = float("inf")
+    for p in (pa, pb):
+        p.set_state(rho, st["m"], E, st["b"])
+    dt_b = pb.compute_dt()
+    dt_a = pa.step(want_dt=True)
+    if damage == "nan_density":
+        assert math.isnan(dt_a) and math.isnan(dt_b)
+    else:
+        assert dt_a == dt_b or (math.isnan(dt_a) and math.isnan(dt_b)), (dt_a, dt_b)
+    say(f"  dt step {dt_a!r}, stand-alone {dt_b!r}")
+
+
 def test_failure_injection_unphysical():
     """Host-side failure injection: a zone with E = 0 (negative gas pressure) and a
     zone with a NaN density are reported by the diagnostics -- WM_ERR_UNPHYSICAL
