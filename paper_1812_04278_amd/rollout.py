@@ -10,9 +10,11 @@ widened to FP64 (the cotangents are FP64 throughout).
 Memory: the forward keeps a checkpoint of the state every ``ckpt_every`` steps;
 the backward re-runs each segment forward from its checkpoint, keeping that
 segment's states (and, with ``store_stages``, the two intermediate RK stages of
-every step, so the adjoint step does not recompute them: 3 states of 8 fields
-per step of the segment; SSP-RK3 only -- the RK4 adjoint recomputes its three
-stage states), and walks it in reverse.  The forward pass keeps the states of
+every step but the segment's last, so the adjoint step does not recompute them:
+3 states of 8 fields per step of the segment; SSP-RK3 only -- the RK4 adjoint
+recomputes its three stage states), and walks it in reverse.  The segment's last
+step is not run forward: its adjoint step recomputes its two stage states, which
+saves the third stage, whose result is the next checkpoint.  The forward pass keeps the states of
 the last segment as it computes them (``keep_last``), so the backward starts
 without re-running that segment.  The time steps of the forward pass are
 recorded and held fixed in the backward (dt is not differentiated).
@@ -94,9 +96,12 @@ class Rollout(torch.autograd.Function):
                     n_run = n1 - n0
                 for n in range(n0, n0 + n_run):
                     Uh, Ub = p.hydro.clone(), p.bface.clone()
-                    if ctx.store_stages:
+                    if ctx.store_stages and n + 1 < n1:
                         U1, U2 = p.step_record(ctx.dts[n])
                     else:
+                        # the segment's last step (or every step without stored
+                        # stages): the adjoint step recomputes its stage states,
+                        # and the step's result, the next checkpoint, is not needed
                         U1 = U2 = None
                         if n + 1 < n1:
                             p.step_dt(ctx.dts[n])
